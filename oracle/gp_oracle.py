@@ -1,0 +1,540 @@
+"""CPU FP64 reference ("oracle") for the preconditioned GP log-marginal-likelihood
+estimator and its derivative (Wenger, Pleiss, Hennig, Cunningham, Gardner:
+"Preconditioning for Scalable Gaussian Process Hyperparameter Optimization").
+
+TEST INFRASTRUCTURE ONLY.  Nothing in the product path may import, call or link
+this module: only the tests, the smoke check and the benchmark's CPU-baseline leg
+use it.  It shares no code with the HIP path.
+
+Two parts:
+
+* exact_mll: the exact targets, Eq. (1) (log marginal likelihood) and Eq. (2)
+  (its derivative), by a dense FP64 Cholesky factorisation (LAPACK potrf).
+* estimate_mll: the stochastic estimator of Algorithms 1 and 2 (Section 4.4),
+  step by step in the paper's order, with dense or row-blocked matrix products:
+  partial pivoted Cholesky preconditioner P = sigma^2 I + L L^T (Section 2.2,
+  "Preconditioning"; supplement S5.3), solves with P through the matrix
+  inversion lemma, preconditioned CG on [y | probes] (one call with many right
+  hand sides, footnote to Section 4.4), the Lanczos tridiagonal from the CG
+  coefficients (supplement S1.2), Lanczos quadrature for the log (Section 2.2,
+  SLQ), the log-determinant decomposition (Section 3) and the derivative
+  decomposition (Section 3.3) with the trace of P^-1 dP computed by the matrix
+  inversion lemma (supplement S3.3).
+
+Readings taken where the paper is silent or loose (each is listed with its reason
+in the design notes):
+
+R-probe  Probes for the preconditioned quadrature are b_i = sigma*eps_i + L*eta_i
+         with Rademacher eps_i (length n) and eta_i (length k), so E[b b^T] = P.
+         Quadrature weight of probe i is rho0_i = b_i^T P^-1 b_i (the first r^T z
+         of preconditioned CG): gamma_i = rho0_i * sum_j tau_1j^2 log(theta_j).
+         This makes (1/ell) sum_i gamma_i unbiased for tr log(P^-1/2 K P^-T/2).
+R-quad   The quadrature sums over the m Ritz values of the m x m tridiagonal
+         produced by m CG steps (indices 1..m).
+R-grad   The derivative probes reuse the forward solves: with a_i = K^-1 b_i and
+         c_i = P^-1 b_i, gamma'_i = a_i^T dK c_i - c_i^T dP c_i, whose expectation
+         is tr(K^-1 dK) - tr(P^-1 dP), the residual trace of Section 3.3.
+R-dP     dP/dtheta of the pivoted Cholesky factor is taken with the pivots held
+         fixed; the rank-k partial pivoted Cholesky equals the Nystrom
+         approximation K_{:S} K_SS^-1 K_{S:} on its pivot set S.  Mode 1 keeps only
+         the outputscale and noise terms (dP/dls = 0); any fixed choice keeps the
+         estimator unbiased because the deterministic term and the control
+         variate cancel in expectation.
+R-chol   Greedy pivoting on the residual diagonal, ties to the lowest index; run
+         exactly k steps, stopping early only when the largest residual diagonal
+         is <= 1e-12 * s; L factors K without the noise term.
+R-cg     x0 = 0; a column stops after the iteration whose updated recurrence
+         residual satisfies ||r|| <= tol * ||b||; its alpha/beta stream ends there.
+R-kern   k(x, x') = s * kappa(r), r^2 = sum_j ((x_j - x'_j) / ls_j)^2, noise
+         sigma^2 on the diagonal; theta = [ls | s | sigma^2] natural parameters.
+R-ritz   Ritz values below 1e-300 are clamped to 1e-300 before the log.
+"""
+from __future__ import annotations
+
+import math
+from fractions import Fraction
+
+import numpy as np
+import scipy.linalg as sla
+
+KIND = {"rbf": 0, "matern32": 1, "matern52": 2}
+SQRT3 = math.sqrt(3.0)
+SQRT5 = math.sqrt(5.0)
+LOG2PI = math.log(2.0 * math.pi)
+PIVOT_BREAKDOWN = 1e-12
+RITZ_FLOOR = 1e-300
+
+
+# ----------------------------------------------------------------------------
+# Kernels (Section 2.1; forms of Rasmussen & Williams 2006, Sec. 4.2)
+# ----------------------------------------------------------------------------
+
+def split_theta(theta, d, ard):
+    theta = np.asarray(theta, dtype=np.float64)
+    p = d if ard else 1
+    if theta.shape != (p + 2,):
+        raise ValueError(f"theta must have {p + 2} entries, got {theta.shape}")
+    ls = np.broadcast_to(theta[:p], (d,)).copy()
+    return ls, float(theta[p]), float(theta[p + 1])
+
+
+def scaled_differences(X1, X2, ls):
+    """(x_p - x_q) / ls per dimension, by direct differences: shape (n1, n2, d)."""
+    return (X1[:, None, :] - X2[None, :, :]) / ls
+
+
+def sqdist(X1, X2, ls):
+    """r^2 by direct differences (no inner-product expansion)."""
+    D = scaled_differences(X1, X2, ls)
+    return np.einsum("pqj,pqj->pq", D, D)
+
+
+def kappa(kind, r2):
+    """Correlation kappa(r) of the stationary kernel, k = s * kappa."""
+    if kind == "rbf":
+        return np.exp(-0.5 * r2)
+    r = np.sqrt(r2)
+    if kind == "matern32":
+        return (1.0 + SQRT3 * r) * np.exp(-SQRT3 * r)
+    if kind == "matern52":
+        return (1.0 + SQRT5 * r + (5.0 / 3.0) * r2) * np.exp(-SQRT5 * r)
+    raise ValueError(kind)
+
+
+def gfun(kind, r2):
+    """g(r) with d kappa / d ls_j = g(r) * dtilde_j^2 / ls_j (dtilde = scaled diff)."""
+    if kind == "rbf":
+        return np.exp(-0.5 * r2)
+    r = np.sqrt(r2)
+    if kind == "matern32":
+        return 3.0 * np.exp(-SQRT3 * r)
+    if kind == "matern52":
+        return (5.0 / 3.0) * (1.0 + SQRT5 * r) * np.exp(-SQRT5 * r)
+    raise ValueError(kind)
+
+
+def kernel_matrix(X1, X2, theta, kind, ard):
+    """K(X1, X2) = s * kappa(r) (no noise)."""
+    ls, s, _ = split_theta(theta, X1.shape[1], ard)
+    return s * kappa(kind, sqdist(X1, X2, ls))
+
+
+def khat_dense(X, theta, kind, ard):
+    """K_hat = K(X, X) + sigma^2 I (Section 2.1)."""
+    ls, s, s2 = split_theta(theta, X.shape[1], ard)
+    K = kernel_matrix(X, X, theta, kind, ard)
+    K[np.diag_indices_from(K)] += s2
+    return K
+
+
+def _row_block(n, d, budget=4e7):
+    return max(1, int(budget // max(1, n * d)))
+
+
+def khat_matvec(X, theta, kind, ard, V, rows=None):
+    """K_hat[rows, :] @ V with K_hat rows built block by block (matrix-free for large n)."""
+    n, d = X.shape
+    ls, s, s2 = split_theta(theta, d, ard)
+    V = np.asarray(V, dtype=np.float64)
+    rows = np.arange(n) if rows is None else np.asarray(rows)
+    out = np.empty((rows.size,) + V.shape[1:])
+    blk = _row_block(n, d)
+    for lo in range(0, rows.size, blk):
+        r = rows[lo:lo + blk]
+        Kb = s * kappa(kind, sqdist(X[r], X, ls))
+        out[lo:lo + blk] = Kb @ V
+        out[lo:lo + blk] += s2 * V[r]
+    return out
+
+
+def dkhat_contract(X, theta, kind, ard, m_rows):
+    """sum_pq M_pq dK_hat_pq / dtheta for every theta, with M given block-of-rows
+    at a time by m_rows(rows) -> (|rows|, n).  Order of the result follows theta."""
+    n, d = X.shape
+    ls, s, s2 = split_theta(theta, d, ard)
+    p = d if ard else 1
+    out = np.zeros(p + 2)
+    blk = _row_block(n, d)
+    for lo in range(0, n, blk):
+        r = np.arange(lo, min(n, lo + blk))
+        Dt = scaled_differences(X[r], X, ls)
+        r2 = np.einsum("pqj,pqj->pq", Dt, Dt)
+        M = m_rows(r)
+        W = s * gfun(kind, r2) * M
+        per_dim = np.einsum("pq,pqj->j", W, Dt * Dt) / ls
+        if ard:
+            out[:p] += per_dim
+        else:
+            out[0] += per_dim.sum()
+        out[p] += np.sum(kappa(kind, r2) * M)
+        out[p + 1] += np.sum(M[np.arange(r.size), r])
+    return out
+
+
+def dkernel_cols(X, theta, kind, ard, cols):
+    """dK[:, cols]/dtheta for the kernel parameters (ls..., s): list of (n, |cols|)."""
+    n, d = X.shape
+    ls, s, _ = split_theta(theta, d, ard)
+    Dt = scaled_differences(X, X[cols], ls)
+    r2 = np.einsum("pqj,pqj->pq", Dt, Dt)
+    g = s * gfun(kind, r2)
+    mats = []
+    if ard:
+        for j in range(d):
+            mats.append(g * Dt[:, :, j] ** 2 / ls[j])
+    else:
+        mats.append(g * r2 / ls[0])
+    mats.append(kappa(kind, r2))
+    return mats
+
+
+# ----------------------------------------------------------------------------
+# Exact targets: Eq. (1) and Eq. (2) via dense Cholesky
+# ----------------------------------------------------------------------------
+
+def exact_mll(X, y, theta, kind, ard):
+    """Exact log p(y | theta) (Eq. 1) and its gradient (Eq. 2) in FP64."""
+    n, d = X.shape
+    Kh = khat_dense(X, theta, kind, ard)
+    R = sla.cholesky(Kh, lower=True, overwrite_a=False, check_finite=True)
+    logdet = 2.0 * np.sum(np.log(np.diag(R)))
+    u = sla.cho_solve((R, True), y)
+    datafit = float(y @ u)
+    logp = -0.5 * (datafit + logdet + n * LOG2PI)
+    Kinv = sla.cho_solve((R, True), np.eye(n))
+    del Kh, R
+    # dL/dtheta = sum_pq dK_hat_pq (u_p u_q / 2 - Kinv_pq / 2)
+    grad = dkhat_contract(X, theta, kind, ard,
+                          lambda r: 0.5 * np.outer(u[r], u) - 0.5 * Kinv[r])
+    return {"logp": logp, "grad": grad, "logdet": logdet, "datafit": datafit, "u": u}
+
+
+def bareiss_det(A):
+    """Exact determinant of a rational matrix by fraction-free Bareiss elimination."""
+    M = [[Fraction(v) for v in row] for row in A]
+    n = len(M)
+    sign, prev = 1, Fraction(1)
+    for k in range(n - 1):
+        if M[k][k] == 0:
+            swap = next((i for i in range(k + 1, n) if M[i][k] != 0), None)
+            if swap is None:
+                return Fraction(0)
+            M[k], M[swap] = M[swap], M[k]
+            sign = -sign
+        for i in range(k + 1, n):
+            for j in range(k + 1, n):
+                M[i][j] = (M[i][j] * M[k][k] - M[i][k] * M[k][j]) / prev
+        prev = M[k][k]
+    return sign * M[n - 1][n - 1]
+
+
+# ----------------------------------------------------------------------------
+# Counter-based Rademacher signs: SplitMix64 (Steele, Lea & Flood 2014)
+# ----------------------------------------------------------------------------
+
+_GAMMA = np.uint64(0x9E3779B97F4A7C15)
+_M1 = np.uint64(0xBF58476D1CE4E5B9)
+_M2 = np.uint64(0x94D049BB133111EB)
+
+
+def splitmix64(seed, counter):
+    """Output number `counter` (0-based) of SplitMix64 started from state `seed`:
+    mix(seed + (counter + 1) * golden_gamma), with the 64-bit finaliser whose
+    shifts are 30, 27, 31."""
+    with np.errstate(over="ignore"):
+        c = np.asarray(counter, dtype=np.uint64)
+        z = np.uint64(seed) + (c + np.uint64(1)) * _GAMMA
+        z = (z ^ (z >> np.uint64(30))) * _M1
+        z = (z ^ (z >> np.uint64(27))) * _M2
+        return z ^ (z >> np.uint64(31))
+
+
+def rademacher(seed, stream, col, count):
+    """Signs for probe column `col`: entry i is +1 when the top bit of SplitMix64
+    output (stream << 56 | col << 32 | i) is clear, else -1.  stream 0 feeds the
+    n-vector eps, stream 1 the k-vector eta."""
+    base = (np.uint64(stream) << np.uint64(56)) | (np.uint64(col) << np.uint64(32))
+    ctr = base + np.arange(count, dtype=np.uint64)
+    top = splitmix64(seed, ctr) >> np.uint64(63)
+    return 1.0 - 2.0 * top.astype(np.float64)
+
+
+def probe_signs(seed, n, k, ell):
+    E = np.stack([rademacher(seed, 0, i, n) for i in range(ell)], axis=1) if ell else np.zeros((n, 0))
+    H = np.stack([rademacher(seed, 1, i, k) for i in range(ell)], axis=1) if ell else np.zeros((k, 0))
+    return E, H
+
+
+# ----------------------------------------------------------------------------
+# Partial pivoted Cholesky and the diagonal-plus-low-rank preconditioner
+# ----------------------------------------------------------------------------
+
+def pivoted_cholesky(X, theta, kind, ard, k):
+    """Greedy partial pivoted Cholesky of K (noise excluded), R-chol.
+    Returns L (n, k) with zero columns after an early stop, pivots, achieved rank."""
+    n, d = X.shape
+    ls, s, _ = split_theta(theta, d, ard)
+    L = np.zeros((n, k))
+    diag = np.full(n, s)
+    piv = []
+    for j in range(k):
+        i = int(np.argmax(diag))
+        if not diag[i] > PIVOT_BREAKDOWN * s:
+            break
+        piv.append(i)
+        kcol = s * kappa(kind, sqdist(X, X[i:i + 1], ls)[:, 0])
+        col = kcol - L[:, :j] @ L[i, :j]
+        pivot_val = math.sqrt(diag[i])
+        L[:, j] = col / pivot_val
+        L[i, j] = pivot_val
+        L[piv[:-1], j] = 0.0
+        diag -= L[:, j] ** 2
+        diag[piv] = 0.0
+    return L, np.array(piv, dtype=np.int64), len(piv)
+
+
+class Preconditioner:
+    """P = sigma^2 I + L L^T, solves by the matrix inversion lemma and its
+    log-determinant by the matrix determinant lemma."""
+
+    def __init__(self, L, sigma2):
+        self.L = L
+        self.s2 = float(sigma2)
+        n, k = L.shape
+        self.C = self.s2 * np.eye(k) + L.T @ L
+        self.Rc = sla.cholesky(self.C, lower=True) if k else np.zeros((0, 0))
+        self.logdet = (n - k) * math.log(self.s2) + 2.0 * float(np.sum(np.log(np.diag(self.Rc))))
+
+    def Cinv(self, V):
+        return sla.cho_solve((self.Rc, True), V) if self.L.shape[1] else V[:0]
+
+    def solve(self, V):
+        """P^-1 V = sigma^-2 (V - L C^-1 L^T V)."""
+        if self.L.shape[1] == 0:
+            return V / self.s2
+        return (V - self.L @ self.Cinv(self.L.T @ V)) / self.s2
+
+    def dense(self):
+        n = self.L.shape[0]
+        return self.s2 * np.eye(n) + self.L @ self.L.T
+
+
+# ----------------------------------------------------------------------------
+# Preconditioned CG, one column at a time (R-cg), and the Lanczos tridiagonal
+# ----------------------------------------------------------------------------
+
+def pcg(matvec, b, psolve, tol, max_iters, callback=None):
+    """Preconditioned CG for K_hat x = b from x0 = 0.  Returns x, the step lengths
+    alpha_j, the conjugacy coefficients beta_j, rho0 = b^T P^-1 b and the final
+    recurrence residual norm.  callback(x) sees every iterate."""
+    x = np.zeros_like(b)
+    r = b.copy()
+    bnorm = float(np.linalg.norm(b))
+    z = psolve(r)
+    p = z.copy()
+    rho = float(r @ z)
+    rho0 = rho
+    alphas, betas = [], []
+    if bnorm == 0.0:
+        return x, np.array(alphas), np.array(betas), rho0, 0.0
+    for _ in range(max_iters):
+        w = matvec(p)
+        pw = float(p @ w)
+        if not pw > 0.0:
+            raise FloatingPointError("p^T K_hat p <= 0: K_hat not positive definite")
+        alpha = rho / pw
+        x += alpha * p
+        r -= alpha * w
+        alphas.append(alpha)
+        if callback is not None:
+            callback(x.copy())
+        if np.linalg.norm(r) <= tol * bnorm:
+            break
+        z = psolve(r)
+        rho_new = float(r @ z)
+        beta = rho_new / rho
+        betas.append(beta)
+        p = z + beta * p
+        rho = rho_new
+    return x, np.array(alphas), np.array(betas), rho0, float(np.linalg.norm(r))
+
+
+def pcg_block(matvec, Bmat, psolve, tol, max_iters):
+    """The same recurrences as pcg, run on every column of Bmat at once: one
+    product with K_hat per iteration serves all still-active columns, and a
+    column that has met its tolerance is frozen.  Returns the solutions, the
+    per-column (alphas, betas), rho0 and final recurrence residual norms."""
+    n, t = Bmat.shape
+    Xs = np.zeros_like(Bmat)
+    R = Bmat.copy()
+    bnorm = np.linalg.norm(Bmat, axis=0)
+    Z = psolve(R)
+    Pd = Z.copy()
+    rho = np.einsum("ij,ij->j", R, Z)
+    rho0 = rho.copy()
+    alphas = [[] for _ in range(t)]
+    betas = [[] for _ in range(t)]
+    active = bnorm > 0.0
+    for _ in range(max_iters):
+        idx = np.flatnonzero(active)
+        if idx.size == 0:
+            break
+        W = matvec(Pd[:, idx])
+        pw = np.einsum("ij,ij->j", Pd[:, idx], W)
+        if not np.all(pw > 0.0):
+            raise FloatingPointError("p^T K_hat p <= 0: K_hat not positive definite")
+        alpha = rho[idx] / pw
+        Xs[:, idx] += alpha * Pd[:, idx]
+        R[:, idx] -= alpha * W
+        for j, c in enumerate(idx):
+            alphas[c].append(alpha[j])
+        done = np.linalg.norm(R[:, idx], axis=0) <= tol * bnorm[idx]
+        active[idx[done]] = False
+        idx = idx[~done]
+        if idx.size == 0:
+            break
+        Zi = psolve(R[:, idx])
+        rho_new = np.einsum("ij,ij->j", R[:, idx], Zi)
+        beta = rho_new / rho[idx]
+        for j, c in enumerate(idx):
+            betas[c].append(beta[j])
+        Pd[:, idx] = Zi + beta * Pd[:, idx]
+        rho[idx] = rho_new
+    coeffs = [(np.array(alphas[c]), np.array(betas[c])) for c in range(t)]
+    return Xs, coeffs, rho0, np.linalg.norm(R, axis=0)
+
+
+def lanczos_tridiag(alphas, betas):
+    """Lanczos tridiagonal of the preconditioned operator from m CG steps
+    (supplement S1.2, citing Saad 2003, Sec. 6.7.3):
+      T_11 = 1/a_0,  T_jj = 1/a_j + b_{j-1}/a_{j-1},  T_{j,j+1} = sqrt(b_{j-1})/a_{j-1}."""
+    m = len(alphas)
+    diag = np.empty(m)
+    off = np.empty(max(0, m - 1))
+    diag[0] = 1.0 / alphas[0]
+    for j in range(1, m):
+        diag[j] = 1.0 / alphas[j] + betas[j - 1] / alphas[j - 1]
+        off[j - 1] = math.sqrt(betas[j - 1]) / alphas[j - 1]
+    return diag, off
+
+
+def slq_log(alphas, betas, rho0):
+    """Lanczos quadrature for b^T P^-1/2 log(P^-1/2 K P^-T/2) P^-T/2 b with nodes
+    theta_j (Ritz values) and weights tau_1j^2 from the eigendecomposition of T
+    (Algorithm 1, scaled by rho0 per R-probe).  Returns (gamma, #clamped)."""
+    if len(alphas) == 0:
+        return 0.0, 0
+    diag, off = lanczos_tridiag(alphas, betas)
+    if len(diag) == 1:
+        lam, tau1 = diag.copy(), np.ones(1)
+    else:
+        lam, vec = sla.eigh_tridiagonal(diag, off)
+        tau1 = vec[0, :]
+    clamped = int(np.sum(lam < RITZ_FLOOR))
+    lam = np.maximum(lam, RITZ_FLOOR)
+    return float(rho0 * np.sum(tau1 ** 2 * np.log(lam))), clamped
+
+
+# ----------------------------------------------------------------------------
+# Algorithms 1 and 2 with the readings above
+# ----------------------------------------------------------------------------
+
+def _precond_terms(X, theta, kind, ard, L, piv, kp, P, Cs, mode):
+    """tr(P^-1 dP/dtheta) by the matrix-inversion-lemma formula of supplement S3.3
+    and the control variates c_i^T dP c_i, for every theta (R-dP)."""
+    n, d = X.shape
+    ls, s, s2 = split_theta(theta, d, ard)
+    p = d if ard else 1
+    Lk = L[:, :kp]
+    ell = Cs.shape[1]
+    tr = np.zeros(p + 2)
+    ctrl = np.zeros((p + 2, ell))
+    # noise: dP/dsigma^2 = I
+    LCinv = P.Cinv(Lk.T).T if kp else np.zeros((n, 0))          # L C^-1
+    tr[p + 1] = (n - np.sum(LCinv * Lk)) / s2
+    ctrl[p + 1] = np.sum(Cs * Cs, axis=0)
+    if kp == 0:
+        return tr, ctrl
+    LS = Lk[piv[:kp], :]                                          # lower triangular
+    dcols = dkernel_cols(X, theta, kind, ard, piv[:kp])           # dK[:, S] per kernel theta
+    LtC = Lk.T @ Cs
+    LtL = Lk.T @ Lk
+    for idx, dKS in enumerate(dcols):
+        if mode == 1 and idx < p:
+            continue
+        E = sla.solve_triangular(LS, dKS.T, lower=True).T        # dK_{:S} L_S^-T
+        F = sla.solve_triangular(LS, sla.solve_triangular(LS, dKS[piv[:kp], :].T, lower=True).T,
+                                 lower=True)                     # L_S^-1 dK_SS L_S^-T
+        F = 0.5 * (F + F.T)
+        diag_dP = 2.0 * np.sum(E * Lk, axis=1) - np.sum((Lk @ F) * Lk, axis=1)
+        dP_L = E @ LtL + Lk @ (E.T @ Lk) - Lk @ (F @ LtL)
+        tr[idx] = (np.sum(diag_dP) - np.sum(LCinv * dP_L)) / s2
+        EtC = E.T @ Cs
+        ctrl[idx] = 2.0 * np.sum(LtC * EtC, axis=0) - np.sum(LtC * (F @ LtC), axis=0)
+    return tr, ctrl
+
+
+def estimate_mll(X, y, theta, kind, ard, rank, num_probes, tol, max_iters, seed,
+                 grad=True, precond_grad=0, signs=None, dense=None):
+    """Preconditioned estimate of log p (Algorithm 1) and, if grad, of its
+    derivative (Algorithm 2) under the readings in the module docstring.
+
+    signs: optional (E, H) Rademacher arrays of shapes (n, ell), (rank, ell)
+    replacing the SplitMix64 stream.  dense: force (True) or forbid (False) a
+    dense K_hat; default dense for n <= 20000."""
+    X = np.ascontiguousarray(X, dtype=np.float64)
+    y = np.asarray(y, dtype=np.float64)
+    n, d = X.shape
+    ls, s, s2 = split_theta(theta, d, ard)
+    if dense is None:
+        dense = n <= 20000
+    Kh = khat_dense(X, theta, kind, ard) if dense else None
+
+    def matvec(V):
+        return Kh @ V if dense else khat_matvec(X, theta, kind, ard, V)
+
+    # preconditioner (pivoted Cholesky) and log det P
+    L, piv, kp = pivoted_cholesky(X, theta, kind, ard, rank)
+    P = Preconditioner(L[:, :kp], s2)
+
+    # probes b_i = sigma eps_i + L eta_i (R-probe)
+    if signs is None:
+        E, H = probe_signs(seed, n, rank, num_probes)
+    else:
+        E, H = signs
+    ell = E.shape[1]
+    B = math.sqrt(s2) * E + L @ H[:rank] if rank else math.sqrt(s2) * E
+    rhs = np.concatenate([y[:, None], B], axis=1)
+
+    # one CG call over all right hand sides (footnote to Section 4.4)
+    t = rhs.shape[1]
+    Xs, coeffs, rho0, resid = pcg_block(matvec, rhs, P.solve, tol, max_iters)
+    iters = np.array([len(a) for a, _ in coeffs], dtype=np.int64)
+
+    gammas = np.zeros(ell)
+    clamped = 0
+    for i in range(ell):
+        a, b = coeffs[i + 1]
+        gammas[i], cl = slq_log(a, b, rho0[i + 1])
+        clamped += cl
+    u = Xs[:, 0]
+    datafit = float(y @ u)
+    logdet_est = P.logdet + (gammas.mean() if ell else 0.0)
+    logp = -0.5 * (datafit + logdet_est + n * LOG2PI)
+    out = {"logp": logp, "datafit": datafit, "logdet_est": logdet_est, "logdet_P": P.logdet,
+           "gammas": gammas, "rho0": rho0, "iters": iters, "coeffs": coeffs, "L": L,
+           "piv": piv, "rank": kp, "solves": Xs, "B": B, "rel_resid": resid / np.maximum(
+               np.linalg.norm(rhs, axis=0), 1e-300), "ritz_clamped": clamped}
+    if not grad:
+        return out
+
+    # derivative (Algorithm 2, R-grad): M = A' C'^T with A' = [u | a_i],
+    # C' = [u/2 | -c_i/(2 ell)]; c_i = P^-1 b_i
+    Cs = P.solve(B)
+    A1 = Xs
+    C1 = np.concatenate([0.5 * u[:, None], -Cs / (2.0 * ell)], axis=1)
+    bil = dkhat_contract(X, theta, kind, ard, lambda r: A1[r] @ C1.T)
+    tr, ctrl = _precond_terms(X, theta, kind, ard, L, piv, kp, P, Cs, precond_grad)
+    g = bil - 0.5 * tr + ctrl.sum(axis=1) / (2.0 * ell)
+    out.update({"grad": g, "bilinear": bil, "tr_precond": tr, "ctrl": ctrl, "precond_solves": Cs})
+    return out

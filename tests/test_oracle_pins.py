@@ -1,0 +1,387 @@
+"""Pins of the CPU oracle against facts the paper and the mathematics fix.
+
+Each test checks an oracle function against something other than itself: an
+exact rational determinant, finite differences, a library routine for a special
+case, an exact expectation over every Rademacher pattern, a closed-form variance,
+or a convergence bound stated in the paper.
+"""
+import itertools
+import math
+import os
+
+import numpy as np
+import pytest
+import scipy.linalg as sla
+import scipy.special as sps
+from scipy.spatial.distance import cdist
+
+from oracle import gp_oracle as go
+import synthgp
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _problem(n, d, kind="rbf", ard=True, seed=0, sigma2=0.05, ls=(0.4, 1.2), dist="uniform"):
+    pr = synthgp.random_problem(n, d, kind, ard, seed=seed, sigma2=sigma2, ls_range=ls, dist=dist)
+    return pr.X, pr.y, pr.theta
+
+
+# ---------------------------------------------------------------- generator
+
+def test_splitmix64_matches_reference_outputs():
+    vals = [int(l, 16) for l in open(os.path.join(GOLDEN, "splitmix64_seed0.txt"))
+            if l.strip() and not l.startswith("#")]
+    got = [int(go.splitmix64(0, i)) for i in range(len(vals))]
+    assert got == vals
+
+
+def test_rademacher_is_balanced_and_stream_separated():
+    e = go.rademacher(7, 0, 3, 200000)
+    assert set(np.unique(e)) == {-1.0, 1.0}
+    assert abs(e.mean()) < 4.0 / math.sqrt(e.size)
+    h = go.rademacher(7, 1, 3, 200000)
+    assert abs(np.mean(e * h)) < 4.0 / math.sqrt(e.size)
+
+
+# ---------------------------------------------------------------- kernels
+
+def test_sqdist_matches_scipy_cdist():
+    rng = np.random.default_rng(3)
+    X1, X2 = rng.standard_normal((17, 5)), rng.standard_normal((9, 5))
+    ls = np.array([0.5, 1.0, 2.0, 0.7, 1.3])
+    np.testing.assert_allclose(go.sqdist(X1, X2, ls), cdist(X1 / ls, X2 / ls, "sqeuclidean"),
+                               rtol=1e-13, atol=1e-13)
+
+
+@pytest.mark.parametrize("kind,nu", [("matern32", 1.5), ("matern52", 2.5)])
+def test_matern_closed_forms_match_bessel_definition(kind, nu):
+    # Matern-nu: 2^(1-nu)/Gamma(nu) (sqrt(2 nu) r)^nu K_nu(sqrt(2 nu) r)
+    r = np.linspace(1e-3, 6.0, 400)
+    z = math.sqrt(2 * nu) * r
+    ref = 2 ** (1 - nu) / sps.gamma(nu) * z ** nu * sps.kv(nu, z)
+    np.testing.assert_allclose(go.kappa(kind, r * r), ref, rtol=1e-12, atol=1e-15)
+
+
+def test_rbf_is_matern_limit():
+    # Matern-nu -> RBF as nu -> infinity; nu = 60 agrees to ~1e-2 near r = 1
+    r = np.linspace(0.05, 2.0, 50)
+    nu = 60.0
+    z = math.sqrt(2 * nu) * r
+    mat = np.exp((1 - nu) * math.log(2) - sps.gammaln(nu) + nu * np.log(z)) * sps.kve(nu, z) * np.exp(-z)
+    np.testing.assert_allclose(go.kappa("rbf", r * r), mat, rtol=2e-2)
+
+
+@pytest.mark.parametrize("kind", ["rbf", "matern32", "matern52"])
+@pytest.mark.parametrize("ard", [True, False])
+def test_kernel_derivative_entries_match_finite_differences(kind, ard):
+    X, _, theta = _problem(12, 3, kind, ard, seed=1)
+    cols = np.array([0, 4, 7])
+    mats = go.dkernel_cols(X, theta, kind, ard, cols)
+    p = len(theta) - 2
+    for i in range(p + 1):
+        h = 1e-6 * theta[i]
+        tp, tm = theta.copy(), theta.copy()
+        tp[i] += h
+        tm[i] -= h
+        fd = (go.kernel_matrix(X, X[cols], tp, kind, ard) - go.kernel_matrix(X, X[cols], tm, kind, ard)) / (2 * h)
+        np.testing.assert_allclose(mats[i], fd, rtol=1e-6, atol=1e-9)
+
+
+# ---------------------------------------------------------------- exact targets
+
+def test_cholesky_logdet_matches_exact_rational_determinant():
+    X, y, theta = _problem(7, 2, "rbf", True, seed=2, sigma2=0.3)
+    Kh = go.khat_dense(X, theta, "rbf", True)
+    det = go.bareiss_det(Kh.tolist())
+    assert det > 0
+    exact_logdet = math.log(det.numerator) - math.log(det.denominator)
+    got = go.exact_mll(X, y, theta, "rbf", True)["logdet"]
+    assert abs(got - exact_logdet) <= 1e-13 * max(1.0, abs(exact_logdet))
+    assert abs(np.linalg.slogdet(Kh)[1] - exact_logdet) <= 1e-12 * max(1.0, abs(exact_logdet))
+
+
+def test_exact_solve_residual():
+    X, y, theta = _problem(300, 3, "matern32", True, seed=3, sigma2=0.01)
+    ex = go.exact_mll(X, y, theta, "matern32", True)
+    Kh = go.khat_dense(X, theta, "matern32", True)
+    assert np.linalg.norm(Kh @ ex["u"] - y) / np.linalg.norm(y) <= 1e-12
+
+
+@pytest.mark.parametrize("kind", ["rbf", "matern32", "matern52"])
+@pytest.mark.parametrize("ard", [True, False])
+def test_exact_gradient_matches_central_differences(kind, ard):
+    X, y, theta = _problem(40, 3, kind, ard, seed=4, sigma2=0.05)
+    g = go.exact_mll(X, y, theta, kind, ard)["grad"]
+    for i in range(len(theta)):
+        h = 1e-5 * theta[i]
+        tp, tm = theta.copy(), theta.copy()
+        tp[i] += h
+        tm[i] -= h
+        fd = (go.exact_mll(X, y, tp, kind, ard)["logp"] - go.exact_mll(X, y, tm, kind, ard)["logp"]) / (2 * h)
+        assert abs(g[i] - fd) <= 1e-6 * max(1.0, abs(fd)), (i, g[i], fd)
+
+
+# ---------------------------------------------------------------- preconditioner
+
+def test_pivoted_cholesky_is_nystrom_on_its_pivots():
+    X, _, theta = _problem(80, 2, "matern52", True, seed=5)
+    L, piv, kp = go.pivoted_cholesky(X, theta, "matern52", True, 12)
+    assert kp == 12 and len(set(piv.tolist())) == 12
+    K = go.kernel_matrix(X, X, theta, "matern52", True)
+    KS = K[:, piv]
+    ny = KS @ np.linalg.solve(K[np.ix_(piv, piv)], KS.T)
+    np.testing.assert_allclose(L @ L.T, ny, atol=1e-10)
+    # L restricted to the pivot rows, in pivot order, is lower triangular
+    LS = L[piv, :]
+    assert np.all(np.triu(LS, 1) == 0.0)
+    # residual diagonal stays non-negative
+    assert np.min(np.diag(K - L @ L.T)) >= -1e-12
+
+
+def test_pivoted_cholesky_trace_decreases_and_full_rank_reproduces_K():
+    X, _, theta = _problem(30, 2, "rbf", True, seed=6, ls=(0.05, 0.1))
+    K = go.kernel_matrix(X, X, theta, "rbf", True)
+    traces = []
+    for k in range(0, 31, 3):
+        L, piv, kp = go.pivoted_cholesky(X, theta, "rbf", True, k)
+        traces.append(np.trace(K - L @ L.T))
+    assert all(b <= a + 1e-12 for a, b in zip(traces, traces[1:]))
+    L, piv, kp = go.pivoted_cholesky(X, theta, "rbf", True, 30)
+    assert kp == 30
+    np.testing.assert_allclose(L @ L.T, K, atol=1e-10)
+
+
+def test_pivoted_cholesky_rbf_1d_decays_exponentially():
+    # supplement S5.3 (Cholesky approximation quality): exponential decay for a 1-D RBF kernel
+    rng = np.random.default_rng(7)
+    X = rng.uniform(0, 1, size=(400, 1))
+    theta = np.array([0.3, 1.0, 0.01])
+    K = go.kernel_matrix(X, X, theta, "rbf", False)
+    res = []
+    for k in (2, 4, 6, 8, 10, 12):
+        L, _, _ = go.pivoted_cholesky(X, theta, "rbf", False, k)
+        res.append(np.trace(K - L @ L.T))
+    ratios = [b / a for a, b in zip(res, res[1:])]
+    assert max(ratios) < 0.1          # at least a factor 10 per two extra columns
+    assert res[-1] < 1e-8 * res[0]
+
+
+def test_pivot_breakdown_on_duplicate_points():
+    X = np.repeat(np.array([[0.1, 0.2], [0.5, 0.9], [0.8, 0.3]]), 4, axis=0)
+    theta = np.array([0.5, 1.0, 0.1])
+    L, piv, kp = go.pivoted_cholesky(X, theta, "rbf", False, 6)
+    assert kp == 3
+    assert np.all(L[:, 3:] == 0.0)
+
+
+def test_woodbury_solve_and_determinant_lemma():
+    X, _, theta = _problem(60, 3, "rbf", True, seed=8, sigma2=0.02)
+    L, _, kp = go.pivoted_cholesky(X, theta, "rbf", True, 9)
+    P = go.Preconditioner(L, 0.02)
+    Pd = P.dense()
+    assert abs(P.logdet - np.linalg.slogdet(Pd)[1]) <= 1e-12 * abs(P.logdet)
+    V = np.random.default_rng(1).standard_normal((60, 4))
+    np.testing.assert_allclose(P.solve(V), np.linalg.solve(Pd, V), rtol=1e-11, atol=1e-11)
+
+
+# ---------------------------------------------------------------- CG and Lanczos
+
+def _tiny_system(n=30, seed=9, k=4, sigma2=0.05):
+    X, _, theta = _problem(n, 2, "matern32", True, seed=seed, sigma2=sigma2)
+    Kh = go.khat_dense(X, theta, "matern32", True)
+    L, _, _ = go.pivoted_cholesky(X, theta, "matern32", True, k)
+    return X, theta, Kh, go.Preconditioner(L, sigma2)
+
+
+def test_pcg_converges_in_n_steps_and_obeys_theorem_s1():
+    X, theta, Kh, P = _tiny_system()
+    n = Kh.shape[0]
+    Pd = P.dense()
+    lam = sla.eigh(Kh, Pd, eigvals_only=True)
+    kappa = lam.max() / lam.min()
+    assert kappa < 1e3
+    b = np.random.default_rng(0).standard_normal(n)
+    xs = np.linalg.solve(Kh, b)
+    rate = (math.sqrt(kappa) - 1) / (math.sqrt(kappa) + 1)
+    e0 = math.sqrt(xs @ Kh @ xs)
+    iterates = []
+    x, a, bb, rho0, _ = go.pcg(lambda v: Kh @ v, b.copy(), P.solve, 0.0, n, callback=iterates.append)
+    assert len(a) == n
+    assert np.linalg.norm(x - xs) / np.linalg.norm(xs) <= 1e-9
+    for m, xm in enumerate(iterates, start=1):
+        err = math.sqrt((xm - xs) @ Kh @ (xm - xs))
+        assert err <= 2.0 * rate ** m * e0 * (1 + 1e-8) + 1e-12
+
+
+def test_pcg_block_matches_single_column_pcg():
+    X, theta, Kh, P = _tiny_system(n=40, seed=10)
+    Bm = np.random.default_rng(2).standard_normal((40, 5))
+    Xs, coeffs, rho0, _ = go.pcg_block(lambda V: Kh @ V, Bm, P.solve, 1e-9, 100)
+    for c in range(5):
+        x, a, b, r0, _ = go.pcg(lambda v: Kh @ v, Bm[:, c].copy(), P.solve, 1e-9, 100)
+        # late CG coefficients amplify rounding differences (matrix-matrix vs
+        # matrix-vector products); the early ones, the solution and the
+        # quadrature value are stable
+        assert abs(len(a) - len(coeffs[c][0])) <= 2
+        np.testing.assert_allclose(Xs[:, c], x, rtol=1e-8, atol=1e-10)
+        np.testing.assert_allclose(coeffs[c][0][:8], a[:8], rtol=1e-9)
+        np.testing.assert_allclose(coeffs[c][1][:8], b[:8], rtol=1e-9)
+        assert abs(rho0[c] - r0) <= 1e-12 * abs(r0)
+        g1, _ = go.slq_log(coeffs[c][0], coeffs[c][1], rho0[c])
+        g2, _ = go.slq_log(a, b, r0)
+        assert abs(g1 - g2) <= 1e-7 * max(1.0, abs(g2))
+
+
+def test_gauss_quadrature_moment_identity():
+    # the m-point Lanczos (Gauss) rule from the CG coefficients integrates
+    # polynomials of degree <= 2m-1 exactly: rho0 e1^T T^p e1 = b^T (P^-1 K)^p P^-1 b
+    X, theta, Kh, P = _tiny_system(n=30, seed=11)
+    b = np.random.default_rng(3).standard_normal(30)
+    m = 5
+    _, a, bb, rho0, _ = go.pcg(lambda v: Kh @ v, b.copy(), P.solve, 0.0, m)
+    diag, off = go.lanczos_tridiag(a, bb)
+    T = np.diag(diag) + np.diag(off, 1) + np.diag(off, -1)
+    v = P.solve(b)
+    for p in range(2 * m):
+        lhs = rho0 * np.linalg.matrix_power(T, p)[0, 0]
+        rhs = b @ v
+        assert abs(lhs - rhs) <= 1e-10 * abs(rhs), (p, lhs, rhs)
+        v = P.solve(Kh @ v)
+
+
+def test_slq_is_exact_when_m_equals_n():
+    X, theta, Kh, P = _tiny_system(n=12, seed=12, k=3)
+    b = np.random.default_rng(4).standard_normal(12)
+    _, a, bb, rho0, _ = go.pcg(lambda v: Kh @ v, b.copy(), P.solve, 0.0, 12)
+    gamma, clamped = go.slq_log(a, bb, rho0)
+    w, V = np.linalg.eigh(P.dense())
+    Pmh = V @ np.diag(w ** -0.5) @ V.T
+    lam, Q = np.linalg.eigh(Pmh @ Kh @ Pmh)
+    ref = b @ Pmh @ (Q @ np.diag(np.log(lam)) @ Q.T) @ Pmh @ b
+    assert clamped == 0
+    assert abs(gamma - ref) <= 1e-8 * max(1.0, abs(ref))
+
+
+# ---------------------------------------------------------------- estimator special cases
+
+def test_perfect_preconditioner_gives_exact_results_with_zero_variance():
+    # k = n: P = K_hat, CG stops after one step, every gamma is 0 (Theorem 1 with g = 0)
+    X, y, theta = _problem(10, 2, "rbf", True, seed=13, sigma2=0.2, ls=(0.05, 0.1))
+    ex = go.exact_mll(X, y, theta, "rbf", True)
+    for seed in (1, 2):
+        es = go.estimate_mll(X, y, theta, "rbf", True, 10, 4, 1e-10, 50, seed)
+        assert es["rank"] == 10
+        assert np.all(es["iters"] == 1)
+        assert np.max(np.abs(es["gammas"])) <= 1e-10
+        assert abs(es["logp"] - ex["logp"]) <= 1e-10 * abs(ex["logp"])
+        np.testing.assert_allclose(es["grad"], ex["grad"], rtol=1e-8, atol=1e-9)
+
+
+def test_no_preconditioner_reduces_to_hutchinson_slq():
+    X, y, theta = _problem(14, 2, "matern52", True, seed=14, sigma2=0.1)
+    n = 14
+    es = go.estimate_mll(X, y, theta, "matern52", True, 0, 6, 0.0, n, seed=5, grad=False)
+    Kh = go.khat_dense(X, theta, "matern52", True)
+    lam, Q = np.linalg.eigh(Kh)
+    logK = Q @ np.diag(np.log(lam)) @ Q.T
+    E, _ = go.probe_signs(5, n, 0, 6)
+    hutch = np.mean([E[:, i] @ logK @ E[:, i] for i in range(6)])
+    assert abs(es["logdet_est"] - hutch) <= 1e-8 * abs(hutch)
+
+
+def _enumerate_estimates(X, y, theta, kind, ard, k, precond_grad=0):
+    n = X.shape[0]
+    vals, grads = [], []
+    for bits in itertools.product((-1.0, 1.0), repeat=n + k):
+        xi = np.array(bits)
+        E = xi[:n, None]
+        H = xi[n:, None]
+        es = go.estimate_mll(X, y, theta, kind, ard, k, 1, 1e-13, n, 0,
+                             grad=True, precond_grad=precond_grad, signs=(E, H))
+        vals.append(es["logdet_est"])
+        grads.append(es["grad"])
+    return np.array(vals), np.array(grads), es
+
+
+@pytest.mark.parametrize("precond_grad", [0, 1])
+def test_estimators_are_unbiased_over_all_sign_patterns(precond_grad):
+    # exact expectation over every Rademacher pattern (n + k = 9 signs)
+    X, y, theta = _problem(7, 2, "rbf", True, seed=15, sigma2=0.1, ls=(0.3, 0.6))
+    vals, grads, es = _enumerate_estimates(X, y, theta, "rbf", True, 2, precond_grad)
+    ex = go.exact_mll(X, y, theta, "rbf", True)
+    assert abs(vals.mean() - ex["logdet"]) <= 1e-9 * abs(ex["logdet"])
+    np.testing.assert_allclose(grads.mean(axis=0), ex["grad"], rtol=1e-8, atol=1e-9)
+    # not trivially exact per pattern
+    assert vals.std() > 1e-6
+
+
+def test_logdet_estimator_variance_matches_rademacher_closed_form():
+    # gamma = xi^T A xi with A = R^T M R, R = [sigma I, L], M = P^-1/2 log(A~) P^-1/2;
+    # Var over Rademacher xi of xi^T A xi = 2 (||A_s||_F^2 - sum_i (A_s)_ii^2)
+    X, y, theta = _problem(7, 2, "rbf", True, seed=16, sigma2=0.1, ls=(0.3, 0.6))
+    vals, _, es = _enumerate_estimates(X, y, theta, "rbf", True, 2)
+    n, k = 7, 2
+    L = es["L"]
+    Pd = 0.1 * np.eye(n) + L @ L.T
+    w, V = np.linalg.eigh(Pd)
+    Pmh = V @ np.diag(w ** -0.5) @ V.T
+    Kh = go.khat_dense(X, theta, "rbf", True)
+    lam, Q = np.linalg.eigh(Pmh @ Kh @ Pmh)
+    M = Pmh @ Q @ np.diag(np.log(lam)) @ Q.T @ Pmh
+    R = np.concatenate([math.sqrt(0.1) * np.eye(n), L], axis=1)
+    A = R.T @ M @ R
+    As = 0.5 * (A + A.T)
+    var = 2.0 * (np.sum(As ** 2) - np.sum(np.diag(As) ** 2))
+    assert abs(vals.var() - var) <= 1e-8 * var
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_precond_trace_and_control_variates_match_dense_finite_differences(mode):
+    X, y, theta = _problem(25, 2, "matern32", True, seed=17, sigma2=0.05)
+    kind, ard, k = "matern32", True, 6
+    L, piv, kp = go.pivoted_cholesky(X, theta, kind, ard, k)
+    P = go.Preconditioner(L[:, :kp], 0.05)
+    Cs = np.random.default_rng(5).standard_normal((25, 3))
+    tr, ctrl = go._precond_terms(X, theta, kind, ard, L, piv, kp, P, Cs, mode)
+
+    def nystrom(th):
+        K = go.kernel_matrix(X, X, th, kind, ard)
+        KS = K[:, piv]
+        return KS @ np.linalg.solve(K[np.ix_(piv, piv)], KS.T)
+
+    Pd = P.dense()
+    p = len(theta) - 2
+    for i in range(len(theta)):
+        if i == p + 1:
+            dP = np.eye(25)
+        elif mode == 1 and i < p:
+            dP = np.zeros((25, 25))
+        else:
+            h = 1e-6 * theta[i]
+            tp, tm = theta.copy(), theta.copy()
+            tp[i] += h
+            tm[i] -= h
+            dP = (nystrom(tp) - nystrom(tm)) / (2 * h)
+        ref_tr = np.trace(np.linalg.solve(Pd, dP))
+        ref_ctrl = np.einsum("pi,pq,qi->i", Cs, dP, Cs)
+        assert abs(tr[i] - ref_tr) <= 1e-6 * max(1.0, abs(ref_tr)), (i, tr[i], ref_tr)
+        np.testing.assert_allclose(ctrl[i], ref_ctrl, rtol=1e-6, atol=1e-8)
+
+
+def test_preconditioning_cuts_variance_as_in_table_s1():
+    # trend pin (Table S1, RBF, d = 1): with a preconditioner of the probe count's
+    # size, bias and variance of the log-likelihood estimate drop by orders of
+    # magnitude against plain Hutchinson.  Smaller n and ell than the paper's.
+    rng = np.random.default_rng(18)
+    n = 600
+    X = rng.standard_normal((n, 1))
+    theta = np.array([1.0, 1.0, 1e-2])
+    y = synthgp.rff_targets(rng, X, 1.0, 1.0, 1e-2, "rbf")
+    ex = go.exact_mll(X, y, theta, "rbf", False)
+    res = {}
+    for k in (0, 16):
+        vals = [go.estimate_mll(X, y, theta, "rbf", False, k, 16, 1e-10, 600, seed, grad=False)["logp"]
+                for seed in range(10)]
+        res[k] = (abs(np.mean(vals) - ex["logp"]) / abs(ex["logp"]), np.var(vals))
+    assert res[16][1] < 1e-3 * res[0][1]
+    assert res[16][0] < 1e-2 * res[0][0] + 1e-12
