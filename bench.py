@@ -1,0 +1,169 @@
+"""Benchmark: preconditioned GP log-likelihood + gradient evaluations per second.
+
+One step = one full gp_mll_grad call (preconditioner build, probes, batched
+preconditioned CG with on-the-fly K_hat tiles, Lanczos quadrature, derivative
+sweep and preconditioner terms) on the n = 100,000, d = 16 RBF-ARD workload
+(rank-100 pivoted Cholesky, 64 probes, CG tolerance 1e-6), inputs resident in
+HBM.  Prints one JSON line.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-fp64] [--no-cpu]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "log-lik+grad evals/sec at n=100k (split-prec vs FP64 GPU); K̂·V MFMA util"
+PEAK_BF16_TFLOPS = 2500.0   # MI355X dense BF16 MFMA
+PEAK_FP64_TFLOPS = 78.6
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def tile_flops(n, d, t):
+    """Algorithmic flops of one K_hat V product: 2 n^2 (d + t) (distance and tile x V
+    contractions) plus n^2 kernel-map evaluations counted as one flop each."""
+    return 2.0 * n * n * (d + t) + float(n) * n
+
+
+def run_gpu(pr, precision, steps, warmup, sync_every=1):
+    import torch
+    from paper_2107_00243_amd import binding as B
+    dev = torch.device("cuda:0")
+    X = torch.tensor(pr.X, device=dev)
+    y = torch.tensor(pr.y, device=dev)
+    prob = B.make_problem(X, y, pr.kernel, pr.ard)
+    opt = B.make_options(precision, pr.num_probes, pr.max_iters, pr.tol, pr.probe_seed, 0, sync_every)
+    ws = B.alloc_workspace(B.gp_workspace_size(prob, opt, pr.rank))
+    logp = torch.zeros(1, dtype=torch.float64, device=dev)
+    grad = torch.zeros(len(pr.theta), dtype=torch.float64, device=dev)
+    st = B.Stats(pr.num_probes, pr.rank)
+    # one evaluation with statistics (untimed) for iteration counts and accuracy
+    B.gp_mll_grad(prob, pr.theta, opt, pr.rank, None, ws, logp, grad, st)
+    torch.cuda.synchronize()
+    info = {"logp": float(logp.cpu()[0]), "grad": grad.cpu().numpy(), "iters_max": int(st.iters_max),
+            "iters_mean": float(np.mean(st.col_iters)), "flags": int(st.flags), "rank": int(st.rank_achieved)}
+    for _ in range(warmup):
+        B.gp_mll_grad(prob, pr.theta, opt, pr.rank, None, ws, logp, grad)
+    torch.cuda.synchronize()
+    log(f"[bench] {precision}: timing {steps} steps")
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        B.gp_mll_grad(prob, pr.theta, opt, pr.rank, None, ws, logp, grad)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    info["ms_per_step"] = 1e3 * dt / steps
+    info["evals_per_s"] = steps / dt
+    # tile-kernel duration in the same launch configuration, HIP events on the stream
+    ms, grid = B.gp_khat_profile(prob, pr.theta, opt, 10, ws)
+    info["tile_ms"] = ms
+    info["tile_grid"] = list(grid)
+    del ws
+    torch.cuda.empty_cache()
+    return info
+
+
+def cpu_baseline(pr, iters, budget_s=12.0):
+    """The CPU oracle's K_hat V (row-blocked direct differences, FP64) timed on a
+    block of rows of the same workload and scaled to one evaluation
+    (iters + 2 products: CG iterations plus about two products' worth of
+    derivative sweep)."""
+    from oracle import gp_oracle as go
+    n = pr.n
+    t = 1 + pr.num_probes
+    V = np.random.default_rng(0).standard_normal((n, t))
+    rows = 64
+    c0, w0 = time.process_time(), time.perf_counter()
+    go.khat_matvec(pr.X, pr.theta, pr.kernel, pr.ard, V, rows=np.arange(rows))
+    w = time.perf_counter() - w0
+    rows = int(min(n, max(rows, rows * budget_s / max(w, 1e-3))))
+    c0, w0 = time.process_time(), time.perf_counter()
+    go.khat_matvec(pr.X, pr.theta, pr.kernel, pr.ard, V, rows=np.arange(rows))
+    wall = time.perf_counter() - w0
+    cpu = time.process_time() - c0
+    per_product = wall * n / rows
+    per_eval = per_product * (iters + 2)
+    return {"value": 1.0 / per_eval, "unit": "evals/s", "cores": max(1, int(round(cpu / wall))),
+            "kind": "oracle",
+            "sample": f"oracle khat_matvec on {rows} of {n} rows x {t} rhs ({wall:.1f} s wall), scaled by "
+                      f"n/rows and by {iters}+2 products per evaluation",
+            "host_cpus": os.cpu_count()}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--fp64-steps", type=int, default=2)
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--n", type=int, default=100000)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(the row-sharded design is described in DESIGN.md); use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import synthgp
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    pr = synthgp.rbf_ard_100k(n=args.n)
+    n, d, t = pr.n, pr.d, 1 + pr.num_probes
+    log(f"[bench] workload rbf_ard_100k n={n} d={d} t={t} rank={pr.rank}")
+
+    bf = run_gpu(pr, "bf16x3", args.steps, args.warmup)
+    log(f"[bench] bf16x3: {bf['ms_per_step']:.2f} ms/eval, iters {bf['iters_max']}, tile {bf['tile_ms']:.3f} ms")
+    out_fp64 = None
+    if not args.no_fp64:
+        f64 = run_gpu(pr, "fp64", args.fp64_steps, 0)
+        log(f"[bench] fp64: {f64['ms_per_step']:.2f} ms/eval, iters {f64['iters_max']}, tile {f64['tile_ms']:.3f} ms")
+        out_fp64 = {
+            "value": f64["evals_per_s"], "ms_per_step": f64["ms_per_step"], "iters_max": f64["iters_max"],
+            "tile_ms": f64["tile_ms"], "tile_tflops": tile_flops(n, d, t) / (f64["tile_ms"] * 1e-3) / 1e12,
+            "tile_frac_fp64_peak": tile_flops(n, d, t) / (f64["tile_ms"] * 1e-3) / 1e12 / PEAK_FP64_TFLOPS,
+        }
+    flops = tile_flops(n, d, t)
+    achieved = flops / (bf["tile_ms"] * 1e-3) / 1e12
+    roofline = {"bound": "mfma", "achieved": achieved, "peak": PEAK_BF16_TFLOPS, "unit": "TFLOP/s",
+                "frac": achieved / PEAK_BF16_TFLOPS, "traffic": None,
+                "kernel": "k_khat_bf16 (K_hat V tile, BF16x3)", "launch_grid": bf["tile_grid"],
+                "algorithmic_flops_per_launch": flops, "avg_launch_ms": bf["tile_ms"]}
+    cpu = None
+    if not args.no_cpu:
+        log("[bench] timing the CPU oracle sample")
+        cpu = cpu_baseline(pr, bf["iters_max"])
+    rec = {
+        "metric": METRIC, "value": bf["evals_per_s"], "unit": "evals/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": bf["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "bf16", "data": "synthetic",
+        "config": {"workload": f"rbf_ard_100k: n={n}, d={d}, RBF ARD ls~LogU[0.1,1], sigma2=1e-3, "
+                               f"rank {pr.rank} pivoted Cholesky, {pr.num_probes} probes, CG tol {pr.tol}, "
+                               f"BF16x3 tiles, FP64 recurrences",
+                   "n": n, "d": d, "num_probes": pr.num_probes, "rank": pr.rank, "precision": "bf16x3",
+                   "cg_iters_max": bf["iters_max"], "cg_iters_mean": bf["iters_mean"]},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "fp64_gpu": out_fp64,
+        "speedup_vs_fp64_gpu": (bf["evals_per_s"] / out_fp64["value"]) if out_fp64 else None,
+    }
+    if out_fp64 is not None:
+        rec["accuracy_vs_fp64_gpu"] = {
+            "rel_logp": abs(bf["logp"] - f64["logp"]) / abs(f64["logp"]),
+            "rel_grad": float(np.linalg.norm(bf["grad"] - f64["grad"]) / np.linalg.norm(f64["grad"])),
+        }
+    print(json.dumps(rec))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,223 @@
+/*
+ * gpmll — preconditioned Gaussian-process log marginal likelihood and its
+ * gradient on AMD Instinct MI355X (gfx950).
+ *
+ * Method: Wenger, Pleiss, Hennig, Cunningham, Gardner, "Preconditioning for
+ * Scalable Gaussian Process Hyperparameter Optimization" (ICML 2022),
+ * Algorithm 1 (log-marginal likelihood) and Algorithm 2 (its derivative),
+ * Section 4.4, with the partial pivoted Cholesky preconditioner (Section 2.2,
+ * "Preconditioning"; supplement S5.3) and the log-determinant decomposition of
+ * Section 3.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Pointers named *_dev are device pointers (hipMalloc / torch CUDA tensors);
+ *   pointers named *_host are host pointers.  The library never allocates
+ *   device memory: every device array it needs lives in the caller's workspace
+ *   (see gp_workspace_size).  It owns no device memory between calls.
+ * - X_dev is n x d, row-major, FP64.  y_dev is n FP64.
+ * - theta_host holds natural (positive) hyperparameters in the order
+ *   [ls_1 .. ls_p | s | sigma^2], p = d for ARD kernels and p = 1 otherwise:
+ *   k(x, x') = s * kappa(r), r^2 = sum_j ((x_j - x'_j) / ls_j)^2, and
+ *   K_hat = K + sigma^2 I (Section 2.1).
+ * - All work is enqueued on `stream`, in order.  Results written to *_dev
+ *   outputs are valid once the stream reaches them.  A call returns after
+ *   enqueueing unless it has to read a device value on the host: the
+ *   convergence poll of CG (gp_options.sync_every > 0) and the optional
+ *   statistics (stats != NULL) do that.
+ * - Calls that share a workspace must not overlap; calls on distinct
+ *   workspaces may run concurrently on distinct streams.
+ * - Every function returns GP_OK (0) or a negative gp_status; gp_strerror
+ *   gives the text.  On an error nothing further is enqueued; work enqueued
+ *   before the error was detected may still run.
+ * - Results are deterministic: fixed inputs, seed and build on the same GPU give
+ *   bitwise-identical outputs (fixed-order reductions, no float atomics).
+ */
+#ifndef GPMLL_H
+#define GPMLL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum gp_status {
+  GP_OK = 0,
+  GP_EINVAL = -1,        /* null pointer, n < 1, d out of range, theta <= 0 or NaN, sizes */
+  GP_EWORKSPACE = -2,    /* workspace smaller than gp_workspace_size */
+  GP_ENOTSPD = -3,       /* p^T K_hat p <= 0 in CG, or the k x k Woodbury matrix not SPD */
+  GP_EHIP = -4,          /* a HIP runtime call failed; see gp_last_hip_error */
+  GP_EUNSUPPORTED = -5   /* device is not gfx950, or an option the build lacks */
+} gp_status;
+
+typedef enum gp_kernel {
+  GP_KERNEL_RBF = 0,        /* kappa = exp(-r^2 / 2) */
+  GP_KERNEL_MATERN32 = 1,   /* kappa = (1 + sqrt3 r) exp(-sqrt3 r) */
+  GP_KERNEL_MATERN52 = 2    /* kappa = (1 + sqrt5 r + 5 r^2 / 3) exp(-sqrt5 r) */
+} gp_kernel;
+
+typedef enum gp_precision {
+  GP_PREC_FP64 = 0,         /* kernel tiles and products in FP64 */
+  GP_PREC_FP32 = 1,         /* kernel tiles in FP32, FP32 MFMA products */
+  GP_PREC_BF16X3 = 2        /* split BF16 (hi + lo) MFMA products, FP32 accumulation */
+} gp_precision;
+
+/* Flags reported in gp_stats.flags. */
+#define GP_FLAG_NOT_CONVERGED 1   /* a CG column hit max_iters before its tolerance */
+#define GP_FLAG_RANK_DEFICIENT 2  /* pivoted Cholesky stopped early (rank_achieved < rank) */
+#define GP_FLAG_RITZ_CLAMPED 4    /* a Ritz value was clamped to 1e-300 before the log */
+
+/* Limits of this build. */
+#define GP_MAX_D 32
+#define GP_MAX_PROBES 255
+#define GP_MAX_RANK 1024
+
+/* The regression problem.  All device arrays stay owned by the caller. */
+typedef struct gp_problem {
+  const double* X_dev;   /* n x d row-major FP64 */
+  const double* y_dev;   /* n FP64 */
+  int64_t n;             /* number of points, >= 1 */
+  int32_t d;             /* input dimension, 1 .. GP_MAX_D */
+  int32_t kernel;        /* gp_kernel */
+  int32_t ard;           /* 1: d lengthscales; 0: one shared lengthscale */
+} gp_problem;
+
+/* Estimator options (Algorithms 1 and 2). */
+typedef struct gp_options {
+  int32_t precision;     /* gp_precision of the K_hat tiles; recurrences are FP64 */
+  int32_t num_probes;    /* ell, 1 .. GP_MAX_PROBES */
+  int32_t max_iters;     /* CG iteration cap per column, >= 1 */
+  double cg_tol;         /* a column stops when ||r|| <= cg_tol * ||b|| (>= 0) */
+  uint64_t seed;         /* probe seed (SplitMix64 counter stream) */
+  int32_t precond_grad;  /* 0: full frozen-pivot dP/dtheta; 1: only the s and sigma^2 terms */
+  int32_t sync_every;    /* poll the convergence flag on the host every q iterations (q >= 1),
+                            or 0 to enqueue all max_iters iterations without a host wait
+                            (iterations after convergence exit at once on the device) */
+} gp_options;
+
+/* Statistics copied to the host when a stats pointer is given (this waits for
+ * the stream).  The optional arrays are filled when non-NULL. */
+typedef struct gp_stats {
+  int32_t num_columns;       /* t = 1 + num_probes */
+  int32_t iters_max;         /* max CG iterations over columns */
+  int32_t rank_achieved;     /* k' <= rank */
+  int32_t flags;             /* GP_FLAG_* */
+  int32_t ritz_clamped;      /* number of clamped Ritz values */
+  int32_t reserved;
+  double logdet_precond;     /* log det P_hat */
+  double datafit;            /* y^T u, u ~ K_hat^-1 y */
+  double logdet_estimate;    /* log det P_hat + mean_i gamma_i */
+  int32_t* col_iters_host;   /* [t] iterations per column, or NULL */
+  double* gammas_host;       /* [num_probes] per-probe quadrature gamma_i, or NULL */
+  double* rel_residual_host; /* [t] final recurrence ||r|| / ||b|| per column, or NULL */
+  int32_t* pivots_host;      /* [rank] pivot rows, -1 after an early stop, or NULL */
+} gp_stats;
+
+/* Host handle of a preconditioner whose device arrays live in a workspace. */
+typedef struct gp_precond gp_precond;
+
+/* Device views of a built preconditioner (valid while its workspace lives). */
+typedef struct gp_precond_view {
+  const double* L_dev;        /* n x rank, column-major (column j contiguous) */
+  const int32_t* pivots_dev;  /* [rank], -1 after an early stop */
+  const double* logdet_dev;   /* log det(sigma^2 I + L L^T), one FP64 */
+  int64_t n;
+  int32_t rank;
+} gp_precond_view;
+
+/*
+ * gp_workspace_size — device bytes the caller must provide to the calls below
+ * for this problem shape, options and preconditioner rank (0 <= rank <=
+ * min(n, GP_MAX_RANK)).  The size is also valid for gp_khat_matvec with
+ * num_rhs <= 1 + num_probes.  Returns GP_EINVAL on bad shapes.
+ */
+int gp_workspace_size(const gp_problem* prob, const gp_options* opt, int32_t rank,
+                      size_t* bytes);
+
+/*
+ * gp_precond_build — partial pivoted Cholesky preconditioner
+ * P_hat = sigma^2 I + L L^T (Section 2.2, "Preconditioning"; supplement S5.3):
+ * `rank` greedy steps on the residual diagonal of K (noise excluded), ties to
+ * the lowest index, stopping early only when the largest residual diagonal is
+ * <= 1e-12 * s; then C = sigma^2 I_k + L^T L, its Cholesky factor and
+ * log det P_hat = (n - k) log sigma^2 + log det C (matrix determinant lemma).
+ * Everything is FP64.  The device arrays are written into `ws`; *out receives
+ * a small host handle (free it with gp_precond_free).  A later gp_mll_* call
+ * given this handle must pass the same problem, theta and workspace.
+ */
+int gp_precond_build(const gp_problem* prob, const double* theta_host, int32_t rank,
+                     void* ws_dev, size_t ws_bytes, hipStream_t stream, gp_precond** out);
+
+/* gp_precond_view_of — device views of a built preconditioner. */
+int gp_precond_view_of(const gp_precond* P, gp_precond_view* view);
+
+/* gp_precond_free — releases the host handle only (the device arrays belong to
+ * the workspace).  NULL is accepted. */
+void gp_precond_free(gp_precond* P);
+
+/*
+ * gp_mll_eval — estimate of log p(y | theta), Algorithm 1 with the
+ * preconditioned probes b_i = sigma eps_i + L eta_i (E[b b^T] = P_hat):
+ * one preconditioned CG call on [y | b_1 .. b_ell] with on-the-fly K_hat
+ * tiles (Section 4.4), the Lanczos tridiagonal from the CG coefficients
+ * (supplement S1.2), Lanczos quadrature gamma_i = rho0_i sum_j tau_1j^2
+ * log theta_j with rho0_i = b_i^T P_hat^-1 b_i, and
+ *   log p ~ -1/2 (y^T u + log det P_hat + mean_i gamma_i + n log 2 pi).
+ * P may be NULL (the preconditioner of opt-independent `rank` is then built in
+ * `ws`).  Writes one FP64 to logp_dev.
+ */
+int gp_mll_eval(const gp_problem* prob, const double* theta_host, const gp_options* opt,
+                int32_t rank, gp_precond* P, void* ws_dev, size_t ws_bytes,
+                hipStream_t stream, double* logp_dev, gp_stats* stats);
+
+/*
+ * gp_mll_grad — the estimate of gp_mll_eval plus the gradient of Algorithm 2,
+ * reusing the forward solves a_i = K_hat^-1 b_i and c_i = P_hat^-1 b_i:
+ *   d/dtheta log p ~ 1/2 u^T dK_hat u
+ *                    - 1/2 [ tr(P_hat^-1 dP_hat)
+ *                            + mean_i (a_i^T dK_hat c_i - c_i^T dP_hat c_i) ]
+ * with dK_hat tiles recomputed on the fly and tr(P_hat^-1 dP_hat) by the matrix
+ * inversion lemma (supplement S3.3).  dP_hat holds the pivots fixed
+ * (precond_grad = 0) or keeps only the s and sigma^2 terms (precond_grad = 1).
+ * Writes one FP64 to logp_dev and p + 2 FP64 to grad_dev, ordered like theta.
+ */
+int gp_mll_grad(const gp_problem* prob, const double* theta_host, const gp_options* opt,
+                int32_t rank, gp_precond* P, void* ws_dev, size_t ws_bytes,
+                hipStream_t stream, double* logp_dev, double* grad_dev, gp_stats* stats);
+
+/*
+ * gp_khat_matvec — W = K_hat V (the product inside every CG iteration) with
+ * tiles of the given precision: V_dev and W_dev are n x num_rhs row-major FP64
+ * (1 <= num_rhs <= 1 + GP_MAX_PROBES).  Uses the workspace for staging.
+ */
+int gp_khat_matvec(const gp_problem* prob, const double* theta_host, int32_t precision,
+                   const double* V_dev, int32_t num_rhs, double* W_dev, void* ws_dev,
+                   size_t ws_bytes, hipStream_t stream);
+
+/*
+ * gp_khat_profile — measurement helper: times the K_hat V tile kernel alone, in
+ * the launch configuration gp_mll_eval uses for the same problem and options.
+ * Fills the search-direction block of the workspace with a fixed pattern, stages
+ * it, then records a hipEvent on `stream`, launches the tile kernel `reps` times,
+ * records a second event, waits for it and writes the mean milliseconds per
+ * launch to *ms_per_launch (host).  Also reports the workgroup grid.
+ */
+int gp_khat_profile(const gp_problem* prob, const double* theta_host, const gp_options* opt, int32_t reps,
+                    void* ws_dev, size_t ws_bytes, hipStream_t stream, double* ms_per_launch,
+                    int64_t* grid_x, int64_t* grid_y);
+
+/* gp_strerror — static text for a gp_status. */
+const char* gp_strerror(int status);
+
+/* gp_last_hip_error — the hipError_t behind the last GP_EHIP on this thread. */
+int gp_last_hip_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GPMLL_H */

@@ -428,7 +428,9 @@ def slq_log(alphas, betas, rho0):
     if len(diag) == 1:
         lam, tau1 = diag.copy(), np.ones(1)
     else:
-        lam, vec = sla.eigh_tridiagonal(diag, off)
+        # implicit QL/QR driver: the relatively robust representation driver can
+        # fail to converge on Lanczos matrices with near-duplicate Ritz values
+        lam, vec = sla.eigh_tridiagonal(diag, off, lapack_driver="stev")
         tau1 = vec[0, :]
     clamped = int(np.sum(lam < RITZ_FLOOR))
     lam = np.maximum(lam, RITZ_FLOOR)

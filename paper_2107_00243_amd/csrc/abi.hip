@@ -1,0 +1,481 @@
+// C-ABI entry points: argument validation, workspace carving and launch
+// sequencing of the preconditioned log-likelihood estimator (Algorithms 1 and 2).
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <mutex>
+#include <vector>
+
+#include "gpmll_impl.h"
+
+namespace gpmll {
+
+hipError_t launch_stage_x(const Ctx& c, const Hyper& h);
+hipError_t launch_stage_x_bwd(const Ctx& c, const Hyper& h);
+hipError_t launch_stage_v(const Ctx& c, const double* V, int ldv, int ncols, const Hyper& h);
+hipError_t launch_khat_tiles(const Ctx& c, const Hyper& h, const int* nact);
+hipError_t launch_khat_reduce(const Ctx& c, const double* V, int ldv, double* W, int ldw, int ncols, double s2,
+                              double* dot_part, const int* nact);
+hipError_t launch_cg_after_product(const Ctx& c, const Hyper& h, int it, double tol);
+hipError_t launch_slq_logp(const Ctx& c, const Hyper& h, const double* y, double* logp);
+hipError_t launch_backward(const Ctx& c, const Hyper& h, int ard, int precond_grad, double* grad);
+
+static size_t al(size_t x) { return (x + 255) / 256 * 256; }
+static int64_t rup(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
+
+Layout make_layout(int64_t n, int d, int ard, int num_probes, int max_iters, int rank, int prec) {
+  Layout L{};
+  L.n = n;
+  L.n_pad = rup(n, kRowBlock);
+  L.d = d;
+  L.p = ard ? d : 1;
+  L.ell = num_probes;
+  L.t = 1 + num_probes;
+  {
+    // tile counts with compiled tile kernels
+    static const int ntts[] = {1, 2, 3, 4, 5, 6, 8, 12, 16};
+    int need = (L.t + 15) / 16, ntt = 16;
+    for (int v : ntts)
+      if (v >= need) {
+        ntt = v;
+        break;
+      }
+    L.tp = 16 * ntt;
+  }
+  L.k = rank;
+  L.max_iters = max_iters;
+  L.prec = prec;
+  L.bprec = prec == GP_PREC_FP64 ? GP_PREC_FP64 : GP_PREC_FP32;
+  if (prec == GP_PREC_BF16X3) {
+    const int dq = (d + 7) / 8 * 8;
+    L.kd = (int)rup(4 * dq, 32);
+  } else {
+    const int nk4 = (d + 3) / 4;
+    L.kd = 4 * (nk4 <= 1 ? 1 : nk4 <= 2 ? 2 : nk4 <= 4 ? 4 : 8);
+  }
+  L.bkd = (int)rup(d, 4);
+  L.bow = (2 * d + 1 + 15) / 16 * 16 + 16;
+  L.nrb = (int)(L.n_pad / kRowBlock);
+  // split the columns so that the tile grid has >= ~2048 workgroups (8 per CU) even
+  // with 256-row workgroups; every split is non-empty
+  int64_t want = (2048 + L.nrb - 1) / L.nrb;
+  if (want < 1) want = 1;
+  int64_t cps = rup((L.n_pad + want - 1) / want, 256);
+  if (cps < 256) cps = 256;
+  L.cols_per_split = cps;
+  L.nsplit = (int)((L.n_pad + cps - 1) / cps);
+  L.nchunk = (int)((n + kChunkRows - 1) / kChunkRows);
+  L.nred = (int)std::min<int64_t>(256, (n + 255) / 256);
+
+  const int64_t np = L.n_pad, tp = L.tp, k = rank;
+  const int64_t kk = std::max<int64_t>(k, 1);
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t o = off;
+    off += al(bytes ? bytes : 1);
+    return o;
+  };
+  const size_t esz = prec == GP_PREC_FP64 ? 8 : (prec == GP_PREC_FP32 ? 4 : 2);
+  const size_t bsz = L.bprec == GP_PREC_FP64 ? 8 : 4;
+  // preconditioner block: offsets depend on (n, d, rank) only, so a preconditioner
+  // built by gp_precond_build sits where every later call expects it
+  L.xs = take(np * d * 8);
+  L.mean = take(GP_MAX_D * 8);
+  L.mean_part = take((size_t)L.nred * GP_MAX_D * 8);
+  L.L = take(n * k * 8);
+  L.diag = take(n * 8);
+  L.ispiv = take(n);
+  L.piv = take(kk * 4);
+  L.amax = take(2 * ((n + 255) / 256) * 16);
+  L.C = take(kk * kk * 8);
+  L.Rc = take(kk * kk * 8);
+  L.Rinv = take(kk * kk * 8);
+  L.Cinv = take(kk * kk * 8);
+  L.logdetP = take(8);
+  L.scal_small = take(64);
+  L.flags = take(64);
+  L.ltr_part = take((size_t)L.nchunk * kk * std::max<int64_t>(kk, 256) * 8);
+  L.precond_end = off;
+  // estimator block
+  L.xfa = take(np * L.kd * esz);
+  L.xfb = take(np * L.kd * esz);
+  L.rowterm = take(np * (prec == GP_PREC_FP64 ? 8 : 4));
+  L.colterm = take(np * (prec == GP_PREC_FP64 ? 8 : 4));
+  L.H = take(kk * num_probes * 8);
+  L.Y = take(kk * tp * 8);
+  L.ltr = take(kk * tp * 8);
+  L.ltr_raw = take(kk * tp * 8);
+  L.Xs = take(np * tp * 8);
+  L.R = take(np * tp * 8);
+  L.Z0 = take(np * tp * 8);
+  L.Pd = take(np * tp * 8);
+  L.W = take(np * tp * 8);
+  L.vfrag = take(np * tp * (prec == GP_PREC_BF16X3 ? 4 : esz));
+  L.wpart = take((size_t)L.nsplit * np * std::max<int64_t>(tp * (prec == GP_PREC_FP64 ? 8 : 4), L.bow * bsz));
+  L.rho = take(tp * 8);
+  L.rho0 = take(tp * 8);
+  L.bnorm = take(tp * 8);
+  L.rnorm2 = take(tp * 8);
+  L.pw = take(2 * tp * 8);
+  L.active = take(tp * 4);
+  L.nactive = take(16);
+  L.iters = take(tp * 4);
+  L.alog = take(tp * max_iters * 8);
+  L.blog = take(tp * max_iters * 8);
+  const int64_t nb64 = (n + 63) / 64, nb256 = (n + 255) / 256;
+  L.dot_part = take((L.nred + nb64 + nb256) * tp * 8);
+  L.gamma = take((num_probes + 4) * 8);
+  L.slq_work = take((size_t)num_probes * 3 * max_iters * 8);
+  L.cprime = take(np * tp * 8);
+  L.bxa = take(np * L.bkd * bsz);
+  L.bxb = take(np * L.bkd * bsz);
+  L.brt = take(np * bsz);
+  L.bct = take(np * bsz);
+  L.bafrag = take(np * tp * bsz);
+  L.bcfrag = take(np * tp * bsz);
+  L.bxaug = take(np * ((2 * d + 1 + 15) / 16 * 16) * bsz);
+  L.bwd_part = take(nb256 * (GP_MAX_D + 1) * 8);
+  L.pg_small = take((4 * kk * kk + kk * tp) * 8);
+  L.omega = take(n * k * 8);
+  L.pg_part = take(((n + k + 255) / 256 + 1) * (GP_MAX_D + 1) * 8);
+  L.total = off;
+  return L;
+}
+
+}  // namespace gpmll
+
+using namespace gpmll;
+
+struct gp_precond {
+  Layout lay;
+  char* ws;
+  std::vector<double> theta;
+  gp_problem prob;
+};
+
+static thread_local int g_last_hip = 0;
+
+#define HIPCHK(expr)                    \
+  do {                                  \
+    hipError_t _e = (expr);             \
+    if (_e != hipSuccess) {             \
+      g_last_hip = (int)_e;             \
+      return GP_EHIP;                   \
+    }                                   \
+  } while (0)
+
+static int check_device() {
+  static std::mutex mu;
+  static std::vector<int> ok;  // per device: 0 unknown, 1 gfx950, -1 other
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(mu);
+  if ((int)ok.size() <= dev) ok.resize(dev + 1, 0);
+  if (ok[dev] == 0) {
+    hipDeviceProp_t prop;
+    HIPCHK(hipGetDeviceProperties(&prop, dev));
+    ok[dev] = (std::strncmp(prop.gcnArchName, "gfx950", 6) == 0) ? 1 : -1;
+  }
+  return ok[dev] == 1 ? GP_OK : GP_EUNSUPPORTED;
+}
+
+static int check_problem(const gp_problem* prob) {
+  if (!prob || !prob->X_dev || !prob->y_dev) return GP_EINVAL;
+  if (prob->n < 1 || prob->d < 1 || prob->d > GP_MAX_D) return GP_EINVAL;
+  if (prob->kernel < 0 || prob->kernel > 2) return GP_EINVAL;
+  if (prob->ard != 0 && prob->ard != 1) return GP_EINVAL;
+  if (prob->n > ((int64_t)1 << 31) - 256) return GP_EINVAL;
+  return GP_OK;
+}
+
+static int check_options(const gp_options* o) {
+  if (!o) return GP_EINVAL;
+  if (o->precision < 0 || o->precision > 2) return GP_EINVAL;
+  if (o->num_probes < 1 || o->num_probes > GP_MAX_PROBES) return GP_EINVAL;
+  if (o->max_iters < 1 || o->max_iters > 100000) return GP_EINVAL;
+  if (!(o->cg_tol >= 0.0) || !std::isfinite(o->cg_tol)) return GP_EINVAL;
+  if (o->precond_grad != 0 && o->precond_grad != 1) return GP_EINVAL;
+  if (o->sync_every < 0) return GP_EINVAL;
+  return GP_OK;
+}
+
+static int check_rank(const gp_problem* prob, int32_t rank) {
+  if (rank < 0 || rank > GP_MAX_RANK || (int64_t)rank > prob->n) return GP_EINVAL;
+  return GP_OK;
+}
+
+static int make_hyper(const gp_problem* prob, const double* theta, Hyper* h) {
+  if (!theta) return GP_EINVAL;
+  const int p = prob->ard ? prob->d : 1;
+  for (int i = 0; i < p + 2; ++i)
+    if (!(theta[i] > 0.0) || !std::isfinite(theta[i])) return GP_EINVAL;
+  std::memset(h, 0, sizeof(*h));
+  h->kind = prob->kernel;
+  h->d = prob->d;
+  for (int j = 0; j < prob->d; ++j) h->inv_ls[j] = 1.0 / theta[prob->ard ? j : 0];
+  h->s = theta[p];
+  h->s2 = theta[p + 1];
+  h->log2s = std::log2(h->s);
+  return GP_OK;
+}
+
+static int check_ws(void* ws, size_t ws_bytes, const Layout& L) {
+  if (!ws) return GP_EINVAL;
+  if ((reinterpret_cast<uintptr_t>(ws) & 255) != 0) return GP_EINVAL;
+  if (ws_bytes < L.total) return GP_EWORKSPACE;
+  return GP_OK;
+}
+
+#define RET_IF(x)            \
+  do {                       \
+    int _r = (x);            \
+    if (_r != GP_OK) return _r; \
+  } while (0)
+
+extern "C" int gp_workspace_size(const gp_problem* prob, const gp_options* opt, int32_t rank, size_t* bytes) {
+  if (!bytes) return GP_EINVAL;
+  if (!prob || prob->n < 1 || prob->d < 1 || prob->d > GP_MAX_D) return GP_EINVAL;
+  RET_IF(check_options(opt));
+  RET_IF(check_rank(prob, rank));
+  Layout L = make_layout(prob->n, prob->d, prob->ard, opt->num_probes, opt->max_iters, rank, opt->precision);
+  *bytes = L.total;
+  return GP_OK;
+}
+
+static int build_precond(const gp_problem* prob, const Hyper& h, const Ctx& c) {
+  HIPCHK(launch_prep(c, prob->X_dev, h));
+  HIPCHK(launch_pivchol(c, h));
+  HIPCHK(launch_precond_finish(c, h));
+  return GP_OK;
+}
+
+extern "C" int gp_precond_build(const gp_problem* prob, const double* theta_host, int32_t rank, void* ws_dev,
+                                size_t ws_bytes, hipStream_t stream, gp_precond** out) {
+  if (!out) return GP_EINVAL;
+  *out = nullptr;
+  RET_IF(check_problem(prob));
+  RET_IF(check_rank(prob, rank));
+  Hyper h;
+  RET_IF(make_hyper(prob, theta_host, &h));
+  RET_IF(check_device());
+  // the preconditioner block of the layout does not depend on the estimator options
+  Layout L = make_layout(prob->n, prob->d, prob->ard, 1, 1, rank, GP_PREC_FP64);
+  if (!ws_dev || (reinterpret_cast<uintptr_t>(ws_dev) & 255) != 0) return GP_EINVAL;
+  if (ws_bytes < L.precond_end) return GP_EWORKSPACE;
+  Ctx c{&L, (char*)ws_dev, stream};
+  HIPCHK(hipMemsetAsync(c.at<int>(L.flags), 0, 64, stream));
+  RET_IF(build_precond(prob, h, c));
+  gp_precond* P = new gp_precond;
+  P->lay = L;
+  P->ws = (char*)ws_dev;
+  P->prob = *prob;
+  const int p = prob->ard ? prob->d : 1;
+  P->theta.assign(theta_host, theta_host + p + 2);
+  *out = P;
+  return GP_OK;
+}
+
+extern "C" int gp_precond_view_of(const gp_precond* P, gp_precond_view* view) {
+  if (!P || !view) return GP_EINVAL;
+  view->L_dev = reinterpret_cast<const double*>(P->ws + P->lay.L);
+  view->pivots_dev = reinterpret_cast<const int32_t*>(P->ws + P->lay.piv);
+  view->logdet_dev = reinterpret_cast<const double*>(P->ws + P->lay.logdetP);
+  view->n = P->lay.n;
+  view->rank = P->lay.k;
+  return GP_OK;
+}
+
+extern "C" void gp_precond_free(gp_precond* P) { delete P; }
+
+static int run_estimator(const gp_problem* prob, const double* theta_host, const gp_options* opt, int32_t rank,
+                         gp_precond* P, void* ws_dev, size_t ws_bytes, hipStream_t stream, double* logp_dev,
+                         double* grad_dev, gp_stats* stats) {
+  RET_IF(check_problem(prob));
+  RET_IF(check_options(opt));
+  RET_IF(check_rank(prob, rank));
+  if (!logp_dev) return GP_EINVAL;
+  Hyper h;
+  RET_IF(make_hyper(prob, theta_host, &h));
+  RET_IF(check_device());
+  Layout L = make_layout(prob->n, prob->d, prob->ard, opt->num_probes, opt->max_iters, rank, opt->precision);
+  RET_IF(check_ws(ws_dev, ws_bytes, L));
+  Ctx c{&L, (char*)ws_dev, stream};
+  const int p = prob->ard ? prob->d : 1;
+  if (P) {
+    // a prebuilt preconditioner must come from the same problem, theta, rank and workspace
+    if (P->ws != (char*)ws_dev || P->lay.k != rank || P->lay.n != prob->n || P->lay.d != prob->d ||
+        P->lay.L != L.L || P->lay.Cinv != L.Cinv || P->prob.X_dev != prob->X_dev)
+      return GP_EINVAL;
+    for (int i = 0; i < p + 2; ++i)
+      if (P->theta[i] != theta_host[i]) return GP_EINVAL;
+    // keep flags[1] (a build-time status); clear the per-evaluation flags
+    HIPCHK(hipMemsetAsync(c.at<int>(L.flags), 0, 4, stream));
+    HIPCHK(hipMemsetAsync(c.at<int>(L.flags) + 2, 0, 56, stream));
+  } else {
+    HIPCHK(hipMemsetAsync(c.at<int>(L.flags), 0, 64, stream));
+    RET_IF(build_precond(prob, h, c));
+  }
+  HIPCHK(launch_stage_x(c, h));
+  HIPCHK(launch_probes(c, prob->y_dev, h, opt->seed));
+  HIPCHK(launch_cg_init(c, h));
+  int* nact = c.at<int>(L.nactive);
+  const int q = opt->sync_every;
+  for (int it = 0; it < opt->max_iters; ++it) {
+    if (q > 0 && it > 0 && it % q == 0) {
+      int host_nact = 0;
+      HIPCHK(hipMemcpyAsync(&host_nact, nact, sizeof(int), hipMemcpyDeviceToHost, stream));
+      HIPCHK(hipStreamSynchronize(stream));
+      if (host_nact == 0) break;
+    }
+    HIPCHK(launch_stage_v(c, c.at<double>(L.Pd), L.tp, L.tp, h));
+    HIPCHK(launch_khat_tiles(c, h, nact));
+    HIPCHK(launch_khat_reduce(c, c.at<double>(L.Pd), L.tp, c.at<double>(L.W), L.tp, L.tp, h.s2,
+                              c.at<double>(L.dot_part), nact));
+    HIPCHK(launch_cg_after_product(c, h, it, opt->cg_tol));
+  }
+  HIPCHK(launch_slq_logp(c, h, prob->y_dev, logp_dev));
+  if (grad_dev) {
+    HIPCHK(launch_stage_x_bwd(c, h));
+    HIPCHK(launch_backward(c, h, prob->ard, opt->precond_grad, grad_dev));
+  }
+  if (stats) {
+    int flags[4];
+    HIPCHK(hipMemcpyAsync(flags, c.at<int>(L.flags), sizeof(flags), hipMemcpyDeviceToHost, stream));
+    int small[2];
+    HIPCHK(hipMemcpyAsync(small, c.at<int>(L.scal_small), sizeof(small), hipMemcpyDeviceToHost, stream));
+    std::vector<int> it(L.tp);
+    HIPCHK(hipMemcpyAsync(it.data(), c.at<int>(L.iters), L.tp * sizeof(int), hipMemcpyDeviceToHost, stream));
+    std::vector<double> sl(L.ell + 2);
+    HIPCHK(hipMemcpyAsync(sl.data(), c.at<double>(L.gamma), sl.size() * sizeof(double), hipMemcpyDeviceToHost, stream));
+    double ldp = 0.0;
+    HIPCHK(hipMemcpyAsync(&ldp, c.at<double>(L.logdetP), sizeof(double), hipMemcpyDeviceToHost, stream));
+    std::vector<double> rn(L.tp), bn(L.tp);
+    HIPCHK(hipMemcpyAsync(rn.data(), c.at<double>(L.rnorm2), L.tp * sizeof(double), hipMemcpyDeviceToHost, stream));
+    HIPCHK(hipMemcpyAsync(bn.data(), c.at<double>(L.bnorm), L.tp * sizeof(double), hipMemcpyDeviceToHost, stream));
+    std::vector<int32_t> pv(std::max(1, rank));
+    if (rank > 0)
+      HIPCHK(hipMemcpyAsync(pv.data(), c.at<int32_t>(L.piv), rank * sizeof(int32_t), hipMemcpyDeviceToHost, stream));
+    HIPCHK(hipStreamSynchronize(stream));
+    if (flags[1] != 0) return flags[1];
+    stats->num_columns = L.t;
+    int mx = 0;
+    for (int i = 0; i < L.t; ++i) mx = std::max(mx, it[i]);
+    stats->iters_max = mx;
+    stats->rank_achieved = rank > 0 ? small[1] : 0;
+    stats->flags = flags[0];
+    stats->ritz_clamped = flags[2];
+    stats->logdet_precond = ldp;
+    stats->datafit = sl[L.ell];
+    stats->logdet_estimate = sl[L.ell + 1];
+    if (stats->col_iters_host)
+      for (int i = 0; i < L.t; ++i) stats->col_iters_host[i] = it[i];
+    if (stats->gammas_host)
+      for (int i = 0; i < L.ell; ++i) stats->gammas_host[i] = sl[i];
+    if (stats->rel_residual_host)
+      for (int i = 0; i < L.t; ++i) stats->rel_residual_host[i] = bn[i] > 0.0 ? rn[i] / bn[i] : 0.0;
+    if (stats->pivots_host)
+      for (int i = 0; i < rank; ++i) stats->pivots_host[i] = pv[i];
+  }
+  return GP_OK;
+}
+
+extern "C" int gp_mll_eval(const gp_problem* prob, const double* theta_host, const gp_options* opt, int32_t rank,
+                           gp_precond* P, void* ws_dev, size_t ws_bytes, hipStream_t stream, double* logp_dev,
+                           gp_stats* stats) {
+  return run_estimator(prob, theta_host, opt, rank, P, ws_dev, ws_bytes, stream, logp_dev, nullptr, stats);
+}
+
+extern "C" int gp_mll_grad(const gp_problem* prob, const double* theta_host, const gp_options* opt, int32_t rank,
+                           gp_precond* P, void* ws_dev, size_t ws_bytes, hipStream_t stream, double* logp_dev,
+                           double* grad_dev, gp_stats* stats) {
+  if (!grad_dev) return GP_EINVAL;
+  return run_estimator(prob, theta_host, opt, rank, P, ws_dev, ws_bytes, stream, logp_dev, grad_dev, stats);
+}
+
+extern "C" int gp_khat_matvec(const gp_problem* prob, const double* theta_host, int32_t precision, const double* V_dev,
+                              int32_t num_rhs, double* W_dev, void* ws_dev, size_t ws_bytes, hipStream_t stream) {
+  RET_IF(check_problem(prob));
+  if (!V_dev || !W_dev) return GP_EINVAL;
+  if (num_rhs < 1 || num_rhs > 1 + GP_MAX_PROBES) return GP_EINVAL;
+  if (precision < 0 || precision > 2) return GP_EINVAL;
+  Hyper h;
+  RET_IF(make_hyper(prob, theta_host, &h));
+  RET_IF(check_device());
+  Layout L = make_layout(prob->n, prob->d, prob->ard, std::max(1, num_rhs - 1), 1, 0, precision);
+  RET_IF(check_ws(ws_dev, ws_bytes, L));
+  Ctx c{&L, (char*)ws_dev, stream};
+  HIPCHK(launch_prep(c, prob->X_dev, h));
+  HIPCHK(launch_stage_x(c, h));
+  HIPCHK(launch_stage_v(c, V_dev, num_rhs, num_rhs, h));
+  HIPCHK(launch_khat_tiles(c, h, nullptr));
+  HIPCHK(launch_khat_reduce(c, V_dev, num_rhs, W_dev, num_rhs, num_rhs, h.s2, nullptr, nullptr));
+  return GP_OK;
+}
+
+namespace gpmll {
+__global__ void k_fill_pattern(double* P, int64_t n, int64_t n_pad, int tp) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n_pad * tp) return;
+  const int64_t i = e / tp;
+  const int c = (int)(e % tp);
+  // deterministic values in [-1, 1): a Weyl sequence of the element index
+  const double v = (i < n) ? 2.0 * (double)((e * 2654435761ull) % 1000003ull) / 1000003.0 - 1.0 : 0.0;
+  P[e] = (c < 1 << 30) ? v : 0.0;
+}
+}  // namespace gpmll
+
+extern "C" int gp_khat_profile(const gp_problem* prob, const double* theta_host, const gp_options* opt, int32_t reps,
+                               void* ws_dev, size_t ws_bytes, hipStream_t stream, double* ms_per_launch,
+                               int64_t* grid_x, int64_t* grid_y) {
+  RET_IF(check_problem(prob));
+  RET_IF(check_options(opt));
+  if (reps < 1 || !ms_per_launch) return GP_EINVAL;
+  Hyper h;
+  RET_IF(make_hyper(prob, theta_host, &h));
+  RET_IF(check_device());
+  Layout L = make_layout(prob->n, prob->d, prob->ard, opt->num_probes, opt->max_iters, 0, opt->precision);
+  RET_IF(check_ws(ws_dev, ws_bytes, L));
+  Ctx c{&L, (char*)ws_dev, stream};
+  HIPCHK(launch_prep(c, prob->X_dev, h));
+  HIPCHK(launch_stage_x(c, h));
+  const int64_t cnt = L.n_pad * L.tp;
+  hipLaunchKernelGGL(k_fill_pattern, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, stream, c.at<double>(L.Pd),
+                     L.n, L.n_pad, L.tp);
+  HIPCHK(hipGetLastError());
+  HIPCHK(launch_stage_v(c, c.at<double>(L.Pd), L.tp, L.tp, h));
+  HIPCHK(launch_khat_tiles(c, h, nullptr));  // warm-up launch
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  hipError_t err = hipEventRecord(e0, stream);
+  for (int r = 0; r < reps && err == hipSuccess; ++r) err = launch_khat_tiles(c, h, nullptr);
+  if (err == hipSuccess) err = hipEventRecord(e1, stream);
+  if (err == hipSuccess) err = hipEventSynchronize(e1);
+  float ms = 0.f;
+  if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  HIPCHK(err);
+  *ms_per_launch = (double)ms / reps;
+  const int ntt = L.tp / 16;
+  int rows_per_wg;
+  if (L.prec == GP_PREC_FP64) rows_per_wg = 64 * (ntt <= 4 ? 2 : 1);
+  else rows_per_wg = 64 * (ntt <= 5 ? 4 : (ntt <= 8 ? 2 : 1));
+  if (grid_x) *grid_x = L.n_pad / rows_per_wg;
+  if (grid_y) *grid_y = L.nsplit;
+  return GP_OK;
+}
+
+extern "C" const char* gp_strerror(int status) {
+  switch (status) {
+    case GP_OK: return "ok";
+    case GP_EINVAL: return "invalid argument (null pointer, size out of range, or non-positive/NaN hyperparameter)";
+    case GP_EWORKSPACE: return "workspace smaller than gp_workspace_size";
+    case GP_ENOTSPD: return "matrix not positive definite (p^T K_hat p <= 0 or Woodbury matrix not SPD)";
+    case GP_EHIP: return "HIP runtime error (see gp_last_hip_error)";
+    case GP_EUNSUPPORTED: return "unsupported device (gfx950 required) or option";
+  }
+  return "unknown status";
+}
+
+extern "C" int gp_last_hip_error(void) { return g_last_hip; }

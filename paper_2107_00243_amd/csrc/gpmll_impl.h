@@ -1,0 +1,109 @@
+// Internal declarations of the gpmll HIP library (gfx950).
+//
+// Data layout in device memory (all inside the caller's workspace):
+//   xs      n_pad x d         FP64  centred, lengthscale-scaled inputs x~ = (x - mean) / ls
+//   xfrag   tile-precision copy of x~ arranged for the MFMA operand loads
+//   rowterm / colterm         per-point FP32 terms of the distance expansion
+//   L       n x rank          FP64  pivoted Cholesky factor, column-major
+//   CG block arrays           n_pad x tp FP64, row-major (tp = columns padded to 16)
+//   vfrag   tile-precision copy of the search directions for the MFMA B operand
+//   wpart   split-K partial products, FP32 (FP64 for FP64 tiles)
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "../../include/gpmll.h"
+
+namespace gpmll {
+
+constexpr int kRowBlock = 256;      // rows per workgroup of the tile kernels; n is padded to this
+constexpr int kColChunk = 32;       // K-dimension of one tile-times-V step (MFMA K for BF16)
+constexpr int kRedBlock = 256;      // threads of the reduction kernels
+constexpr int kChunkRows = 2048;    // rows per partial of the n-reductions (L^T R, Gram)
+
+// Hyperparameters as the kernels consume them.
+struct Hyper {
+  int kind;      // gp_kernel
+  int d;
+  double inv_ls[GP_MAX_D];
+  double s;      // outputscale
+  double s2;     // noise variance
+  double log2s;  // log2(s)
+};
+
+// Kernel correlation kappa(r^2) and the derivative factor g(r^2) with
+// d kappa / d ls_j = g * dtilde_j^2 / ls_j (FP64, used by the FP64 tiles, the
+// pivoted Cholesky and the preconditioner derivative).
+__device__ inline void kappa_g64(int kind, double r2, double* kap, double* g) {
+  const double sqrt3 = 1.7320508075688772, sqrt5 = 2.23606797749979;
+  if (kind == GP_KERNEL_RBF) {
+    double e = exp(-0.5 * r2);
+    *kap = e;
+    *g = e;
+  } else if (kind == GP_KERNEL_MATERN32) {
+    double r = sqrt(r2);
+    double e = exp(-sqrt3 * r);
+    *kap = (1.0 + sqrt3 * r) * e;
+    *g = 3.0 * e;
+  } else {
+    double r = sqrt(r2);
+    double e = exp(-sqrt5 * r);
+    *kap = (1.0 + sqrt5 * r + (5.0 / 3.0) * r2) * e;
+    *g = (5.0 / 3.0) * (1.0 + sqrt5 * r) * e;
+  }
+}
+
+__device__ inline double kappa64(int kind, double r2) {
+  double k, g;
+  kappa_g64(kind, r2, &k, &g);
+  return k;
+}
+
+// Workspace carving.  Offsets are bytes from the workspace base, 256-aligned.
+struct Layout {
+  int64_t n, n_pad;
+  int d, p, t, tp, k, ell, max_iters, prec;
+  int bprec;            // precision of the derivative sweep operands (FP64 or FP32)
+  int kd;               // K-extent of the staged distance operand (elements)
+  int bkd;              // K-extent of the derivative sweep's distance operand
+  int bow;              // row width of the derivative sweep's per-row outputs
+  int nsplit;           // column splits of the tile kernels
+  int64_t cols_per_split;
+  int nchunk;           // row chunks of the n-reductions
+  int nrb;              // row blocks of kRowBlock rows
+  int nred;             // blocks of the row-parallel reductions (<= 256)
+  // preconditioner block (offsets independent of the estimator options)
+  size_t xs, mean, mean_part, L, diag, ispiv, piv, amax, C, Rc, Rinv, Cinv, logdetP, scal_small, flags, ltr_part;
+  size_t precond_end;
+  // estimator block
+  size_t xfa, xfb, rowterm, colterm, H, Y, ltr, ltr_raw;
+  size_t Xs, R, Z0, Pd, W, vfrag, wpart;
+  size_t rho, rho0, bnorm, rnorm2, pw, active, nactive, iters, alog, blog;
+  size_t dot_part, gamma, slq_work;
+  size_t cprime, bxa, bxb, brt, bct, bafrag, bcfrag, bxaug, bwd_part, pg_small, omega, pg_part;
+  size_t total;
+};
+
+Layout make_layout(int64_t n, int d, int ard, int num_probes, int max_iters, int rank, int prec);
+
+struct Ctx {
+  const Layout* lay;
+  char* ws;
+  hipStream_t st;
+  template <class T>
+  T* at(size_t off) const { return reinterpret_cast<T*>(ws + off); }
+};
+
+// Small integer slots: scal_small[0] pivoted-Cholesky stop flag, [1] achieved rank.
+// flags[0] GP_FLAG_* bits, [1] deferred gp_status, [2] clamped Ritz values.
+
+hipError_t launch_prep(const Ctx& c, const double* X, const Hyper& h);
+hipError_t launch_pivchol(const Ctx& c, const Hyper& h);
+hipError_t launch_precond_finish(const Ctx& c, const Hyper& h);
+hipError_t launch_probes(const Ctx& c, const double* y, const Hyper& h, uint64_t seed);
+hipError_t launch_cg_init(const Ctx& c, const Hyper& h);
+
+}  // namespace gpmll

@@ -1,0 +1,407 @@
+// Batched preconditioned CG over the t = 1 + ell right hand sides [y | b_1..b_ell]
+// (one CG call with many right hand sides: footnote to Section 4.4; preconditioned
+// CG: Section 2.2 and supplement S1.1), all recurrences in FP64.
+//
+// Per iteration and per active column c:
+//   w = K_hat p;  alpha = rho / p.w;  x += alpha p;  r -= alpha w;
+//   stop the column once ||r|| <= tol ||b||;
+//   z = P_hat^-1 r = (r - L C^-1 L^T r) / sigma^2   (matrix inversion lemma);
+//   beta = r.z / rho;  rho = r.z;  p = z + beta p.
+// alpha and beta are logged per column for the Lanczos tridiagonal.
+//
+// Reductions over n are two-stage with a fixed order: row-block partials, then one
+// workgroup per column.  No floating-point atomics.
+#include "gpmll_impl.h"
+
+namespace gpmll {
+
+// ---- row-block partial column dots: part[b][c] = sum_{rows of b} A[i][c] * B[i][c]
+__global__ void k_coldot_part(const double* __restrict__ A, const double* __restrict__ B, int64_t n, int tp,
+                              int64_t rows_per_block, double* __restrict__ part) {
+  __shared__ double red[256];
+  const int G = 256 / tp;
+  const int c = threadIdx.x % tp, rg = threadIdx.x / tp;
+  const int64_t r0 = (int64_t)blockIdx.x * rows_per_block, r1 = min(n, r0 + rows_per_block);
+  double s = 0.0;
+  if (rg < G)
+    for (int64_t r = r0 + rg; r < r1; r += G) s += A[r * tp + c] * B[r * tp + c];
+  red[threadIdx.x] = (rg < G) ? s : 0.0;
+  __syncthreads();
+  if (threadIdx.x < tp) {
+    double t = 0.0;
+    for (int q = 0; q < G; ++q) t += red[q * tp + threadIdx.x];
+    part[(int64_t)blockIdx.x * tp + threadIdx.x] = t;
+  }
+}
+
+// sum of nblk partials of column blockIdx.x (one workgroup per column)
+__device__ double column_total(const double* __restrict__ part, int nblk, int tp, int c) {
+  __shared__ double red[256];
+  double s = 0.0;
+  for (int b = threadIdx.x; b < nblk; b += blockDim.x) s += part[(int64_t)b * tp + c];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int off = blockDim.x / 2; off > 0; off >>= 1) {
+    if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+    __syncthreads();
+  }
+  double r = red[0];
+  __syncthreads();
+  return r;
+}
+
+// CG start: bnorm = ||b||, rho = rho0 = r.z, masks; Pd = Z0 copy happens in k_copy
+__global__ void k_cg_start(const double* __restrict__ part_bb, int nblk_bb, const double* __restrict__ part_rz,
+                           int nblk_rz, int tp,
+                           int t, double* __restrict__ bnorm, double* __restrict__ rho, double* __restrict__ rho0,
+                           int* __restrict__ active, int* __restrict__ iters, int* __restrict__ nactive) {
+  const int c = blockIdx.x;
+  const double bb = column_total(part_bb, nblk_bb, tp, c);
+  const double rz = column_total(part_rz, nblk_rz, tp, c);
+  if (threadIdx.x == 0) {
+    bnorm[c] = sqrt(bb);
+    rho[c] = rz;
+    rho0[c] = rz;
+    const int act = (c < t && bb > 0.0) ? 1 : 0;
+    active[c] = act;
+    iters[c] = 0;
+    if (act) atomicAdd(nactive, 1);
+  }
+}
+
+__global__ void k_copy(const double* __restrict__ a, double* __restrict__ b, int64_t count) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < count) b[e] = a[e];
+}
+
+__global__ void k_zero_int(int* p) { *p = 0; }
+
+// alpha = rho / p.w for active columns; logs alpha; p.w <= 0 is a hard error
+__global__ void k_cg_alpha(const double* __restrict__ part_pw, int nblk, int tp, int it, int max_iters,
+                           const double* __restrict__ rho, const int* __restrict__ active, double* __restrict__ alpha,
+                           double* __restrict__ alog, int* __restrict__ status, const int* __restrict__ nactive) {
+  if (*nactive == 0) return;
+  const int c = blockIdx.x;
+  const double pw = column_total(part_pw, nblk, tp, c);
+  if (threadIdx.x == 0) {
+    double a = 0.0;
+    if (active[c]) {
+      if (!(pw > 0.0)) {
+        *status = GP_ENOTSPD;
+      } else {
+        a = rho[c] / pw;
+        alog[(int64_t)c * max_iters + it] = a;
+      }
+    }
+    alpha[c] = a;
+  }
+}
+
+// x += alpha p; r -= alpha w (active columns); partial ||r||^2
+__global__ void k_cg_update(double* __restrict__ X, double* __restrict__ R, const double* __restrict__ P,
+                            const double* __restrict__ W, const double* __restrict__ alpha,
+                            const int* __restrict__ active, int64_t n, int tp, int64_t rows_per_block,
+                            double* __restrict__ part, const int* __restrict__ nactive) {
+  if (*nactive == 0) return;
+  __shared__ double red[256];
+  const int G = 256 / tp;
+  const int c = threadIdx.x % tp, rg = threadIdx.x / tp;
+  const int64_t r0 = (int64_t)blockIdx.x * rows_per_block, r1 = min(n, r0 + rows_per_block);
+  double s = 0.0;
+  if (rg < G && active[c]) {
+    const double a = alpha[c];
+    for (int64_t r = r0 + rg; r < r1; r += G) {
+      const int64_t e = r * tp + c;
+      X[e] += a * P[e];
+      const double rv = R[e] - a * W[e];
+      R[e] = rv;
+      s += rv * rv;
+    }
+  }
+  red[threadIdx.x] = (rg < G) ? s : 0.0;
+  __syncthreads();
+  if (threadIdx.x < tp) {
+    double t = 0.0;
+    for (int q = 0; q < G; ++q) t += red[q * tp + threadIdx.x];
+    part[(int64_t)blockIdx.x * tp + threadIdx.x] = t;
+  }
+}
+
+// convergence test after the update: iteration count, residual, mask
+__global__ void k_cg_check(const double* __restrict__ part_rr, int nblk, int tp, int it, double tol,
+                           const double* __restrict__ bnorm, int* __restrict__ active, int* __restrict__ iters,
+                           double* __restrict__ rnorm, int* __restrict__ nactive_next,
+                           const int* __restrict__ nactive) {
+  if (*nactive == 0) return;
+  const int c = blockIdx.x;
+  const double rr = column_total(part_rr, nblk, tp, c);
+  if (threadIdx.x == 0 && active[c]) {
+    iters[c] = it + 1;
+    rnorm[c] = sqrt(rr);
+    if (sqrt(rr) <= tol * bnorm[c]) active[c] = 0;
+    else atomicAdd(nactive_next, 1);
+  }
+}
+
+// beta = r.z / rho; rho = r.z (active columns)
+__global__ void k_cg_beta(const double* __restrict__ part_rz, int nblk, int tp, int it, int max_iters,
+                          double* __restrict__ rho, const int* __restrict__ active, double* __restrict__ beta,
+                          double* __restrict__ blog, const int* __restrict__ nactive) {
+  if (*nactive == 0) return;
+  const int c = blockIdx.x;
+  const double rz = column_total(part_rz, nblk, tp, c);
+  if (threadIdx.x == 0) {
+    double b = 0.0;
+    if (active[c]) {
+      b = rz / rho[c];
+      rho[c] = rz;
+      blog[(int64_t)c * max_iters + it] = b;
+    }
+    beta[c] = b;
+  }
+}
+
+// p = z + beta p (active columns)
+__global__ void k_cg_p(double* __restrict__ P, const double* __restrict__ Z, const double* __restrict__ beta,
+                       const int* __restrict__ active, int64_t n, int tp, const int* __restrict__ nactive) {
+  if (*nactive == 0) return;
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n * tp) return;
+  const int c = (int)(e % tp);
+  if (active[c]) P[e] = Z[e] + beta[c] * P[e];
+}
+
+__global__ void k_swap_count(int* __restrict__ nactive, int* __restrict__ nactive_next) {
+  *nactive = *nactive_next;
+  *nactive_next = 0;
+}
+
+// ---------------------------------------------------------------------------
+// Woodbury apply Z = (R - L Y) / sigma^2 with Y = C^-1 L^T R, C^-1 = Rinv^T Rinv.
+// ---------------------------------------------------------------------------
+
+// part[chunk][l][c] = sum_{i in chunk} L[l*n + i] R[i*tp + c]; 64 x 64 tiles, 4 x 4 per thread
+__global__ __launch_bounds__(256) void k_ltr_part(const double* __restrict__ L, const double* __restrict__ R, int64_t n,
+                                                  int k, int tp, int64_t chunk, double* __restrict__ part,
+                                                  const int* __restrict__ nactive) {
+  if (nactive != nullptr && *nactive == 0) return;
+  __shared__ double As[16][65], Bs[16][65];
+  const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
+  const int l0 = blockIdx.y * 64, c0 = blockIdx.z * 64;
+  const int64_t r0 = (int64_t)blockIdx.x * chunk, r1 = min(n, r0 + chunk);
+  double acc[4][4] = {};
+  for (int64_t base = r0; base < r1; base += 16) {
+    for (int e = threadIdx.x; e < 16 * 64; e += 256) {
+      const int rr = e % 16, col = e / 16;
+      const int64_t i = base + rr;
+      As[rr][col] = (i < r1 && l0 + col < k) ? L[(int64_t)(l0 + col) * n + i] : 0.0;
+    }
+    for (int e = threadIdx.x; e < 16 * 64; e += 256) {
+      const int rr = e / 64, col = e % 64;
+      const int64_t i = base + rr;
+      Bs[rr][col] = (i < r1 && c0 + col < tp) ? R[i * tp + c0 + col] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int rr = 0; rr < 16; ++rr) {
+      double av[4], bv[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        av[q] = As[rr][ty * 4 + q];
+        bv[q] = Bs[rr][tx * 4 + q];
+      }
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] += av[a] * bv[b];
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const int l = l0 + ty * 4 + a, c = c0 + tx * 4 + b;
+      if (l < k && c < tp) part[((int64_t)blockIdx.x * k + l) * tp + c] = acc[a][b];
+    }
+}
+
+__global__ void k_ltr_final(const double* __restrict__ part, int nchunk, int k, int tp, double* __restrict__ out,
+                            const int* __restrict__ nactive) {
+  if (nactive != nullptr && *nactive == 0) return;
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= k * tp) return;
+  double s = 0.0;
+  for (int q = 0; q < nchunk; ++q) s += part[(int64_t)q * k * tp + e];
+  out[e] = s;
+}
+
+// out[l][c] = sum_m M[l][m] in[m][c] with M = Rinv (lower, trans = 0) or Rinv^T (upper, trans = 1)
+__global__ void k_tri_apply(const double* __restrict__ Rinv, const double* __restrict__ in, int k, int tp, int trans,
+                            double* __restrict__ out, const int* __restrict__ nactive) {
+  if (nactive != nullptr && *nactive == 0) return;
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= k * tp) return;
+  const int l = e / tp, c = e % tp;
+  double s = 0.0;
+  if (!trans)
+    for (int m = 0; m <= l; ++m) s += Rinv[l * k + m] * in[m * tp + c];
+  else
+    for (int m = l; m < k; ++m) s += Rinv[m * k + l] * in[m * tp + c];
+  out[e] = s;
+}
+
+// Z = (R - L Y) / sigma^2 on a 64 x 64 tile, plus partial r.z per column
+__global__ __launch_bounds__(256) void k_z_apply(const double* __restrict__ L, const double* __restrict__ Y,
+                                                 const double* __restrict__ R, int64_t n, int k, int tp,
+                                                 double inv_s2, double* __restrict__ Z, double* __restrict__ part,
+                                                 const int* __restrict__ nactive) {
+  if (nactive != nullptr && *nactive == 0) return;
+  __shared__ double As[16][65], Bs[16][65];
+  __shared__ double red[16][64];
+  const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
+  const int64_t i0 = (int64_t)blockIdx.x * 64;
+  const int c0 = blockIdx.y * 64;
+  double acc[4][4] = {};
+  for (int lb = 0; lb < k; lb += 16) {
+    for (int e = threadIdx.x; e < 16 * 64; e += 256) {
+      const int ll = e / 64, rr = e % 64;
+      const int64_t i = i0 + rr;
+      As[ll][rr] = (i < n && lb + ll < k) ? L[(int64_t)(lb + ll) * n + i] : 0.0;
+      const int c = c0 + rr;
+      Bs[ll][rr] = (lb + ll < k && c < tp) ? Y[(lb + ll) * tp + c] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int ll = 0; ll < 16; ++ll) {
+      double av[4], bv[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        av[q] = As[ll][ty * 4 + q];
+        bv[q] = Bs[ll][tx * 4 + q];
+      }
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] += av[a] * bv[b];
+    }
+    __syncthreads();
+  }
+  double rz[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    const int64_t i = i0 + ty * 4 + a;
+    if (i >= n) continue;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const int c = c0 + tx * 4 + b;
+      if (c >= tp) continue;
+      const double r = R[i * tp + c];
+      const double z = (r - acc[a][b]) * inv_s2;
+      Z[i * tp + c] = z;
+      rz[b] += r * z;
+    }
+  }
+  if (part == nullptr) return;
+#pragma unroll
+  for (int b = 0; b < 4; ++b) red[ty][tx * 4 + b] = rz[b];
+  __syncthreads();
+  if (threadIdx.x < 64) {
+    double s = 0.0;
+    for (int q = 0; q < 16; ++q) s += red[q][threadIdx.x];
+    const int c = c0 + threadIdx.x;
+    if (c < tp) part[(int64_t)blockIdx.x * tp + c] = s;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+
+static unsigned nb_for(int64_t count, int bs) { return (unsigned)((count + bs - 1) / bs); }
+
+// dst (k x tp) = L^T Rsrc
+hipError_t launch_ltr(const Ctx& c, const double* Rsrc, double* dst, const int* nact) {
+  const Layout& L = *c.lay;
+  hipLaunchKernelGGL(k_ltr_part, dim3(L.nchunk, (L.k + 63) / 64, (L.tp + 63) / 64), dim3(256), 0, c.st,
+                     c.at<double>(L.L), Rsrc, L.n, L.k, L.tp, (int64_t)kChunkRows, c.at<double>(L.ltr_part), nact);
+  hipLaunchKernelGGL(k_ltr_final, dim3(nb_for((int64_t)L.k * L.tp, 256)), dim3(256), 0, c.st,
+                     c.at<double>(L.ltr_part), L.nchunk, L.k, L.tp, dst, nact);
+  return hipGetLastError();
+}
+
+hipError_t launch_woodbury(const Ctx& c, const Hyper& h, const double* Rsrc, double* Zdst, const int* nact,
+                           double* rz_part) {
+  const Layout& L = *c.lay;
+  const double inv_s2 = 1.0 / h.s2;
+  if (L.k > 0) {
+    hipError_t e = launch_ltr(c, Rsrc, c.at<double>(L.ltr), nact);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_tri_apply, dim3(nb_for((int64_t)L.k * L.tp, 256)), dim3(256), 0, c.st, c.at<double>(L.Rinv),
+                       c.at<double>(L.ltr), L.k, L.tp, 0, c.at<double>(L.Y), nact);
+    hipLaunchKernelGGL(k_tri_apply, dim3(nb_for((int64_t)L.k * L.tp, 256)), dim3(256), 0, c.st, c.at<double>(L.Rinv),
+                       c.at<double>(L.Y), L.k, L.tp, 1, c.at<double>(L.ltr), nact);
+  }
+  hipLaunchKernelGGL(k_z_apply, dim3(nb_for(L.n, 64), (L.tp + 63) / 64), dim3(256), 0, c.st, c.at<double>(L.L),
+                     c.at<double>(L.ltr), Rsrc, L.n, L.k, L.tp, inv_s2, Zdst, rz_part, nact);
+  return hipGetLastError();
+}
+
+hipError_t launch_cg_init(const Ctx& c, const Hyper& h) {
+  const Layout& L = *c.lay;
+  const int64_t rpb = (L.n + L.nred - 1) / L.nred;
+  double* part = c.at<double>(L.dot_part);
+  double* part2 = part + (int64_t)L.nred * L.tp;
+  hipLaunchKernelGGL(k_coldot_part, dim3(L.nred), dim3(256), 0, c.st, c.at<double>(L.R), c.at<double>(L.R), L.n, L.tp,
+                     rpb, part);
+  // Z0 = P^-1 B; the z-apply partials have one row per 64-row tile
+  hipError_t e = launch_woodbury(c, h, c.at<double>(L.R), c.at<double>(L.Z0), nullptr, part2);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(1), 0, c.st, c.at<int>(L.nactive));
+  hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(1), 0, c.st, c.at<int>(L.nactive) + 1);
+  // the z-apply partial count differs from nred: reduce them with their own count
+  hipLaunchKernelGGL(k_cg_start, dim3(L.tp), dim3(256), 0, c.st, part, L.nred, part2, (int)nb_for(L.n, 64), L.tp, L.t,
+                     c.at<double>(L.bnorm), c.at<double>(L.rho), c.at<double>(L.rho0), c.at<int>(L.active),
+                     c.at<int>(L.iters), c.at<int>(L.nactive));
+  const int64_t cnt = L.n_pad * L.tp;
+  hipLaunchKernelGGL(k_copy, dim3(nb_for(cnt, 256)), dim3(256), 0, c.st, c.at<double>(L.Z0), c.at<double>(L.Pd), cnt);
+  return hipGetLastError();
+}
+
+// one CG iteration after the K_hat product has been reduced into W with p.w partials
+hipError_t launch_cg_after_product(const Ctx& c, const Hyper& h, int it, double tol) {
+  const Layout& L = *c.lay;
+  const int64_t rpb = (L.n + L.nred - 1) / L.nred;
+  double* part = c.at<double>(L.dot_part);
+  int* nact = c.at<int>(L.nactive);
+  int* nact_next = nact + 1;
+  double* sc = c.at<double>(L.pw);  // alpha[tp] then beta[tp]
+  double* alpha = sc;
+  double* beta = sc + L.tp;
+  const int nzblk = (int)nb_for(L.n, 64);
+  hipLaunchKernelGGL(k_cg_alpha, dim3(L.tp), dim3(256), 0, c.st, part, (int)nb_for(L.n, 256), L.tp, it, L.max_iters,
+                     c.at<double>(L.rho), c.at<int>(L.active), alpha, c.at<double>(L.alog), c.at<int>(L.flags) + 1,
+                     nact);
+  hipLaunchKernelGGL(k_cg_update, dim3(L.nred), dim3(256), 0, c.st, c.at<double>(L.Xs), c.at<double>(L.R),
+                     c.at<double>(L.Pd), c.at<double>(L.W), alpha, c.at<int>(L.active), L.n, L.tp, rpb, part, nact);
+  hipLaunchKernelGGL(k_cg_check, dim3(L.tp), dim3(256), 0, c.st, part, L.nred, L.tp, it, tol, c.at<double>(L.bnorm),
+                     c.at<int>(L.active), c.at<int>(L.iters), c.at<double>(L.rnorm2), nact_next, nact);
+  double* rzpart = part + (int64_t)L.nred * L.tp;
+  hipError_t e = launch_woodbury(c, h, c.at<double>(L.R), c.at<double>(L.W), nact, rzpart);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_cg_beta, dim3(L.tp), dim3(256), 0, c.st, rzpart, nzblk, L.tp, it, L.max_iters,
+                     c.at<double>(L.rho), c.at<int>(L.active), beta, c.at<double>(L.blog), nact);
+  hipLaunchKernelGGL(k_cg_p, dim3(nb_for(L.n * L.tp, 256)), dim3(256), 0, c.st, c.at<double>(L.Pd),
+                     c.at<double>(L.W), beta, c.at<int>(L.active), L.n, L.tp, nact);
+  hipLaunchKernelGGL(k_swap_count, dim3(1), dim3(1), 0, c.st, nact, nact_next);
+  return hipGetLastError();
+}
+
+hipError_t launch_coldot(const Ctx& c, const double* A, const double* B, double* part) {
+  const Layout& L = *c.lay;
+  const int64_t rpb = (L.n + L.nred - 1) / L.nred;
+  hipLaunchKernelGGL(k_coldot_part, dim3(L.nred), dim3(256), 0, c.st, A, B, L.n, L.tp, rpb, part);
+  return hipGetLastError();
+}
+
+}  // namespace gpmll

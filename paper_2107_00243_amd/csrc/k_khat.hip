@@ -1,0 +1,727 @@
+// Matrix-free W = K_hat V with kernel tiles built on the fly (the product inside
+// every CG iteration; Section 4.4 and its complexity paragraph: O(n^2) per
+// product, never storing K_hat).
+//
+// Each workgroup owns 64*RG rows (four waves of 16*RG rows) and streams one column
+// range (split-K) in steps of 32 columns.  Per step and per 16 x 16 sub-tile:
+//   1. MFMA distance product in the transposed orientation, D[j][i] = x'_j . x'_i,
+//      accumulated on top of the per-row term (C operand) -> the lane holding
+//      column i of D owns 4 consecutive j of that row i;
+//   2. the kernel map in registers (exp2 of the log2-domain argument for RBF,
+//      sqrt/exp2/polynomial for Matern), the exact diagonal on diagonal tiles;
+//   3. those 4 + 4 values are exactly one row-slice of the A operand of the
+//      second MFMA (tile x V) under a fixed permutation of the 32 contraction
+//      indices, which the staged V fragments share.
+// Operands are pre-arranged "fragment-major" in global memory so that every LDS
+// read is one contiguous 16-byte (or 4/8-byte) slot per lane.
+//
+// Precisions: BF16X3 splits every operand into bf16 hi + lo; the distance uses
+// the (hi, hi, lo, lo) x (hi, lo, hi, lo) K-concatenation (all four cross
+// products), the tile x V product the three products hi.hi + hi.lo + lo.hi, all
+// with FP32 accumulation.  FP32 uses v_mfma_f32_16x16x4_f32, FP64 uses
+// v_mfma_f64_16x16x4_f64.
+#include "gpmll_impl.h"
+
+#ifndef GPMLL_KHAT_PART
+#define GPMLL_KHAT_PART 0
+#endif
+
+namespace gpmll {
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+constexpr float kLog2e = 1.4426950408889634f;
+
+// Row (within a 16-row block) of accumulator slot v in lane group g = lane/16 for
+// the 16x16x4 MFMA outputs: FP32 holds rows 4g + v, FP64 holds rows g + 4v.
+template <typename T>
+__device__ __host__ constexpr int acc_row(int g, int v) {
+  return sizeof(T) == 8 ? g + 4 * v : 4 * g + v;
+}
+
+__device__ inline uint32_t pack_bf16(float a, float b) {
+  f32x2 v = {a, b};
+  return __builtin_bit_cast(uint32_t, __builtin_convertvector(v, bf16x2));
+}
+
+// hi = RNE(a), lo = RNE(a - hi) for a pair; returns packed hi and lo words
+__device__ inline void split_pair(float a, float b, uint32_t* hi, uint32_t* lo) {
+  uint32_t h = pack_bf16(a, b);
+  float ha = __builtin_bit_cast(float, h << 16);
+  float hb = __builtin_bit_cast(float, h & 0xffff0000u);
+  *hi = h;
+  *lo = pack_bf16(a - ha, b - hb);
+}
+
+__device__ inline float bf16_lo_f(uint32_t w) { return __builtin_bit_cast(float, w << 16); }
+__device__ inline float bf16_hi_f(uint32_t w) { return __builtin_bit_cast(float, w & 0xffff0000u); }
+
+// kernel value from the MFMA argument q (FP32 tiles): RBF q = log2 k; Matern q = r^2
+template <int KIND>
+__device__ inline float map32(float q, float s) {
+  if (KIND == GP_KERNEL_RBF) {
+    return __builtin_amdgcn_exp2f(q);
+  } else if (KIND == GP_KERNEL_MATERN32) {
+    const float a = 1.7320508075688772f;
+    float r = __builtin_sqrtf(fmaxf(q, 0.0f));
+    float e = __builtin_amdgcn_exp2f(-a * kLog2e * r);
+    return s * fmaf(a, r, 1.0f) * e;
+  } else {
+    const float a = 2.23606797749979f;
+    float q0 = fmaxf(q, 0.0f);
+    float r = __builtin_sqrtf(q0);
+    float e = __builtin_amdgcn_exp2f(-a * kLog2e * r);
+    return s * fmaf(5.0f / 3.0f, q0, fmaf(a, r, 1.0f)) * e;
+  }
+}
+
+template <int KIND>
+__device__ inline double map64(double q, double s) {
+  q = q > 0.0 ? q : 0.0;
+  return s * kappa64(KIND, q);
+}
+
+// ---------------------------------------------------------------------------
+// Tile kernels
+// ---------------------------------------------------------------------------
+
+struct TileArgs {
+  int64_t n_pad;
+  int64_t n_valid;          // rows/columns >= n_valid carry zero operands
+  int64_t cols_per_split;   // multiple of 32
+  int tp;                   // leading dimension of the partial output
+  float s32;
+  double s64;
+};
+
+// cooperative copy of `count` 16-byte units from three contiguous sources into LDS
+__device__ inline void copy_units(u32x4* dst, const u32x4* a, int na, const u32x4* b, int nb, const u32x4* c,
+                                  int nc, int tid, int nthreads) {
+  const int total = na + nb + nc;
+  for (int e = tid; e < total; e += nthreads) {
+    u32x4 v;
+    if (e < na) v = a[e];
+    else if (e < na + nb) v = b[e - na];
+    else v = c[e - na - nb];
+    dst[e] = v;
+  }
+}
+
+#if GPMLL_KHAT_PART == 0
+// ---------------------------------------------------------------------------
+// Staging of the inputs x~ into the MFMA fragment layouts, and the row and
+// column terms of the distance expansion.  RBF: x' = sqrt(log2 e) x~ on both
+// sides, q = x'_i.x'_j - |x'_i|^2/2 - |x'_j|^2/2 + log2 s = log2 k.  Matern:
+// x'_B = sqrt2 x~, x'_A = -x'_B, q = |x'_i|^2/2 + |x'_j|^2/2 - x'_i.x'_j = r^2.
+// FP64 and the derivative sweep: as Matern, q = r^2.  Norms are those of the
+// represented (rounded) operands, so q is a true squared distance of slightly
+// perturbed points.
+// ---------------------------------------------------------------------------
+
+__global__ void k_stage_x_bf16(const double* __restrict__ xs, int64_t n_pad, int d, int dq, int nkc, int kind,
+                               float log2s, u32x4* __restrict__ xfa, u32x4* __restrict__ xfb,
+                               float* __restrict__ rowterm, float* __restrict__ colterm) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_pad) return;
+  const bool rbf = kind == GP_KERNEL_RBF;
+  const double scale = rbf ? 1.2011224087864498 /* sqrt(log2 e) */ : 1.4142135623730951;
+  uint16_t hi[GP_MAX_D], lo[GP_MAX_D];
+  double nrm = 0.0;
+  for (int q = 0; q < dq; ++q) {
+    float x = q < d ? (float)(scale * xs[i * d + q]) : 0.0f;
+    uint32_t h, l;
+    split_pair(x, 0.0f, &h, &l);
+    hi[q] = (uint16_t)(h & 0xffffu);
+    lo[q] = (uint16_t)(l & 0xffffu);
+    double rep = (double)bf16_lo_f(hi[q]) + (double)bf16_lo_f(lo[q]);
+    nrm += rep * rep;
+  }
+  const uint16_t sgn = rbf ? 0 : 0x8000;
+  const int kd = nkc * 32;
+  const int64_t tile = i / 16;
+  const int li = (int)(i % 16);
+  for (int kc = 0; kc < nkc; ++kc) {
+    for (int g = 0; g < 4; ++g) {
+      uint32_t wa[4], wb[4];
+      for (int w = 0; w < 4; ++w) {
+        uint16_t ea[2], eb[2];
+        for (int h2 = 0; h2 < 2; ++h2) {
+          int k = kc * 32 + g * 8 + w * 2 + h2;
+          int seg = k / dq, q = k % dq;
+          ea[h2] = eb[h2] = 0;
+          if (k < 4 * dq && k < kd) {
+            // A side: [hi | hi | lo | lo], B side: [hi | lo | hi | lo]
+            uint16_t va = (seg < 2) ? hi[q] : lo[q];
+            uint16_t vb = (seg % 2 == 0) ? hi[q] : lo[q];
+            ea[h2] = (va & 0x7fff) == 0 ? 0 : (uint16_t)(va ^ sgn);
+            eb[h2] = vb;
+          }
+        }
+        wa[w] = (uint32_t)ea[0] | ((uint32_t)ea[1] << 16);
+        wb[w] = (uint32_t)eb[0] | ((uint32_t)eb[1] << 16);
+      }
+      const int64_t slot = (tile * nkc + kc) * 64 + li + 16 * g;
+      xfa[slot] = u32x4{wa[0], wa[1], wa[2], wa[3]};
+      xfb[slot] = u32x4{wb[0], wb[1], wb[2], wb[3]};
+    }
+  }
+  if (rbf) {
+    rowterm[i] = (float)(-0.5 * nrm + (double)log2s);
+    colterm[i] = (float)(-0.5 * nrm);
+  } else {
+    rowterm[i] = (float)(0.5 * nrm);
+    colterm[i] = (float)(0.5 * nrm);
+  }
+}
+
+// log2form: RBF in the log2 domain (FP32 forward tiles); otherwise q = r^2
+template <typename T>
+__global__ void k_stage_x_fp(const double* __restrict__ xs, int64_t n_pad, int d, int nk4, int log2form,
+                             double log2s, T* __restrict__ xfa, T* __restrict__ xfb, T* __restrict__ rowterm,
+                             T* __restrict__ colterm) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_pad) return;
+  const bool rbf32 = log2form != 0;
+  const double scale = rbf32 ? 1.2011224087864498 : 1.4142135623730951;
+  const int64_t tile = i / 16;
+  const int li = (int)(i % 16);
+  double nrm = 0.0;
+  for (int q = 0; q < nk4 * 4; ++q) {
+    T x = q < d ? (T)(scale * xs[i * d + q]) : (T)0;
+    double rep = (double)x;
+    nrm += rep * rep;
+    const int64_t slot = (tile * nk4 + q / 4) * 64 + li + 16 * (q % 4);
+    xfb[slot] = x;
+    xfa[slot] = rbf32 ? x : -x;
+  }
+  if (rbf32) {
+    rowterm[i] = (T)(-0.5 * nrm + log2s);
+    colterm[i] = (T)(-0.5 * nrm);
+  } else {
+    rowterm[i] = (T)(0.5 * nrm);
+    colterm[i] = (T)(0.5 * nrm);
+  }
+}
+
+// V (rows < nrows, columns < ncols of an FP64 row-major array with leading
+// dimension ldv) -> fragment-major tile-precision copy; everything else zero.
+// BF16: fragment (jb, tt, piece) lane l holds rows jb*32 + perm(l/16, s), s < 8,
+// perm(g, s) = 4g + s (s < 4) or 16 + 4g + s - 4, column tt*16 + l%16.
+__global__ void k_stage_v_bf16(const double* __restrict__ V, int64_t nrows, int ldv, int ncols, int64_t n_pad,
+                               int ntt, u32x4* __restrict__ vfrag) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;  // (jb, tt, lane)
+  const int64_t total = (n_pad / 32) * ntt * 64;
+  if (e >= total) return;
+  const int lane = (int)(e % 64);
+  const int tt = (int)((e / 64) % ntt);
+  const int64_t jb = e / (64 * ntt);
+  const int g = lane / 16, col = tt * 16 + lane % 16;
+  // FP64 -> hi + lo: hi = RNE(v), lo = RNE(v - hi) with v - hi taken in FP64
+  uint32_t h[4], l[4];
+  for (int w = 0; w < 4; ++w) {
+    int64_t j0 = jb * 32 + (2 * w < 4 ? 4 * g + 2 * w : 16 + 4 * g + (2 * w - 4));
+    int64_t j1 = j0 + 1;
+    double a = (j0 < nrows && col < ncols) ? V[j0 * ldv + col] : 0.0;
+    double b = (j1 < nrows && col < ncols) ? V[j1 * ldv + col] : 0.0;
+    uint32_t hh = pack_bf16((float)a, (float)b);
+    double ra = a - (double)bf16_lo_f(hh), rb = b - (double)bf16_hi_f(hh);
+    h[w] = hh;
+    l[w] = pack_bf16((float)ra, (float)rb);
+  }
+  vfrag[((jb * ntt + tt) * 2 + 0) * 64 + lane] = u32x4{h[0], h[1], h[2], h[3]};
+  vfrag[((jb * ntt + tt) * 2 + 1) * 64 + lane] = u32x4{l[0], l[1], l[2], l[3]};
+}
+
+// FP32/FP64: fragment (j16, tt, v) lane l holds row j16*16 + acc_row(l/16, v), column tt*16 + l%16
+template <typename T>
+__global__ void k_stage_v_fp(const double* __restrict__ V, int64_t nrows, int ldv, int ncols, int64_t n_pad,
+                             int ntt, T* __restrict__ vfrag) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;  // (j16, tt, v, lane)
+  const int64_t total = (n_pad / 16) * ntt * 4 * 64;
+  if (e >= total) return;
+  const int lane = (int)(e % 64);
+  const int v = (int)((e / 64) % 4);
+  const int tt = (int)((e / 256) % ntt);
+  const int64_t j16 = e / (256 * ntt);
+  const int64_t j = j16 * 16 + acc_row<T>(lane / 16, v);
+  const int col = tt * 16 + lane % 16;
+  vfrag[e] = (j < nrows && col < ncols) ? (T)V[j * ldv + col] : (T)0;
+}
+
+// W[i][c] = sum_s wpart[s][i][c] + sigma^2 V[i][c] (FP64, fixed order), rows < nrows,
+// columns < ncols; optionally the per-block partial dots V[:,c].W[:,c].
+template <typename T>
+__global__ void k_khat_reduce(const T* __restrict__ wpart, int nsplit, int64_t n_pad, int tp,
+                              const double* __restrict__ V, int ldv, double* __restrict__ W, int ldw, int64_t nrows,
+                              int ncols, double s2, double* __restrict__ dot_part, const int* __restrict__ nactive) {
+  if (nactive != nullptr && *nactive == 0) return;
+  __shared__ double red[256];
+  const int G = 256 / ncols;
+  const int c = threadIdx.x % ncols, rg = threadIdx.x / ncols;
+  const int64_t r0 = (int64_t)blockIdx.x * 256;
+  double dot = 0.0;
+  if (rg < G) {
+    for (int64_t r = r0 + rg; r < min(nrows, r0 + 256); r += G) {
+      double w = 0.0;
+      for (int s = 0; s < nsplit; ++s) w += (double)wpart[((int64_t)s * n_pad + r) * tp + c];
+      const double v = V[r * ldv + c];
+      w += s2 * v;
+      W[r * ldw + c] = w;
+      dot += v * w;
+    }
+  }
+  if (dot_part == nullptr) return;
+  red[threadIdx.x] = (rg < G) ? dot : 0.0;
+  __syncthreads();
+  if (threadIdx.x < ncols) {
+    double s = 0.0;
+    for (int q = 0; q < G; ++q) s += red[q * ncols + threadIdx.x];
+    dot_part[(int64_t)blockIdx.x * ncols + threadIdx.x] = s;
+  }
+}
+
+#endif  // part 0
+
+#if GPMLL_KHAT_PART == 1
+template <int KIND, int NKC, int NTT, int RG>
+__global__ __launch_bounds__(256, 2) void k_khat_bf16(const u32x4* __restrict__ xfa, const u32x4* __restrict__ xfb,
+                                                      const float* __restrict__ rowterm,
+                                                      const float* __restrict__ colterm,
+                                                      const u32x4* __restrict__ vfrag, float* __restrict__ wpart,
+                                                      TileArgs a, const int* __restrict__ nactive) {
+  if (nactive != nullptr && *nactive == 0) return;
+  constexpr int A_U = 2 * NKC * 64, V_U = NTT * 2 * 64, C_U = 8;
+  constexpr int STAGE = A_U + V_U + C_U;
+  constexpr int PER = (STAGE + 255) / 256;
+  __shared__ u32x4 lds[2][STAGE];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int g = lane >> 4, li = lane & 15;
+  const int64_t blk_row0 = (int64_t)blockIdx.x * (64 * RG);
+  const int64_t row0 = blk_row0 + wave * (16 * RG);
+  const int64_t c_begin = (int64_t)blockIdx.y * a.cols_per_split;
+  const int64_t c_end = min(a.n_pad, c_begin + a.cols_per_split);
+  if (c_begin >= c_end) return;
+
+  u32x4 xb[RG][NKC];
+  f32x4 rt[RG];
+  f32x4 acc[RG][NTT];
+#pragma unroll
+  for (int rg = 0; rg < RG; ++rg) {
+#pragma unroll
+    for (int kc = 0; kc < NKC; ++kc) xb[rg][kc] = xfb[((row0 / 16 + rg) * NKC + kc) * 64 + lane];
+    float r = rowterm[row0 + rg * 16 + li];
+    rt[rg] = f32x4{r, r, r, r};
+#pragma unroll
+    for (int tt = 0; tt < NTT; ++tt) acc[rg][tt] = f32x4{0.f, 0.f, 0.f, 0.f};
+  }
+
+  auto src_a = [&](int64_t c) { return xfa + (c / 16) * NKC * 64; };
+  auto src_v = [&](int64_t c) { return vfrag + (c / 32) * NTT * 2 * 64; };
+  auto src_c = [&](int64_t c) { return reinterpret_cast<const u32x4*>(colterm + c); };
+
+  copy_units(lds[0], src_a(c_begin), A_U, src_v(c_begin), V_U, src_c(c_begin), C_U, tid, 256);
+  __syncthreads();
+  int buf = 0;
+  for (int64_t c = c_begin; c < c_end; c += 32) {
+    const bool has_next = c + 32 < c_end;
+    u32x4 pre[PER];
+    if (has_next) {
+      const u32x4* sa = src_a(c + 32);
+      const u32x4* sv = src_v(c + 32);
+      const u32x4* sc = src_c(c + 32);
+#pragma unroll
+      for (int q = 0; q < PER; ++q) {
+        int e = tid + q * 256;
+        if (e < STAGE) pre[q] = (e < A_U) ? sa[e] : (e < A_U + V_U ? sv[e - A_U] : sc[e - A_U - V_U]);
+      }
+    }
+    const u32x4* A = lds[buf];
+    const u32x4* Vf = A + A_U;
+    const float* ct = reinterpret_cast<const float*>(A + A_U + V_U);
+    const bool diag = (c + 32 > row0) && (c < row0 + 16 * RG);
+    f32x4 ctv[2];
+    ctv[0] = *reinterpret_cast<const f32x4*>(ct + 4 * g);
+    ctv[1] = *reinterpret_cast<const f32x4*>(ct + 16 + 4 * g);
+    u32x4 ph[RG], pl[RG];
+#pragma unroll
+    for (int rg = 0; rg < RG; ++rg) {
+#pragma unroll
+      for (int js = 0; js < 2; ++js) {
+        f32x4 dd = rt[rg];
+#pragma unroll
+        for (int kc = 0; kc < NKC; ++kc)
+          dd = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, A[(js * NKC + kc) * 64 + lane]),
+                                                       __builtin_bit_cast(bf16x8, xb[rg][kc]), dd, 0, 0, 0);
+        float kv[4];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) kv[v] = map32<KIND>(dd[v] + ctv[js][v], a.s32);
+        if (diag) {
+          const int64_t i = row0 + rg * 16 + li;
+#pragma unroll
+          for (int v = 0; v < 4; ++v)
+            if (i == c + js * 16 + 4 * g + v) kv[v] = a.s32;
+        }
+        uint32_t h0, l0, h1, l1;
+        split_pair(kv[0], kv[1], &h0, &l0);
+        split_pair(kv[2], kv[3], &h1, &l1);
+        ph[rg][2 * js] = h0;
+        ph[rg][2 * js + 1] = h1;
+        pl[rg][2 * js] = l0;
+        pl[rg][2 * js + 1] = l1;
+      }
+    }
+#pragma unroll
+    for (int tt = 0; tt < NTT; ++tt) {
+      const bf16x8 vh = __builtin_bit_cast(bf16x8, Vf[(tt * 2 + 0) * 64 + lane]);
+      const bf16x8 vl = __builtin_bit_cast(bf16x8, Vf[(tt * 2 + 1) * 64 + lane]);
+#pragma unroll
+      for (int rg = 0; rg < RG; ++rg) {
+        const bf16x8 h = __builtin_bit_cast(bf16x8, ph[rg]);
+        const bf16x8 l = __builtin_bit_cast(bf16x8, pl[rg]);
+        acc[rg][tt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(h, vh, acc[rg][tt], 0, 0, 0);
+        acc[rg][tt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(h, vl, acc[rg][tt], 0, 0, 0);
+        acc[rg][tt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(l, vh, acc[rg][tt], 0, 0, 0);
+      }
+    }
+    if (has_next) {
+#pragma unroll
+      for (int q = 0; q < PER; ++q) {
+        int e = tid + q * 256;
+        if (e < STAGE) lds[buf ^ 1][e] = pre[q];
+      }
+    }
+    __syncthreads();
+    buf ^= 1;
+  }
+  float* out = wpart + (int64_t)blockIdx.y * a.n_pad * a.tp;
+#pragma unroll
+  for (int rg = 0; rg < RG; ++rg)
+#pragma unroll
+    for (int tt = 0; tt < NTT; ++tt)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) out[(row0 + rg * 16 + 4 * g + v) * a.tp + tt * 16 + li] = acc[rg][tt][v];
+}
+
+#endif  // part 1
+
+#if GPMLL_KHAT_PART == 2 || GPMLL_KHAT_PART == 3
+// FP32 / FP64 tiles with v_mfma_{f32,f64}_16x16x4.  The accumulator -> operand
+// hand-off: the lane holding D[j = acc_row(l/16, v)][i = l%16] supplies the A
+// operand of MFMA number v, whose K index l/16 stands for that j.
+template <typename T>
+struct FpMfma;
+template <>
+struct FpMfma<float> {
+  typedef f32x4 acc_t;
+  __device__ static acc_t mfma(float a, float b, acc_t c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+};
+template <>
+struct FpMfma<double> {
+  typedef f64x4 acc_t;
+  __device__ static acc_t mfma(double a, double b, acc_t c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+};
+
+template <typename T, int KIND, int NK4, int NTT, int RG>
+__global__ __launch_bounds__(256, 2) void k_khat_fp(const T* __restrict__ xfa, const T* __restrict__ xfb,
+                                                    const T* __restrict__ rowterm, const T* __restrict__ colterm,
+                                                    const T* __restrict__ vfrag, T* __restrict__ wpart, TileArgs a,
+                                                    const int* __restrict__ nactive) {
+  if (nactive != nullptr && *nactive == 0) return;
+  typedef typename FpMfma<T>::acc_t acc_t;
+  // stage of 16 columns: A fragments NK4*64, V fragments NTT*4*64, column terms 16
+  constexpr int A_E = NK4 * 64, V_E = NTT * 4 * 64, C_E = 16;
+  constexpr int STAGE = A_E + V_E + C_E;
+  constexpr int PER = (STAGE + 255) / 256;
+  __shared__ T lds[2][STAGE];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int g = lane >> 4, li = lane & 15;
+  const int64_t row0 = (int64_t)blockIdx.x * (64 * RG) + wave * (16 * RG);
+  const int64_t c_begin = (int64_t)blockIdx.y * a.cols_per_split;
+  const int64_t c_end = min(a.n_pad, c_begin + a.cols_per_split);
+  if (c_begin >= c_end) return;
+
+  T xb[RG][NK4];
+  acc_t rt[RG];
+  acc_t acc[RG][NTT];
+#pragma unroll
+  for (int rg = 0; rg < RG; ++rg) {
+#pragma unroll
+    for (int kc = 0; kc < NK4; ++kc) xb[rg][kc] = xfb[((row0 / 16 + rg) * NK4 + kc) * 64 + lane];
+    T r = rowterm[row0 + rg * 16 + li];
+    rt[rg] = acc_t{r, r, r, r};
+#pragma unroll
+    for (int tt = 0; tt < NTT; ++tt) acc[rg][tt] = acc_t{0, 0, 0, 0};
+  }
+  auto load = [&](int64_t c, int e) -> T {
+    if (e < A_E) return xfa[(c / 16) * NK4 * 64 + e];
+    if (e < A_E + V_E) return vfrag[(c / 16) * NTT * 4 * 64 + (e - A_E)];
+    return colterm[c + (e - A_E - V_E)];
+  };
+  for (int e = tid; e < STAGE; e += 256) lds[0][e] = load(c_begin, e);
+  __syncthreads();
+  int buf = 0;
+  for (int64_t c = c_begin; c < c_end; c += 16) {
+    const bool has_next = c + 16 < c_end;
+    T pre[PER];
+    if (has_next) {
+#pragma unroll
+      for (int q = 0; q < PER; ++q) {
+        int e = tid + q * 256;
+        if (e < STAGE) pre[q] = load(c + 16, e);
+      }
+    }
+    const T* A = lds[buf];
+    const T* Vf = A + A_E;
+    const T* ct = A + A_E + V_E;
+    const bool diag = (c + 16 > row0) && (c < row0 + 16 * RG);
+    T ctv[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) ctv[v] = ct[acc_row<T>(g, v)];
+    T kv[RG][4];
+#pragma unroll
+    for (int rg = 0; rg < RG; ++rg) {
+      acc_t dd = rt[rg];
+#pragma unroll
+      for (int kc = 0; kc < NK4; ++kc) dd = FpMfma<T>::mfma(A[kc * 64 + lane], xb[rg][kc], dd);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        T q = dd[v] + ctv[v];
+        if constexpr (sizeof(T) == 4) kv[rg][v] = map32<KIND>(q, a.s32);
+        else kv[rg][v] = map64<KIND>(q, a.s64);
+      }
+      if (diag) {
+        const int64_t i = row0 + rg * 16 + li;
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+          if (i == c + acc_row<T>(g, v)) kv[rg][v] = (sizeof(T) == 4) ? (T)a.s32 : (T)a.s64;
+      }
+    }
+#pragma unroll
+    for (int tt = 0; tt < NTT; ++tt) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const T bv = Vf[(tt * 4 + v) * 64 + lane];
+#pragma unroll
+        for (int rg = 0; rg < RG; ++rg) acc[rg][tt] = FpMfma<T>::mfma(kv[rg][v], bv, acc[rg][tt]);
+      }
+    }
+    if (has_next) {
+#pragma unroll
+      for (int q = 0; q < PER; ++q) {
+        int e = tid + q * 256;
+        if (e < STAGE) lds[buf ^ 1][e] = pre[q];
+      }
+    }
+    __syncthreads();
+    buf ^= 1;
+  }
+  T* out = wpart + (int64_t)blockIdx.y * a.n_pad * a.tp;
+#pragma unroll
+  for (int rg = 0; rg < RG; ++rg)
+#pragma unroll
+    for (int tt = 0; tt < NTT; ++tt)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) out[(row0 + rg * 16 + acc_row<T>(g, v)) * a.tp + tt * 16 + li] = acc[rg][tt][v];
+}
+
+#endif  // parts 2, 3
+
+// ---------------------------------------------------------------------------
+// dispatch: NTT = tp / 16 takes the values of kSupportedNtt; the distance
+// K-extent takes 1..4 chunks of 32 (BF16) or 1, 2, 4, 8 chunks of 4 (FP32/FP64).
+// Each precision is compiled in its own translation unit (GPMLL_KHAT_PART).
+// ---------------------------------------------------------------------------
+
+hipError_t khat_tiles_bf16(const Ctx& c, const Hyper& h, const TileArgs& ta, const int* nact);
+hipError_t khat_tiles_fp32(const Ctx& c, const Hyper& h, const TileArgs& ta, const int* nact);
+hipError_t khat_tiles_fp64(const Ctx& c, const Hyper& h, const TileArgs& ta, const int* nact);
+
+#define GPMLL_NTT_CASES(M) M(1) M(2) M(3) M(4) M(5) M(6) M(8) M(12) M(16)
+
+#if GPMLL_KHAT_PART == 1
+namespace {
+template <int KIND, int NKC, int NTT>
+hipError_t run_bf16(const Ctx& c, const TileArgs& ta, const int* nact) {
+  const Layout& L = *c.lay;
+  constexpr int RG = NTT <= 5 ? 4 : (NTT <= 8 ? 2 : 1);
+  dim3 grid((unsigned)(L.n_pad / (64 * RG)), (unsigned)L.nsplit);
+  hipLaunchKernelGGL((k_khat_bf16<KIND, NKC, NTT, RG>), grid, dim3(256), 0, c.st, c.at<u32x4>(L.xfa),
+                     c.at<u32x4>(L.xfb), c.at<float>(L.rowterm), c.at<float>(L.colterm), c.at<u32x4>(L.vfrag),
+                     c.at<float>(L.wpart), ta, nact);
+  return hipGetLastError();
+}
+template <int KIND, int NKC>
+hipError_t sel_bf16_ntt(const Ctx& c, const TileArgs& ta, const int* nact, int ntt) {
+  switch (ntt) {
+#define CASE(N) case N: return run_bf16<KIND, NKC, N>(c, ta, nact);
+    GPMLL_NTT_CASES(CASE)
+#undef CASE
+  }
+  return hipErrorInvalidValue;
+}
+template <int KIND>
+hipError_t sel_bf16(const Ctx& c, const TileArgs& ta, const int* nact) {
+  const Layout& L = *c.lay;
+  const int ntt = L.tp / 16;
+  switch (L.kd / 32) {
+    case 1: return sel_bf16_ntt<KIND, 1>(c, ta, nact, ntt);
+    case 2: return sel_bf16_ntt<KIND, 2>(c, ta, nact, ntt);
+    case 3: return sel_bf16_ntt<KIND, 3>(c, ta, nact, ntt);
+    case 4: return sel_bf16_ntt<KIND, 4>(c, ta, nact, ntt);
+  }
+  return hipErrorInvalidValue;
+}
+}  // namespace
+hipError_t khat_tiles_bf16(const Ctx& c, const Hyper& h, const TileArgs& ta, const int* nact) {
+  switch (h.kind) {
+    case GP_KERNEL_RBF: return sel_bf16<GP_KERNEL_RBF>(c, ta, nact);
+    case GP_KERNEL_MATERN32: return sel_bf16<GP_KERNEL_MATERN32>(c, ta, nact);
+    default: return sel_bf16<GP_KERNEL_MATERN52>(c, ta, nact);
+  }
+}
+#endif
+
+#if GPMLL_KHAT_PART == 2 || GPMLL_KHAT_PART == 3
+namespace {
+template <typename T, int KIND, int NK4, int NTT>
+hipError_t run_fp(const Ctx& c, const TileArgs& ta, const int* nact) {
+  const Layout& L = *c.lay;
+  constexpr int RG = (sizeof(T) == 8) ? (NTT <= 4 ? 2 : 1) : (NTT <= 5 ? 4 : (NTT <= 8 ? 2 : 1));
+  dim3 grid((unsigned)(L.n_pad / (64 * RG)), (unsigned)L.nsplit);
+  hipLaunchKernelGGL((k_khat_fp<T, KIND, NK4, NTT, RG>), grid, dim3(256), 0, c.st, c.at<T>(L.xfa), c.at<T>(L.xfb),
+                     c.at<T>(L.rowterm), c.at<T>(L.colterm), c.at<T>(L.vfrag), c.at<T>(L.wpart), ta, nact);
+  return hipGetLastError();
+}
+template <typename T, int KIND, int NK4>
+hipError_t sel_fp_ntt(const Ctx& c, const TileArgs& ta, const int* nact, int ntt) {
+  switch (ntt) {
+#define CASE(N) case N: return run_fp<T, KIND, NK4, N>(c, ta, nact);
+    GPMLL_NTT_CASES(CASE)
+#undef CASE
+  }
+  return hipErrorInvalidValue;
+}
+template <typename T, int KIND>
+hipError_t sel_fp(const Ctx& c, const TileArgs& ta, const int* nact) {
+  const Layout& L = *c.lay;
+  const int ntt = L.tp / 16;
+  switch (L.kd / 4) {
+    case 1: return sel_fp_ntt<T, KIND, 1>(c, ta, nact, ntt);
+    case 2: return sel_fp_ntt<T, KIND, 2>(c, ta, nact, ntt);
+    case 4: return sel_fp_ntt<T, KIND, 4>(c, ta, nact, ntt);
+    case 8: return sel_fp_ntt<T, KIND, 8>(c, ta, nact, ntt);
+  }
+  return hipErrorInvalidValue;
+}
+template <typename T>
+hipError_t khat_tiles_fp(const Ctx& c, const Hyper& h, const TileArgs& ta, const int* nact) {
+  switch (h.kind) {
+    case GP_KERNEL_RBF: return sel_fp<T, GP_KERNEL_RBF>(c, ta, nact);
+    case GP_KERNEL_MATERN32: return sel_fp<T, GP_KERNEL_MATERN32>(c, ta, nact);
+    default: return sel_fp<T, GP_KERNEL_MATERN52>(c, ta, nact);
+  }
+}
+}  // namespace
+#if GPMLL_KHAT_PART == 2
+hipError_t khat_tiles_fp32(const Ctx& c, const Hyper& h, const TileArgs& ta, const int* nact) {
+  return khat_tiles_fp<float>(c, h, ta, nact);
+}
+#else
+hipError_t khat_tiles_fp64(const Ctx& c, const Hyper& h, const TileArgs& ta, const int* nact) {
+  return khat_tiles_fp<double>(c, h, ta, nact);
+}
+#endif
+#endif
+
+#if GPMLL_KHAT_PART == 0
+hipError_t launch_stage_x(const Ctx& c, const Hyper& h) {
+  const Layout& L = *c.lay;
+  const unsigned nb = (unsigned)((L.n_pad + 255) / 256);
+  if (L.prec == GP_PREC_BF16X3) {
+    const int dq = (L.d + 7) / 8 * 8;
+    hipLaunchKernelGGL(k_stage_x_bf16, dim3(nb), dim3(256), 0, c.st, c.at<double>(L.xs), L.n_pad, L.d, dq,
+                       L.kd / 32, h.kind, (float)h.log2s, c.at<u32x4>(L.xfa), c.at<u32x4>(L.xfb),
+                       c.at<float>(L.rowterm), c.at<float>(L.colterm));
+  } else if (L.prec == GP_PREC_FP32) {
+    hipLaunchKernelGGL(k_stage_x_fp<float>, dim3(nb), dim3(256), 0, c.st, c.at<double>(L.xs), L.n_pad, L.d,
+                       L.kd / 4, h.kind == GP_KERNEL_RBF ? 1 : 0, h.log2s, c.at<float>(L.xfa), c.at<float>(L.xfb),
+                       c.at<float>(L.rowterm), c.at<float>(L.colterm));
+  } else {
+    hipLaunchKernelGGL(k_stage_x_fp<double>, dim3(nb), dim3(256), 0, c.st, c.at<double>(L.xs), L.n_pad, L.d,
+                       L.kd / 4, 0, h.log2s, c.at<double>(L.xfa), c.at<double>(L.xfb), c.at<double>(L.rowterm),
+                       c.at<double>(L.colterm));
+  }
+  return hipGetLastError();
+}
+
+// distance operands of the derivative sweep (always q = r^2)
+hipError_t launch_stage_x_bwd(const Ctx& c, const Hyper& h) {
+  const Layout& L = *c.lay;
+  (void)h;
+  const unsigned nb = (unsigned)((L.n_pad + 255) / 256);
+  if (L.bprec == GP_PREC_FP64)
+    hipLaunchKernelGGL(k_stage_x_fp<double>, dim3(nb), dim3(256), 0, c.st, c.at<double>(L.xs), L.n_pad, L.d,
+                       L.bkd / 4, 0, 0.0, c.at<double>(L.bxa), c.at<double>(L.bxb), c.at<double>(L.brt),
+                       c.at<double>(L.bct));
+  else
+    hipLaunchKernelGGL(k_stage_x_fp<float>, dim3(nb), dim3(256), 0, c.st, c.at<double>(L.xs), L.n_pad, L.d,
+                       L.bkd / 4, 0, 0.0, c.at<float>(L.bxa), c.at<float>(L.bxb), c.at<float>(L.brt),
+                       c.at<float>(L.bct));
+  return hipGetLastError();
+}
+
+hipError_t launch_stage_v(const Ctx& c, const double* V, int ldv, int ncols, const Hyper& h) {
+  const Layout& L = *c.lay;
+  (void)h;
+  const int ntt = L.tp / 16;
+  if (L.prec == GP_PREC_BF16X3) {
+    const int64_t total = (L.n_pad / 32) * ntt * 64;
+    hipLaunchKernelGGL(k_stage_v_bf16, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, c.st, V, L.n, ldv,
+                       ncols, L.n_pad, ntt, c.at<u32x4>(L.vfrag));
+  } else if (L.prec == GP_PREC_FP32) {
+    const int64_t total = (L.n_pad / 16) * ntt * 256;
+    hipLaunchKernelGGL(k_stage_v_fp<float>, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, c.st, V, L.n, ldv,
+                       ncols, L.n_pad, ntt, c.at<float>(L.vfrag));
+  } else {
+    const int64_t total = (L.n_pad / 16) * ntt * 256;
+    hipLaunchKernelGGL(k_stage_v_fp<double>, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, c.st, V, L.n,
+                       ldv, ncols, L.n_pad, ntt, c.at<double>(L.vfrag));
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_khat_tiles(const Ctx& c, const Hyper& h, const int* nact) {
+  const Layout& L = *c.lay;
+  TileArgs ta;
+  ta.n_pad = L.n_pad;
+  ta.n_valid = L.n;
+  ta.cols_per_split = L.cols_per_split;
+  ta.tp = L.tp;
+  ta.s32 = (float)h.s;
+  ta.s64 = h.s;
+  if (L.prec == GP_PREC_BF16X3) return khat_tiles_bf16(c, h, ta, nact);
+  if (L.prec == GP_PREC_FP32) return khat_tiles_fp32(c, h, ta, nact);
+  return khat_tiles_fp64(c, h, ta, nact);
+}
+
+hipError_t launch_khat_reduce(const Ctx& c, const double* V, int ldv, double* W, int ldw, int ncols, double s2,
+                              double* dot_part, const int* nact) {
+  const Layout& L = *c.lay;
+  const unsigned nb = (unsigned)((L.n + 255) / 256);
+  if (L.prec == GP_PREC_FP64)
+    hipLaunchKernelGGL(k_khat_reduce<double>, dim3(nb), dim3(256), 0, c.st, c.at<double>(L.wpart), L.nsplit, L.n_pad,
+                       L.tp, V, ldv, W, ldw, L.n, ncols, s2, dot_part, nact);
+  else
+    hipLaunchKernelGGL(k_khat_reduce<float>, dim3(nb), dim3(256), 0, c.st, c.at<float>(L.wpart), L.nsplit, L.n_pad,
+                       L.tp, V, ldv, W, ldw, L.n, ncols, s2, dot_part, nact);
+  return hipGetLastError();
+}
+
+#endif  // part 0
+
+}  // namespace gpmll

@@ -1,0 +1,398 @@
+// Input staging, the partial pivoted Cholesky preconditioner and the probes.
+//
+// Preconditioner: P_hat = sigma^2 I + L L^T with L from a greedy partial pivoted
+// Cholesky factorisation of K (Section 2.2, "Preconditioning", diagonal-plus-low-rank
+// preconditioners; supplement S5.3).  Solves use the matrix inversion lemma with
+// C = sigma^2 I_k + L^T L; log det P_hat = (n - k) log sigma^2 + log det C.
+// Probes: b_i = sigma * eps_i + L * eta_i with Rademacher eps_i, eta_i drawn from a
+// SplitMix64 counter stream (Steele, Lea & Flood 2014), so that E[b b^T] = P_hat.
+#include "gpmll_impl.h"
+
+namespace gpmll {
+
+// ---------------------------------------------------------------------------
+// Column means and the scaled inputs x~ = (x - mean) / ls
+// ---------------------------------------------------------------------------
+
+__global__ void k_colsum_part(const double* __restrict__ X, int64_t n, int d, int64_t rows_per_block,
+                              double* __restrict__ part) {
+  __shared__ double red[8][GP_MAX_D];
+  const int j = threadIdx.x % GP_MAX_D;
+  const int g = threadIdx.x / GP_MAX_D;  // 8 row groups
+  const int64_t r0 = (int64_t)blockIdx.x * rows_per_block;
+  const int64_t r1 = min(n, r0 + rows_per_block);
+  double acc = 0.0;
+  if (j < d)
+    for (int64_t r = r0 + g; r < r1; r += 8) acc += X[r * d + j];
+  red[g][j] = acc;
+  __syncthreads();
+  if (g == 0 && j < d) {
+    double s = 0.0;
+    for (int q = 0; q < 8; ++q) s += red[q][j];
+    part[(int64_t)blockIdx.x * GP_MAX_D + j] = s;
+  }
+}
+
+__global__ void k_colmean_final(const double* __restrict__ part, int nblk, int64_t n, int d,
+                                double* __restrict__ mean) {
+  const int j = threadIdx.x;
+  if (j >= d) return;
+  double s = 0.0;
+  for (int b = 0; b < nblk; ++b) s += part[(int64_t)b * GP_MAX_D + j];
+  mean[j] = s / (double)n;
+}
+
+__global__ void k_scale(const double* __restrict__ X, const double* __restrict__ mean, int64_t n,
+                        int64_t n_pad, Hyper h, double* __restrict__ xs) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_pad) return;
+  for (int j = 0; j < h.d; ++j)
+    xs[i * h.d + j] = (i < n) ? (X[i * h.d + j] - mean[j]) * h.inv_ls[j] : 0.0;
+}
+
+// ---------------------------------------------------------------------------
+// Partial pivoted Cholesky: one launch per step.  Each launch
+//   1. reduces the previous step's per-block (value, index) maxima of the residual
+//      diagonal to the pivot (larger value wins, ties to the lower index),
+//   2. writes column j of L:  L[r, j] = (K[r, piv] - sum_{l<j} L[r, l] L[piv, l]) / sqrt(d_piv),
+//      with L[piv, j] = sqrt(d_piv) and zeros on earlier pivot rows,
+//   3. updates the residual diagonal and emits this block's maximum for step j+1.
+// A step whose largest residual is <= 1e-12 * s stops the factorisation: it and
+// all later steps leave their columns zero and record pivot -1.
+// ---------------------------------------------------------------------------
+
+struct ArgMax {
+  double v;
+  int64_t i;
+};
+
+__device__ inline ArgMax amax_better(ArgMax a, ArgMax b) {
+  if (b.v > a.v || (b.v == a.v && b.i < a.i)) return b;
+  return a;
+}
+
+__device__ ArgMax block_argmax(ArgMax x) {
+  __shared__ double sv[kRedBlock];
+  __shared__ int64_t si[kRedBlock];
+  sv[threadIdx.x] = x.v;
+  si[threadIdx.x] = x.i;
+  __syncthreads();
+  for (int off = blockDim.x / 2; off > 0; off >>= 1) {
+    if (threadIdx.x < off) {
+      ArgMax a{sv[threadIdx.x], si[threadIdx.x]};
+      ArgMax b{sv[threadIdx.x + off], si[threadIdx.x + off]};
+      a = amax_better(a, b);
+      sv[threadIdx.x] = a.v;
+      si[threadIdx.x] = a.i;
+    }
+    __syncthreads();
+  }
+  ArgMax r{sv[0], si[0]};
+  __syncthreads();
+  return r;
+}
+
+__global__ void k_pivchol_init(int64_t n, int k, double s, double* __restrict__ L,
+                               double* __restrict__ diag, int8_t* __restrict__ ispiv,
+                               int32_t* __restrict__ piv, ArgMax* __restrict__ amax, int* __restrict__ stop) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) {
+    diag[i] = s;
+    ispiv[i] = 0;
+    for (int j = 0; j < k; ++j) L[(int64_t)j * n + i] = 0.0;
+  }
+  if (i < k) piv[i] = -1;
+  // every entry ties at s: the block maximum is its first row
+  if (threadIdx.x == 0) {
+    const int64_t first = (int64_t)blockIdx.x * blockDim.x;
+    amax[blockIdx.x] = ArgMax{first < n ? s : -1.0, first < n ? first : (int64_t)n};
+  }
+  if (i == 0) {
+    stop[0] = 0;  // stop flag
+    stop[1] = k;  // achieved rank
+  }
+}
+
+__global__ void k_pivchol_step(int j, int64_t n, int k, int nblk, Hyper h, const double* __restrict__ xs,
+                               double* __restrict__ L, double* __restrict__ diag, int8_t* __restrict__ ispiv,
+                               int32_t* __restrict__ piv, const ArgMax* __restrict__ amax_in,
+                               ArgMax* __restrict__ amax_out, int* __restrict__ stop) {
+  __shared__ double Lp[GP_MAX_RANK];
+  __shared__ double xp[GP_MAX_D];
+  __shared__ ArgMax pivot;
+  __shared__ int halted;
+  if (threadIdx.x == 0) halted = *stop;
+  __syncthreads();
+  if (halted) return;
+  // 1. pivot of this step
+  ArgMax loc{-1.0, (int64_t)n};
+  for (int b = threadIdx.x; b < nblk; b += blockDim.x) loc = amax_better(loc, amax_in[b]);
+  ArgMax best = block_argmax(loc);
+  if (threadIdx.x == 0) pivot = best;
+  __syncthreads();
+  const double dpiv = pivot.v;
+  const int64_t ip = pivot.i;
+  if (!(dpiv > 1e-12 * h.s)) {
+    // breakdown: stop here (all blocks see the same pivot and agree)
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      stop[0] = 1;
+      stop[1] = j;
+    }
+    return;
+  }
+  for (int l = threadIdx.x; l < j; l += blockDim.x) Lp[l] = L[(int64_t)l * n + ip];
+  for (int q = threadIdx.x; q < h.d; q += blockDim.x) xp[q] = xs[ip * h.d + q];
+  __syncthreads();
+  const double sq = sqrt(dpiv);
+  const double inv = 1.0 / sq;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  ArgMax mine{-1.0, (int64_t)n};
+  if (i < n) {
+    double lij;
+    if (i == ip) {
+      lij = sq;
+    } else if (ispiv[i]) {
+      lij = 0.0;
+    } else {
+      double r2 = 0.0;
+      for (int q = 0; q < h.d; ++q) {
+        double df = xs[i * h.d + q] - xp[q];
+        r2 += df * df;
+      }
+      double kv = h.s * kappa64(h.kind, r2);
+      double dot = 0.0;
+      for (int l = 0; l < j; ++l) dot += L[(int64_t)l * n + i] * Lp[l];
+      lij = (kv - dot) * inv;
+    }
+    L[(int64_t)j * n + i] = lij;
+    double dn;
+    if (i == ip || ispiv[i]) {
+      dn = 0.0;
+    } else {
+      dn = diag[i] - lij * lij;
+      mine = ArgMax{dn, i};
+    }
+    diag[i] = dn;
+  }
+  ArgMax bm = block_argmax(mine);
+  if (threadIdx.x == 0) amax_out[blockIdx.x] = bm;
+  if (i == ip) ispiv[i] = 1;
+  if (blockIdx.x == 0 && threadIdx.x == 0) piv[j] = (int32_t)ip;
+}
+
+// ---------------------------------------------------------------------------
+// C = sigma^2 I + L^T L (partials over row chunks, then a fixed-order sum),
+// its Cholesky factor Rc, the inverse Rinv = Rc^-1, C^-1 and log det P_hat.
+// ---------------------------------------------------------------------------
+
+__global__ void k_gram_part(const double* __restrict__ L, int64_t n, int k, int64_t chunk,
+                            double* __restrict__ part) {
+  // block (tile a, tile b, chunk): 16 x 16 tile of L^T L over one row chunk
+  __shared__ double la[16][65], lb[16][65];
+  const int ta = blockIdx.x, tb = blockIdx.y;
+  if (tb > ta) return;
+  const int a0 = ta * 16, b0 = tb * 16;
+  const int64_t r0 = (int64_t)blockIdx.z * chunk, r1 = min(n, r0 + chunk);
+  const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
+  double acc = 0.0;
+  for (int64_t base = r0; base < r1; base += 64) {
+    for (int e = threadIdx.x; e < 16 * 64; e += blockDim.x) {
+      int c = e / 64, rr = e % 64;
+      int64_t r = base + rr;
+      la[c][rr] = (a0 + c < k && r < r1) ? L[(int64_t)(a0 + c) * n + r] : 0.0;
+      lb[c][rr] = (b0 + c < k && r < r1) ? L[(int64_t)(b0 + c) * n + r] : 0.0;
+    }
+    __syncthreads();
+    for (int rr = 0; rr < 64; ++rr) acc += la[ty][rr] * lb[tx][rr];
+    __syncthreads();
+  }
+  const int a = a0 + ty, b = b0 + tx;
+  if (a < k && b < k) part[((int64_t)blockIdx.z * k + a) * k + b] = acc;
+}
+
+__global__ void k_gram_final(const double* __restrict__ part, int nchunk, int k, double s2,
+                             double* __restrict__ C) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= k * k) return;
+  const int a = e / k, b = e % k;
+  const int hi = a > b ? a : b, lo = a > b ? b : a;
+  double s = 0.0;
+  for (int q = 0; q < nchunk; ++q) s += part[((int64_t)q * k + hi) * k + lo];
+  C[e] = s + (a == b ? s2 : 0.0);
+}
+
+// Right-looking Cholesky of the k x k matrix C (row-major) by one workgroup,
+// then the lower-triangular inverse, C^-1 = Rinv^T Rinv and the log-determinant.
+__global__ void k_small_chol(int64_t n, int k, double s2, const double* __restrict__ C,
+                             double* __restrict__ Rc, double* __restrict__ Rinv, double* __restrict__ Cinv,
+                             double* __restrict__ logdetP, int* __restrict__ status) {
+  __shared__ int bad;
+  __shared__ double red[1024];
+  if (threadIdx.x == 0) bad = 0;
+  for (int e = threadIdx.x; e < k * k; e += blockDim.x) Rc[e] = C[e];
+  __syncthreads();
+  for (int j = 0; j < k; ++j) {
+    if (threadIdx.x == 0) {
+      double v = Rc[j * k + j];
+      if (!(v > 0.0)) {
+        bad = 1;
+        v = 1.0;
+      }
+      Rc[j * k + j] = sqrt(v);
+    }
+    __syncthreads();
+    const double piv = Rc[j * k + j];
+    for (int i = j + 1 + threadIdx.x; i < k; i += blockDim.x) Rc[i * k + j] /= piv;
+    __syncthreads();
+    const int m = k - j - 1;
+    for (int e = threadIdx.x; e < m * m; e += blockDim.x) {
+      int i = j + 1 + e / m, l = j + 1 + e % m;
+      if (l <= i) Rc[i * k + l] -= Rc[i * k + j] * Rc[l * k + j];
+    }
+    __syncthreads();
+  }
+  for (int e = threadIdx.x; e < k * k; e += blockDim.x) {
+    int i = e / k, l = e % k;
+    if (l > i) Rc[e] = 0.0;
+  }
+  __syncthreads();
+  // Rinv column c: solve Rc x = e_c by forward substitution (one thread per column)
+  for (int c = threadIdx.x; c < k; c += blockDim.x) {
+    for (int i = 0; i < k; ++i) {
+      double acc = (i == c) ? 1.0 : 0.0;
+      for (int l = c; l < i; ++l) acc -= Rc[i * k + l] * Rinv[l * k + c];
+      Rinv[i * k + c] = (i < c) ? 0.0 : acc / Rc[i * k + i];
+    }
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < k * k; e += blockDim.x) {
+    int a = e / k, b = e % k;
+    int lo = a > b ? a : b;
+    double s = 0.0;
+    for (int l = lo; l < k; ++l) s += Rinv[l * k + a] * Rinv[l * k + b];
+    Cinv[e] = s;
+  }
+  double acc = 0.0;
+  for (int j = threadIdx.x; j < k; j += blockDim.x) acc += log(Rc[j * k + j]);
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+    for (int q = 0; q < (int)blockDim.x; ++q) s += red[q];
+    *logdetP = (double)(n - k) * log(s2) + 2.0 * s;
+    if (bad) *status = GP_ENOTSPD;
+  }
+}
+
+__global__ void k_logdet_noprecond(int64_t n, double s2, double* logdetP) {
+  *logdetP = (double)n * log(s2);
+}
+
+// ---------------------------------------------------------------------------
+// Probes
+// ---------------------------------------------------------------------------
+
+__device__ inline uint64_t splitmix64(uint64_t seed, uint64_t ctr) {
+  uint64_t z = seed + (ctr + 1ull) * 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+// sign +1 when the top bit of output (stream << 56 | col << 32 | idx) is clear
+__device__ inline double rademacher(uint64_t seed, uint64_t stream, uint64_t col, uint64_t idx) {
+  uint64_t v = splitmix64(seed, (stream << 56) | (col << 32) | idx);
+  return (v >> 63) ? -1.0 : 1.0;
+}
+
+__global__ void k_eta(uint64_t seed, int k, int ell, double* __restrict__ H) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= k * ell) return;
+  const int l = e / ell, c = e % ell;
+  H[e] = rademacher(seed, 1, (uint64_t)c, (uint64_t)l);
+}
+
+// R = [y | sigma eps + L eta] (n_pad x tp row-major), Xs = 0, padding zero
+__global__ void k_probes(const double* __restrict__ y, const double* __restrict__ L,
+                         const double* __restrict__ H, int64_t n, int64_t n_pad, int k, int ell, int tp,
+                         double sigma, uint64_t seed, double* __restrict__ R, double* __restrict__ Xs) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_pad) return;
+  double* row = R + i * tp;
+  double* xrow = Xs + i * tp;
+  for (int c = 0; c < tp; ++c) xrow[c] = 0.0;
+  if (i >= n) {
+    for (int c = 0; c < tp; ++c) row[c] = 0.0;
+    return;
+  }
+  row[0] = y[i];
+  for (int c = 0; c < ell; ++c) {
+    double acc = sigma * rademacher(seed, 0, (uint64_t)c, (uint64_t)i);
+    for (int l = 0; l < k; ++l) acc += L[(int64_t)l * n + i] * H[l * ell + c];
+    row[1 + c] = acc;
+  }
+  for (int c = 1 + ell; c < tp; ++c) row[c] = 0.0;
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+
+hipError_t launch_prep(const Ctx& c, const double* X, const Hyper& h) {
+  const Layout& L = *c.lay;
+  const int64_t rows_per_block = (L.n + L.nred - 1) / L.nred;
+  hipLaunchKernelGGL(k_colsum_part, dim3(L.nred), dim3(256), 0, c.st, X, L.n, L.d, rows_per_block,
+                     c.at<double>(L.mean_part));
+  hipLaunchKernelGGL(k_colmean_final, dim3(1), dim3(GP_MAX_D), 0, c.st, c.at<double>(L.mean_part), L.nred,
+                     L.n, L.d, c.at<double>(L.mean));
+  hipLaunchKernelGGL(k_scale, dim3((unsigned)((L.n_pad + 255) / 256)), dim3(256), 0, c.st, X,
+                     c.at<double>(L.mean), L.n, L.n_pad, h, c.at<double>(L.xs));
+  return hipGetLastError();
+}
+
+hipError_t launch_pivchol(const Ctx& c, const Hyper& h) {
+  const Layout& L = *c.lay;
+  const int nblk = (int)((L.n + kRedBlock - 1) / kRedBlock);
+  ArgMax* am = c.at<ArgMax>(L.amax);
+  int* stop = c.at<int>(L.scal_small);
+  hipLaunchKernelGGL(k_pivchol_init, dim3(nblk), dim3(kRedBlock), 0, c.st, L.n, L.k, h.s, c.at<double>(L.L),
+                     c.at<double>(L.diag), c.at<int8_t>(L.ispiv), c.at<int32_t>(L.piv), am, stop);
+  for (int j = 0; j < L.k; ++j) {
+    ArgMax* in = am + (j % 2) * nblk;
+    ArgMax* out = am + ((j + 1) % 2) * nblk;
+    hipLaunchKernelGGL(k_pivchol_step, dim3(nblk), dim3(kRedBlock), 0, c.st, j, L.n, L.k, nblk, h,
+                       c.at<double>(L.xs), c.at<double>(L.L), c.at<double>(L.diag), c.at<int8_t>(L.ispiv),
+                       c.at<int32_t>(L.piv), in, out, stop);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_precond_finish(const Ctx& c, const Hyper& h) {
+  const Layout& L = *c.lay;
+  if (L.k == 0) {
+    hipLaunchKernelGGL(k_logdet_noprecond, dim3(1), dim3(1), 0, c.st, L.n, h.s2, c.at<double>(L.logdetP));
+    return hipGetLastError();
+  }
+  const int tiles = (L.k + 15) / 16;
+  hipLaunchKernelGGL(k_gram_part, dim3(tiles, tiles, L.nchunk), dim3(256), 0, c.st, c.at<double>(L.L), L.n,
+                     L.k, (int64_t)kChunkRows, c.at<double>(L.ltr_part));
+  hipLaunchKernelGGL(k_gram_final, dim3((L.k * L.k + 255) / 256), dim3(256), 0, c.st,
+                     c.at<double>(L.ltr_part), L.nchunk, L.k, h.s2, c.at<double>(L.C));
+  hipLaunchKernelGGL(k_small_chol, dim3(1), dim3(1024), 0, c.st, L.n, L.k, h.s2, c.at<double>(L.C),
+                     c.at<double>(L.Rc), c.at<double>(L.Rinv), c.at<double>(L.Cinv), c.at<double>(L.logdetP),
+                     c.at<int>(L.flags) + 1);
+  return hipGetLastError();
+}
+
+hipError_t launch_probes(const Ctx& c, const double* y, const Hyper& h, uint64_t seed) {
+  const Layout& L = *c.lay;
+  if (L.k > 0)
+    hipLaunchKernelGGL(k_eta, dim3((L.k * L.ell + 255) / 256), dim3(256), 0, c.st, seed, L.k, L.ell,
+                       c.at<double>(L.H));
+  hipLaunchKernelGGL(k_probes, dim3((unsigned)((L.n_pad + 255) / 256)), dim3(256), 0, c.st, y,
+                     c.at<double>(L.L), c.at<double>(L.H), L.n, L.n_pad, L.k, L.ell, L.tp, sqrt(h.s2), seed,
+                     c.at<double>(L.R), c.at<double>(L.Xs));
+  return hipGetLastError();
+}
+
+}  // namespace gpmll

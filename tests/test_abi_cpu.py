@@ -1,0 +1,159 @@
+"""C-ABI checks that need no GPU: the library loads, exports every function the
+header declares, the ctypes structures match the C layout, and host-side argument
+validation rejects bad inputs before any device call."""
+import ctypes
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+from paper_2107_00243_amd import binding as B
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "gpmll.h")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(B.LIB_PATH):
+        pytest.fail("libgpmll.so is not built (run python -m paper_2107_00243_amd.build)")
+    return B.load()
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:int|void|const char\*)\s+(gp_\w+)\s*\(", src, re.M)))
+
+
+def test_header_declares_the_bound_functions():
+    assert declared_functions() == sorted(B.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol(lib):
+    out = subprocess.run(["nm", "-D", "--defined-only", B.LIB_PATH], stdout=subprocess.PIPE, text=True).stdout
+    syms = {l.split()[-1] for l in out.splitlines() if l.strip()}
+    for name in declared_functions():
+        assert name in syms, name
+        assert hasattr(lib, name)
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    prog = tmp_path / "layout.c"
+    prog.write_text(r'''
+#define __HIP_PLATFORM_AMD__ 1
+#include <stdio.h>
+#include <stddef.h>
+#include "gpmll.h"
+#define P(T, F) printf(#T "." #F " %zu\n", offsetof(T, F))
+int main(void) {
+  printf("gp_problem %zu\n", sizeof(gp_problem));
+  printf("gp_options %zu\n", sizeof(gp_options));
+  printf("gp_stats %zu\n", sizeof(gp_stats));
+  printf("gp_precond_view %zu\n", sizeof(gp_precond_view));
+  P(gp_problem, n); P(gp_problem, d); P(gp_problem, ard);
+  P(gp_options, cg_tol); P(gp_options, seed); P(gp_options, precond_grad); P(gp_options, sync_every);
+  P(gp_stats, logdet_precond); P(gp_stats, logdet_estimate); P(gp_stats, col_iters_host); P(gp_stats, pivots_host);
+  P(gp_precond_view, n); P(gp_precond_view, rank);
+  return 0;
+}
+''')
+    exe = tmp_path / "layout"
+    r = subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), "-I", "/opt/rocm/include", str(prog), "-o",
+                        str(exe)], stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
+    assert r.returncode == 0, r.stdout
+    got = dict(l.rsplit(" ", 1) for l in subprocess.run([str(exe)], stdout=subprocess.PIPE,
+                                                         text=True).stdout.splitlines())
+    types = {"gp_problem": B.gp_problem, "gp_options": B.gp_options, "gp_stats": B.gp_stats,
+             "gp_precond_view": B.gp_precond_view}
+    for key, val in got.items():
+        if "." in key:
+            t, f = key.split(".")
+            assert getattr(types[t], f).offset == int(val), key
+        else:
+            assert ctypes.sizeof(types[key]) == int(val), key
+
+
+def _fake_problem(n=100, d=3, kernel=0, ard=1):
+    return B.gp_problem(0x1000, 0x2000, n, d, kernel, ard)
+
+
+def test_workspace_size_is_positive_and_grows(lib):
+    o = B.make_options("bf16x3", 64, 200)
+    s1 = B.gp_workspace_size(_fake_problem(1000, 16), o, 10)
+    s2 = B.gp_workspace_size(_fake_problem(2000, 16), o, 10)
+    assert 0 < s1 < s2
+
+
+@pytest.mark.parametrize("mutate", [
+    lambda p, o: setattr(p, "n", 0),
+    lambda p, o: setattr(p, "d", 0),
+    lambda p, o: setattr(p, "d", 33),
+    lambda p, o: setattr(p, "kernel", 3),
+    lambda p, o: setattr(p, "ard", 2),
+    lambda p, o: setattr(o, "num_probes", 0),
+    lambda p, o: setattr(o, "num_probes", 256),
+    lambda p, o: setattr(o, "max_iters", 0),
+    lambda p, o: setattr(o, "cg_tol", -1.0),
+    lambda p, o: setattr(o, "cg_tol", float("nan")),
+    lambda p, o: setattr(o, "precision", 3),
+    lambda p, o: setattr(o, "precond_grad", 2),
+    lambda p, o: setattr(o, "sync_every", -1),
+])
+def test_invalid_shapes_and_options_are_rejected(lib, mutate):
+    p, o = _fake_problem(), B.make_options("fp64", 4, 10)
+    mutate(p, o)
+    out = ctypes.c_size_t(0)
+    r1 = lib.gp_workspace_size(ctypes.byref(p), ctypes.byref(o), 2, ctypes.byref(out))
+    theta = np.array([0.5, 0.5, 0.5, 1.0, 0.1])
+    tp = theta.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    r2 = lib.gp_mll_eval(ctypes.byref(p), tp, ctypes.byref(o), 2, None, ctypes.c_void_p(0x10000), 1 << 30, None,
+                         ctypes.c_void_p(0x3000), None)
+    assert r1 == B.GP_EINVAL or r2 == B.GP_EINVAL
+    assert r2 == B.GP_EINVAL
+
+
+@pytest.mark.parametrize("bad", [0.0, -1.0, float("nan"), float("inf")])
+@pytest.mark.parametrize("pos", [0, 3, 4])
+def test_nonpositive_or_nan_theta_is_rejected(lib, bad, pos):
+    p, o = _fake_problem(), B.make_options("fp64", 4, 10)
+    theta = np.array([0.5, 0.5, 0.5, 1.0, 0.1])
+    theta[pos] = bad
+    tp = theta.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    logp = ctypes.c_void_p(0x3000)
+    assert lib.gp_mll_eval(ctypes.byref(p), tp, ctypes.byref(o), 2, None, ctypes.c_void_p(0x10000), 1 << 30, None,
+                           logp, None) == B.GP_EINVAL
+    assert lib.gp_mll_grad(ctypes.byref(p), tp, ctypes.byref(o), 2, None, ctypes.c_void_p(0x10000), 1 << 30, None,
+                           logp, ctypes.c_void_p(0x4000), None) == B.GP_EINVAL
+    h = ctypes.c_void_p()
+    assert lib.gp_precond_build(ctypes.byref(p), tp, 2, ctypes.c_void_p(0x10000), 1 << 30, None,
+                                ctypes.byref(h)) == B.GP_EINVAL
+
+
+def test_null_pointers_and_rank_bounds_are_rejected(lib):
+    o = B.make_options("fp64", 4, 10)
+    theta = np.array([0.5, 0.5, 0.5, 1.0, 0.1])
+    tp = theta.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    ws = ctypes.c_void_p(0x10000)
+    p = _fake_problem()
+    p_nox = B.gp_problem(0, 0x2000, 100, 3, 0, 1)
+    for prob, rank, logp in ((p_nox, 2, 0x3000), (p, -1, 0x3000), (p, 101, 0x3000), (p, 2, 0)):
+        assert lib.gp_mll_eval(ctypes.byref(prob), tp, ctypes.byref(o), rank, None, ws, 1 << 30, None,
+                               ctypes.c_void_p(logp), None) == B.GP_EINVAL
+    assert lib.gp_mll_grad(ctypes.byref(p), tp, ctypes.byref(o), 2, None, ws, 1 << 30, None,
+                           ctypes.c_void_p(0x3000), None, None) == B.GP_EINVAL
+    assert lib.gp_workspace_size(ctypes.byref(p), ctypes.byref(o), 2, None) == B.GP_EINVAL
+    assert lib.gp_khat_matvec(ctypes.byref(p), tp, 0, None, 4, ctypes.c_void_p(0x5000), ws, 1 << 30, None) == B.GP_EINVAL
+    assert lib.gp_khat_matvec(ctypes.byref(p), tp, 0, ctypes.c_void_p(0x5000), 0, ctypes.c_void_p(0x5000), ws,
+                              1 << 30, None) == B.GP_EINVAL
+
+
+def test_strerror_covers_every_status(lib):
+    for code in (0, -1, -2, -3, -4, -5):
+        assert B.gp_strerror(code) and B.gp_strerror(code) != "unknown status"
+    assert B.gp_strerror(-99) == "unknown status"
+
+
+def test_precond_free_accepts_null(lib):
+    lib.gp_precond_free(None)

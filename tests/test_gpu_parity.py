@@ -1,0 +1,283 @@
+"""Parity of the HIP path (through the C-ABI) with the CPU oracle on the same
+seeded inputs.  Marked gpu: they need an MI355X and the built library."""
+import sys
+
+import numpy as np
+import pytest
+
+import synthgp
+from oracle import gp_oracle as go
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from paper_2107_00243_amd import binding as B  # noqa: E402
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    if not torch.cuda.is_available():
+        pytest.fail("no GPU visible")
+    B.load()
+    return torch.device("cuda:0")
+
+
+def run_estimator(pr, precision, rank=None, num_probes=None, tol=None, max_iters=None, grad=True,
+                  precond_grad=0, sync_every=1, seed=None):
+    rank = pr.rank if rank is None else rank
+    num_probes = pr.num_probes if num_probes is None else num_probes
+    tol = pr.tol if tol is None else tol
+    max_iters = pr.max_iters if max_iters is None else max_iters
+    seed = pr.probe_seed if seed is None else seed
+    say(f"[gpu] estimator {pr.name} n={pr.n} d={pr.d} {pr.kernel} ard={pr.ard} prec={precision} k={rank} "
+        f"ell={num_probes} tol={tol} grad={grad}")
+    dev = torch.device("cuda:0")
+    X = torch.tensor(pr.X, device=dev)
+    y = torch.tensor(pr.y, device=dev)
+    prob = B.make_problem(X, y, pr.kernel, pr.ard)
+    opt = B.make_options(precision, num_probes, max_iters, tol, seed, precond_grad, sync_every)
+    ws = B.alloc_workspace(B.gp_workspace_size(prob, opt, rank))
+    logp = torch.zeros(1, dtype=torch.float64, device=dev)
+    g = torch.zeros(len(pr.theta), dtype=torch.float64, device=dev)
+    st = B.Stats(num_probes, rank)
+    if grad:
+        B.gp_mll_grad(prob, pr.theta, opt, rank, None, ws, logp, g, st)
+    else:
+        B.gp_mll_eval(prob, pr.theta, opt, rank, None, ws, logp, st)
+    torch.cuda.synchronize()
+    return {"logp": float(logp.cpu()[0]), "grad": g.cpu().numpy(), "stats": st}
+
+
+def oracle(pr, rank=None, num_probes=None, tol=None, max_iters=None, grad=True, precond_grad=0, seed=None):
+    return go.estimate_mll(pr.X, pr.y, pr.theta, pr.kernel, pr.ard, pr.rank if rank is None else rank,
+                           pr.num_probes if num_probes is None else num_probes, pr.tol if tol is None else tol,
+                           pr.max_iters if max_iters is None else max_iters,
+                           pr.probe_seed if seed is None else seed, grad=grad, precond_grad=precond_grad)
+
+
+def rel(a, b):
+    return abs(a - b) / max(abs(b), 1e-300)
+
+
+def relvec(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / max(np.linalg.norm(b), 1e-300))
+
+
+FP64_LP, FP64_G = 1e-7, 1e-5
+
+# ---------------------------------------------------------------- K_hat V tiles
+
+MATVEC_TOL = {"fp64": 1e-12, "fp32": 2e-5, "bf16x3": 2e-4}
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "bf16x3"])
+@pytest.mark.parametrize("kernel", ["rbf", "matern32", "matern52"])
+@pytest.mark.parametrize("n,d,nrhs", [(1000, 3, 17), (777, 8, 33), (1300, 16, 65), (300, 20, 5)])
+def test_khat_matvec_matches_oracle(precision, kernel, n, d, nrhs):
+    pr = synthgp.random_problem(n, d, kernel, ard=True, seed=n + d, ls_range=(0.5, 2.0), dist="normal")
+    say(f"[gpu] khat_matvec n={n} d={d} rhs={nrhs} {kernel} {precision}")
+    dev = torch.device("cuda:0")
+    rng = np.random.default_rng(7)
+    V = rng.standard_normal((n, nrhs))
+    X = torch.tensor(pr.X, device=dev)
+    y = torch.tensor(pr.y, device=dev)
+    prob = B.make_problem(X, y, kernel, True)
+    opt = B.make_options(precision, max(1, nrhs - 1), 1)
+    ws = B.alloc_workspace(B.gp_workspace_size(prob, opt, 0))
+    Vd = torch.tensor(V, device=dev)
+    Wd = torch.zeros_like(Vd)
+    B.gp_khat_matvec(prob, pr.theta, precision, Vd, Wd, ws)
+    W = Wd.cpu().numpy()
+    ref = go.khat_matvec(pr.X, pr.theta, kernel, True, V)
+    # error relative to |K_hat| |V| row by row (the scale of the summed terms)
+    Kabs = np.abs(go.khat_dense(pr.X, pr.theta, kernel, True))
+    scale = Kabs @ np.abs(V)
+    err = np.max(np.abs(W - ref) / scale)
+    say(f"    max scaled error {err:.3e}")
+    assert err < MATVEC_TOL[precision]
+
+
+def test_khat_matvec_ragged_and_tiny_sizes():
+    for n in (1, 5, 16, 17, 255, 257):
+        pr = synthgp.random_problem(n, 2, "rbf", ard=False, seed=n)
+        dev = torch.device("cuda:0")
+        say(f"[gpu] khat_matvec tiny n={n}")
+        X = torch.tensor(pr.X, device=dev)
+        y = torch.tensor(pr.y, device=dev)
+        prob = B.make_problem(X, y, "rbf", False)
+        opt = B.make_options("fp64", 2, 1)
+        ws = B.alloc_workspace(B.gp_workspace_size(prob, opt, 0))
+        V = np.random.default_rng(n).standard_normal((n, 3))
+        Vd = torch.tensor(V, device=dev)
+        Wd = torch.zeros_like(Vd)
+        B.gp_khat_matvec(prob, pr.theta, "fp64", Vd, Wd, ws)
+        np.testing.assert_allclose(Wd.cpu().numpy(), go.khat_matvec(pr.X, pr.theta, "rbf", False, V),
+                                   rtol=1e-11, atol=1e-12)
+
+
+# ---------------------------------------------------------------- preconditioner
+
+@pytest.mark.parametrize("kernel,ard", [("rbf", False), ("matern52", True), ("matern32", True)])
+def test_pivoted_cholesky_matches_oracle(kernel, ard):
+    pr = synthgp.random_problem(1500, 4, kernel, ard=ard, seed=11, dist="normal")
+    dev = torch.device("cuda:0")
+    say(f"[gpu] precond build {kernel}")
+    X = torch.tensor(pr.X, device=dev)
+    y = torch.tensor(pr.y, device=dev)
+    prob = B.make_problem(X, y, kernel, ard)
+    opt = B.make_options("fp64", 4, 10)
+    rank = 40
+    ws = B.alloc_workspace(B.gp_workspace_size(prob, opt, rank))
+    h = B.gp_precond_build(prob, pr.theta, rank, ws)
+    v = B.gp_precond_view_of(h)
+    torch.cuda.synchronize()
+    n = pr.n
+    Lg = np.frombuffer(ws.cpu().numpy().tobytes(), dtype=np.uint8)  # whole workspace on host
+    base = ws.data_ptr()
+    L = Lg[v.L_dev - base: v.L_dev - base + n * rank * 8].view(np.float64).reshape(rank, n).T
+    piv = Lg[v.pivots_dev - base: v.pivots_dev - base + rank * 4].view(np.int32)
+    logdet = Lg[v.logdet_dev - base: v.logdet_dev - base + 8].view(np.float64)[0]
+    B.gp_precond_free(h)
+    Lr, pivr, kp = go.pivoted_cholesky(pr.X, pr.theta, kernel, ard, rank)
+    assert kp == rank
+    np.testing.assert_array_equal(piv, pivr)
+    np.testing.assert_allclose(L, Lr, rtol=1e-9, atol=1e-11)
+    P = go.Preconditioner(Lr, pr.theta[-1])
+    assert rel(logdet, P.logdet) < 1e-11
+
+
+def test_pivoted_cholesky_breakdown_sets_rank_and_flag():
+    base = np.array([[0.1, 0.2], [0.5, 0.9], [0.8, 0.3]])
+    X = np.repeat(base, 40, axis=0)
+    pr = synthgp.GPProblem("dup", X, np.sin(X[:, 0]), np.array([0.5, 1.0, 0.1]), "rbf", False, rank=6,
+                           num_probes=4, tol=1e-8, max_iters=50, precision="fp64")
+    out = run_estimator(pr, "fp64")
+    ref = oracle(pr)
+    assert out["stats"].rank_achieved == 3 and ref["rank"] == 3
+    assert out["stats"].flags & B.FLAG_RANK_DEFICIENT
+    assert rel(out["logp"], ref["logp"]) < 1e-9
+
+
+# ---------------------------------------------------------------- estimator
+
+def _check_tight(out, ref, lp_tol, g_tol):
+    st = out["stats"]
+    iters_ok = np.array_equal(st.col_iters, ref["iters"])
+    say(f"    logp {out['logp']:.12g} ref {ref['logp']:.12g} rel {rel(out['logp'], ref['logp']):.2e}; "
+        f"grad rel {relvec(out['grad'], ref['grad']):.2e}; iters gpu {st.col_iters.max()} ref {ref['iters'].max()} "
+        f"equal={iters_ok}")
+    assert rel(out["logp"], ref["logp"]) < lp_tol
+    assert relvec(out["grad"], ref["grad"]) < g_tol
+    return iters_ok
+
+
+# FP64 tiles against the FP64 oracle: both run the same recurrences, but late CG
+# steps amplify differences in summation order, so agreement is ~1e-8, not 1e-15
+
+
+def test_plain_rbf_fp64_matches_oracle_tightly():
+    pr = synthgp.plain_rbf_1000()
+    out = run_estimator(pr, "fp64")
+    ref = oracle(pr)
+    _check_tight(out, ref, FP64_LP, FP64_G)
+    # where the residual plateaus near the tolerance, rounding moves the stopping
+    # step of a column by a few iterations; the quadrature values stay put
+    assert np.max(np.abs(out["stats"].col_iters - ref["iters"])) <= max(2, 0.1 * ref["iters"].max())
+    np.testing.assert_allclose(out["stats"].gammas, ref["gammas"], rtol=1e-6, atol=1e-8)
+    assert out["stats"].rank_achieved == pr.rank
+    assert np.array_equal(out["stats"].pivots, ref["piv"])
+
+
+@pytest.mark.parametrize("kernel,ard,precision,lp_tol,g_tol", [
+    ("rbf", True, "fp64", FP64_LP, FP64_G),
+    ("matern32", True, "fp64", FP64_LP, FP64_G),
+    ("matern52", False, "fp64", FP64_LP, FP64_G),
+    ("matern52", True, "fp32", 1e-3, 1e-2),
+    ("rbf", True, "fp32", 1e-3, 1e-2),
+    ("rbf", True, "bf16x3", 1e-3, 1e-2),
+    ("matern32", True, "bf16x3", 1e-3, 1e-2),
+])
+def test_estimator_matches_oracle(kernel, ard, precision, lp_tol, g_tol):
+    pr = synthgp.random_problem(1111, 5, kernel, ard=ard, seed=3, dist="normal", rank=20, num_probes=12,
+                                sigma2=0.02, tol=1e-7)
+    out = run_estimator(pr, precision)
+    ref = oracle(pr)
+    _check_tight(out, ref, lp_tol, g_tol)
+
+
+def test_matern52_ard_20k_recipe_at_reduced_n_fp32():
+    pr = synthgp.matern52_ard_20k(n=3000)
+    out = run_estimator(pr, "fp32")
+    ref = oracle(pr)
+    _check_tight(out, ref, 1e-3, 1e-2)
+
+
+def test_rbf_ard_100k_recipe_at_reduced_n_bf16x3():
+    pr = synthgp.rbf_ard_100k(n=2500)
+    out = run_estimator(pr, "bf16x3")
+    ref = oracle(pr)
+    _check_tight(out, ref, 1e-3, 1e-2)
+
+
+@pytest.mark.parametrize("precond_grad", [0, 1])
+def test_precond_grad_modes(precond_grad):
+    pr = synthgp.random_problem(900, 3, "matern32", ard=True, seed=5, rank=15, num_probes=8, tol=1e-8)
+    out = run_estimator(pr, "fp64", precond_grad=precond_grad)
+    ref = oracle(pr, precond_grad=precond_grad)
+    _check_tight(out, ref, FP64_LP, FP64_G)
+
+
+def test_no_preconditioner_rank_zero():
+    pr = synthgp.random_problem(700, 2, "rbf", ard=True, seed=6, num_probes=6, tol=1e-8, sigma2=0.1)
+    out = run_estimator(pr, "fp64", rank=0)
+    ref = oracle(pr, rank=0)
+    _check_tight(out, ref, FP64_LP, FP64_G)
+
+
+def test_single_probe_and_iteration_cap():
+    pr = synthgp.random_problem(500, 3, "rbf", ard=True, seed=8, rank=5, num_probes=1, tol=0.0, max_iters=7)
+    out = run_estimator(pr, "fp64")
+    ref = oracle(pr)
+    assert out["stats"].flags & B.FLAG_NOT_CONVERGED
+    assert np.all(out["stats"].col_iters == 7) and np.all(ref["iters"] == 7)
+    _check_tight(out, ref, 1e-10, 1e-8)  # seven iterations: no late-step amplification
+
+
+def test_eval_without_grad_and_without_host_sync():
+    pr = synthgp.plain_rbf_1000(n=800)
+    a = run_estimator(pr, "fp64", grad=False, sync_every=0)
+    b = run_estimator(pr, "fp64", grad=True, sync_every=3)
+    assert a["logp"] == b["logp"]
+
+
+def test_results_are_bitwise_deterministic():
+    pr = synthgp.rbf_ard_100k(n=3000)
+    a = run_estimator(pr, "bf16x3")
+    b = run_estimator(pr, "bf16x3")
+    assert a["logp"] == b["logp"]
+    assert np.array_equal(a["grad"], b["grad"])
+
+
+def test_gradient_matches_central_differences_of_the_estimator():
+    # with fixed probes the estimate is a smooth function of theta away from pivot
+    # changes; the returned gradient approximates d/dtheta of the *exact* log p
+    pr = synthgp.random_problem(600, 2, "rbf", ard=True, seed=9, rank=30, num_probes=16, tol=1e-10,
+                                sigma2=0.05)
+    out = run_estimator(pr, "fp64")
+    ex = go.exact_mll(pr.X, pr.y, pr.theta, pr.kernel, pr.ard)
+    fd = np.zeros_like(pr.theta)
+    for i in range(len(pr.theta)):
+        h = 1e-5 * pr.theta[i]
+        tp, tm = pr.theta.copy(), pr.theta.copy()
+        tp[i] += h
+        tm[i] -= h
+        fd[i] = (go.exact_mll(pr.X, pr.y, tp, pr.kernel, pr.ard)["logp"]
+                 - go.exact_mll(pr.X, pr.y, tm, pr.kernel, pr.ard)["logp"]) / (2 * h)
+    say(f"    grad {out['grad']} exact {ex['grad']} fd {fd}")
+    assert relvec(fd, ex["grad"]) < 1e-6
+    assert relvec(out["grad"], fd) < 5e-2
