@@ -288,6 +288,78 @@ __global__ void k_khat_reduce(const T* __restrict__ wpart, int nsplit, int64_t n
 #endif  // part 0
 
 #if GPMLL_KHAT_PART == 1
+// One 32-column step of the BF16x3 tile kernel for one wave (RG row groups of 16).
+// DIAG: the step's columns overlap the wave's rows; the diagonal gets exactly s.
+template <int KIND, int NKC, int NTT, int RG, bool DIAG>
+__device__ __forceinline__ void bf16_step(const u32x4* __restrict__ A, const u32x4* (&xb)[RG], const u32x4 (&xbv)[RG][NKC],
+                                          const f32x4 (&rt)[RG], f32x4 (&acc)[RG][NTT], int lane, int64_t row0,
+                                          int64_t c, float s32) {
+  constexpr int A_U = 2 * NKC * 64, V_U = NTT * 2 * 64;
+  const int g = lane >> 4, li = lane & 15;
+  const u32x4* Vf = A + A_U;
+  const float* ct = reinterpret_cast<const float*>(A + A_U + V_U);
+  const f32x4 ct0 = *reinterpret_cast<const f32x4*>(ct + 4 * g);
+  const f32x4 ct1 = *reinterpret_cast<const f32x4*>(ct + 16 + 4 * g);
+  u32x4 ph[RG], pl[RG];
+#pragma unroll
+  for (int rg = 0; rg < RG; ++rg) {
+#pragma unroll
+    for (int js = 0; js < 2; ++js) {
+      f32x4 dd = rt[rg];
+#pragma unroll
+      for (int kc = 0; kc < NKC; ++kc)
+        dd = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, A[(js * NKC + kc) * 64 + lane]),
+                                                     __builtin_bit_cast(bf16x8, xbv[rg][kc]), dd, 0, 0, 0);
+      const f32x4 ctv = js ? ct1 : ct0;
+      float kv[4];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) kv[v] = map32<KIND>(dd[v] + ctv[v], s32);
+      if constexpr (DIAG) {
+        const int64_t i = row0 + rg * 16 + li;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) kv[v] = (i == c + js * 16 + 4 * g + v) ? s32 : kv[v];
+      }
+      uint32_t h0, l0, h1, l1;
+      split_pair(kv[0], kv[1], &h0, &l0);
+      split_pair(kv[2], kv[3], &h1, &l1);
+      ph[rg][2 * js] = h0;
+      ph[rg][2 * js + 1] = h1;
+      pl[rg][2 * js] = l0;
+      pl[rg][2 * js + 1] = l1;
+    }
+  }
+#pragma unroll
+  for (int tt = 0; tt < NTT; ++tt) {
+    const bf16x8 vh = __builtin_bit_cast(bf16x8, Vf[(tt * 2 + 0) * 64 + lane]);
+    const bf16x8 vl = __builtin_bit_cast(bf16x8, Vf[(tt * 2 + 1) * 64 + lane]);
+#pragma unroll
+    for (int rg = 0; rg < RG; ++rg) {
+      const bf16x8 h = __builtin_bit_cast(bf16x8, ph[rg]);
+      const bf16x8 l = __builtin_bit_cast(bf16x8, pl[rg]);
+      acc[rg][tt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(h, vh, acc[rg][tt], 0, 0, 0);
+      acc[rg][tt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(h, vl, acc[rg][tt], 0, 0, 0);
+      acc[rg][tt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(l, vh, acc[rg][tt], 0, 0, 0);
+    }
+  }
+}
+
+// Stage for one 32-column step, copied global -> LDS without registers
+// (global_load_lds_dwordx4: each wave instruction moves one contiguous 1 KB
+// chunk): [A fragments 2 x NKC | V fragments NTT x {hi, lo} | column terms].
+template <int NKC, int NTT>
+__device__ __forceinline__ void bf16_issue_stage(u32x4* dst, const u32x4* __restrict__ xfa,
+                                                 const u32x4* __restrict__ vfrag, const float* __restrict__ colterm,
+                                                 int64_t c, int wave, int lane) {
+  constexpr int NCH = 2 * NKC + 2 * NTT + 1;
+  for (int ch = wave; ch < NCH; ch += 4) {
+    const u32x4* src;
+    if (ch < 2 * NKC) src = xfa + (c / 16) * NKC * 64 + ch * 64 + lane;
+    else if (ch < 2 * NKC + 2 * NTT) src = vfrag + (c / 32) * NTT * 128 + (ch - 2 * NKC) * 64 + lane;
+    else src = reinterpret_cast<const u32x4*>(colterm + c) + (lane < 8 ? lane : 7);
+    __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void*)(dst + ch * 64), 16, 0, 0);
+  }
+}
+
 template <int KIND, int NKC, int NTT, int RG>
 __global__ __launch_bounds__(256, 2) void k_khat_bf16(const u32x4* __restrict__ xfa, const u32x4* __restrict__ xfb,
                                                       const float* __restrict__ rowterm,
@@ -295,106 +367,43 @@ __global__ __launch_bounds__(256, 2) void k_khat_bf16(const u32x4* __restrict__ 
                                                       const u32x4* __restrict__ vfrag, float* __restrict__ wpart,
                                                       TileArgs a, const int* __restrict__ nactive) {
   if (nactive != nullptr && *nactive == 0) return;
-  constexpr int A_U = 2 * NKC * 64, V_U = NTT * 2 * 64, C_U = 8;
+  constexpr int A_U = 2 * NKC * 64, V_U = NTT * 2 * 64, C_U = 64;
   constexpr int STAGE = A_U + V_U + C_U;
-  constexpr int PER = (STAGE + 255) / 256;
   __shared__ u32x4 lds[2][STAGE];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int g = lane >> 4, li = lane & 15;
-  const int64_t blk_row0 = (int64_t)blockIdx.x * (64 * RG);
-  const int64_t row0 = blk_row0 + wave * (16 * RG);
+  const int64_t row0 = (int64_t)blockIdx.x * (64 * RG) + wave * (16 * RG);
   const int64_t c_begin = (int64_t)blockIdx.y * a.cols_per_split;
   const int64_t c_end = min(a.n_pad, c_begin + a.cols_per_split);
   if (c_begin >= c_end) return;
 
-  u32x4 xb[RG][NKC];
+  u32x4 xbv[RG][NKC];
+  const u32x4* xb[RG];
   f32x4 rt[RG];
   f32x4 acc[RG][NTT];
 #pragma unroll
   for (int rg = 0; rg < RG; ++rg) {
+    xb[rg] = xfb + (row0 / 16 + rg) * NKC * 64 + lane;
 #pragma unroll
-    for (int kc = 0; kc < NKC; ++kc) xb[rg][kc] = xfb[((row0 / 16 + rg) * NKC + kc) * 64 + lane];
-    float r = rowterm[row0 + rg * 16 + li];
+    for (int kc = 0; kc < NKC; ++kc) xbv[rg][kc] = xb[rg][kc * 64];
+    const float r = rowterm[row0 + rg * 16 + li];
     rt[rg] = f32x4{r, r, r, r};
 #pragma unroll
     for (int tt = 0; tt < NTT; ++tt) acc[rg][tt] = f32x4{0.f, 0.f, 0.f, 0.f};
   }
 
-  auto src_a = [&](int64_t c) { return xfa + (c / 16) * NKC * 64; };
-  auto src_v = [&](int64_t c) { return vfrag + (c / 32) * NTT * 2 * 64; };
-  auto src_c = [&](int64_t c) { return reinterpret_cast<const u32x4*>(colterm + c); };
-
-  copy_units(lds[0], src_a(c_begin), A_U, src_v(c_begin), V_U, src_c(c_begin), C_U, tid, 256);
+  bf16_issue_stage<NKC, NTT>(lds[0], xfa, vfrag, colterm, c_begin, wave, lane);
+  __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
   int buf = 0;
   for (int64_t c = c_begin; c < c_end; c += 32) {
-    const bool has_next = c + 32 < c_end;
-    u32x4 pre[PER];
-    if (has_next) {
-      const u32x4* sa = src_a(c + 32);
-      const u32x4* sv = src_v(c + 32);
-      const u32x4* sc = src_c(c + 32);
-#pragma unroll
-      for (int q = 0; q < PER; ++q) {
-        int e = tid + q * 256;
-        if (e < STAGE) pre[q] = (e < A_U) ? sa[e] : (e < A_U + V_U ? sv[e - A_U] : sc[e - A_U - V_U]);
-      }
-    }
-    const u32x4* A = lds[buf];
-    const u32x4* Vf = A + A_U;
-    const float* ct = reinterpret_cast<const float*>(A + A_U + V_U);
+    if (c + 32 < c_end) bf16_issue_stage<NKC, NTT>(lds[buf ^ 1], xfa, vfrag, colterm, c + 32, wave, lane);
     const bool diag = (c + 32 > row0) && (c < row0 + 16 * RG);
-    f32x4 ctv[2];
-    ctv[0] = *reinterpret_cast<const f32x4*>(ct + 4 * g);
-    ctv[1] = *reinterpret_cast<const f32x4*>(ct + 16 + 4 * g);
-    u32x4 ph[RG], pl[RG];
-#pragma unroll
-    for (int rg = 0; rg < RG; ++rg) {
-#pragma unroll
-      for (int js = 0; js < 2; ++js) {
-        f32x4 dd = rt[rg];
-#pragma unroll
-        for (int kc = 0; kc < NKC; ++kc)
-          dd = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, A[(js * NKC + kc) * 64 + lane]),
-                                                       __builtin_bit_cast(bf16x8, xb[rg][kc]), dd, 0, 0, 0);
-        float kv[4];
-#pragma unroll
-        for (int v = 0; v < 4; ++v) kv[v] = map32<KIND>(dd[v] + ctv[js][v], a.s32);
-        if (diag) {
-          const int64_t i = row0 + rg * 16 + li;
-#pragma unroll
-          for (int v = 0; v < 4; ++v)
-            if (i == c + js * 16 + 4 * g + v) kv[v] = a.s32;
-        }
-        uint32_t h0, l0, h1, l1;
-        split_pair(kv[0], kv[1], &h0, &l0);
-        split_pair(kv[2], kv[3], &h1, &l1);
-        ph[rg][2 * js] = h0;
-        ph[rg][2 * js + 1] = h1;
-        pl[rg][2 * js] = l0;
-        pl[rg][2 * js + 1] = l1;
-      }
-    }
-#pragma unroll
-    for (int tt = 0; tt < NTT; ++tt) {
-      const bf16x8 vh = __builtin_bit_cast(bf16x8, Vf[(tt * 2 + 0) * 64 + lane]);
-      const bf16x8 vl = __builtin_bit_cast(bf16x8, Vf[(tt * 2 + 1) * 64 + lane]);
-#pragma unroll
-      for (int rg = 0; rg < RG; ++rg) {
-        const bf16x8 h = __builtin_bit_cast(bf16x8, ph[rg]);
-        const bf16x8 l = __builtin_bit_cast(bf16x8, pl[rg]);
-        acc[rg][tt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(h, vh, acc[rg][tt], 0, 0, 0);
-        acc[rg][tt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(h, vl, acc[rg][tt], 0, 0, 0);
-        acc[rg][tt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(l, vh, acc[rg][tt], 0, 0, 0);
-      }
-    }
-    if (has_next) {
-#pragma unroll
-      for (int q = 0; q < PER; ++q) {
-        int e = tid + q * 256;
-        if (e < STAGE) lds[buf ^ 1][e] = pre[q];
-      }
-    }
+    if (diag)
+      bf16_step<KIND, NKC, NTT, RG, true>(lds[buf], xb, xbv, rt, acc, lane, row0, c, a.s32);
+    else
+      bf16_step<KIND, NKC, NTT, RG, false>(lds[buf], xb, xbv, rt, acc, lane, row0, c, a.s32);
+    __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
     buf ^= 1;
   }
