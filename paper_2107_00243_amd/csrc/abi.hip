@@ -65,6 +65,7 @@ Layout make_layout(int64_t n, int d, int ard, int num_probes, int max_iters, int
   L.cols_per_split = cps;
   L.nsplit = (int)((L.n_pad + cps - 1) / cps);
   L.nchunk = (int)((n + kChunkRows - 1) / kChunkRows);
+  L.nchunk_ltr = (int)((n + kLtrRows - 1) / kLtrRows);
   L.nred = (int)std::min<int64_t>(256, (n + 255) / 256);
 
   const int64_t np = L.n_pad, tp = L.tp, k = rank;
@@ -94,7 +95,7 @@ Layout make_layout(int64_t n, int d, int ard, int num_probes, int max_iters, int
   L.logdetP = take(8);
   L.scal_small = take(64);
   L.flags = take(64);
-  L.ltr_part = take((size_t)L.nchunk * kk * std::max<int64_t>(kk, 256) * 8);
+  L.ltr_part = take((size_t)L.nchunk * kk * kk * 8);
   L.precond_end = off;
   // estimator block
   L.xfa = take(np * L.kd * esz);
@@ -105,6 +106,7 @@ Layout make_layout(int64_t n, int d, int ard, int num_probes, int max_iters, int
   L.Y = take(kk * tp * 8);
   L.ltr = take(kk * tp * 8);
   L.ltr_raw = take(kk * tp * 8);
+  L.ltr_part2 = take((size_t)L.nchunk_ltr * kk * tp * 8);
   L.Xs = take(np * tp * 8);
   L.R = take(np * tp * 8);
   L.Z0 = take(np * tp * 8);
@@ -123,7 +125,7 @@ Layout make_layout(int64_t n, int d, int ard, int num_probes, int max_iters, int
   L.alog = take(tp * max_iters * 8);
   L.blog = take(tp * max_iters * 8);
   const int64_t nb64 = (n + 63) / 64, nb256 = (n + 255) / 256;
-  L.dot_part = take((L.nred + nb64 + nb256) * tp * 8);
+  L.dot_part = take((L.nred + 2 * nb64 + nb256) * tp * 8);
   L.gamma = take((num_probes + 4) * 8);
   L.slq_work = take((size_t)num_probes * 3 * max_iters * 8);
   L.cprime = take(np * tp * 8);
@@ -131,8 +133,9 @@ Layout make_layout(int64_t n, int d, int ard, int num_probes, int max_iters, int
   L.bxb = take(np * L.bkd * bsz);
   L.brt = take(np * bsz);
   L.bct = take(np * bsz);
-  L.bafrag = take(np * tp * bsz);
-  L.bcfrag = take(np * tp * bsz);
+  const size_t frag_row = std::max<size_t>(tp * bsz, (size_t)bwd_nkm(L.t) * 64);  // bytes per row
+  L.bafrag = take(np * frag_row);
+  L.bcfrag = take(np * frag_row);
   L.bxaug = take(np * ((2 * d + 1 + 15) / 16 * 16) * bsz);
   L.bwd_part = take(nb256 * (GP_MAX_D + 1) * 8);
   L.pg_small = take((4 * kk * kk + kk * tp) * 8);

@@ -22,7 +22,8 @@ namespace gpmll {
 constexpr int kRowBlock = 256;      // rows per workgroup of the tile kernels; n is padded to this
 constexpr int kColChunk = 32;       // K-dimension of one tile-times-V step (MFMA K for BF16)
 constexpr int kRedBlock = 256;      // threads of the reduction kernels
-constexpr int kChunkRows = 2048;    // rows per partial of the n-reductions (L^T R, Gram)
+constexpr int kChunkRows = 2048;    // rows per partial of the Gram reduction L^T L
+constexpr int kLtrRows = 256;       // rows per partial of L^T R (many workgroups in flight)
 
 // Hyperparameters as the kernels consume them.
 struct Hyper {
@@ -72,14 +73,15 @@ struct Layout {
   int bow;              // row width of the derivative sweep's per-row outputs
   int nsplit;           // column splits of the tile kernels
   int64_t cols_per_split;
-  int nchunk;           // row chunks of the n-reductions
+  int nchunk;           // row chunks of the Gram reduction
+  int nchunk_ltr;       // row chunks of the L^T R reduction
   int nrb;              // row blocks of kRowBlock rows
   int nred;             // blocks of the row-parallel reductions (<= 256)
   // preconditioner block (offsets independent of the estimator options)
   size_t xs, mean, mean_part, L, diag, ispiv, piv, amax, C, Rc, Rinv, Cinv, logdetP, scal_small, flags, ltr_part;
   size_t precond_end;
   // estimator block
-  size_t xfa, xfb, rowterm, colterm, H, Y, ltr, ltr_raw;
+  size_t xfa, xfb, rowterm, colterm, H, Y, ltr, ltr_raw, ltr_part2;
   size_t Xs, R, Z0, Pd, W, vfrag, wpart;
   size_t rho, rho0, bnorm, rnorm2, pw, active, nactive, iters, alog, blog;
   size_t dot_part, gamma, slq_work;
@@ -88,6 +90,17 @@ struct Layout {
 };
 
 Layout make_layout(int64_t n, int d, int ard, int num_probes, int max_iters, int rank, int prec);
+
+// 32-wide K chunks of the BF16x3 M-tile contraction over t columns split as
+// (hi, hi, lo) x (hi, lo, hi), rounded up to a compiled chunk count
+inline int bwd_nkm(int t) {
+  const int tq = (t + 7) / 8 * 8;
+  const int nkm = (3 * tq + 31) / 32;
+  static const int ok[] = {1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12, 14, 16, 18, 20, 22, 24};
+  for (int v : ok)
+    if (v >= nkm) return v;
+  return 24;
+}
 
 struct Ctx {
   const Layout* lay;

@@ -259,6 +259,270 @@ __global__ void k_bwd_rows(const T* __restrict__ rows, int nsplit, int64_t n, in
 }
 
 // ---------------------------------------------------------------------------
+// BF16x3 derivative sweep.  Same tile walk as the BF16x3 K_hat V kernel and the
+// same staged distance operands (q = log2 k for RBF, q = r^2 for Matern).  The M
+// tile M^T[q][p] = C'_q . A'_p uses the split (hi, hi, lo) x (hi, lo, hi) along the
+// contraction; W = s g M and M kappa come out in the distance layout (lane = row
+// p, 4 + 4 columns q), so W feeds W [x~ | x~^2] on MFMA as the A operand (same
+// column permutation as the K_hat V kernel) while rowsum(W) and sum_q M kappa
+// are per-lane sums finished across the four lane groups at the end.
+// ---------------------------------------------------------------------------
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+__device__ inline uint32_t bw_pack_bf16(float a, float b) {
+  f32x2 v = {a, b};
+  return __builtin_bit_cast(uint32_t, __builtin_convertvector(v, bf16x2));
+}
+__device__ inline void bw_split_pair(float a, float b, uint32_t* hi, uint32_t* lo) {
+  uint32_t h = bw_pack_bf16(a, b);
+  float ha = __builtin_bit_cast(float, h << 16);
+  float hb = __builtin_bit_cast(float, h & 0xffff0000u);
+  *hi = h;
+  *lo = bw_pack_bf16(a - ha, b - hb);
+}
+
+// rows of an FP64 (n_pad x ld) array as 3-piece BF16 MFMA fragments along K:
+// A side [hi | hi | lo], B side [hi | lo | hi], each piece tq wide, K padded to 32 * nkm
+__global__ void k_stage_rows_bf16x3(const double* __restrict__ M, int64_t n_pad, int ld, int ncols, int tq, int nkm,
+                                    int bside, u32x4* __restrict__ frag) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;  // (tile, kc, lane)
+  if (e >= (n_pad / 16) * nkm * 64) return;
+  const int lane = (int)(e % 64);
+  const int kc = (int)((e / 64) % nkm);
+  const int64_t tile = e / (64 * nkm);
+  const int64_t row = tile * 16 + lane % 16;
+  uint32_t w[4];
+  for (int q = 0; q < 4; ++q) {
+    uint16_t hv[2];
+    for (int h2 = 0; h2 < 2; ++h2) {
+      const int k = kc * 32 + (lane / 16) * 8 + q * 2 + h2;
+      const int seg = k / tq, col = k % tq;
+      uint16_t out = 0;
+      if (seg < 3 && col < ncols) {
+        const double x = M[row * ld + col];
+        uint32_t hh, ll;
+        bw_split_pair((float)x, 0.0f, &hh, &ll);
+        // lo from the FP64 residual
+        const double rem = x - (double)__builtin_bit_cast(float, (hh & 0xffffu) << 16);
+        const uint16_t hi16 = (uint16_t)(hh & 0xffffu);
+        const uint16_t lo16 = (uint16_t)(bw_pack_bf16((float)rem, 0.0f) & 0xffffu);
+        const bool use_hi = bside ? (seg != 1) : (seg != 2);
+        out = use_hi ? hi16 : lo16;
+      }
+      hv[h2] = out;
+    }
+    w[q] = (uint32_t)hv[0] | ((uint32_t)hv[1] << 16);
+  }
+  frag[e] = u32x4{w[0], w[1], w[2], w[3]};
+}
+
+// [x~ | x~^2] (2d columns, padded to 16 * nxt) as hi/lo B fragments with the
+// K_hat V kernel's column permutation: fragment (jb, tt, piece) lane l holds rows
+// jb*32 + perm(l/16, s), perm(g, s) = 4g + s (s < 4) or 16 + 4g + s - 4
+__global__ void k_stage_xaug_bf16(const double* __restrict__ xs, int64_t n, int64_t n_pad, int d, int nxt,
+                                  u32x4* __restrict__ frag) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;  // (jb, tt, lane)
+  if (e >= (n_pad / 32) * nxt * 64) return;
+  const int lane = (int)(e % 64);
+  const int tt = (int)((e / 64) % nxt);
+  const int64_t jb = e / (64 * nxt);
+  const int g = lane / 16, col = tt * 16 + lane % 16;
+  uint32_t h[4], l[4];
+  for (int w = 0; w < 4; ++w) {
+    double v2[2];
+    for (int h2 = 0; h2 < 2; ++h2) {
+      const int s = 2 * w + h2;
+      const int64_t q = jb * 32 + (s < 4 ? 4 * g + s : 16 + 4 * g + (s - 4));
+      double val = 0.0;
+      if (q < n) {
+        if (col < d) val = xs[q * d + col];
+        else if (col < 2 * d) {
+          const double x = xs[q * d + col - d];
+          val = x * x;
+        }
+      }
+      v2[h2] = val;
+    }
+    const uint32_t hh = bw_pack_bf16((float)v2[0], (float)v2[1]);
+    const double ra = v2[0] - (double)__builtin_bit_cast(float, hh << 16);
+    const double rb = v2[1] - (double)__builtin_bit_cast(float, hh & 0xffff0000u);
+    h[w] = hh;
+    l[w] = bw_pack_bf16((float)ra, (float)rb);
+  }
+  frag[((jb * nxt + tt) * 2 + 0) * 64 + lane] = u32x4{h[0], h[1], h[2], h[3]};
+  frag[((jb * nxt + tt) * 2 + 1) * 64 + lane] = u32x4{l[0], l[1], l[2], l[3]};
+}
+
+struct BwdBfArgs {
+  int64_t n_pad;
+  int64_t cols_per_split;
+  int ow, nbt;
+  float s, inv_s;
+};
+
+template <int KIND>
+__device__ inline void bw_map(float q, float s, float inv_s, float* kap, float* sg) {
+  const float log2e = 1.4426950408889634f;
+  if (KIND == GP_KERNEL_RBF) {
+    const float k = __builtin_amdgcn_exp2f(q);  // q = log2 k
+    *sg = k;
+    *kap = k * inv_s;
+  } else if (KIND == GP_KERNEL_MATERN32) {
+    const float a = 1.7320508075688772f;
+    const float r = __builtin_sqrtf(fmaxf(q, 0.0f));
+    const float e = __builtin_amdgcn_exp2f(-a * log2e * r);
+    *kap = fmaf(a, r, 1.0f) * e;
+    *sg = s * 3.0f * e;
+  } else {
+    const float a = 2.23606797749979f;
+    const float q0 = fmaxf(q, 0.0f);
+    const float r = __builtin_sqrtf(q0);
+    const float e = __builtin_amdgcn_exp2f(-a * log2e * r);
+    *kap = fmaf(5.0f / 3.0f, q0, fmaf(a, r, 1.0f)) * e;
+    *sg = s * (5.0f / 3.0f) * fmaf(a, r, 1.0f) * e;
+  }
+}
+
+template <int KIND, int NKC, int NKM, int NXT, int RG>
+__global__ __launch_bounds__(256, 2) void k_bwd_bf16(const u32x4* __restrict__ xfa, const u32x4* __restrict__ xfb,
+                                                     const float* __restrict__ rowterm,
+                                                     const float* __restrict__ colterm,
+                                                     const u32x4* __restrict__ afr, const u32x4* __restrict__ cfr,
+                                                     const u32x4* __restrict__ xau, float* __restrict__ out,
+                                                     BwdBfArgs a) {
+  constexpr int A_U = 2 * NKC * 64, C_U = 2 * NKM * 64, X_U = NXT * 2 * 64, T_U = 8;
+  constexpr int STAGE = A_U + C_U + X_U + T_U;
+  constexpr int PER = (STAGE + 255) / 256;
+  __shared__ u32x4 lds[STAGE];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int g = lane >> 4, li = lane & 15;
+  const int64_t row0 = (int64_t)blockIdx.x * (64 * RG) + wave * (16 * RG);
+  const int64_t c_begin = (int64_t)blockIdx.y * a.cols_per_split;
+  const int64_t c_end = min(a.n_pad, c_begin + a.cols_per_split);
+  if (c_begin >= c_end) return;
+  u32x4 xbv[RG][NKC], abv[RG][NKM];
+  f32x4 rt[RG];
+  f32x4 acc[RG][NXT];
+  float rs[RG], mk[RG];
+#pragma unroll
+  for (int rg = 0; rg < RG; ++rg) {
+#pragma unroll
+    for (int kc = 0; kc < NKC; ++kc) xbv[rg][kc] = xfb[((row0 / 16 + rg) * NKC + kc) * 64 + lane];
+#pragma unroll
+    for (int kc = 0; kc < NKM; ++kc) abv[rg][kc] = afr[((row0 / 16 + rg) * NKM + kc) * 64 + lane];
+    const float r = rowterm[row0 + rg * 16 + li];
+    rt[rg] = f32x4{r, r, r, r};
+#pragma unroll
+    for (int tt = 0; tt < NXT; ++tt) acc[rg][tt] = f32x4{0.f, 0.f, 0.f, 0.f};
+    rs[rg] = 0.f;
+    mk[rg] = 0.f;
+  }
+  for (int64_t c = c_begin; c < c_end; c += 32) {
+    u32x4 pre[PER];
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      int e = tid + q * 256;
+      e = e < STAGE ? e : STAGE - 1;
+      const u32x4* src;
+      if (e < A_U) src = xfa + (c / 16) * NKC * 64 + e;
+      else if (e < A_U + C_U) src = cfr + (c / 16) * NKM * 64 + (e - A_U);
+      else if (e < A_U + C_U + X_U) src = xau + (c / 32) * NXT * 128 + (e - A_U - C_U);
+      else src = reinterpret_cast<const u32x4*>(colterm + c) + (e - A_U - C_U - X_U);
+      pre[q] = *src;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int e = tid + q * 256;
+      if (e < STAGE) lds[e] = pre[q];
+    }
+    __syncthreads();
+    const u32x4* A = lds;
+    const u32x4* Cf = lds + A_U;
+    const u32x4* Xf = Cf + C_U;
+    const float* ct = reinterpret_cast<const float*>(Xf + X_U);
+    const bool diag = (c + 32 > row0) && (c < row0 + 16 * RG);
+    u32x4 wh[RG], wl[RG];
+#pragma unroll
+    for (int rg = 0; rg < RG; ++rg) {
+#pragma unroll
+      for (int js = 0; js < 2; ++js) {
+        f32x4 dd = rt[rg];
+#pragma unroll
+        for (int kc = 0; kc < NKC; ++kc)
+          dd = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, A[(js * NKC + kc) * 64 + lane]),
+                                                       __builtin_bit_cast(bf16x8, xbv[rg][kc]), dd, 0, 0, 0);
+        f32x4 mm = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int kc = 0; kc < NKM; ++kc)
+          mm = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, Cf[(js * NKM + kc) * 64 + lane]),
+                                                       __builtin_bit_cast(bf16x8, abv[rg][kc]), mm, 0, 0, 0);
+        const f32x4 ctv = *reinterpret_cast<const f32x4*>(ct + js * 16 + 4 * g);
+        float wv[4];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          float kap, sg;
+          bw_map<KIND>(dd[v] + ctv[v], a.s, a.inv_s, &kap, &sg);
+          if (diag && row0 + rg * 16 + li == c + js * 16 + 4 * g + v) {
+            kap = 1.0f;
+            sg = 0.0f;
+          }
+          wv[v] = sg * mm[v];
+          rs[rg] += wv[v];
+          mk[rg] += kap * mm[v];
+        }
+        uint32_t h0, l0, h1, l1;
+        bw_split_pair(wv[0], wv[1], &h0, &l0);
+        bw_split_pair(wv[2], wv[3], &h1, &l1);
+        wh[rg][2 * js] = h0;
+        wh[rg][2 * js + 1] = h1;
+        wl[rg][2 * js] = l0;
+        wl[rg][2 * js + 1] = l1;
+      }
+    }
+#pragma unroll
+    for (int tt = 0; tt < NXT; ++tt) {
+      const bf16x8 xh = __builtin_bit_cast(bf16x8, Xf[(tt * 2 + 0) * 64 + lane]);
+      const bf16x8 xl = __builtin_bit_cast(bf16x8, Xf[(tt * 2 + 1) * 64 + lane]);
+#pragma unroll
+      for (int rg = 0; rg < RG; ++rg) {
+        const bf16x8 h = __builtin_bit_cast(bf16x8, wh[rg]);
+        const bf16x8 l = __builtin_bit_cast(bf16x8, wl[rg]);
+        acc[rg][tt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(h, xh, acc[rg][tt], 0, 0, 0);
+        acc[rg][tt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(h, xl, acc[rg][tt], 0, 0, 0);
+        acc[rg][tt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(l, xh, acc[rg][tt], 0, 0, 0);
+      }
+    }
+  }
+  float* o = out + (int64_t)blockIdx.y * a.n_pad * a.ow;
+#pragma unroll
+  for (int rg = 0; rg < RG; ++rg) {
+    // [x~ | x~^2] products land in columns 1 .. 2d of the row record
+#pragma unroll
+    for (int tt = 0; tt < NXT; ++tt)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int col = tt * 16 + li;
+        if (col + 1 < a.nbt * 16) o[(row0 + rg * 16 + 4 * g + v) * a.ow + 1 + col] = acc[rg][tt][v];
+      }
+    // per-lane partial sums over q: finish across the four lane groups (same row p = li)
+    float r1 = rs[rg], m1 = mk[rg];
+    r1 += __shfl_xor(r1, 16);
+    r1 += __shfl_xor(r1, 32);
+    m1 += __shfl_xor(m1, 16);
+    m1 += __shfl_xor(m1, 32);
+    if (g == 0) {
+      o[(row0 + rg * 16 + li) * a.ow + 0] = r1;
+      o[(row0 + rg * 16 + li) * a.ow + a.nbt * 16] = m1;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Preconditioner derivative terms
 // ---------------------------------------------------------------------------
 
@@ -416,30 +680,50 @@ __global__ void k_pg_contract(const double* __restrict__ xs, const int32_t* __re
   }
 }
 
-// gradient assembly (natural parameters [ls | s | sigma^2])
+// gradient assembly (natural parameters [ls | s | sigma^2]); one workgroup,
+// fixed-order tree reductions
+__device__ double block_sum256(double v) {
+  __shared__ double red[256];
+  red[threadIdx.x] = v;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+    __syncthreads();
+  }
+  const double r = red[0];
+  __syncthreads();
+  return r;
+}
+
 __global__ void k_grad_final(const double* __restrict__ bwd_part, int nb_bwd, const double* __restrict__ pg_part,
                              int nb_pg, const double* __restrict__ trm_part, const double* __restrict__ cc_part,
                              int nb_dot, int tp, int ell, int64_t n, int k, int ard, Hyper h,
                              const double* __restrict__ Cinv, int have_precond, double* __restrict__ grad) {
-  if (threadIdx.x != 0) return;
+  __shared__ double bil[GP_MAX_D + 1], pg[GP_MAX_D + 1];
   const int d = h.d;
-  double bil[GP_MAX_D + 1], pg[GP_MAX_D + 1];
   for (int j = 0; j <= d; ++j) {
     double s = 0.0, q = 0.0;
-    for (int b = 0; b < nb_bwd; ++b) s += bwd_part[(int64_t)b * (GP_MAX_D + 1) + j];
-    for (int b = 0; b < nb_pg; ++b) q += pg_part[(int64_t)b * (GP_MAX_D + 1) + j];
-    bil[j] = s;
-    pg[j] = have_precond ? q : 0.0;
-  }
-  double trm = 0.0, cc = 0.0;
-  for (int b = 0; b < nb_dot; ++b)
-    for (int c = 0; c < tp; ++c) {
-      trm += trm_part[(int64_t)b * tp + c];
-      if (c >= 1 && c <= ell) cc += cc_part[(int64_t)b * tp + c];
+    for (int b = threadIdx.x; b < nb_bwd; b += 256) s += bwd_part[(int64_t)b * (GP_MAX_D + 1) + j];
+    for (int b = threadIdx.x; b < nb_pg; b += 256) q += pg_part[(int64_t)b * (GP_MAX_D + 1) + j];
+    s = block_sum256(s);
+    q = block_sum256(q);
+    if (threadIdx.x == 0) {
+      bil[j] = s;
+      pg[j] = have_precond ? q : 0.0;
     }
-  double trCinv = 0.0;
-  for (int j = 0; j < k; ++j) trCinv += Cinv[j * k + j];
-  const double trPinv = (double)(n - k) / h.s2 + trCinv;
+  }
+  double trm = 0.0, cc = 0.0, tci = 0.0;
+  for (int e = threadIdx.x; e < nb_dot * tp; e += 256) {
+    const int c = e % tp;
+    trm += trm_part[e];
+    if (c >= 1 && c <= ell) cc += cc_part[e];
+  }
+  for (int j = threadIdx.x; j < k; j += 256) tci += Cinv[(int64_t)j * k + j];
+  trm = block_sum256(trm);
+  cc = block_sum256(cc);
+  tci = block_sum256(tci);
+  if (threadIdx.x != 0) return;
+  const double trPinv = (double)(n - k) / h.s2 + tci;
   const int p = ard ? d : 1;
   if (ard) {
     for (int j = 0; j < d; ++j) grad[j] = bil[j] + pg[j];
@@ -485,6 +769,80 @@ static hipError_t run_bwd_tiles(const Ctx& c, const Hyper& h, BwdArgs ba, const 
   return hipGetLastError();
 }
 
+namespace {
+template <int KIND, int NKC, int NKM, int NXT>
+hipError_t run_bwd_bf16(const Ctx& c, const BwdBfArgs& ba) {
+  const Layout& L = *c.lay;
+  constexpr int RG = 2;
+  dim3 grid((unsigned)(L.n_pad / (64 * RG)), (unsigned)L.nsplit);
+  hipLaunchKernelGGL((k_bwd_bf16<KIND, NKC, NKM, NXT, RG>), grid, dim3(256), 0, c.st, c.at<u32x4>(L.xfa),
+                     c.at<u32x4>(L.xfb), c.at<float>(L.rowterm), c.at<float>(L.colterm), c.at<u32x4>(L.bafrag),
+                     c.at<u32x4>(L.bcfrag), c.at<u32x4>(L.bxaug), c.at<float>(L.wpart), ba);
+  return hipGetLastError();
+}
+template <int KIND, int NKC, int NXT>
+hipError_t sel_bwd_nkm(const Ctx& c, const BwdBfArgs& ba, int nkm) {
+  switch (nkm) {
+#define CASE(N) case N: return run_bwd_bf16<KIND, NKC, N, NXT>(c, ba);
+    CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8) CASE(9) CASE(10) CASE(11) CASE(12)
+    CASE(14) CASE(16) CASE(18) CASE(20) CASE(22) CASE(24)
+#undef CASE
+  }
+  return hipErrorInvalidValue;
+}
+template <int KIND>
+hipError_t sel_bwd(const Ctx& c, const BwdBfArgs& ba, int nkc, int nkm, int nxt) {
+  if (nxt == 1) {
+    switch (nkc) {
+      case 1: return sel_bwd_nkm<KIND, 1, 1>(c, ba, nkm);
+      case 2: return sel_bwd_nkm<KIND, 2, 1>(c, ba, nkm);
+    }
+  } else if (nxt == 2) {
+    switch (nkc) {
+      case 2: return sel_bwd_nkm<KIND, 2, 2>(c, ba, nkm);
+    }
+  } else if (nxt == 3) {
+    switch (nkc) {
+      case 3: return sel_bwd_nkm<KIND, 3, 3>(c, ba, nkm);
+    }
+  } else if (nxt == 4) {
+    switch (nkc) {
+      case 3: return sel_bwd_nkm<KIND, 3, 4>(c, ba, nkm);
+      case 4: return sel_bwd_nkm<KIND, 4, 4>(c, ba, nkm);
+    }
+  }
+  return hipErrorInvalidValue;
+}
+}  // namespace
+
+hipError_t launch_bwd_bf16(const Ctx& c, const Hyper& h) {
+  const Layout& L = *c.lay;
+  const int tq = (L.t + 7) / 8 * 8;
+  const int nkm = bwd_nkm(L.t);
+  const int nxt = (2 * L.d + 15) / 16;
+  const int nkc = L.kd / 32;
+  const int64_t nfr = (L.n_pad / 16) * nkm * 64;
+  hipLaunchKernelGGL(k_stage_rows_bf16x3, dim3((unsigned)((nfr + 255) / 256)), dim3(256), 0, c.st,
+                     c.at<double>(L.Xs), L.n_pad, L.tp, L.t, tq, nkm, 1, c.at<u32x4>(L.bafrag));
+  hipLaunchKernelGGL(k_stage_rows_bf16x3, dim3((unsigned)((nfr + 255) / 256)), dim3(256), 0, c.st,
+                     c.at<double>(L.cprime), L.n_pad, L.tp, L.t, tq, nkm, 0, c.at<u32x4>(L.bcfrag));
+  const int64_t nxf = (L.n_pad / 32) * nxt * 64;
+  hipLaunchKernelGGL(k_stage_xaug_bf16, dim3((unsigned)((nxf + 255) / 256)), dim3(256), 0, c.st, c.at<double>(L.xs),
+                     L.n, L.n_pad, L.d, nxt, c.at<u32x4>(L.bxaug));
+  BwdBfArgs ba;
+  ba.n_pad = L.n_pad;
+  ba.cols_per_split = L.cols_per_split;
+  ba.ow = L.bow;
+  ba.nbt = (2 * L.d + 1 + 15) / 16;
+  ba.s = (float)h.s;
+  ba.inv_s = (float)(1.0 / h.s);
+  switch (h.kind) {
+    case GP_KERNEL_RBF: return sel_bwd<GP_KERNEL_RBF>(c, ba, nkc, nkm, nxt);
+    case GP_KERNEL_MATERN32: return sel_bwd<GP_KERNEL_MATERN32>(c, ba, nkc, nkm, nxt);
+    default: return sel_bwd<GP_KERNEL_MATERN52>(c, ba, nkc, nkm, nxt);
+  }
+}
+
 hipError_t launch_backward(const Ctx& c, const Hyper& h, int ard, int precond_grad, double* grad) {
   const Layout& L = *c.lay;
   const int tp = L.tp;
@@ -504,7 +862,9 @@ hipError_t launch_backward(const Ctx& c, const Hyper& h, int ard, int precond_gr
   const int64_t nfr_x = (L.n_pad / 16) * ba.nbt * 256;
   const bool f64 = L.bprec == GP_PREC_FP64;
   hipError_t e;
-  if (f64) {
+  if (L.prec == GP_PREC_BF16X3) {
+    e = launch_bwd_bf16(c, h);
+  } else if (f64) {
     hipLaunchKernelGGL(k_stage_rows16x4<double>, dim3(nbk(nfr_t, 256)), dim3(256), 0, c.st, c.at<double>(L.Xs),
                        L.n_pad, tp, tp, ba.nkt, c.at<double>(L.bafrag));
     hipLaunchKernelGGL(k_stage_rows16x4<double>, dim3(nbk(nfr_t, 256)), dim3(256), 0, c.st, c.at<double>(L.cprime),
@@ -573,7 +933,7 @@ hipError_t launch_backward(const Ctx& c, const Hyper& h, int ard, int precond_gr
     hipLaunchKernelGGL(k_pg_contract, dim3(nb_pg), dim3(256), 0, c.st, c.at<double>(L.xs), c.at<int32_t>(L.piv), kpp,
                        L.n, L.k, Om, Psi, h, precond_grad, pg_part);
   }
-  hipLaunchKernelGGL(k_grad_final, dim3(1), dim3(64), 0, c.st, bwd_part, (int)nbr, pg_part, (int)nb_pg, trm_part,
+  hipLaunchKernelGGL(k_grad_final, dim3(1), dim3(256), 0, c.st, bwd_part, (int)nbr, pg_part, (int)nb_pg, trm_part,
                      cc_part, L.nred, tp, L.ell, L.n, L.k, ard, h, c.at<double>(L.Cinv), L.k > 0 ? 1 : 0, grad);
   return hipGetLastError();
 }

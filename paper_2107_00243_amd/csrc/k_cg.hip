@@ -323,10 +323,10 @@ static unsigned nb_for(int64_t count, int bs) { return (unsigned)((count + bs - 
 // dst (k x tp) = L^T Rsrc
 hipError_t launch_ltr(const Ctx& c, const double* Rsrc, double* dst, const int* nact) {
   const Layout& L = *c.lay;
-  hipLaunchKernelGGL(k_ltr_part, dim3(L.nchunk, (L.k + 63) / 64, (L.tp + 63) / 64), dim3(256), 0, c.st,
-                     c.at<double>(L.L), Rsrc, L.n, L.k, L.tp, (int64_t)kChunkRows, c.at<double>(L.ltr_part), nact);
+  hipLaunchKernelGGL(k_ltr_part, dim3(L.nchunk_ltr, (L.k + 63) / 64, (L.tp + 63) / 64), dim3(256), 0, c.st,
+                     c.at<double>(L.L), Rsrc, L.n, L.k, L.tp, (int64_t)kLtrRows, c.at<double>(L.ltr_part2), nact);
   hipLaunchKernelGGL(k_ltr_final, dim3(nb_for((int64_t)L.k * L.tp, 256)), dim3(256), 0, c.st,
-                     c.at<double>(L.ltr_part), L.nchunk, L.k, L.tp, dst, nact);
+                     c.at<double>(L.ltr_part2), L.nchunk_ltr, L.k, L.tp, dst, nact);
   return hipGetLastError();
 }
 
@@ -379,7 +379,7 @@ hipError_t launch_cg_after_product(const Ctx& c, const Hyper& h, int it, double 
   double* alpha = sc;
   double* beta = sc + L.tp;
   const int nzblk = (int)nb_for(L.n, 64);
-  hipLaunchKernelGGL(k_cg_alpha, dim3(L.tp), dim3(256), 0, c.st, part, (int)nb_for(L.n, 256), L.tp, it, L.max_iters,
+  hipLaunchKernelGGL(k_cg_alpha, dim3(L.tp), dim3(256), 0, c.st, part, (int)nb_for(L.n, 64), L.tp, it, L.max_iters,
                      c.at<double>(L.rho), c.at<int>(L.active), alpha, c.at<double>(L.alog), c.at<int>(L.flags) + 1,
                      nact);
   hipLaunchKernelGGL(k_cg_update, dim3(L.nred), dim3(256), 0, c.st, c.at<double>(L.Xs), c.at<double>(L.R),

@@ -254,19 +254,23 @@ __global__ void k_stage_v_fp(const double* __restrict__ V, int64_t nrows, int ld
 }
 
 // W[i][c] = sum_s wpart[s][i][c] + sigma^2 V[i][c] (FP64, fixed order), rows < nrows,
-// columns < ncols; optionally the per-block partial dots V[:,c].W[:,c].
+// columns < ncols; optionally per-block partial dots V[:,c].W[:,c].  Block: 64 rows
+// x 64 columns (thread = column x 4 row lanes), grid (ceil(nrows/64), ceil(ncols/64)).
 template <typename T>
-__global__ void k_khat_reduce(const T* __restrict__ wpart, int nsplit, int64_t n_pad, int tp,
-                              const double* __restrict__ V, int ldv, double* __restrict__ W, int ldw, int64_t nrows,
-                              int ncols, double s2, double* __restrict__ dot_part, const int* __restrict__ nactive) {
+__global__ __launch_bounds__(256) void k_khat_reduce(const T* __restrict__ wpart, int nsplit, int64_t n_pad, int tp,
+                                                     const double* __restrict__ V, int ldv, double* __restrict__ W,
+                                                     int ldw, int64_t nrows, int ncols, double s2,
+                                                     double* __restrict__ dot_part, const int* __restrict__ nactive) {
   if (nactive != nullptr && *nactive == 0) return;
-  __shared__ double red[256];
-  const int G = 256 / ncols;
-  const int c = threadIdx.x % ncols, rg = threadIdx.x / ncols;
-  const int64_t r0 = (int64_t)blockIdx.x * 256;
+  __shared__ double red[4][64];
+  const int cl = threadIdx.x % 64, lane4 = threadIdx.x / 64;
+  const int c = blockIdx.y * 64 + cl;
+  const int64_t r0 = (int64_t)blockIdx.x * 64;
   double dot = 0.0;
-  if (rg < G) {
-    for (int64_t r = r0 + rg; r < min(nrows, r0 + 256); r += G) {
+  if (c < ncols) {
+    for (int q = lane4; q < 64; q += 4) {
+      const int64_t r = r0 + q;
+      if (r >= nrows) break;
       double w = 0.0;
       for (int s = 0; s < nsplit; ++s) w += (double)wpart[((int64_t)s * n_pad + r) * tp + c];
       const double v = V[r * ldv + c];
@@ -276,13 +280,10 @@ __global__ void k_khat_reduce(const T* __restrict__ wpart, int nsplit, int64_t n
     }
   }
   if (dot_part == nullptr) return;
-  red[threadIdx.x] = (rg < G) ? dot : 0.0;
+  red[lane4][cl] = dot;
   __syncthreads();
-  if (threadIdx.x < ncols) {
-    double s = 0.0;
-    for (int q = 0; q < G; ++q) s += red[q * ncols + threadIdx.x];
-    dot_part[(int64_t)blockIdx.x * ncols + threadIdx.x] = s;
-  }
+  if (lane4 == 0 && c < ncols)
+    dot_part[(int64_t)blockIdx.x * ncols + c] = red[0][cl] + red[1][cl] + red[2][cl] + red[3][cl];
 }
 
 #endif  // part 0
@@ -672,6 +673,7 @@ hipError_t launch_stage_x(const Ctx& c, const Hyper& h) {
 hipError_t launch_stage_x_bwd(const Ctx& c, const Hyper& h) {
   const Layout& L = *c.lay;
   (void)h;
+  if (L.prec == GP_PREC_BF16X3) return hipSuccess;  // the BF16x3 sweep reuses the forward operands
   const unsigned nb = (unsigned)((L.n_pad + 255) / 256);
   if (L.bprec == GP_PREC_FP64)
     hipLaunchKernelGGL(k_stage_x_fp<double>, dim3(nb), dim3(256), 0, c.st, c.at<double>(L.xs), L.n_pad, L.d,
@@ -721,12 +723,12 @@ hipError_t launch_khat_tiles(const Ctx& c, const Hyper& h, const int* nact) {
 hipError_t launch_khat_reduce(const Ctx& c, const double* V, int ldv, double* W, int ldw, int ncols, double s2,
                               double* dot_part, const int* nact) {
   const Layout& L = *c.lay;
-  const unsigned nb = (unsigned)((L.n + 255) / 256);
+  const dim3 nb((unsigned)((L.n + 63) / 64), (unsigned)((ncols + 63) / 64));
   if (L.prec == GP_PREC_FP64)
-    hipLaunchKernelGGL(k_khat_reduce<double>, dim3(nb), dim3(256), 0, c.st, c.at<double>(L.wpart), L.nsplit, L.n_pad,
+    hipLaunchKernelGGL(k_khat_reduce<double>, nb, dim3(256), 0, c.st, c.at<double>(L.wpart), L.nsplit, L.n_pad,
                        L.tp, V, ldv, W, ldw, L.n, ncols, s2, dot_part, nact);
   else
-    hipLaunchKernelGGL(k_khat_reduce<float>, dim3(nb), dim3(256), 0, c.st, c.at<float>(L.wpart), L.nsplit, L.n_pad,
+    hipLaunchKernelGGL(k_khat_reduce<float>, nb, dim3(256), 0, c.st, c.at<float>(L.wpart), L.nsplit, L.n_pad,
                        L.tp, V, ldv, W, ldw, L.n, ncols, s2, dot_part, nact);
   return hipGetLastError();
 }

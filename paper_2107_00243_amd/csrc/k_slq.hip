@@ -59,10 +59,49 @@ __device__ void tridiag_eig_first_row(double* a, double* b, double* z, int m) {
   }
 }
 
-// one thread per probe column c = 1 + i
+// one workgroup per probe column c = 1 + blockIdx.x; the eigen-solve runs on one
+// lane with the tridiagonal in LDS (3 * max_iters doubles of dynamic shared memory)
 __global__ void k_slq(const double* __restrict__ alog, const double* __restrict__ blog,
                       const int* __restrict__ iters, const double* __restrict__ rho0, int ell, int max_iters,
-                      double* __restrict__ work, double* __restrict__ gamma, int* __restrict__ clamp) {
+                      double* __restrict__ gamma, int* __restrict__ clamp) {
+  extern __shared__ double sm_tri[];
+  const int i = blockIdx.x;
+  if (i >= ell || threadIdx.x != 0) return;
+  const int c = 1 + i;
+  const int m = iters[c];
+  double* a = sm_tri;
+  double* b = a + max_iters;
+  double* z = b + max_iters;
+  const double* al = alog + (int64_t)c * max_iters;
+  const double* be = blog + (int64_t)c * max_iters;
+  if (m == 0) {
+    gamma[i] = 0.0;
+    return;
+  }
+  a[0] = 1.0 / al[0];
+  for (int j = 1; j < m; ++j) {
+    a[j] = 1.0 / al[j] + be[j - 1] / al[j - 1];
+    b[j - 1] = sqrt(be[j - 1]) / al[j - 1];
+  }
+  tridiag_eig_first_row(a, b, z, m);
+  double s = 0.0;
+  int cl = 0;
+  for (int j = 0; j < m; ++j) {
+    double th = a[j];
+    if (th < 1e-300) {
+      th = 1e-300;
+      ++cl;
+    }
+    s += z[j] * z[j] * log(th);
+  }
+  gamma[i] = rho0[c] * s;
+  if (cl) atomicAdd(clamp, cl);
+}
+
+// the same with the tridiagonal in global memory (iteration caps above 2730)
+__global__ void k_slq_global(const double* __restrict__ alog, const double* __restrict__ blog,
+                             const int* __restrict__ iters, const double* __restrict__ rho0, int ell, int max_iters,
+                             double* __restrict__ work, double* __restrict__ gamma, int* __restrict__ clamp) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= ell) return;
   const int c = 1 + i;
@@ -144,9 +183,14 @@ hipError_t launch_slq_logp(const Ctx& c, const Hyper& h, const double* y, double
   (void)h;
   const Layout& L = *c.lay;
   double* sl = c.at<double>(L.gamma);  // gamma[ell] | datafit | logdet_est
-  hipLaunchKernelGGL(k_slq, dim3((L.ell + 63) / 64), dim3(64), 0, c.st, c.at<double>(L.alog), c.at<double>(L.blog),
-                     c.at<int>(L.iters), c.at<double>(L.rho0), L.ell, L.max_iters, c.at<double>(L.slq_work), sl,
-                     c.at<int>(L.flags) + 2);
+  const size_t smem = (size_t)3 * L.max_iters * sizeof(double);
+  if (smem <= 64 * 1024)
+    hipLaunchKernelGGL(k_slq, dim3(L.ell), dim3(64), smem, c.st, c.at<double>(L.alog), c.at<double>(L.blog),
+                       c.at<int>(L.iters), c.at<double>(L.rho0), L.ell, L.max_iters, sl, c.at<int>(L.flags) + 2);
+  else
+    hipLaunchKernelGGL(k_slq_global, dim3((L.ell + 63) / 64), dim3(64), 0, c.st, c.at<double>(L.alog),
+                       c.at<double>(L.blog), c.at<int>(L.iters), c.at<double>(L.rho0), L.ell, L.max_iters,
+                       c.at<double>(L.slq_work), sl, c.at<int>(L.flags) + 2);
   const unsigned nb = (unsigned)((L.n + 255) / 256);
   double* part = c.at<double>(L.dot_part);
   hipLaunchKernelGGL(k_dot_y, dim3(nb), dim3(256), 0, c.st, y, c.at<double>(L.Xs), L.n, L.tp, part);
