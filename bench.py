@@ -124,6 +124,8 @@ def main():
 
     bf = run_gpu(pr, "bf16x3", args.steps, args.warmup)
     log(f"[bench] bf16x3: {bf['ms_per_step']:.2f} ms/eval, iters {bf['iters_max']}, tile {bf['tile_ms']:.3f} ms")
+    h16 = run_gpu(pr, "fp16x3", args.steps, args.warmup)
+    log(f"[bench] fp16x3: {h16['ms_per_step']:.2f} ms/eval, iters {h16['iters_max']}, tile {h16['tile_ms']:.3f} ms")
     out_fp64 = None
     if not args.no_fp64:
         f64 = run_gpu(pr, "fp64", args.fp64_steps, 0)
@@ -156,11 +158,19 @@ def main():
         "cpu_baseline": cpu,
         "fp64_gpu": out_fp64,
         "speedup_vs_fp64_gpu": (bf["evals_per_s"] / out_fp64["value"]) if out_fp64 else None,
+        "fp16x3_gpu": {"value": h16["evals_per_s"], "ms_per_step": h16["ms_per_step"],
+                       "iters_max": h16["iters_max"], "tile_ms": h16["tile_ms"],
+                       "tile_tflops": tile_flops(n, d, t) / (h16["tile_ms"] * 1e-3) / 1e12,
+                       "speedup_vs_fp64_gpu": (h16["evals_per_s"] / out_fp64["value"]) if out_fp64 else None},
     }
     if out_fp64 is not None:
         rec["accuracy_vs_fp64_gpu"] = {
             "rel_logp": abs(bf["logp"] - f64["logp"]) / abs(f64["logp"]),
             "rel_grad": float(np.linalg.norm(bf["grad"] - f64["grad"]) / np.linalg.norm(f64["grad"])),
+        }
+        rec["fp16x3_gpu"]["accuracy_vs_fp64_gpu"] = {
+            "rel_logp": abs(h16["logp"] - f64["logp"]) / abs(f64["logp"]),
+            "rel_grad": float(np.linalg.norm(h16["grad"] - f64["grad"]) / np.linalg.norm(f64["grad"])),
         }
     print(json.dumps(rec))
 

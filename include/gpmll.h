@@ -63,7 +63,10 @@ typedef enum gp_kernel {
 typedef enum gp_precision {
   GP_PREC_FP64 = 0,         /* kernel tiles and products in FP64 */
   GP_PREC_FP32 = 1,         /* kernel tiles in FP32, FP32 MFMA products */
-  GP_PREC_BF16X3 = 2        /* split BF16 (hi + lo) MFMA products, FP32 accumulation */
+  GP_PREC_BF16X3 = 2,       /* split BF16 (hi + lo) MFMA products, FP32 accumulation */
+  GP_PREC_FP16X3 = 3        /* distance as BF16X3; tile x V in split FP16 (hi + lo), with the kernel
+                               values scaled by 2^15 and each column of V by a power of two so that
+                               both fit the FP16 range (exact scalings, undone in FP64) */
 } gp_precision;
 
 /* Flags reported in gp_stats.flags. */
@@ -88,7 +91,7 @@ typedef struct gp_problem {
 
 /* Estimator options (Algorithms 1 and 2). */
 typedef struct gp_options {
-  int32_t precision;     /* gp_precision of the K_hat tiles; recurrences are FP64 */
+  int32_t precision;     /* gp_precision of the K_hat tiles (0..3); recurrences are FP64 */
   int32_t num_probes;    /* ell, 1 .. GP_MAX_PROBES */
   int32_t max_iters;     /* CG iteration cap per column, >= 1 */
   double cg_tol;         /* a column stops when ||r|| <= cg_tol * ||b|| (>= 0) */

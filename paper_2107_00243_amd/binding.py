@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(HERE, "libgpmll.so")
 
 GP_OK, GP_EINVAL, GP_EWORKSPACE, GP_ENOTSPD, GP_EHIP, GP_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
 KERNELS = {"rbf": 0, "matern32": 1, "matern52": 2}
-PRECISIONS = {"fp64": 0, "fp32": 1, "bf16x3": 2}
+PRECISIONS = {"fp64": 0, "fp32": 1, "bf16x3": 2, "fp16x3": 3}
 FLAG_NOT_CONVERGED, FLAG_RANK_DEFICIENT, FLAG_RITZ_CLAMPED = 1, 2, 4
 MAX_D, MAX_PROBES, MAX_RANK = 32, 255, 1024
 

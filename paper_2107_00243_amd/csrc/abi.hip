@@ -14,7 +14,7 @@ hipError_t launch_stage_x(const Ctx& c, const Hyper& h);
 hipError_t launch_stage_x_bwd(const Ctx& c, const Hyper& h);
 hipError_t launch_stage_v(const Ctx& c, const double* V, int ldv, int ncols, const Hyper& h);
 hipError_t launch_khat_tiles(const Ctx& c, const Hyper& h, const int* nact);
-hipError_t launch_khat_reduce(const Ctx& c, const double* V, int ldv, double* W, int ldw, int ncols, double s2,
+hipError_t launch_khat_reduce(const Ctx& c, const double* V, int ldv, double* W, int ldw, int ncols, const Hyper& h,
                               double* dot_part, const int* nact);
 hipError_t launch_cg_after_product(const Ctx& c, const Hyper& h, int it, double tol);
 hipError_t launch_slq_logp(const Ctx& c, const Hyper& h, const double* y, double* logp);
@@ -46,7 +46,7 @@ Layout make_layout(int64_t n, int d, int ard, int num_probes, int max_iters, int
   L.max_iters = max_iters;
   L.prec = prec;
   L.bprec = prec == GP_PREC_FP64 ? GP_PREC_FP64 : GP_PREC_FP32;
-  if (prec == GP_PREC_BF16X3) {
+  if (prec == GP_PREC_BF16X3 || prec == GP_PREC_FP16X3) {
     const int dq = (d + 7) / 8 * 8;
     L.kd = (int)rup(4 * dq, 32);
   } else {
@@ -76,6 +76,7 @@ Layout make_layout(int64_t n, int d, int ard, int num_probes, int max_iters, int
     off += al(bytes ? bytes : 1);
     return o;
   };
+  const bool split16 = prec == GP_PREC_BF16X3 || prec == GP_PREC_FP16X3;
   const size_t esz = prec == GP_PREC_FP64 ? 8 : (prec == GP_PREC_FP32 ? 4 : 2);
   const size_t bsz = L.bprec == GP_PREC_FP64 ? 8 : 4;
   // preconditioner block: offsets depend on (n, d, rank) only, so a preconditioner
@@ -112,7 +113,8 @@ Layout make_layout(int64_t n, int d, int ard, int num_probes, int max_iters, int
   L.Z0 = take(np * tp * 8);
   L.Pd = take(np * tp * 8);
   L.W = take(np * tp * 8);
-  L.vfrag = take(np * tp * (prec == GP_PREC_BF16X3 ? 4 : esz));
+  L.vfrag = take(np * tp * (split16 ? 4 : esz));
+  L.vscale = take(2 * tp * 4);
   L.wpart = take((size_t)L.nsplit * np * std::max<int64_t>(tp * (prec == GP_PREC_FP64 ? 8 : 4), L.bow * bsz));
   L.rho = take(tp * 8);
   L.rho0 = take(tp * 8);
@@ -193,7 +195,7 @@ static int check_problem(const gp_problem* prob) {
 
 static int check_options(const gp_options* o) {
   if (!o) return GP_EINVAL;
-  if (o->precision < 0 || o->precision > 2) return GP_EINVAL;
+  if (o->precision < 0 || o->precision > 3) return GP_EINVAL;
   if (o->num_probes < 1 || o->num_probes > GP_MAX_PROBES) return GP_EINVAL;
   if (o->max_iters < 1 || o->max_iters > 100000) return GP_EINVAL;
   if (!(o->cg_tol >= 0.0) || !std::isfinite(o->cg_tol)) return GP_EINVAL;
@@ -332,7 +334,7 @@ static int run_estimator(const gp_problem* prob, const double* theta_host, const
     }
     HIPCHK(launch_stage_v(c, c.at<double>(L.Pd), L.tp, L.tp, h));
     HIPCHK(launch_khat_tiles(c, h, nact));
-    HIPCHK(launch_khat_reduce(c, c.at<double>(L.Pd), L.tp, c.at<double>(L.W), L.tp, L.tp, h.s2,
+    HIPCHK(launch_khat_reduce(c, c.at<double>(L.Pd), L.tp, c.at<double>(L.W), L.tp, L.tp, h,
                               c.at<double>(L.dot_part), nact));
     HIPCHK(launch_cg_after_product(c, h, it, opt->cg_tol));
   }
@@ -400,7 +402,7 @@ extern "C" int gp_khat_matvec(const gp_problem* prob, const double* theta_host, 
   RET_IF(check_problem(prob));
   if (!V_dev || !W_dev) return GP_EINVAL;
   if (num_rhs < 1 || num_rhs > 1 + GP_MAX_PROBES) return GP_EINVAL;
-  if (precision < 0 || precision > 2) return GP_EINVAL;
+  if (precision < 0 || precision > 3) return GP_EINVAL;
   Hyper h;
   RET_IF(make_hyper(prob, theta_host, &h));
   RET_IF(check_device());
@@ -411,7 +413,7 @@ extern "C" int gp_khat_matvec(const gp_problem* prob, const double* theta_host, 
   HIPCHK(launch_stage_x(c, h));
   HIPCHK(launch_stage_v(c, V_dev, num_rhs, num_rhs, h));
   HIPCHK(launch_khat_tiles(c, h, nullptr));
-  HIPCHK(launch_khat_reduce(c, V_dev, num_rhs, W_dev, num_rhs, num_rhs, h.s2, nullptr, nullptr));
+  HIPCHK(launch_khat_reduce(c, V_dev, num_rhs, W_dev, num_rhs, num_rhs, h, nullptr, nullptr));
   return GP_OK;
 }
 
@@ -463,6 +465,7 @@ extern "C" int gp_khat_profile(const gp_problem* prob, const double* theta_host,
   const int ntt = L.tp / 16;
   int rows_per_wg;
   if (L.prec == GP_PREC_FP64) rows_per_wg = 64 * (ntt <= 4 ? 2 : 1);
+  else if (L.prec == GP_PREC_BF16X3 || L.prec == GP_PREC_FP16X3) rows_per_wg = 256;
   else rows_per_wg = 64 * (ntt <= 5 ? 4 : (ntt <= 8 ? 2 : 1));
   if (grid_x) *grid_x = L.n_pad / rows_per_wg;
   if (grid_y) *grid_y = L.nsplit;

@@ -82,7 +82,7 @@ struct Layout {
   size_t precond_end;
   // estimator block
   size_t xfa, xfb, rowterm, colterm, H, Y, ltr, ltr_raw, ltr_part2;
-  size_t Xs, R, Z0, Pd, W, vfrag, wpart;
+  size_t Xs, R, Z0, Pd, W, vfrag, vscale, wpart;
   size_t rho, rho0, bnorm, rnorm2, pw, active, nactive, iters, alog, blog;
   size_t dot_part, gamma, slq_work;
   size_t cprime, bxa, bxb, brt, bct, bafrag, bcfrag, bxaug, bwd_part, pg_small, omega, pg_part;

@@ -362,15 +362,16 @@ struct BwdBfArgs {
   int64_t cols_per_split;
   int ow, nbt;
   float s, inv_s;
+  float rbf_sg, rbf_kap;  // RBF: s g = rbf_sg * exp2(q), kappa = rbf_kap * exp2(q)
 };
 
 template <int KIND>
-__device__ inline void bw_map(float q, float s, float inv_s, float* kap, float* sg) {
+__device__ inline void bw_map(float q, float s, float rbf_sg, float rbf_kap, float* kap, float* sg) {
   const float log2e = 1.4426950408889634f;
   if (KIND == GP_KERNEL_RBF) {
-    const float k = __builtin_amdgcn_exp2f(q);  // q = log2 k
-    *sg = k;
-    *kap = k * inv_s;
+    const float k = __builtin_amdgcn_exp2f(q);  // q: log2 of the staged kernel value
+    *sg = k * rbf_sg;
+    *kap = k * rbf_kap;
   } else if (KIND == GP_KERNEL_MATERN32) {
     const float a = 1.7320508075688772f;
     const float r = __builtin_sqrtf(fmaxf(q, 0.0f));
@@ -466,7 +467,7 @@ __global__ __launch_bounds__(256, 2) void k_bwd_bf16(const u32x4* __restrict__ x
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           float kap, sg;
-          bw_map<KIND>(dd[v] + ctv[v], a.s, a.inv_s, &kap, &sg);
+          bw_map<KIND>(dd[v] + ctv[v], a.s, a.rbf_sg, a.rbf_kap, &kap, &sg);
           if (diag && row0 + rg * 16 + li == c + js * 16 + 4 * g + v) {
             kap = 1.0f;
             sg = 0.0f;
@@ -836,6 +837,13 @@ hipError_t launch_bwd_bf16(const Ctx& c, const Hyper& h) {
   ba.nbt = (2 * L.d + 1 + 15) / 16;
   ba.s = (float)h.s;
   ba.inv_s = (float)(1.0 / h.s);
+  if (L.prec == GP_PREC_FP16X3) {  // staged RBF values are 2^15 kappa
+    ba.rbf_sg = (float)(h.s / 32768.0);
+    ba.rbf_kap = 1.0f / 32768.0f;
+  } else {  // staged RBF values are s kappa
+    ba.rbf_sg = 1.0f;
+    ba.rbf_kap = (float)(1.0 / h.s);
+  }
   switch (h.kind) {
     case GP_KERNEL_RBF: return sel_bwd<GP_KERNEL_RBF>(c, ba, nkc, nkm, nxt);
     case GP_KERNEL_MATERN32: return sel_bwd<GP_KERNEL_MATERN32>(c, ba, nkc, nkm, nxt);
@@ -862,7 +870,7 @@ hipError_t launch_backward(const Ctx& c, const Hyper& h, int ard, int precond_gr
   const int64_t nfr_x = (L.n_pad / 16) * ba.nbt * 256;
   const bool f64 = L.bprec == GP_PREC_FP64;
   hipError_t e;
-  if (L.prec == GP_PREC_BF16X3) {
+  if (L.prec == GP_PREC_BF16X3 || L.prec == GP_PREC_FP16X3) {
     e = launch_bwd_bf16(c, h);
   } else if (f64) {
     hipLaunchKernelGGL(k_stage_rows16x4<double>, dim3(nbk(nfr_t, 256)), dim3(256), 0, c.st, c.at<double>(L.Xs),

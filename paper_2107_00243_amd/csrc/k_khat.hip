@@ -22,6 +22,8 @@
 // v_mfma_f64_16x16x4_f64.
 #include "gpmll_impl.h"
 
+#include <algorithm>
+
 #ifndef GPMLL_KHAT_PART
 #define GPMLL_KHAT_PART 0
 #endif
@@ -56,6 +58,22 @@ __device__ inline void split_pair(float a, float b, uint32_t* hi, uint32_t* lo) 
   float hb = __builtin_bit_cast(float, h & 0xffff0000u);
   *hi = h;
   *lo = pack_bf16(a - ha, b - hb);
+}
+
+typedef _Float16 f16x2 __attribute__((ext_vector_type(2)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+
+__device__ inline uint32_t pack_f16(float a, float b) {
+  f32x2 v = {a, b};
+  return __builtin_bit_cast(uint32_t, __builtin_convertvector(v, f16x2));
+}
+
+// FP16 split of a pair: hi = RNE(a), lo = RNE(a - hi)
+__device__ inline void split_pair_f16(float a, float b, uint32_t* hi, uint32_t* lo) {
+  const uint32_t h = pack_f16(a, b);
+  const f32x2 hf = __builtin_convertvector(__builtin_bit_cast(f16x2, h), f32x2);
+  *hi = h;
+  *lo = pack_f16(a - hf[0], b - hf[1]);
 }
 
 __device__ inline float bf16_lo_f(uint32_t w) { return __builtin_bit_cast(float, w << 16); }
@@ -123,8 +141,10 @@ __device__ inline void copy_units(u32x4* dst, const u32x4* a, int na, const u32x
 // perturbed points.
 // ---------------------------------------------------------------------------
 
+// rbf_add: added to the RBF row term (log2 s for BF16X3 tiles; 15 for FP16X3 tiles,
+// whose kernel values are 2^15 kappa)
 __global__ void k_stage_x_bf16(const double* __restrict__ xs, int64_t n_pad, int d, int dq, int nkc, int kind,
-                               float log2s, u32x4* __restrict__ xfa, u32x4* __restrict__ xfb,
+                               float rbf_add, u32x4* __restrict__ xfa, u32x4* __restrict__ xfb,
                                float* __restrict__ rowterm, float* __restrict__ colterm) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n_pad) return;
@@ -171,7 +191,7 @@ __global__ void k_stage_x_bf16(const double* __restrict__ xs, int64_t n_pad, int
     }
   }
   if (rbf) {
-    rowterm[i] = (float)(-0.5 * nrm + (double)log2s);
+    rowterm[i] = (float)(-0.5 * nrm + (double)rbf_add);
     colterm[i] = (float)(-0.5 * nrm);
   } else {
     rowterm[i] = (float)(0.5 * nrm);
@@ -237,6 +257,66 @@ __global__ void k_stage_v_bf16(const double* __restrict__ V, int64_t nrows, int 
   vfrag[((jb * ntt + tt) * 2 + 1) * 64 + lane] = u32x4{l[0], l[1], l[2], l[3]};
 }
 
+// column maxima of |V| as float bit patterns (non-negative floats order like their
+// bits, so the integer maximum is exact and order-independent)
+__global__ void k_colmax(const double* __restrict__ V, int64_t nrows, int ldv, int ncols, uint32_t* __restrict__ cm) {
+  __shared__ uint32_t red[256];
+  const int c = blockIdx.y;
+  uint32_t m = 0;
+  for (int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x; r < nrows; r += (int64_t)gridDim.x * 256) {
+    const float v = fabsf((float)V[r * ldv + c]);
+    const uint32_t b = __builtin_bit_cast(uint32_t, v);
+    m = b > m ? b : m;
+  }
+  red[threadIdx.x] = m;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if (threadIdx.x < off) red[threadIdx.x] = max(red[threadIdx.x], red[threadIdx.x + off]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) atomicMax(cm + c, red[0]);
+}
+
+__global__ void k_zero_u32(uint32_t* p, int count) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < count) p[e] = 0;
+}
+
+// power-of-two scale that brings a column's maximum into [2^13, 2^14)
+__device__ __host__ inline float f16_col_scale(uint32_t maxbits) {
+  const float m = __builtin_bit_cast(float, maxbits);
+  if (!(m > 0.0f)) return 1.0f;
+  int e;
+  frexpf(m, &e);  // m = f * 2^e, f in [0.5, 1)
+  return ldexpf(1.0f, 14 - e);
+}
+
+// as k_stage_v_bf16 with FP16 hi + lo of (scale_c * V)
+__global__ void k_stage_v_f16(const double* __restrict__ V, int64_t nrows, int ldv, int ncols, int64_t n_pad, int ntt,
+                              const uint32_t* __restrict__ cm, u32x4* __restrict__ vfrag) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;  // (jb, tt, lane)
+  const int64_t total = (n_pad / 32) * ntt * 64;
+  if (e >= total) return;
+  const int lane = (int)(e % 64);
+  const int tt = (int)((e / 64) % ntt);
+  const int64_t jb = e / (64 * ntt);
+  const int g = lane / 16, col = tt * 16 + lane % 16;
+  const double sc = (col < ncols) ? (double)f16_col_scale(cm[col]) : 1.0;
+  uint32_t h[4], l[4];
+  for (int w = 0; w < 4; ++w) {
+    int64_t j0 = jb * 32 + (2 * w < 4 ? 4 * g + 2 * w : 16 + 4 * g + (2 * w - 4));
+    int64_t j1 = j0 + 1;
+    double a = (j0 < nrows && col < ncols) ? sc * V[j0 * ldv + col] : 0.0;
+    double b = (j1 < nrows && col < ncols) ? sc * V[j1 * ldv + col] : 0.0;
+    const uint32_t hh = pack_f16((float)a, (float)b);
+    const f32x2 hf = __builtin_convertvector(__builtin_bit_cast(f16x2, hh), f32x2);
+    h[w] = hh;
+    l[w] = pack_f16((float)(a - (double)hf[0]), (float)(b - (double)hf[1]));
+  }
+  vfrag[((jb * ntt + tt) * 2 + 0) * 64 + lane] = u32x4{h[0], h[1], h[2], h[3]};
+  vfrag[((jb * ntt + tt) * 2 + 1) * 64 + lane] = u32x4{l[0], l[1], l[2], l[3]};
+}
+
 // FP32/FP64: fragment (j16, tt, v) lane l holds row j16*16 + acc_row(l/16, v), column tt*16 + l%16
 template <typename T>
 __global__ void k_stage_v_fp(const double* __restrict__ V, int64_t nrows, int ldv, int ncols, int64_t n_pad,
@@ -260,13 +340,16 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_khat_reduce(const T* __restrict__ wpart, int nsplit, int64_t n_pad, int tp,
                                                      const double* __restrict__ V, int ldv, double* __restrict__ W,
                                                      int ldw, int64_t nrows, int ncols, double s2,
-                                                     double* __restrict__ dot_part, const int* __restrict__ nactive) {
+                                                     double* __restrict__ dot_part, const int* __restrict__ nactive,
+                                                     const uint32_t* __restrict__ colmax, double fac_s) {
   if (nactive != nullptr && *nactive == 0) return;
   __shared__ double red[4][64];
   const int cl = threadIdx.x % 64, lane4 = threadIdx.x / 64;
   const int c = blockIdx.y * 64 + cl;
   const int64_t r0 = (int64_t)blockIdx.x * 64;
   double dot = 0.0;
+  // FP16X3 partials carry the factors 2^15 / s (kernel values) and scale_c (column)
+  const double fac = (colmax != nullptr && c < ncols) ? fac_s / (double)f16_col_scale(colmax[c]) : 1.0;
   if (c < ncols) {
     for (int q = lane4; q < 64; q += 4) {
       const int64_t r = r0 + q;
@@ -274,7 +357,7 @@ __global__ __launch_bounds__(256) void k_khat_reduce(const T* __restrict__ wpart
       double w = 0.0;
       for (int s = 0; s < nsplit; ++s) w += (double)wpart[((int64_t)s * n_pad + r) * tp + c];
       const double v = V[r * ldv + c];
-      w += s2 * v;
+      w = w * fac + s2 * v;
       W[r * ldw + c] = w;
       dot += v * w;
     }
@@ -289,58 +372,119 @@ __global__ __launch_bounds__(256) void k_khat_reduce(const T* __restrict__ wpart
 #endif  // part 0
 
 #if GPMLL_KHAT_PART == 1
-// One 32-column step of the BF16x3 tile kernel for one wave (RG row groups of 16).
-// DIAG: the step's columns overlap the wave's rows; the diagonal gets exactly s.
-template <int KIND, int NKC, int NTT, int RG, bool DIAG>
-__device__ __forceinline__ void bf16_step(const u32x4* __restrict__ A, const u32x4* (&xb)[RG], const u32x4 (&xbv)[RG][NKC],
-                                          const f32x4 (&rt)[RG], f32x4 (&acc)[RG][NTT], int lane, int64_t row0,
-                                          int64_t c, float s32) {
-  constexpr int A_U = 2 * NKC * 64, V_U = NTT * 2 * 64;
+// Software-pipelined BF16x3 tile kernel.  Per wave (RG row groups of 16 rows)
+// and per 32-column step j:
+//   distance MFMAs of step j+1          (16 MFMAs for d <= 16)
+//   tile x V MFMAs of step j            (3 * NTT * RG MFMAs)
+//   kernel map + hi/lo split of step j+1 (VALU), interleaved with the MFMAs above
+// so the matrix pipe and the vector ALU of one wave work at the same time.  Stage
+// data (distance A fragments, V fragments, column terms) rotate through three LDS
+// buffers: step j reads V of stage j and A of stage j+1 while stage j+2 lands.
+
+// distance accumulators of one step: dd[rg][js] (lane = row i, 4 consecutive j)
+template <int NKC, int RG>
+__device__ __forceinline__ void bf16_distance(const u32x4* __restrict__ A, const u32x4 (&xbv)[RG][NKC],
+                                              const f32x4 (&rt)[RG], f32x4 (&dd)[RG][2], int lane) {
+#pragma unroll
+  for (int rg = 0; rg < RG; ++rg)
+#pragma unroll
+    for (int js = 0; js < 2; ++js) dd[rg][js] = rt[rg];
+#pragma unroll
+  for (int kc = 0; kc < NKC; ++kc)
+#pragma unroll
+    for (int rg = 0; rg < RG; ++rg)
+#pragma unroll
+      for (int js = 0; js < 2; ++js)
+        dd[rg][js] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, A[(js * NKC + kc) * 64 + lane]),
+                                                             __builtin_bit_cast(bf16x8, xbv[rg][kc]), dd[rg][js], 0,
+                                                             0, 0);
+}
+
+// kernel map and hi/lo split of one step: dd -> (ph, pl); DIAG puts s on i == j
+template <int KIND, int RG, bool DIAG, bool F16>
+__device__ __forceinline__ void bf16_map(const f32x4 (&dd)[RG][2], const float* __restrict__ ct, u32x4 (&ph)[RG],
+                                         u32x4 (&pl)[RG], int lane, int64_t row0, int64_t c, float s32) {
   const int g = lane >> 4, li = lane & 15;
-  const u32x4* Vf = A + A_U;
-  const float* ct = reinterpret_cast<const float*>(A + A_U + V_U);
   const f32x4 ct0 = *reinterpret_cast<const f32x4*>(ct + 4 * g);
   const f32x4 ct1 = *reinterpret_cast<const f32x4*>(ct + 16 + 4 * g);
-  u32x4 ph[RG], pl[RG];
 #pragma unroll
-  for (int rg = 0; rg < RG; ++rg) {
+  for (int rg = 0; rg < RG; ++rg)
 #pragma unroll
     for (int js = 0; js < 2; ++js) {
-      f32x4 dd = rt[rg];
-#pragma unroll
-      for (int kc = 0; kc < NKC; ++kc)
-        dd = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, A[(js * NKC + kc) * 64 + lane]),
-                                                     __builtin_bit_cast(bf16x8, xbv[rg][kc]), dd, 0, 0, 0);
       const f32x4 ctv = js ? ct1 : ct0;
       float kv[4];
 #pragma unroll
-      for (int v = 0; v < 4; ++v) kv[v] = map32<KIND>(dd[v] + ctv[v], s32);
+      for (int v = 0; v < 4; ++v) kv[v] = map32<KIND>(dd[rg][js][v] + ctv[v], s32);
       if constexpr (DIAG) {
         const int64_t i = row0 + rg * 16 + li;
 #pragma unroll
         for (int v = 0; v < 4; ++v) kv[v] = (i == c + js * 16 + 4 * g + v) ? s32 : kv[v];
       }
       uint32_t h0, l0, h1, l1;
-      split_pair(kv[0], kv[1], &h0, &l0);
-      split_pair(kv[2], kv[3], &h1, &l1);
+      if constexpr (F16) {
+        split_pair_f16(kv[0], kv[1], &h0, &l0);
+        split_pair_f16(kv[2], kv[3], &h1, &l1);
+      } else {
+        split_pair(kv[0], kv[1], &h0, &l0);
+        split_pair(kv[2], kv[3], &h1, &l1);
+      }
       ph[rg][2 * js] = h0;
       ph[rg][2 * js + 1] = h1;
       pl[rg][2 * js] = l0;
       pl[rg][2 * js + 1] = l1;
     }
+}
+
+// tile x V MFMAs of one step: acc += P V with P = hi + lo, V = hi + lo (3 products)
+template <bool F16>
+__device__ __forceinline__ f32x4 mfma16(u32x4 a, u32x4 b, f32x4 c) {
+  if constexpr (F16)
+    return __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(f16x8, a), __builtin_bit_cast(f16x8, b), c, 0, 0, 0);
+  else
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b), c, 0, 0,
+                                                   0);
+}
+
+template <int NTT, int RG, bool F16>
+__device__ __forceinline__ void bf16_tile_v(const u32x4* __restrict__ Vf, const u32x4 (&ph)[RG], const u32x4 (&pl)[RG],
+                                            f32x4 (&acc)[RG][NTT], int lane) {
+  if constexpr (F16) {
+#pragma unroll
+    for (int tt = 0; tt < NTT; ++tt) {
+      const u32x4 vh = Vf[(tt * 2 + 0) * 64 + lane];
+      const u32x4 vl = Vf[(tt * 2 + 1) * 64 + lane];
+#pragma unroll
+      for (int rg = 0; rg < RG; ++rg) acc[rg][tt] = mfma16<true>(ph[rg], vh, acc[rg][tt]);
+#pragma unroll
+      for (int rg = 0; rg < RG; ++rg) acc[rg][tt] = mfma16<true>(ph[rg], vl, acc[rg][tt]);
+#pragma unroll
+      for (int rg = 0; rg < RG; ++rg) acc[rg][tt] = mfma16<true>(pl[rg], vh, acc[rg][tt]);
+    }
+    return;
   }
 #pragma unroll
   for (int tt = 0; tt < NTT; ++tt) {
     const bf16x8 vh = __builtin_bit_cast(bf16x8, Vf[(tt * 2 + 0) * 64 + lane]);
     const bf16x8 vl = __builtin_bit_cast(bf16x8, Vf[(tt * 2 + 1) * 64 + lane]);
 #pragma unroll
-    for (int rg = 0; rg < RG; ++rg) {
-      const bf16x8 h = __builtin_bit_cast(bf16x8, ph[rg]);
-      const bf16x8 l = __builtin_bit_cast(bf16x8, pl[rg]);
-      acc[rg][tt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(h, vh, acc[rg][tt], 0, 0, 0);
-      acc[rg][tt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(h, vl, acc[rg][tt], 0, 0, 0);
-      acc[rg][tt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(l, vh, acc[rg][tt], 0, 0, 0);
-    }
+    for (int rg = 0; rg < RG; ++rg)
+      acc[rg][tt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, ph[rg]), vh, acc[rg][tt], 0, 0, 0);
+#pragma unroll
+    for (int rg = 0; rg < RG; ++rg)
+      acc[rg][tt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, ph[rg]), vl, acc[rg][tt], 0, 0, 0);
+#pragma unroll
+    for (int rg = 0; rg < RG; ++rg)
+      acc[rg][tt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, pl[rg]), vh, acc[rg][tt], 0, 0, 0);
+  }
+}
+
+// interleave: one MFMA, then two VALU instructions, for the tile x V MFMAs
+template <int NMFMA>
+__device__ __forceinline__ void bf16_interleave_hint() {
+#pragma unroll
+  for (int i = 0; i < NMFMA; ++i) {
+    __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);  // MFMA
+    __builtin_amdgcn_sched_group_barrier(0x002, 2, 0);  // VALU
   }
 }
 
@@ -361,7 +505,7 @@ __device__ __forceinline__ void bf16_issue_stage(u32x4* dst, const u32x4* __rest
   }
 }
 
-template <int KIND, int NKC, int NTT, int RG>
+template <int KIND, int NKC, int NTT, int RG, bool F16>
 __global__ __launch_bounds__(256, 2) void k_khat_bf16(const u32x4* __restrict__ xfa, const u32x4* __restrict__ xfb,
                                                       const float* __restrict__ rowterm,
                                                       const float* __restrict__ colterm,
@@ -370,44 +514,70 @@ __global__ __launch_bounds__(256, 2) void k_khat_bf16(const u32x4* __restrict__ 
   if (nactive != nullptr && *nactive == 0) return;
   constexpr int A_U = 2 * NKC * 64, V_U = NTT * 2 * 64, C_U = 64;
   constexpr int STAGE = A_U + V_U + C_U;
-  __shared__ u32x4 lds[2][STAGE];
+  __shared__ u32x4 lds[3][STAGE];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int g = lane >> 4, li = lane & 15;
   const int64_t row0 = (int64_t)blockIdx.x * (64 * RG) + wave * (16 * RG);
   const int64_t c_begin = (int64_t)blockIdx.y * a.cols_per_split;
   const int64_t c_end = min(a.n_pad, c_begin + a.cols_per_split);
   if (c_begin >= c_end) return;
+  const int nsteps = (int)((c_end - c_begin) / 32);
 
   u32x4 xbv[RG][NKC];
-  const u32x4* xb[RG];
   f32x4 rt[RG];
   f32x4 acc[RG][NTT];
 #pragma unroll
   for (int rg = 0; rg < RG; ++rg) {
-    xb[rg] = xfb + (row0 / 16 + rg) * NKC * 64 + lane;
 #pragma unroll
-    for (int kc = 0; kc < NKC; ++kc) xbv[rg][kc] = xb[rg][kc * 64];
+    for (int kc = 0; kc < NKC; ++kc) xbv[rg][kc] = xfb[((row0 / 16 + rg) * NKC + kc) * 64 + lane];
     const float r = rowterm[row0 + rg * 16 + li];
     rt[rg] = f32x4{r, r, r, r};
 #pragma unroll
     for (int tt = 0; tt < NTT; ++tt) acc[rg][tt] = f32x4{0.f, 0.f, 0.f, 0.f};
   }
+  auto is_diag = [&](int64_t c) { return (c + 32 > row0) && (c < row0 + 16 * RG); };
 
+  // prologue: stages 0 and 1 in flight, P of step 0
   bf16_issue_stage<NKC, NTT>(lds[0], xfa, vfrag, colterm, c_begin, wave, lane);
+  if (nsteps > 1) bf16_issue_stage<NKC, NTT>(lds[1], xfa, vfrag, colterm, c_begin + 32, wave, lane);
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
-  int buf = 0;
-  for (int64_t c = c_begin; c < c_end; c += 32) {
-    if (c + 32 < c_end) bf16_issue_stage<NKC, NTT>(lds[buf ^ 1], xfa, vfrag, colterm, c + 32, wave, lane);
-    const bool diag = (c + 32 > row0) && (c < row0 + 16 * RG);
-    if (diag)
-      bf16_step<KIND, NKC, NTT, RG, true>(lds[buf], xb, xbv, rt, acc, lane, row0, c, a.s32);
-    else
-      bf16_step<KIND, NKC, NTT, RG, false>(lds[buf], xb, xbv, rt, acc, lane, row0, c, a.s32);
+  u32x4 ph[RG], pl[RG];
+  {
+    f32x4 dd[RG][2];
+    bf16_distance<NKC, RG>(lds[0], xbv, rt, dd, lane);
+    const float* ct = reinterpret_cast<const float*>(lds[0] + A_U + V_U);
+    if (is_diag(c_begin)) bf16_map<KIND, RG, true, F16>(dd, ct, ph, pl, lane, row0, c_begin, a.s32);
+    else bf16_map<KIND, RG, false, F16>(dd, ct, ph, pl, lane, row0, c_begin, a.s32);
+  }
+  int cur = 0;
+  for (int j = 0; j + 1 < nsteps; ++j) {
+    const int nxt = cur == 2 ? 0 : cur + 1;
+    const int far = nxt == 2 ? 0 : nxt + 1;
+    const int64_t cn = c_begin + (int64_t)(j + 1) * 32;
+    if (j + 2 < nsteps) bf16_issue_stage<NKC, NTT>(lds[far], xfa, vfrag, colterm, cn + 32, wave, lane);
+    f32x4 dd[RG][2];
+    bf16_distance<NKC, RG>(lds[nxt], xbv, rt, dd, lane);
+    u32x4 nph[RG], npl[RG];
+    const float* ctn = reinterpret_cast<const float*>(lds[nxt] + A_U + V_U);
+    if (is_diag(cn)) {
+      bf16_tile_v<NTT, RG, F16>(lds[cur] + A_U, ph, pl, acc, lane);
+      bf16_map<KIND, RG, true, F16>(dd, ctn, nph, npl, lane, row0, cn, a.s32);
+    } else {
+      bf16_tile_v<NTT, RG, F16>(lds[cur] + A_U, ph, pl, acc, lane);
+      bf16_map<KIND, RG, false, F16>(dd, ctn, nph, npl, lane, row0, cn, a.s32);
+    }
+#pragma unroll
+    for (int rg = 0; rg < RG; ++rg) {
+      ph[rg] = nph[rg];
+      pl[rg] = npl[rg];
+    }
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
-    buf ^= 1;
+    cur = nxt;
   }
+  bf16_tile_v<NTT, RG, F16>(lds[cur] + A_U, ph, pl, acc, lane);
+
   float* out = wpart + (int64_t)blockIdx.y * a.n_pad * a.tp;
 #pragma unroll
   for (int rg = 0; rg < RG; ++rg)
@@ -555,43 +725,47 @@ hipError_t khat_tiles_fp64(const Ctx& c, const Hyper& h, const TileArgs& ta, con
 
 #if GPMLL_KHAT_PART == 1
 namespace {
-template <int KIND, int NKC, int NTT>
+template <int KIND, int NKC, int NTT, bool F16>
 hipError_t run_bf16(const Ctx& c, const TileArgs& ta, const int* nact) {
   const Layout& L = *c.lay;
   constexpr int RG = NTT <= 5 ? 4 : (NTT <= 8 ? 2 : 1);
   dim3 grid((unsigned)(L.n_pad / (64 * RG)), (unsigned)L.nsplit);
-  hipLaunchKernelGGL((k_khat_bf16<KIND, NKC, NTT, RG>), grid, dim3(256), 0, c.st, c.at<u32x4>(L.xfa),
+  hipLaunchKernelGGL((k_khat_bf16<KIND, NKC, NTT, RG, F16>), grid, dim3(256), 0, c.st, c.at<u32x4>(L.xfa),
                      c.at<u32x4>(L.xfb), c.at<float>(L.rowterm), c.at<float>(L.colterm), c.at<u32x4>(L.vfrag),
                      c.at<float>(L.wpart), ta, nact);
   return hipGetLastError();
 }
-template <int KIND, int NKC>
+template <int KIND, int NKC, bool F16>
 hipError_t sel_bf16_ntt(const Ctx& c, const TileArgs& ta, const int* nact, int ntt) {
   switch (ntt) {
-#define CASE(N) case N: return run_bf16<KIND, NKC, N>(c, ta, nact);
+#define CASE(N) case N: return run_bf16<KIND, NKC, N, F16>(c, ta, nact);
     GPMLL_NTT_CASES(CASE)
 #undef CASE
   }
   return hipErrorInvalidValue;
 }
-template <int KIND>
+template <int KIND, bool F16>
 hipError_t sel_bf16(const Ctx& c, const TileArgs& ta, const int* nact) {
   const Layout& L = *c.lay;
   const int ntt = L.tp / 16;
   switch (L.kd / 32) {
-    case 1: return sel_bf16_ntt<KIND, 1>(c, ta, nact, ntt);
-    case 2: return sel_bf16_ntt<KIND, 2>(c, ta, nact, ntt);
-    case 3: return sel_bf16_ntt<KIND, 3>(c, ta, nact, ntt);
-    case 4: return sel_bf16_ntt<KIND, 4>(c, ta, nact, ntt);
+    case 1: return sel_bf16_ntt<KIND, 1, F16>(c, ta, nact, ntt);
+    case 2: return sel_bf16_ntt<KIND, 2, F16>(c, ta, nact, ntt);
+    case 3: return sel_bf16_ntt<KIND, 3, F16>(c, ta, nact, ntt);
+    case 4: return sel_bf16_ntt<KIND, 4, F16>(c, ta, nact, ntt);
   }
   return hipErrorInvalidValue;
 }
 }  // namespace
 hipError_t khat_tiles_bf16(const Ctx& c, const Hyper& h, const TileArgs& ta, const int* nact) {
+  const bool f16 = c.lay->prec == GP_PREC_FP16X3;
   switch (h.kind) {
-    case GP_KERNEL_RBF: return sel_bf16<GP_KERNEL_RBF>(c, ta, nact);
-    case GP_KERNEL_MATERN32: return sel_bf16<GP_KERNEL_MATERN32>(c, ta, nact);
-    default: return sel_bf16<GP_KERNEL_MATERN52>(c, ta, nact);
+    case GP_KERNEL_RBF:
+      return f16 ? sel_bf16<GP_KERNEL_RBF, true>(c, ta, nact) : sel_bf16<GP_KERNEL_RBF, false>(c, ta, nact);
+    case GP_KERNEL_MATERN32:
+      return f16 ? sel_bf16<GP_KERNEL_MATERN32, true>(c, ta, nact) : sel_bf16<GP_KERNEL_MATERN32, false>(c, ta, nact);
+    default:
+      return f16 ? sel_bf16<GP_KERNEL_MATERN52, true>(c, ta, nact) : sel_bf16<GP_KERNEL_MATERN52, false>(c, ta, nact);
   }
 }
 #endif
@@ -652,10 +826,11 @@ hipError_t khat_tiles_fp64(const Ctx& c, const Hyper& h, const TileArgs& ta, con
 hipError_t launch_stage_x(const Ctx& c, const Hyper& h) {
   const Layout& L = *c.lay;
   const unsigned nb = (unsigned)((L.n_pad + 255) / 256);
-  if (L.prec == GP_PREC_BF16X3) {
+  if (L.prec == GP_PREC_BF16X3 || L.prec == GP_PREC_FP16X3) {
     const int dq = (L.d + 7) / 8 * 8;
+    const float rbf_add = L.prec == GP_PREC_FP16X3 ? 15.0f : (float)h.log2s;
     hipLaunchKernelGGL(k_stage_x_bf16, dim3(nb), dim3(256), 0, c.st, c.at<double>(L.xs), L.n_pad, L.d, dq,
-                       L.kd / 32, h.kind, (float)h.log2s, c.at<u32x4>(L.xfa), c.at<u32x4>(L.xfb),
+                       L.kd / 32, h.kind, rbf_add, c.at<u32x4>(L.xfa), c.at<u32x4>(L.xfb),
                        c.at<float>(L.rowterm), c.at<float>(L.colterm));
   } else if (L.prec == GP_PREC_FP32) {
     hipLaunchKernelGGL(k_stage_x_fp<float>, dim3(nb), dim3(256), 0, c.st, c.at<double>(L.xs), L.n_pad, L.d,
@@ -673,7 +848,7 @@ hipError_t launch_stage_x(const Ctx& c, const Hyper& h) {
 hipError_t launch_stage_x_bwd(const Ctx& c, const Hyper& h) {
   const Layout& L = *c.lay;
   (void)h;
-  if (L.prec == GP_PREC_BF16X3) return hipSuccess;  // the BF16x3 sweep reuses the forward operands
+  if (L.prec == GP_PREC_BF16X3 || L.prec == GP_PREC_FP16X3) return hipSuccess;  // reused by the split sweep
   const unsigned nb = (unsigned)((L.n_pad + 255) / 256);
   if (L.bprec == GP_PREC_FP64)
     hipLaunchKernelGGL(k_stage_x_fp<double>, dim3(nb), dim3(256), 0, c.st, c.at<double>(L.xs), L.n_pad, L.d,
@@ -690,7 +865,15 @@ hipError_t launch_stage_v(const Ctx& c, const double* V, int ldv, int ncols, con
   const Layout& L = *c.lay;
   (void)h;
   const int ntt = L.tp / 16;
-  if (L.prec == GP_PREC_BF16X3) {
+  if (L.prec == GP_PREC_FP16X3) {
+    uint32_t* cm = c.at<uint32_t>(L.vscale);
+    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(256), 0, c.st, cm, L.tp);
+    const unsigned gx = (unsigned)std::min<int64_t>(64, (L.n + 255) / 256);
+    hipLaunchKernelGGL(k_colmax, dim3(gx, (unsigned)ncols), dim3(256), 0, c.st, V, L.n, ldv, ncols, cm);
+    const int64_t total = (L.n_pad / 32) * ntt * 64;
+    hipLaunchKernelGGL(k_stage_v_f16, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, c.st, V, L.n, ldv, ncols,
+                       L.n_pad, ntt, cm, c.at<u32x4>(L.vfrag));
+  } else if (L.prec == GP_PREC_BF16X3) {
     const int64_t total = (L.n_pad / 32) * ntt * 64;
     hipLaunchKernelGGL(k_stage_v_bf16, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, c.st, V, L.n, ldv,
                        ncols, L.n_pad, ntt, c.at<u32x4>(L.vfrag));
@@ -715,21 +898,28 @@ hipError_t launch_khat_tiles(const Ctx& c, const Hyper& h, const int* nact) {
   ta.tp = L.tp;
   ta.s32 = (float)h.s;
   ta.s64 = h.s;
-  if (L.prec == GP_PREC_BF16X3) return khat_tiles_bf16(c, h, ta, nact);
+  if (L.prec == GP_PREC_BF16X3 || L.prec == GP_PREC_FP16X3) {
+    // FP16X3 kernel values are 2^15 kappa: the tile carries no outputscale
+    if (L.prec == GP_PREC_FP16X3) ta.s32 = 32768.0f;
+    return khat_tiles_bf16(c, h, ta, nact);
+  }
   if (L.prec == GP_PREC_FP32) return khat_tiles_fp32(c, h, ta, nact);
   return khat_tiles_fp64(c, h, ta, nact);
 }
 
-hipError_t launch_khat_reduce(const Ctx& c, const double* V, int ldv, double* W, int ldw, int ncols, double s2,
+hipError_t launch_khat_reduce(const Ctx& c, const double* V, int ldv, double* W, int ldw, int ncols, const Hyper& h,
                               double* dot_part, const int* nact) {
   const Layout& L = *c.lay;
   const dim3 nb((unsigned)((L.n + 63) / 64), (unsigned)((ncols + 63) / 64));
+  const bool f16 = L.prec == GP_PREC_FP16X3;
+  const uint32_t* cm = f16 ? c.at<uint32_t>(L.vscale) : nullptr;
+  const double fac_s = f16 ? h.s / 32768.0 : 1.0;
   if (L.prec == GP_PREC_FP64)
     hipLaunchKernelGGL(k_khat_reduce<double>, nb, dim3(256), 0, c.st, c.at<double>(L.wpart), L.nsplit, L.n_pad,
-                       L.tp, V, ldv, W, ldw, L.n, ncols, s2, dot_part, nact);
+                       L.tp, V, ldv, W, ldw, L.n, ncols, h.s2, dot_part, nact, cm, fac_s);
   else
     hipLaunchKernelGGL(k_khat_reduce<float>, nb, dim3(256), 0, c.st, c.at<float>(L.wpart), L.nsplit, L.n_pad,
-                       L.tp, V, ldv, W, ldw, L.n, ncols, s2, dot_part, nact);
+                       L.tp, V, ldv, W, ldw, L.n, ncols, h.s2, dot_part, nact, cm, fac_s);
   return hipGetLastError();
 }
 

@@ -72,10 +72,10 @@ FP64_LP, FP64_G = 1e-7, 1e-5
 
 # ---------------------------------------------------------------- K_hat V tiles
 
-MATVEC_TOL = {"fp64": 1e-12, "fp32": 2e-5, "bf16x3": 2e-4}
+MATVEC_TOL = {"fp64": 1e-12, "fp32": 2e-5, "bf16x3": 2e-4, "fp16x3": 1e-4}
 
 
-@pytest.mark.parametrize("precision", ["fp64", "fp32", "bf16x3"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "bf16x3", "fp16x3"])
 @pytest.mark.parametrize("kernel", ["rbf", "matern32", "matern52"])
 @pytest.mark.parametrize("n,d,nrhs", [(1000, 3, 17), (777, 8, 33), (1300, 16, 65), (300, 20, 5)])
 def test_khat_matvec_matches_oracle(precision, kernel, n, d, nrhs):
@@ -201,6 +201,8 @@ def test_plain_rbf_fp64_matches_oracle_tightly():
     ("rbf", True, "fp32", 1e-3, 1e-2),
     ("rbf", True, "bf16x3", 1e-3, 1e-2),
     ("matern32", True, "bf16x3", 1e-3, 1e-2),
+    ("rbf", True, "fp16x3", 1e-3, 1e-2),
+    ("matern52", True, "fp16x3", 1e-3, 1e-2),
 ])
 def test_estimator_matches_oracle(kernel, ard, precision, lp_tol, g_tol):
     pr = synthgp.random_problem(1111, 5, kernel, ard=ard, seed=3, dist="normal", rank=20, num_probes=12,
@@ -217,9 +219,10 @@ def test_matern52_ard_20k_recipe_at_reduced_n_fp32():
     _check_tight(out, ref, 1e-3, 1e-2)
 
 
-def test_rbf_ard_100k_recipe_at_reduced_n_bf16x3():
+@pytest.mark.parametrize("precision", ["bf16x3", "fp16x3"])
+def test_rbf_ard_100k_recipe_at_reduced_n_split_precision(precision):
     pr = synthgp.rbf_ard_100k(n=2500)
-    out = run_estimator(pr, "bf16x3")
+    out = run_estimator(pr, precision)
     ref = oracle(pr)
     _check_tight(out, ref, 1e-3, 1e-2)
 
