@@ -97,7 +97,7 @@ def test_workspace_size_is_positive_and_grows(lib):
     lambda p, o: setattr(o, "max_iters", 0),
     lambda p, o: setattr(o, "cg_tol", -1.0),
     lambda p, o: setattr(o, "cg_tol", float("nan")),
-    lambda p, o: setattr(o, "precision", 3),
+    lambda p, o: setattr(o, "precision", 4),
     lambda p, o: setattr(o, "precond_grad", 2),
     lambda p, o: setattr(o, "sync_every", -1),
 ])
