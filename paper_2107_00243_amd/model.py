@@ -27,6 +27,7 @@ class GPMarginalLikelihood:
         self.logp = torch.zeros(1, dtype=torch.float64, device=device)
         self.grad = torch.zeros(self.num_params, dtype=torch.float64, device=device)
         self.last_stats = None
+        self.want_stats = False
 
     def evaluate(self, theta, with_grad=True, stats=False):
         """log p (and the gradient w.r.t. natural theta) as device tensors."""
@@ -46,7 +47,7 @@ class GPMLL(torch.autograd.Function):
     @staticmethod
     def forward(ctx, model: GPMarginalLikelihood, log_theta: torch.Tensor):
         theta = torch.exp(log_theta.detach().to(torch.float64).cpu())
-        logp, grad = model.evaluate(theta.numpy(), with_grad=True)
+        logp, grad = model.evaluate(theta.numpy(), with_grad=True, stats=model.want_stats)
         g = grad.detach().cpu()
         ctx.save_for_backward(theta * g)
         return logp.detach().cpu().reshape(())

@@ -284,3 +284,28 @@ def test_gradient_matches_central_differences_of_the_estimator():
     say(f"    grad {out['grad']} exact {ex['grad']} fd {fd}")
     assert relvec(fd, ex["grad"]) < 1e-6
     assert relvec(out["grad"], fd) < 5e-2
+
+
+# ---------------------------------------------------------------- Adam driver
+
+def test_adam_on_the_autograd_function_follows_the_oracle_trajectory():
+    # three Adam steps on log theta through GPMLL; the same steps driven by the
+    # oracle's estimate (same probes) give the same trajectory
+    import torch as T
+    from paper_2107_00243_amd.model import GPMarginalLikelihood
+    from paper_2107_00243_amd.train import adam_fit
+    pr = synthgp.gmm_matern32_300k(n=1500)
+    say(f"[gpu] adam driver n={pr.n} d={pr.d}")
+    model = GPMarginalLikelihood(pr.X, pr.y, pr.kernel, pr.ard, 40, 16, 400, 1e-8, "fp64", pr.probe_seed)
+    hist, theta = adam_fit(model, pr.theta, steps=3, lr=0.1, log=say)
+    lt = T.tensor(np.log(pr.theta), requires_grad=True)
+    opt = T.optim.Adam([lt], lr=0.1)
+    for step in range(3):
+        th = np.exp(lt.detach().numpy())
+        ref = go.estimate_mll(pr.X, pr.y, th, pr.kernel, pr.ard, 40, 16, 1e-8, 400, pr.probe_seed)
+        assert rel(hist[step]["logp"], ref["logp"]) < 1e-7
+        opt.zero_grad()
+        lt.grad = T.tensor(-(th * ref["grad"]))
+        opt.step()
+    np.testing.assert_allclose(theta, np.exp(lt.detach().numpy()), rtol=1e-6)
+    assert hist[-1]["logp"] > hist[0]["logp"]
