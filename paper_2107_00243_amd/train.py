@@ -57,7 +57,7 @@ def adam_fit(model: GPMarginalLikelihood, theta0, steps=20, lr=0.1, checkpoint=N
         (-logp).backward()
         opt.step()
         st = model.last_stats
-        rec = {"step": step, "logp": float(logp), "seconds": time.perf_counter() - t0,
+        rec = {"step": step, "logp": float(logp.detach()), "seconds": time.perf_counter() - t0,
                "theta": np.exp(log_theta.detach().numpy()).tolist()}
         if st is not None:
             rec["cg_iters"] = int(st.iters_max)
