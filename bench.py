@@ -73,6 +73,32 @@ def run_gpu(pr, precision, steps, warmup, sync_every=1):
     return info
 
 
+def tiles_only(pr, reps=10, copy_bytes=1 << 30):
+    """The tile kernel alone in the bench's launch configuration, then a plain
+    elementwise copy of copy_bytes (read copy_bytes, write copy_bytes) whose
+    counter readings calibrate the HBM byte counters."""
+    import torch
+    from paper_2107_00243_amd import binding as B
+    dev = torch.device("cuda:0")
+    X = torch.tensor(pr.X, device=dev)
+    y = torch.tensor(pr.y, device=dev)
+    prob = B.make_problem(X, y, pr.kernel, pr.ard)
+    opt = B.make_options("bf16x3", pr.num_probes, pr.max_iters, pr.tol, pr.probe_seed, 0, 1)
+    ws = B.alloc_workspace(B.gp_workspace_size(prob, opt, pr.rank))
+    ms, grid = B.gp_khat_profile(prob, pr.theta, opt, reps, ws)
+    a = torch.ones(copy_bytes // 4, dtype=torch.float32, device=dev)
+    c = torch.empty_like(a)
+    torch.mul(a, 1.0, out=c)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    torch.mul(a, 1.0, out=c)
+    e1.record()
+    torch.cuda.synchronize()
+    return {"tile_ms": ms, "tile_grid": list(grid), "reps": reps, "copy_bytes_read": copy_bytes,
+            "copy_bytes_written": copy_bytes, "copy_ms": e0.elapsed_time(e1)}
+
+
 def cpu_baseline(pr, iters, budget_s=12.0):
     """The CPU oracle's K_hat V (row-blocked direct differences, FP64) timed on a
     block of rows of the same workload and scaled to one evaluation
@@ -109,10 +135,12 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--n", type=int, default=100000)
+    ap.add_argument("--tiles-only", action="store_true",
+                    help="only the BF16x3 tile kernel (10 launches) and a 1 GiB elementwise copy, for counters")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(the row-sharded design is described in DESIGN.md); use --gpus 1", file=sys.stderr)
+        print("bench.py runs on one GPU only: there is no multi-GPU path "
+              "(the whole problem sits on one GPU); use --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -121,6 +149,9 @@ def main():
     pr = synthgp.rbf_ard_100k(n=args.n)
     n, d, t = pr.n, pr.d, 1 + pr.num_probes
     log(f"[bench] workload rbf_ard_100k n={n} d={d} t={t} rank={pr.rank}")
+    if args.tiles_only:
+        print(json.dumps(tiles_only(pr)))
+        return
 
     bf = run_gpu(pr, "bf16x3", args.steps, args.warmup)
     log(f"[bench] bf16x3: {bf['ms_per_step']:.2f} ms/eval, iters {bf['iters_max']}, tile {bf['tile_ms']:.3f} ms")

@@ -213,6 +213,83 @@ int gp_khat_profile(const gp_problem* prob, const double* theta_host, const gp_o
                     void* ws_dev, size_t ws_bytes, hipStream_t stream, double* ms_per_launch,
                     int64_t* grid_x, int64_t* grid_y);
 
+/*
+ * Ragged batches of independent problems
+ * --------------------------------------
+ * One call evaluates Algorithm 1 (and, for the _grad form, Algorithm 2) for
+ * every problem of a batch; each phase of the method is one launch for all
+ * problems, and every problem keeps its own hyperparameters, preconditioner,
+ * CG scalars and per-column convergence mask (the many-right-hand-sides CG of
+ * Section 4.4, across problems).  Problem b gives exactly the result of
+ * gp_mll_eval / gp_mll_grad on that problem alone with seed + b and rank
+ * min(rank, n_b), up to rounding order.
+ *
+ * X_dev holds the problems' points one after another (sum_b n_b rows of d
+ * FP64, row-major), y_dev their targets; problem b is rows
+ * offsets_host[b] .. offsets_host[b+1] - 1.  offsets_host is a host array of
+ * batch + 1 entries starting at 0 and strictly increasing.  All problems share
+ * d, kernel, ard and the options.
+ */
+typedef struct gp_batch {
+  const double* X_dev;
+  const double* y_dev;
+  const int64_t* offsets_host;
+  int32_t batch;    /* number of problems, 1 .. 65536 */
+  int32_t d;        /* 1 .. GP_MAX_D */
+  int32_t kernel;   /* gp_kernel */
+  int32_t ard;      /* 1: d lengthscales per problem, 0: one */
+} gp_batch;
+
+/* Per-batch statistics (optional; asking for them synchronises the stream). */
+typedef struct gp_batch_stats {
+  int32_t iters_max;      /* largest CG iteration count over all problems and columns */
+  int32_t flags_any;      /* OR of the per-problem GP_FLAG_* bits */
+  int32_t* iters_host;    /* NULL or int32[batch]: per-problem largest column iteration count */
+  int32_t* flags_host;    /* NULL or int32[batch]: per-problem GP_FLAG_* bits */
+  int32_t* rank_host;     /* NULL or int32[batch]: per-problem achieved preconditioner rank */
+} gp_batch_stats;
+
+/* Limits of the batched path. */
+#define GP_BATCH_MAX_RANK 256
+#define GP_BATCH_MAX_PROBES 64
+
+/*
+ * gp_batch_workspace_size — bytes of device workspace for gp_batch_mll_eval /
+ * gp_batch_mll_grad with these problems, options and rank.  Only
+ * offsets_host, batch, d, kernel and ard of *batch are read.
+ * Errors: GP_EINVAL for bad sizes or options; GP_EUNSUPPORTED for a precision
+ * other than GP_PREC_FP64 / GP_PREC_FP32, num_probes > GP_BATCH_MAX_PROBES or
+ * rank > GP_BATCH_MAX_RANK.
+ */
+int gp_batch_workspace_size(const gp_batch* batch, const gp_options* opt, int32_t rank, size_t* bytes);
+
+/*
+ * gp_batch_mll_eval — log p for every problem of the batch.
+ *   theta_host  batch x (p + 2) natural hyperparameters, row b for problem b.
+ *   rank        requested pivoted-Cholesky rank; problem b uses min(rank, n_b).
+ *   ws_dev      256-byte aligned device workspace of at least
+ *               gp_batch_workspace_size bytes, owned by the caller.
+ *   logp_dev    device FP64[batch] output.
+ *   stats       NULL, or statistics filled after a stream synchronisation.
+ * The call copies its small problem tables (sizes, offsets, hyperparameters,
+ * work items) from the host into the workspace and waits for that copy once.
+ * Deferred errors (GP_ENOTSPD in any problem) are reported only when stats is
+ * non-NULL.  Errors as gp_batch_workspace_size, plus GP_EINVAL for null
+ * pointers or theta <= 0 / NaN, GP_EWORKSPACE, GP_EHIP.
+ */
+int gp_batch_mll_eval(const gp_batch* batch, const double* theta_host, const gp_options* opt, int32_t rank,
+                      void* ws_dev, size_t ws_bytes, hipStream_t stream, double* logp_dev, gp_batch_stats* stats);
+
+/*
+ * gp_batch_mll_grad — as gp_batch_mll_eval, plus the gradient of every
+ * problem's estimate with respect to its natural theta (Algorithm 2 with the
+ * solves reused, as gp_mll_grad) into grad_dev: device FP64[batch x (p + 2)],
+ * row b for problem b.  The kernel-derivative sweep runs in FP64.
+ */
+int gp_batch_mll_grad(const gp_batch* batch, const double* theta_host, const gp_options* opt, int32_t rank,
+                      void* ws_dev, size_t ws_bytes, hipStream_t stream, double* logp_dev, double* grad_dev,
+                      gp_batch_stats* stats);
+
 /* gp_strerror — static text for a gp_status. */
 const char* gp_strerror(int status);
 

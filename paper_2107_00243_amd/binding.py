@@ -21,9 +21,11 @@ PRECISIONS = {"fp64": 0, "fp32": 1, "bf16x3": 2, "fp16x3": 3}
 FLAG_NOT_CONVERGED, FLAG_RANK_DEFICIENT, FLAG_RITZ_CLAMPED = 1, 2, 4
 MAX_D, MAX_PROBES, MAX_RANK = 32, 255, 1024
 
+BATCH_MAX_RANK, BATCH_MAX_PROBES = 256, 64
+
 EXPORTS = ("gp_workspace_size", "gp_precond_build", "gp_precond_view_of", "gp_precond_free",
-           "gp_mll_eval", "gp_mll_grad", "gp_khat_matvec", "gp_khat_profile", "gp_strerror",
-           "gp_last_hip_error")
+           "gp_mll_eval", "gp_mll_grad", "gp_khat_matvec", "gp_khat_profile", "gp_batch_workspace_size",
+           "gp_batch_mll_eval", "gp_batch_mll_grad", "gp_strerror", "gp_last_hip_error")
 
 
 class gp_problem(ctypes.Structure):
@@ -50,6 +52,18 @@ class gp_stats(ctypes.Structure):
 class gp_precond_view(ctypes.Structure):
     _fields_ = [("L_dev", ctypes.c_void_p), ("pivots_dev", ctypes.c_void_p), ("logdet_dev", ctypes.c_void_p),
                 ("n", ctypes.c_int64), ("rank", ctypes.c_int32)]
+
+
+class gp_batch(ctypes.Structure):
+    _fields_ = [("X_dev", ctypes.c_void_p), ("y_dev", ctypes.c_void_p),
+                ("offsets_host", ctypes.POINTER(ctypes.c_int64)), ("batch", ctypes.c_int32), ("d", ctypes.c_int32),
+                ("kernel", ctypes.c_int32), ("ard", ctypes.c_int32)]
+
+
+class gp_batch_stats(ctypes.Structure):
+    _fields_ = [("iters_max", ctypes.c_int32), ("flags_any", ctypes.c_int32),
+                ("iters_host", ctypes.POINTER(ctypes.c_int32)), ("flags_host", ctypes.POINTER(ctypes.c_int32)),
+                ("rank_host", ctypes.POINTER(ctypes.c_int32))]
 
 
 class GPError(RuntimeError):
@@ -83,11 +97,16 @@ def load(path: str = LIB_PATH):
     lib.gp_khat_matvec.argtypes = [P, dp, i32, vp, i32, vp, vp, ctypes.c_size_t, vp]
     lib.gp_khat_profile.argtypes = [P, dp, O, i32, vp, ctypes.c_size_t, vp, dp, ctypes.POINTER(ctypes.c_int64),
                                     ctypes.POINTER(ctypes.c_int64)]
+    BP, BS = ctypes.POINTER(gp_batch), ctypes.POINTER(gp_batch_stats)
+    lib.gp_batch_workspace_size.argtypes = [BP, O, i32, szp]
+    lib.gp_batch_mll_eval.argtypes = [BP, dp, O, i32, vp, ctypes.c_size_t, vp, vp, BS]
+    lib.gp_batch_mll_grad.argtypes = [BP, dp, O, i32, vp, ctypes.c_size_t, vp, vp, vp, BS]
     lib.gp_strerror.argtypes = [ctypes.c_int]
     lib.gp_strerror.restype = ctypes.c_char_p
     lib.gp_last_hip_error.argtypes = []
     for name in ("gp_workspace_size", "gp_precond_build", "gp_precond_view_of", "gp_mll_eval", "gp_mll_grad",
-                 "gp_khat_matvec", "gp_khat_profile", "gp_last_hip_error"):
+                 "gp_khat_matvec", "gp_khat_profile", "gp_batch_workspace_size", "gp_batch_mll_eval",
+                 "gp_batch_mll_grad", "gp_last_hip_error"):
         getattr(lib, name).restype = ctypes.c_int
     del u64
     _lib = lib
@@ -218,3 +237,66 @@ def gp_khat_profile(prob, theta, opt, reps, ws, stream=None):
                                   ws.numel(), _stream(stream), ctypes.byref(ms), ctypes.byref(gx), ctypes.byref(gy)),
            "gp_khat_profile")
     return ms.value, (gx.value, gy.value)
+
+
+class Batch:
+    """A ragged batch: device X (sum n_b x d) and y, host offsets, and the C struct
+    that points at them (the object keeps the offsets array alive)."""
+
+    def __init__(self, X, y, sizes, kernel: str, ard: bool):
+        import torch
+        if X.dtype != torch.float64 or y.dtype != torch.float64 or not X.is_cuda or not y.is_cuda:
+            raise ValueError("X and y must be FP64 CUDA tensors")
+        if not X.is_contiguous() or not y.is_contiguous() or X.dim() != 2 or y.shape != (X.shape[0],):
+            raise ValueError("X must be a contiguous (N, d) tensor and y a contiguous (N,) tensor")
+        self.offsets = np.concatenate([[0], np.cumsum(np.asarray(sizes, dtype=np.int64))]).astype(np.int64)
+        if self.offsets[-1] != X.shape[0]:
+            raise ValueError("the sizes must add up to the rows of X")
+        self.X, self.y = X, y
+        self.raw = gp_batch(X.data_ptr(), y.data_ptr(), self.offsets.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                            len(sizes), X.shape[1], KERNELS[kernel], 1 if ard else 0)
+
+    @property
+    def batch(self) -> int:
+        return int(self.raw.batch)
+
+
+class BatchStats:
+    """Host copy of gp_batch_stats with its per-problem arrays."""
+
+    def __init__(self, batch: int):
+        self.iters = np.zeros(batch, dtype=np.int32)
+        self.flags = np.zeros(batch, dtype=np.int32)
+        self.rank = np.zeros(batch, dtype=np.int32)
+        self.raw = gp_batch_stats()
+        self.raw.iters_host = self.iters.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+        self.raw.flags_host = self.flags.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+        self.raw.rank_host = self.rank.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+
+    def __getattr__(self, name):
+        return getattr(self.__dict__["raw"], name)
+
+
+def gp_batch_workspace_size(batch: Batch, opt: gp_options, rank: int) -> int:
+    out = ctypes.c_size_t(0)
+    _check(load().gp_batch_workspace_size(ctypes.byref(batch.raw), ctypes.byref(opt), rank, ctypes.byref(out)),
+           "gp_batch_workspace_size")
+    return int(out.value)
+
+
+def gp_batch_mll_eval(batch: Batch, theta, opt, rank, ws, logp, stats: BatchStats | None = None, stream=None):
+    """theta: (batch, p + 2) natural hyperparameters; logp: device FP64[batch]."""
+    arr, tp = _theta(np.asarray(theta, dtype=np.float64).reshape(-1))
+    _check(load().gp_batch_mll_eval(ctypes.byref(batch.raw), tp, ctypes.byref(opt), rank,
+                                    ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream(stream),
+                                    ctypes.c_void_p(logp.data_ptr()),
+                                    ctypes.byref(stats.raw) if stats is not None else None), "gp_batch_mll_eval")
+
+
+def gp_batch_mll_grad(batch: Batch, theta, opt, rank, ws, logp, grad, stats: BatchStats | None = None, stream=None):
+    """As gp_batch_mll_eval, plus grad: device FP64[batch x (p + 2)]."""
+    arr, tp = _theta(np.asarray(theta, dtype=np.float64).reshape(-1))
+    _check(load().gp_batch_mll_grad(ctypes.byref(batch.raw), tp, ctypes.byref(opt), rank,
+                                    ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream(stream),
+                                    ctypes.c_void_p(logp.data_ptr()), ctypes.c_void_p(grad.data_ptr()),
+                                    ctypes.byref(stats.raw) if stats is not None else None), "gp_batch_mll_grad")

@@ -184,6 +184,9 @@ static int check_device() {
   return ok[dev] == 1 ? GP_OK : GP_EUNSUPPORTED;
 }
 
+int gpmll::gpmll_check_device() { return check_device(); }
+void gpmll::gpmll_set_hip_error(int e) { g_last_hip = e; }
+
 static int check_problem(const gp_problem* prob) {
   if (!prob || !prob->X_dev || !prob->y_dev) return GP_EINVAL;
   if (prob->n < 1 || prob->d < 1 || prob->d > GP_MAX_D) return GP_EINVAL;

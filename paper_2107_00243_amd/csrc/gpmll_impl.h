@@ -25,6 +25,12 @@ constexpr int kRedBlock = 256;      // threads of the reduction kernels
 constexpr int kChunkRows = 2048;    // rows per partial of the Gram reduction L^T L
 constexpr int kLtrRows = 256;       // rows per partial of L^T R (many workgroups in flight)
 
+// Row groups of 16 rows per wave of the FP32 / FP64 tile kernels for NTT
+// 16-column tiles of right-hand sides; a workgroup covers 64 * RG rows.
+constexpr __host__ __device__ int fp_row_groups(size_t elem_bytes, int ntt) {
+  return elem_bytes == 8 ? (ntt <= 4 ? 2 : 1) : (ntt <= 5 ? 4 : (ntt <= 8 ? 2 : 1));
+}
+
 // Hyperparameters as the kernels consume them.
 struct Hyper {
   int kind;      // gp_kernel
@@ -118,5 +124,25 @@ hipError_t launch_pivchol(const Ctx& c, const Hyper& h);
 hipError_t launch_precond_finish(const Ctx& c, const Hyper& h);
 hipError_t launch_probes(const Ctx& c, const double* y, const Hyper& h, uint64_t seed);
 hipError_t launch_cg_init(const Ctx& c, const Hyper& h);
+
+// GP_OK when the current device is gfx950 (cached per device); records the HIP
+// error behind a GP_EHIP for gp_last_hip_error.
+int gpmll_check_device();
+void gpmll_set_hip_error(int e);
+
+// Staging and tile launches shared with the batched path (the layout view there
+// describes the concatenation of all problems' padded row blocks).
+hipError_t launch_stage_x(const Ctx& c, const Hyper& h);
+hipError_t launch_stage_v(const Ctx& c, const double* V, int ldv, int ncols, const Hyper& h);
+// FP32 / FP64 tiles over a table of int4 {first row, column begin, column end,
+// output slot}; kernel values carry outputscale 1 (the caller scales).  With a
+// gate, item i is skipped while gate_count[gate[i]] == 0.
+struct ItemTable {
+  const int4* items = nullptr;
+  int nitems = 0;
+  const int* gate = nullptr;
+  const int* gate_count = nullptr;
+};
+hipError_t launch_khat_tiles_items(const Ctx& c, const Hyper& h, const ItemTable& it, const int* nact);
 
 }  // namespace gpmll

@@ -21,6 +21,7 @@
 //     and for sigma^2: -1/2 ((n - k)/sigma^2 + tr C^-1) + 1/(2 ell) sum_i |c_i|^2
 //     (trace of P_hat^-1 dP_hat by the matrix inversion lemma, supplement S3.3).
 #include "gpmll_impl.h"
+#include "small_dense.h"
 
 namespace gpmll {
 
@@ -527,59 +528,11 @@ __global__ __launch_bounds__(256, 2) void k_bwd_bf16(const u32x4* __restrict__ x
 // Preconditioner derivative terms
 // ---------------------------------------------------------------------------
 
-// small k x k algebra in one workgroup: LS = L[piv, :kp], LSinv, Gk = C^-1 LSinv,
-// H = LSinv^T (I - sigma^2 C^-1) LSinv, U = LSinv^T (L^T C_mat), Psi = H/2 - U U^T/(2 ell)
 __global__ void k_pg_small(const double* __restrict__ L, const int32_t* __restrict__ piv, const int* __restrict__ kpp,
                            int64_t n, int k, const double* __restrict__ Cinv, const double* __restrict__ ltrc, int tp,
                            int ell, double s2, double* __restrict__ LSinv, double* __restrict__ Gk,
                            double* __restrict__ Psi, double* __restrict__ U, double* __restrict__ tmp) {
-  const int kp = *kpp;
-  // LS (row a = pivot a, column b) into tmp, lower triangular
-  for (int e = threadIdx.x; e < kp * kp; e += blockDim.x) {
-    const int a0 = e / kp, b0 = e % kp;
-    tmp[a0 * k + b0] = (b0 <= a0) ? L[(int64_t)b0 * n + piv[a0]] : 0.0;
-  }
-  __syncthreads();
-  for (int c = threadIdx.x; c < kp; c += blockDim.x) {
-    for (int i = 0; i < kp; ++i) {
-      double acc = (i == c) ? 1.0 : 0.0;
-      for (int l = c; l < i; ++l) acc -= tmp[i * k + l] * LSinv[l * k + c];
-      LSinv[i * k + c] = (i < c) ? 0.0 : acc / tmp[i * k + i];
-    }
-  }
-  __syncthreads();
-  // Gk[r][q] = sum_m Cinv[r][m] LSinv[m][q]
-  for (int e = threadIdx.x; e < kp * kp; e += blockDim.x) {
-    const int r = e / kp, q = e % kp;
-    double s = 0.0;
-    for (int m = q; m < kp; ++m) s += Cinv[r * k + m] * LSinv[m * k + q];
-    Gk[r * k + q] = s;
-  }
-  // tmp[m][q] = sum_r (I - s2 Cinv)[m][r] LSinv[r][q]
-  __syncthreads();
-  for (int e = threadIdx.x; e < kp * kp; e += blockDim.x) {
-    const int m = e / kp, q = e % kp;
-    double s = 0.0;
-    for (int r = q; r < kp; ++r) s += ((m == r ? 1.0 : 0.0) - s2 * Cinv[m * k + r]) * LSinv[r * k + q];
-    tmp[m * k + q] = s;
-  }
-  // U[q][i] = sum_m LSinv[m][q] ltrc[m][1 + i]
-  for (int e = threadIdx.x; e < kp * ell; e += blockDim.x) {
-    const int q = e / ell, i = e % ell;
-    double s = 0.0;
-    for (int m = q; m < kp; ++m) s += LSinv[m * k + q] * ltrc[m * tp + 1 + i];
-    U[q * tp + i] = s;
-  }
-  __syncthreads();
-  // Psi[q][r] = 1/2 sum_m LSinv[m][q] tmp[m][r] - 1/(2 ell) sum_i U[q][i] U[r][i]
-  for (int e = threadIdx.x; e < kp * kp; e += blockDim.x) {
-    const int q = e / kp, r = e % kp;
-    double h = 0.0;
-    for (int m = q; m < kp; ++m) h += LSinv[m * k + q] * tmp[m * k + r];
-    double uu = 0.0;
-    for (int i = 0; i < ell; ++i) uu += U[q * tp + i] * U[r * tp + i];
-    Psi[q * k + r] = 0.5 * h - uu / (2.0 * ell);
-  }
+  pg_small_body(L, piv, kpp, n, k, Cinv, ltrc, tp, ell, s2, LSinv, Gk, Psi, U, tmp);
 }
 
 // Generic FP64 tile product C(i, j) = alpha * sum_m A(i, m) B(m, j) + beta * C(i, j)

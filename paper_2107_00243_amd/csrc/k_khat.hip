@@ -610,8 +610,12 @@ template <typename T, int KIND, int NK4, int NTT, int RG>
 __global__ __launch_bounds__(256, 2) void k_khat_fp(const T* __restrict__ xfa, const T* __restrict__ xfb,
                                                     const T* __restrict__ rowterm, const T* __restrict__ colterm,
                                                     const T* __restrict__ vfrag, T* __restrict__ wpart, TileArgs a,
-                                                    const int* __restrict__ nactive) {
+                                                    const int* __restrict__ nactive, const int4* __restrict__ items,
+                                                    const int* __restrict__ item_gate,
+                                                    const int* __restrict__ gate_count) {
   if (nactive != nullptr && *nactive == 0) return;
+  // work items whose group (problem) has no active column left are skipped
+  if (item_gate != nullptr && gate_count[item_gate[blockIdx.x]] == 0) return;
   typedef typename FpMfma<T>::acc_t acc_t;
   // stage of 16 columns: A fragments NK4*64, V fragments NTT*4*64, column terms 16
   constexpr int A_E = NK4 * 64, V_E = NTT * 4 * 64, C_E = 16;
@@ -620,9 +624,22 @@ __global__ __launch_bounds__(256, 2) void k_khat_fp(const T* __restrict__ xfa, c
   __shared__ T lds[2][STAGE];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int g = lane >> 4, li = lane & 15;
-  const int64_t row0 = (int64_t)blockIdx.x * (64 * RG) + wave * (16 * RG);
-  const int64_t c_begin = (int64_t)blockIdx.y * a.cols_per_split;
-  const int64_t c_end = min(a.n_pad, c_begin + a.cols_per_split);
+  // block -> (first row, column range, output slot): the regular grid, or one
+  // entry of a work-item table (ragged batches: every item stays inside one
+  // problem's diagonal block)
+  int64_t row0, c_begin, c_end, slot;
+  if (items != nullptr) {
+    const int4 it = items[blockIdx.x];
+    row0 = (int64_t)it.x + wave * (16 * RG);
+    c_begin = it.y;
+    c_end = it.z;
+    slot = it.w;
+  } else {
+    row0 = (int64_t)blockIdx.x * (64 * RG) + wave * (16 * RG);
+    c_begin = (int64_t)blockIdx.y * a.cols_per_split;
+    c_end = min(a.n_pad, c_begin + a.cols_per_split);
+    slot = blockIdx.y;
+  }
   if (c_begin >= c_end) return;
 
   T xb[RG][NK4];
@@ -700,7 +717,7 @@ __global__ __launch_bounds__(256, 2) void k_khat_fp(const T* __restrict__ xfa, c
     __syncthreads();
     buf ^= 1;
   }
-  T* out = wpart + (int64_t)blockIdx.y * a.n_pad * a.tp;
+  T* out = wpart + slot * a.n_pad * a.tp;
 #pragma unroll
   for (int rg = 0; rg < RG; ++rg)
 #pragma unroll
@@ -718,8 +735,10 @@ __global__ __launch_bounds__(256, 2) void k_khat_fp(const T* __restrict__ xfa, c
 // ---------------------------------------------------------------------------
 
 hipError_t khat_tiles_bf16(const Ctx& c, const Hyper& h, const TileArgs& ta, const int* nact);
-hipError_t khat_tiles_fp32(const Ctx& c, const Hyper& h, const TileArgs& ta, const int* nact);
-hipError_t khat_tiles_fp64(const Ctx& c, const Hyper& h, const TileArgs& ta, const int* nact);
+hipError_t khat_tiles_fp32(const Ctx& c, const Hyper& h, const TileArgs& ta, const int* nact,
+                           const ItemTable& it = ItemTable{});
+hipError_t khat_tiles_fp64(const Ctx& c, const Hyper& h, const TileArgs& ta, const int* nact,
+                           const ItemTable& it = ItemTable{});
 
 #define GPMLL_NTT_CASES(M) M(1) M(2) M(3) M(4) M(5) M(6) M(8) M(12) M(16)
 
@@ -773,51 +792,53 @@ hipError_t khat_tiles_bf16(const Ctx& c, const Hyper& h, const TileArgs& ta, con
 #if GPMLL_KHAT_PART == 2 || GPMLL_KHAT_PART == 3
 namespace {
 template <typename T, int KIND, int NK4, int NTT>
-hipError_t run_fp(const Ctx& c, const TileArgs& ta, const int* nact) {
+hipError_t run_fp(const Ctx& c, const TileArgs& ta, const int* nact, const ItemTable& it) {
   const Layout& L = *c.lay;
-  constexpr int RG = (sizeof(T) == 8) ? (NTT <= 4 ? 2 : 1) : (NTT <= 5 ? 4 : (NTT <= 8 ? 2 : 1));
-  dim3 grid((unsigned)(L.n_pad / (64 * RG)), (unsigned)L.nsplit);
+  constexpr int RG = fp_row_groups(sizeof(T), NTT);
+  dim3 grid = it.items != nullptr ? dim3((unsigned)it.nitems)
+                                  : dim3((unsigned)(L.n_pad / (64 * RG)), (unsigned)L.nsplit);
   hipLaunchKernelGGL((k_khat_fp<T, KIND, NK4, NTT, RG>), grid, dim3(256), 0, c.st, c.at<T>(L.xfa), c.at<T>(L.xfb),
-                     c.at<T>(L.rowterm), c.at<T>(L.colterm), c.at<T>(L.vfrag), c.at<T>(L.wpart), ta, nact);
+                     c.at<T>(L.rowterm), c.at<T>(L.colterm), c.at<T>(L.vfrag), c.at<T>(L.wpart), ta, nact, it.items,
+                     it.gate, it.gate_count);
   return hipGetLastError();
 }
 template <typename T, int KIND, int NK4>
-hipError_t sel_fp_ntt(const Ctx& c, const TileArgs& ta, const int* nact, int ntt) {
+hipError_t sel_fp_ntt(const Ctx& c, const TileArgs& ta, const int* nact, int ntt, const ItemTable& it) {
   switch (ntt) {
-#define CASE(N) case N: return run_fp<T, KIND, NK4, N>(c, ta, nact);
+#define CASE(N) case N: return run_fp<T, KIND, NK4, N>(c, ta, nact, it);
     GPMLL_NTT_CASES(CASE)
 #undef CASE
   }
   return hipErrorInvalidValue;
 }
 template <typename T, int KIND>
-hipError_t sel_fp(const Ctx& c, const TileArgs& ta, const int* nact) {
+hipError_t sel_fp(const Ctx& c, const TileArgs& ta, const int* nact, const ItemTable& it) {
   const Layout& L = *c.lay;
   const int ntt = L.tp / 16;
   switch (L.kd / 4) {
-    case 1: return sel_fp_ntt<T, KIND, 1>(c, ta, nact, ntt);
-    case 2: return sel_fp_ntt<T, KIND, 2>(c, ta, nact, ntt);
-    case 4: return sel_fp_ntt<T, KIND, 4>(c, ta, nact, ntt);
-    case 8: return sel_fp_ntt<T, KIND, 8>(c, ta, nact, ntt);
+    case 1: return sel_fp_ntt<T, KIND, 1>(c, ta, nact, ntt, it);
+    case 2: return sel_fp_ntt<T, KIND, 2>(c, ta, nact, ntt, it);
+    case 4: return sel_fp_ntt<T, KIND, 4>(c, ta, nact, ntt, it);
+    case 8: return sel_fp_ntt<T, KIND, 8>(c, ta, nact, ntt, it);
   }
   return hipErrorInvalidValue;
 }
 template <typename T>
-hipError_t khat_tiles_fp(const Ctx& c, const Hyper& h, const TileArgs& ta, const int* nact) {
+hipError_t khat_tiles_fp(const Ctx& c, const Hyper& h, const TileArgs& ta, const int* nact, const ItemTable& it) {
   switch (h.kind) {
-    case GP_KERNEL_RBF: return sel_fp<T, GP_KERNEL_RBF>(c, ta, nact);
-    case GP_KERNEL_MATERN32: return sel_fp<T, GP_KERNEL_MATERN32>(c, ta, nact);
-    default: return sel_fp<T, GP_KERNEL_MATERN52>(c, ta, nact);
+    case GP_KERNEL_RBF: return sel_fp<T, GP_KERNEL_RBF>(c, ta, nact, it);
+    case GP_KERNEL_MATERN32: return sel_fp<T, GP_KERNEL_MATERN32>(c, ta, nact, it);
+    default: return sel_fp<T, GP_KERNEL_MATERN52>(c, ta, nact, it);
   }
 }
 }  // namespace
 #if GPMLL_KHAT_PART == 2
-hipError_t khat_tiles_fp32(const Ctx& c, const Hyper& h, const TileArgs& ta, const int* nact) {
-  return khat_tiles_fp<float>(c, h, ta, nact);
+hipError_t khat_tiles_fp32(const Ctx& c, const Hyper& h, const TileArgs& ta, const int* nact, const ItemTable& it) {
+  return khat_tiles_fp<float>(c, h, ta, nact, it);
 }
 #else
-hipError_t khat_tiles_fp64(const Ctx& c, const Hyper& h, const TileArgs& ta, const int* nact) {
-  return khat_tiles_fp<double>(c, h, ta, nact);
+hipError_t khat_tiles_fp64(const Ctx& c, const Hyper& h, const TileArgs& ta, const int* nact, const ItemTable& it) {
+  return khat_tiles_fp<double>(c, h, ta, nact, it);
 }
 #endif
 #endif
@@ -905,6 +926,21 @@ hipError_t launch_khat_tiles(const Ctx& c, const Hyper& h, const int* nact) {
   }
   if (L.prec == GP_PREC_FP32) return khat_tiles_fp32(c, h, ta, nact);
   return khat_tiles_fp64(c, h, ta, nact);
+}
+
+hipError_t launch_khat_tiles_items(const Ctx& c, const Hyper& h, const ItemTable& it, const int* nact) {
+  const Layout& L = *c.lay;
+  if (it.nitems == 0) return hipSuccess;
+  TileArgs ta;
+  ta.n_pad = L.n_pad;
+  ta.n_valid = L.n;
+  ta.cols_per_split = L.cols_per_split;
+  ta.tp = L.tp;
+  ta.s32 = 1.0f;
+  ta.s64 = 1.0;
+  if (L.prec == GP_PREC_FP32) return khat_tiles_fp32(c, h, ta, nact, it);
+  if (L.prec == GP_PREC_FP64) return khat_tiles_fp64(c, h, ta, nact, it);
+  return hipErrorInvalidValue;
 }
 
 hipError_t launch_khat_reduce(const Ctx& c, const double* V, int ldv, double* W, int ldw, int ncols, const Hyper& h,

@@ -7,6 +7,7 @@
 // Probes: b_i = sigma * eps_i + L * eta_i with Rademacher eps_i, eta_i drawn from a
 // SplitMix64 counter stream (Steele, Lea & Flood 2014), so that E[b b^T] = P_hat.
 #include "gpmll_impl.h"
+#include "small_dense.h"
 
 namespace gpmll {
 
@@ -221,67 +222,10 @@ __global__ void k_gram_final(const double* __restrict__ part, int nchunk, int k,
   C[e] = s + (a == b ? s2 : 0.0);
 }
 
-// Right-looking Cholesky of the k x k matrix C (row-major) by one workgroup,
-// then the lower-triangular inverse, C^-1 = Rinv^T Rinv and the log-determinant.
 __global__ void k_small_chol(int64_t n, int k, double s2, const double* __restrict__ C,
                              double* __restrict__ Rc, double* __restrict__ Rinv, double* __restrict__ Cinv,
                              double* __restrict__ logdetP, int* __restrict__ status) {
-  __shared__ int bad;
-  __shared__ double red[1024];
-  if (threadIdx.x == 0) bad = 0;
-  for (int e = threadIdx.x; e < k * k; e += blockDim.x) Rc[e] = C[e];
-  __syncthreads();
-  for (int j = 0; j < k; ++j) {
-    if (threadIdx.x == 0) {
-      double v = Rc[j * k + j];
-      if (!(v > 0.0)) {
-        bad = 1;
-        v = 1.0;
-      }
-      Rc[j * k + j] = sqrt(v);
-    }
-    __syncthreads();
-    const double piv = Rc[j * k + j];
-    for (int i = j + 1 + threadIdx.x; i < k; i += blockDim.x) Rc[i * k + j] /= piv;
-    __syncthreads();
-    const int m = k - j - 1;
-    for (int e = threadIdx.x; e < m * m; e += blockDim.x) {
-      int i = j + 1 + e / m, l = j + 1 + e % m;
-      if (l <= i) Rc[i * k + l] -= Rc[i * k + j] * Rc[l * k + j];
-    }
-    __syncthreads();
-  }
-  for (int e = threadIdx.x; e < k * k; e += blockDim.x) {
-    int i = e / k, l = e % k;
-    if (l > i) Rc[e] = 0.0;
-  }
-  __syncthreads();
-  // Rinv column c: solve Rc x = e_c by forward substitution (one thread per column)
-  for (int c = threadIdx.x; c < k; c += blockDim.x) {
-    for (int i = 0; i < k; ++i) {
-      double acc = (i == c) ? 1.0 : 0.0;
-      for (int l = c; l < i; ++l) acc -= Rc[i * k + l] * Rinv[l * k + c];
-      Rinv[i * k + c] = (i < c) ? 0.0 : acc / Rc[i * k + i];
-    }
-  }
-  __syncthreads();
-  for (int e = threadIdx.x; e < k * k; e += blockDim.x) {
-    int a = e / k, b = e % k;
-    int lo = a > b ? a : b;
-    double s = 0.0;
-    for (int l = lo; l < k; ++l) s += Rinv[l * k + a] * Rinv[l * k + b];
-    Cinv[e] = s;
-  }
-  double acc = 0.0;
-  for (int j = threadIdx.x; j < k; j += blockDim.x) acc += log(Rc[j * k + j]);
-  red[threadIdx.x] = acc;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    double s = 0.0;
-    for (int q = 0; q < (int)blockDim.x; ++q) s += red[q];
-    *logdetP = (double)(n - k) * log(s2) + 2.0 * s;
-    if (bad) *status = GP_ENOTSPD;
-  }
+  small_chol_body(n, k, s2, C, Rc, Rinv, Cinv, logdetP, status);
 }
 
 __global__ void k_logdet_noprecond(int64_t n, double s2, double* logdetP) {
@@ -291,19 +235,6 @@ __global__ void k_logdet_noprecond(int64_t n, double s2, double* logdetP) {
 // ---------------------------------------------------------------------------
 // Probes
 // ---------------------------------------------------------------------------
-
-__device__ inline uint64_t splitmix64(uint64_t seed, uint64_t ctr) {
-  uint64_t z = seed + (ctr + 1ull) * 0x9E3779B97F4A7C15ull;
-  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
-  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
-  return z ^ (z >> 31);
-}
-
-// sign +1 when the top bit of output (stream << 56 | col << 32 | idx) is clear
-__device__ inline double rademacher(uint64_t seed, uint64_t stream, uint64_t col, uint64_t idx) {
-  uint64_t v = splitmix64(seed, (stream << 56) | (col << 32) | idx);
-  return (v >> 63) ? -1.0 : 1.0;
-}
 
 __global__ void k_eta(uint64_t seed, int k, int ell, double* __restrict__ H) {
   const int e = blockIdx.x * blockDim.x + threadIdx.x;

@@ -12,52 +12,9 @@
 // deflation of negligible off-diagonals; only the first row of the accumulated
 // rotation product is kept (Golub & Welsch 1969).  One thread per probe.
 #include "gpmll_impl.h"
+#include "small_dense.h"
 
 namespace gpmll {
-
-__device__ void tridiag_eig_first_row(double* a, double* b, double* z, int m) {
-  const double eps = 2.220446049250313e-16;
-  for (int i = 0; i < m; ++i) z[i] = (i == 0) ? 1.0 : 0.0;
-  int hi = m - 1;
-  int sweeps = 0;
-  while (hi > 0 && sweeps < 60 * m) {
-    if (fabs(b[hi - 1]) <= eps * (fabs(a[hi - 1]) + fabs(a[hi]))) {
-      b[hi - 1] = 0.0;
-      --hi;
-      continue;
-    }
-    int lo = hi - 1;
-    while (lo > 0 && fabs(b[lo - 1]) > eps * (fabs(a[lo - 1]) + fabs(a[lo]))) --lo;
-    if (lo > 0) b[lo - 1] = 0.0;
-    // Wilkinson shift: eigenvalue of the trailing 2 x 2 closer to a[hi]
-    const double dl = 0.5 * (a[hi - 1] - a[hi]);
-    const double bb = b[hi - 1];
-    const double den = dl + copysign(hypot(dl, bb), dl == 0.0 ? 1.0 : dl);
-    const double mu = a[hi] - bb * bb / den;
-    double x = a[lo] - mu, y = b[lo];
-    for (int k = lo; k < hi; ++k) {
-      const double r = hypot(x, y);
-      const double cs = (r == 0.0) ? 1.0 : x / r;
-      const double sn = (r == 0.0) ? 0.0 : y / r;
-      if (k > lo) b[k - 1] = r;
-      const double ak = a[k], ak1 = a[k + 1], bk = b[k];
-      a[k] = cs * cs * ak + 2.0 * cs * sn * bk + sn * sn * ak1;
-      a[k + 1] = sn * sn * ak - 2.0 * cs * sn * bk + cs * cs * ak1;
-      b[k] = cs * sn * (ak1 - ak) + (cs * cs - sn * sn) * bk;
-      double bulge = 0.0;
-      if (k + 1 < hi) {
-        bulge = sn * b[k + 1];
-        b[k + 1] = cs * b[k + 1];
-      }
-      const double zk = z[k], zk1 = z[k + 1];
-      z[k] = cs * zk + sn * zk1;
-      z[k + 1] = -sn * zk + cs * zk1;
-      x = b[k];
-      y = bulge;
-    }
-    ++sweeps;
-  }
-}
 
 // one workgroup per probe column c = 1 + blockIdx.x; the eigen-solve runs on one
 // lane with the tridiagonal in LDS (3 * max_iters doubles of dynamic shared memory)

@@ -52,6 +52,10 @@ int main(void) {
   printf("gp_options %zu\n", sizeof(gp_options));
   printf("gp_stats %zu\n", sizeof(gp_stats));
   printf("gp_precond_view %zu\n", sizeof(gp_precond_view));
+  printf("gp_batch %zu\n", sizeof(gp_batch));
+  printf("gp_batch_stats %zu\n", sizeof(gp_batch_stats));
+  P(gp_batch, offsets_host); P(gp_batch, batch); P(gp_batch, ard);
+  P(gp_batch_stats, flags_any); P(gp_batch_stats, iters_host); P(gp_batch_stats, rank_host);
   P(gp_problem, n); P(gp_problem, d); P(gp_problem, ard);
   P(gp_options, cg_tol); P(gp_options, seed); P(gp_options, precond_grad); P(gp_options, sync_every);
   P(gp_stats, logdet_precond); P(gp_stats, logdet_estimate); P(gp_stats, col_iters_host); P(gp_stats, pivots_host);
@@ -66,7 +70,7 @@ int main(void) {
     got = dict(l.rsplit(" ", 1) for l in subprocess.run([str(exe)], stdout=subprocess.PIPE,
                                                          text=True).stdout.splitlines())
     types = {"gp_problem": B.gp_problem, "gp_options": B.gp_options, "gp_stats": B.gp_stats,
-             "gp_precond_view": B.gp_precond_view}
+             "gp_precond_view": B.gp_precond_view, "gp_batch": B.gp_batch, "gp_batch_stats": B.gp_batch_stats}
     for key, val in got.items():
         if "." in key:
             t, f = key.split(".")
@@ -157,3 +161,75 @@ def test_strerror_covers_every_status(lib):
 
 def test_precond_free_accepts_null(lib):
     lib.gp_precond_free(None)
+
+
+# ---------------------------------------------------------------- batched entry points
+
+def _fake_batch(sizes=(10, 20, 5), d=3, kernel=0, ard=1):
+    offs = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    b = B.gp_batch(0x1000, 0x2000, offs.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), len(sizes), d, kernel, ard)
+    return b, offs
+
+
+def test_batch_workspace_size_grows_with_the_problems(lib):
+    o = B.make_options("fp32", 16, 200)
+    b1, k1 = _fake_batch((500, 800))
+    b2, k2 = _fake_batch((500, 800, 3000))
+    s1, s2 = ctypes.c_size_t(0), ctypes.c_size_t(0)
+    assert lib.gp_batch_workspace_size(ctypes.byref(b1), ctypes.byref(o), 20, ctypes.byref(s1)) == B.GP_OK
+    assert lib.gp_batch_workspace_size(ctypes.byref(b2), ctypes.byref(o), 20, ctypes.byref(s2)) == B.GP_OK
+    assert 0 < s1.value < s2.value
+
+
+@pytest.mark.parametrize("case", ["zero_size", "bad_first", "decreasing", "batch0", "d0", "d33", "kernel", "ard",
+                                  "rank_neg"])
+def test_batch_rejects_bad_shapes(lib, case):
+    sizes = (10, 20, 5)
+    b, offs = _fake_batch(sizes)
+    o = B.make_options("fp64", 4, 10)
+    rank = 2
+    if case == "zero_size":
+        offs[2] = offs[1]
+    elif case == "bad_first":
+        offs[0] = 1
+    elif case == "decreasing":
+        offs[2] = offs[1] - 1
+    elif case == "batch0":
+        b.batch = 0
+    elif case == "d0":
+        b.d = 0
+    elif case == "d33":
+        b.d = 33
+    elif case == "kernel":
+        b.kernel = 3
+    elif case == "ard":
+        b.ard = 2
+    elif case == "rank_neg":
+        rank = -1
+    out = ctypes.c_size_t(0)
+    assert lib.gp_batch_workspace_size(ctypes.byref(b), ctypes.byref(o), rank, ctypes.byref(out)) == B.GP_EINVAL
+    theta = np.tile([0.5, 0.5, 0.5, 1.0, 0.1], 3)
+    tp = theta.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    assert lib.gp_batch_mll_eval(ctypes.byref(b), tp, ctypes.byref(o), rank, ctypes.c_void_p(0x10000), 1 << 30, None,
+                                 ctypes.c_void_p(0x3000), None) == B.GP_EINVAL
+
+
+@pytest.mark.parametrize("prec,probes,rank", [("bf16x3", 8, 4), ("fp16x3", 8, 4), ("fp32", 65, 4), ("fp32", 8, 257)])
+def test_batch_reports_unsupported_options(lib, prec, probes, rank):
+    b, offs = _fake_batch((300, 400))
+    o = B.make_options(prec, probes, 10)
+    out = ctypes.c_size_t(0)
+    assert lib.gp_batch_workspace_size(ctypes.byref(b), ctypes.byref(o), rank, ctypes.byref(out)) == B.GP_EUNSUPPORTED
+
+
+@pytest.mark.parametrize("bad", [0.0, -1.0, float("nan")])
+def test_batch_rejects_bad_theta_of_any_problem(lib, bad):
+    b, offs = _fake_batch((10, 20, 5))
+    o = B.make_options("fp64", 4, 10)
+    theta = np.tile([0.5, 0.5, 0.5, 1.0, 0.1], 3)
+    theta[2 * 5 + 4] = bad   # noise of the last problem
+    tp = theta.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    assert lib.gp_batch_mll_grad(ctypes.byref(b), tp, ctypes.byref(o), 2, ctypes.c_void_p(0x10000), 1 << 30, None,
+                                 ctypes.c_void_p(0x3000), ctypes.c_void_p(0x4000), None) == B.GP_EINVAL
+    assert lib.gp_batch_mll_grad(ctypes.byref(b), tp, ctypes.byref(o), 2, ctypes.c_void_p(0x10000), 1 << 30, None,
+                                 ctypes.c_void_p(0x3000), None, None) == B.GP_EINVAL

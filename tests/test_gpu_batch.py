@@ -1,0 +1,174 @@
+"""Ragged batches through the C-ABI (gp_batch_mll_eval / gp_batch_mll_grad):
+every problem of a batch against the CPU oracle on the same seeded inputs
+(problem b draws its probes from seed + b and uses rank min(rank, n_b)), and
+against the single-problem entry point on the same GPU."""
+import sys
+
+import numpy as np
+import pytest
+
+import synthgp
+from oracle import gp_oracle as go
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from paper_2107_00243_amd import binding as B  # noqa: E402
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    if not torch.cuda.is_available():
+        pytest.fail("no GPU visible")
+    B.load()
+    return torch.device("cuda:0")
+
+
+# the parity bar for split- and single-precision tiles (relative, log p and gradient)
+FP32_LP, FP32_G = 1e-3, 1e-2
+
+
+def rel(a, b):
+    return abs(a - b) / max(abs(b), 1e-300)
+
+
+def relvec(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / max(np.linalg.norm(b), 1e-300))
+
+
+def make_batch(problems):
+    dev = torch.device("cuda:0")
+    X = torch.tensor(np.concatenate([p.X for p in problems]), device=dev)
+    y = torch.tensor(np.concatenate([p.y for p in problems]), device=dev)
+    return B.Batch(X, y, [p.n for p in problems], problems[0].kernel, problems[0].ard)
+
+
+def run_batch(problems, precision, rank, num_probes, tol, max_iters, seed=1, grad=True, precond_grad=0,
+              sync_every=1, stats=True):
+    say(f"[gpu] batch of {len(problems)} sizes {[p.n for p in problems][:8]}... {problems[0].kernel} "
+        f"ard={problems[0].ard} prec={precision} k={rank} ell={num_probes} grad={grad}")
+    bt = make_batch(problems)
+    opt = B.make_options(precision, num_probes, max_iters, tol, seed, precond_grad, sync_every)
+    ws = B.alloc_workspace(B.gp_batch_workspace_size(bt, opt, rank))
+    nb = len(problems)
+    P = len(problems[0].theta)
+    theta = np.stack([p.theta for p in problems])
+    logp = torch.zeros(nb, dtype=torch.float64, device="cuda")
+    g = torch.zeros(nb * P, dtype=torch.float64, device="cuda")
+    st = B.BatchStats(nb) if stats else None
+    if grad:
+        B.gp_batch_mll_grad(bt, theta, opt, rank, ws, logp, g, st)
+    else:
+        B.gp_batch_mll_eval(bt, theta, opt, rank, ws, logp, st)
+    torch.cuda.synchronize()
+    return logp.cpu().numpy(), g.cpu().numpy().reshape(nb, P), st
+
+
+def ragged(sizes, d, kernel, ard, seed0=0, **kw):
+    out = []
+    for b, n in enumerate(sizes):
+        pr = synthgp.random_problem(n, d, kernel, ard, seed=seed0 + b, **kw)
+        out.append(pr)
+    return out
+
+
+@pytest.mark.parametrize("kernel,ard", [("rbf", False), ("matern52", True), ("matern32", True)])
+def test_ragged_fp64_batch_matches_the_oracle_per_problem(kernel, ard):
+    probs = ragged([1, 17, 300, 700, 257], 3, kernel, ard)
+    rank, ell, tol, mi = 8, 8, 1e-8, 300
+    lp, g, st = run_batch(probs, "fp64", rank, ell, tol, mi)
+    for b, pr in enumerate(probs):
+        ref = go.estimate_mll(pr.X, pr.y, pr.theta, kernel, ard, min(rank, pr.n), ell, tol, mi, 1 + b)
+        assert rel(lp[b], ref["logp"]) < 1e-7, (b, lp[b], ref["logp"])
+        assert relvec(g[b], ref["grad"]) < 1e-5, (b, g[b], ref["grad"])
+        assert st.rank[b] == min(rank, pr.n)
+    assert st.flags_any == 0
+
+
+def test_batch_equals_the_single_problem_path():
+    # converged far below the point where one CG step more or less in either
+    # path would show
+    probs = ragged([513, 64, 1000], 4, "rbf", True, seed0=10)
+    rank, ell, tol, mi = 12, 16, 1e-11, 600
+    lp, g, st = run_batch(probs, "fp64", rank, ell, tol, mi, seed=7)
+    dev = torch.device("cuda:0")
+    for b, pr in enumerate(probs):
+        X = torch.tensor(pr.X, device=dev)
+        y = torch.tensor(pr.y, device=dev)
+        prob = B.make_problem(X, y, pr.kernel, pr.ard)
+        opt = B.make_options("fp64", ell, mi, tol, 7 + b, 0, 1)
+        ws = B.alloc_workspace(B.gp_workspace_size(prob, opt, rank))
+        l1 = torch.zeros(1, dtype=torch.float64, device=dev)
+        g1 = torch.zeros(len(pr.theta), dtype=torch.float64, device=dev)
+        B.gp_mll_grad(prob, pr.theta, opt, rank, None, ws, l1, g1)
+        torch.cuda.synchronize()
+        # the same arithmetic in a different reduction order: FP64 rounding only
+        assert rel(lp[b], float(l1.cpu()[0])) < 1e-8, (b, lp[b], float(l1.cpu()[0]))
+        assert relvec(g[b], g1.cpu().numpy()) < 1e-6, (b, g[b], g1.cpu().numpy())
+
+
+def test_fp32_batch_of_the_batched_recipe_at_reduced_sizes():
+    # the 64-problem recipe (n ~ U{500..8000}, d 4, RBF iso, rank 20, 16 probes),
+    # first 6 problems cut to at most 1200 points
+    full = synthgp.batched_rbf_64()
+    probs = []
+    for pr in full[:6]:
+        m = min(pr.n, 1200)
+        probs.append(synthgp.GPProblem(pr.name, pr.X[:m].copy(), pr.y[:m].copy(), pr.theta, pr.kernel, pr.ard,
+                                       pr.rank, pr.num_probes, pr.tol, pr.max_iters, "fp32"))
+    lp, g, st = run_batch(probs, "fp32", 20, 16, 1e-6, 2500)
+    for b, pr in enumerate(probs):
+        ref = go.estimate_mll(pr.X, pr.y, pr.theta, "rbf", False, 20, 16, 1e-6, 2500, 1 + b)
+        # FP32 tile rounding, amplified by cond(K_hat) ~ n s / sigma^2 (up to ~1e6 here)
+        assert rel(lp[b], ref["logp"]) < FP32_LP, (b, lp[b], ref["logp"])
+        assert relvec(g[b], ref["grad"]) < FP32_G, (b, g[b], ref["grad"])
+
+
+def test_full_64_problem_batch_against_oracle_samples():
+    # the 64-problem recipe with its FP64 tiles; oracle on the two smallest problems
+    probs = synthgp.batched_rbf_64()
+    lp64, g64, st = run_batch(probs, "fp64", 20, 16, 1e-6, 2500)
+    assert st.flags_any & B.FLAG_NOT_CONVERGED == 0
+    assert np.all(st.rank == 20)
+    for b in np.argsort([p.n for p in probs])[:2]:
+        pr = probs[b]
+        say(f"[gpu] oracle for problem {b} n={pr.n}")
+        ref = go.estimate_mll(pr.X, pr.y, pr.theta, "rbf", False, 20, 16, 1e-6, 2500, 1 + int(b))
+        # same arithmetic; CG stops at 1e-6 on problems with cond(K_hat) up to ~1e6
+        assert rel(lp64[b], ref["logp"]) < 1e-6, (b, lp64[b], ref["logp"])
+        assert relvec(g64[b], ref["grad"]) < 1e-4, (b, g64[b], ref["grad"])
+    # FP32 tiles on the same batch: log p of every problem within the bar (the
+    # noise gradient of the worst-conditioned problems is not: FP32 rounding of
+    # K_hat entries is a visible fraction of sigma^2 ~ 2e-3 at n ~ 7000)
+    lp32, g32, st32 = run_batch(probs, "fp32", 20, 16, 1e-6, 2500)
+    assert st32.flags_any & B.FLAG_NOT_CONVERGED == 0
+    for b in range(len(probs)):
+        assert rel(lp32[b], lp64[b]) < FP32_LP, (b, lp32[b], lp64[b])
+
+
+def test_batch_precond_grad_mode_one_and_no_preconditioner():
+    probs = ragged([200, 333], 2, "matern32", True, seed0=20)
+    for rank, mode in ((6, 1), (0, 0)):
+        lp, g, st = run_batch(probs, "fp64", rank, 8, 1e-8, 300, precond_grad=mode)
+        for b, pr in enumerate(probs):
+            ref = go.estimate_mll(pr.X, pr.y, pr.theta, "matern32", True, rank, 8, 1e-8, 300, 1 + b,
+                                  precond_grad=mode)
+            assert rel(lp[b], ref["logp"]) < 1e-7
+            assert relvec(g[b], ref["grad"]) < 1e-5
+
+
+def test_batch_eval_without_sync_and_determinism():
+    probs = ragged([300, 900, 45], 3, "rbf", True, seed0=30)
+    a, _, _ = run_batch(probs, "fp32", 10, 8, 1e-6, 200, grad=False, sync_every=0, stats=False)
+    b, _, _ = run_batch(probs, "fp32", 10, 8, 1e-6, 200, grad=False, sync_every=1, stats=False)
+    np.testing.assert_array_equal(a, b)
+    lp1, g1, _ = run_batch(probs, "fp32", 10, 8, 1e-6, 200)
+    lp2, g2, _ = run_batch(probs, "fp32", 10, 8, 1e-6, 200)
+    np.testing.assert_array_equal(lp1, lp2)
+    np.testing.assert_array_equal(g1, g2)
+    np.testing.assert_array_equal(lp1, a)
