@@ -6,7 +6,10 @@ sweep and preconditioner terms) on the n = 100,000, d = 16 RBF-ARD workload
 (rank-100 pivoted Cholesky, 64 probes, CG tolerance 1e-6), inputs resident in
 HBM.  Prints one JSON line.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-fp64] [--no-cpu]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-fp64] [--no-cpu] [--no-batch]
+
+Besides the headline line it reports the FP16X3 and FP64 tile precisions on the same
+workload and the 64-problem ragged batch (gp_batch_mll_grad) as extra fields.
 """
 from __future__ import annotations
 
@@ -24,6 +27,27 @@ sys.path.insert(0, ROOT)
 METRIC = "log-lik+grad evals/sec at n=100k (split-prec vs FP64 GPU); K̂·V MFMA util"
 PEAK_BF16_TFLOPS = 2500.0   # MI355X dense BF16 MFMA
 PEAK_FP64_TFLOPS = 78.6
+
+
+# Counter readings of one k_khat_bf16 launch on this workload (rocprofv3 --pmc
+# FETCH_SIZE, then WRITE_SIZE, KiB per dispatch, over `bench.py --tiles-only`),
+# each scaled by what the same counter reads for a 1 GiB elementwise copy, and the
+# MFMA counters of the same launches.  They describe the kernel source whose hash
+# is given; once that source changes they are stale and are not reported.
+TILE_COUNTERS = {
+    "kernel_source_sha256_16": "74d4d05e074c0c18",
+    "fetch_kib": 333810.6, "fetch_scale": 1048576.0 / 524307.1,
+    "write_kib": 187680.0, "write_scale": 1.0,
+    "mfma_insts": 3.718e8, "mfma_busy_cycles": 5.949e9, "gui_active_per_xcd": 8.113e7 / 8,
+}
+
+
+def bf16_tile_source_hash():
+    import hashlib
+    src = open(os.path.join(ROOT, "paper_2107_00243_amd", "csrc", "k_khat.hip")).read()
+    a = src.index("#if GPMLL_KHAT_PART == 1\n")
+    b = src.index("#endif  // part 1", a)
+    return hashlib.sha256(src[a:b].encode()).hexdigest()[:16]
 
 
 def log(msg):
@@ -71,6 +95,45 @@ def run_gpu(pr, precision, steps, warmup, sync_every=1):
     del ws
     torch.cuda.empty_cache()
     return info
+
+
+def run_batched(steps, warmup):
+    """The 64-problem ragged batch (n_b ~ U{500..8000}, d 4, RBF, rank 20, 16 probes,
+    FP64 tiles): one gp_batch_mll_grad call evaluates log p and the gradient of all
+    64 problems."""
+    import torch
+    import synthgp
+    from paper_2107_00243_amd import binding as B
+    probs = synthgp.batched_rbf_64()
+    pr0 = probs[0]
+    dev = torch.device("cuda:0")
+    X = torch.tensor(np.concatenate([p.X for p in probs]), device=dev)
+    y = torch.tensor(np.concatenate([p.y for p in probs]), device=dev)
+    bt = B.Batch(X, y, [p.n for p in probs], pr0.kernel, pr0.ard)
+    opt = B.make_options(pr0.precision, pr0.num_probes, pr0.max_iters, pr0.tol, pr0.probe_seed, 0, 1)
+    ws = B.alloc_workspace(B.gp_batch_workspace_size(bt, opt, pr0.rank))
+    theta = np.stack([p.theta for p in probs])
+    nb, P = len(probs), len(pr0.theta)
+    logp = torch.zeros(nb, dtype=torch.float64, device=dev)
+    grad = torch.zeros(nb * P, dtype=torch.float64, device=dev)
+    st = B.BatchStats(nb)
+    B.gp_batch_mll_grad(bt, theta, opt, pr0.rank, ws, logp, grad, st)
+    for _ in range(warmup):
+        B.gp_batch_mll_grad(bt, theta, opt, pr0.rank, ws, logp, grad)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        B.gp_batch_mll_grad(bt, theta, opt, pr0.rank, ws, logp, grad)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    n = np.array([p.n for p in probs], dtype=np.float64)
+    pair_iters = float(np.sum(n * n * st.iters))
+    return {"value": 1.0 / dt, "unit": "batch evals/s (64 problems, log p + gradient each)",
+            "problems_per_s": nb / dt, "ms_per_batch": 1e3 * dt, "steps": steps, "precision": pr0.precision,
+            "problems": nb, "n_min": int(n.min()), "n_max": int(n.max()), "sum_n": int(n.sum()),
+            "cg_iters_max": int(st.iters_max), "cg_iters_median": float(np.median(st.iters)),
+            "kernel_pair_evaluations_in_cg": pair_iters,
+            "flags_any": int(st.flags_any)}
 
 
 def tiles_only(pr, reps=10, copy_bytes=1 << 30):
@@ -134,6 +197,7 @@ def main():
     ap.add_argument("--fp64-steps", type=int, default=2)
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-batch", action="store_true", help="skip the 64-problem ragged batch")
     ap.add_argument("--n", type=int, default=100000)
     ap.add_argument("--tiles-only", action="store_true",
                     help="only the BF16x3 tile kernel (10 launches) and a 1 GiB elementwise copy, for counters")
@@ -172,6 +236,20 @@ def main():
                 "frac": achieved / PEAK_BF16_TFLOPS, "traffic": None,
                 "kernel": "k_khat_bf16 (K_hat V tile, BF16x3)", "launch_grid": bf["tile_grid"],
                 "algorithmic_flops_per_launch": flops, "avg_launch_ms": bf["tile_ms"]}
+    tc = TILE_COUNTERS
+    if n == 100000 and bf16_tile_source_hash() == tc["kernel_source_sha256_16"]:
+        roofline["traffic"] = 1024.0 * (tc["fetch_kib"] * tc["fetch_scale"] + tc["write_kib"] * tc["write_scale"])
+        roofline["traffic_unit"] = "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)"
+        roofline["traffic_gbps"] = roofline["traffic"] / (bf["tile_ms"] * 1e-3) / 1e9
+        issued = tc["mfma_insts"] * 16384.0
+        roofline["issued_mfma_flops_per_launch"] = issued
+        roofline["issued_mfma_frac_of_peak"] = issued / (bf["tile_ms"] * 1e-3) / 1e12 / PEAK_BF16_TFLOPS
+        roofline["mfma_busy_frac"] = tc["mfma_busy_cycles"] / (tc["gui_active_per_xcd"] * 1024)
+    batched = None
+    if not args.no_batch:
+        log("[bench] 64-problem ragged batch")
+        batched = run_batched(2, 1)
+        log(f"[bench] batch: {batched['ms_per_batch']:.1f} ms per call, iters max {batched['cg_iters_max']}")
     cpu = None
     if not args.no_cpu:
         log("[bench] timing the CPU oracle sample")
@@ -189,6 +267,7 @@ def main():
         "cpu_baseline": cpu,
         "fp64_gpu": out_fp64,
         "speedup_vs_fp64_gpu": (bf["evals_per_s"] / out_fp64["value"]) if out_fp64 else None,
+        "batched_rbf_64": batched,
         "fp16x3_gpu": {"value": h16["evals_per_s"], "ms_per_step": h16["ms_per_step"],
                        "iters_max": h16["iters_max"], "tile_ms": h16["tile_ms"],
                        "tile_tflops": tile_flops(n, d, t) / (h16["tile_ms"] * 1e-3) / 1e12,
