@@ -12,10 +12,6 @@ namespace gpmll {
 
 hipError_t launch_stage_x(const Ctx& c, const Hyper& h);
 hipError_t launch_stage_x_bwd(const Ctx& c, const Hyper& h);
-hipError_t launch_stage_v(const Ctx& c, const double* V, int ldv, int ncols, const Hyper& h);
-hipError_t launch_khat_tiles(const Ctx& c, const Hyper& h, const int* nact);
-hipError_t launch_khat_reduce(const Ctx& c, const double* V, int ldv, double* W, int ldw, int ncols, const Hyper& h,
-                              double* dot_part, const int* nact);
 hipError_t launch_cg_after_product(const Ctx& c, const Hyper& h, int it, double tol);
 hipError_t launch_slq_logp(const Ctx& c, const Hyper& h, const double* y, double* logp);
 hipError_t launch_backward(const Ctx& c, const Hyper& h, int ard, int precond_grad, double* grad);
@@ -124,6 +120,7 @@ Layout make_layout(int64_t n, int d, int ard, int num_probes, int max_iters, int
   L.active = take(tp * 4);
   L.nactive = take(16);
   L.iters = take(tp * 4);
+  L.colmap = take(tp * 4);
   L.alog = take(tp * max_iters * 8);
   L.blog = take(tp * max_iters * 8);
   const int64_t nb64 = (n + 63) / 64, nb256 = (n + 255) / 256;
@@ -186,6 +183,14 @@ static int check_device() {
 
 int gpmll::gpmll_check_device() { return check_device(); }
 void gpmll::gpmll_set_hip_error(int e) { g_last_hip = e; }
+
+// fewest compiled 16-column tiles holding nact columns (at most full)
+static int compact_ntt(int nact, int full) {
+  static const int ok[] = {1, 2, 3, 4, 5, 6, 8, 12, 16};
+  for (int v : ok)
+    if (16 * v >= nact && v <= full) return v;
+  return full;
+}
 
 static int check_problem(const gp_problem* prob) {
   if (!prob || !prob->X_dev || !prob->y_dev) return GP_EINVAL;
@@ -328,17 +333,28 @@ static int run_estimator(const gp_problem* prob, const double* theta_host, const
   HIPCHK(launch_cg_init(c, h));
   int* nact = c.at<int>(L.nactive);
   const int q = opt->sync_every;
+  // With the host polling the active-column count, the product of an iteration
+  // runs only over the active columns, packed to the fewest 16-column tiles
+  // (the count read last is an upper bound: columns only ever stop).
+  const int full_ntt = L.tp / 16;
+  int host_nact = L.t;
   for (int it = 0; it < opt->max_iters; ++it) {
     if (q > 0 && it > 0 && it % q == 0) {
-      int host_nact = 0;
       HIPCHK(hipMemcpyAsync(&host_nact, nact, sizeof(int), hipMemcpyDeviceToHost, stream));
       HIPCHK(hipStreamSynchronize(stream));
       if (host_nact == 0) break;
     }
-    HIPCHK(launch_stage_v(c, c.at<double>(L.Pd), L.tp, L.tp, h));
-    HIPCHK(launch_khat_tiles(c, h, nact));
-    HIPCHK(launch_khat_reduce(c, c.at<double>(L.Pd), L.tp, c.at<double>(L.W), L.tp, L.tp, h,
-                              c.at<double>(L.dot_part), nact));
+    int ntt = full_ntt;
+    const int* cmap = nullptr;
+    if (q > 0) {
+      ntt = compact_ntt(host_nact, full_ntt);
+      HIPCHK(launch_colmap(c));
+      cmap = c.at<int>(L.colmap);
+    }
+    HIPCHK(launch_stage_v(c, c.at<double>(L.Pd), L.tp, 16 * ntt, h, cmap, ntt));
+    HIPCHK(launch_khat_tiles(c, h, nact, ntt));
+    HIPCHK(launch_khat_reduce(c, c.at<double>(L.Pd), L.tp, c.at<double>(L.W), L.tp, 16 * ntt, h,
+                              c.at<double>(L.dot_part), nact, cmap, L.tp));
     HIPCHK(launch_cg_after_product(c, h, it, opt->cg_tol));
   }
   HIPCHK(launch_slq_logp(c, h, prob->y_dev, logp_dev));

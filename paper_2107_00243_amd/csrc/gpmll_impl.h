@@ -89,7 +89,7 @@ struct Layout {
   // estimator block
   size_t xfa, xfb, rowterm, colterm, H, Y, ltr, ltr_raw, ltr_part2;
   size_t Xs, R, Z0, Pd, W, vfrag, vscale, wpart;
-  size_t rho, rho0, bnorm, rnorm2, pw, active, nactive, iters, alog, blog;
+  size_t rho, rho0, bnorm, rnorm2, pw, active, nactive, iters, colmap, alog, blog;
   size_t dot_part, gamma, slq_work;
   size_t cprime, bxa, bxb, brt, bct, bafrag, bcfrag, bxaug, bwd_part, pg_small, omega, pg_part;
   size_t total;
@@ -133,7 +133,19 @@ void gpmll_set_hip_error(int e);
 // Staging and tile launches shared with the batched path (the layout view there
 // describes the concatenation of all problems' padded row blocks).
 hipError_t launch_stage_x(const Ctx& c, const Hyper& h);
-hipError_t launch_stage_v(const Ctx& c, const double* V, int ldv, int ncols, const Hyper& h);
+// V staging: ncols staged columns taken through colmap (null: the first ncols
+// columns), laid out for ntt 16-column tiles (0: all of tp).
+hipError_t launch_stage_v(const Ctx& c, const double* V, int ldv, int ncols, const Hyper& h,
+                          const int* colmap = nullptr, int ntt = 0);
+// Tile launch over ntt 16-column tiles of staged V (0: all of tp).
+hipError_t launch_khat_tiles(const Ctx& c, const Hyper& h, const int* nact, int ntt = 0);
+// W (columns through colmap, as staged) = s * sum of split partials + sigma^2 V,
+// and per-64-row-block partials of V.W at dot_part[block * ldpart + column].
+hipError_t launch_khat_reduce(const Ctx& c, const double* V, int ldv, double* W, int ldw, int ncols, const Hyper& h,
+                              double* dot_part, const int* nact, const int* colmap = nullptr, int ldpart = 0);
+// colmap[0 .. tp) = the active columns in increasing order, then -1 (from the CG masks)
+hipError_t launch_colmap(const Ctx& c);
+
 // FP32 / FP64 tiles over a table of int4 {first row, column begin, column end,
 // output slot}; kernel values carry outputscale 1 (the caller scales).  With a
 // gate, item i is skipped while gate_count[gate[i]] == 0.

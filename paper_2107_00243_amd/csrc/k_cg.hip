@@ -171,6 +171,15 @@ __global__ void k_cg_p(double* __restrict__ P, const double* __restrict__ Z, con
   if (active[c]) P[e] = Z[e] + beta[c] * P[e];
 }
 
+// colmap = active columns in increasing order, then -1 (one lane: tp <= 256)
+__global__ void k_colmap(const int* __restrict__ active, int tp, int* __restrict__ colmap) {
+  if (threadIdx.x != 0) return;
+  int m = 0;
+  for (int c = 0; c < tp; ++c)
+    if (active[c]) colmap[m++] = c;
+  for (; m < tp; ++m) colmap[m] = -1;
+}
+
 __global__ void k_swap_count(int* __restrict__ nactive, int* __restrict__ nactive_next) {
   *nactive = *nactive_next;
   *nactive_next = 0;
@@ -394,6 +403,12 @@ hipError_t launch_cg_after_product(const Ctx& c, const Hyper& h, int it, double 
   hipLaunchKernelGGL(k_cg_p, dim3(nb_for(L.n * L.tp, 256)), dim3(256), 0, c.st, c.at<double>(L.Pd),
                      c.at<double>(L.W), beta, c.at<int>(L.active), L.n, L.tp, nact);
   hipLaunchKernelGGL(k_swap_count, dim3(1), dim3(1), 0, c.st, nact, nact_next);
+  return hipGetLastError();
+}
+
+hipError_t launch_colmap(const Ctx& c) {
+  const Layout& L = *c.lay;
+  hipLaunchKernelGGL(k_colmap, dim3(1), dim3(64), 0, c.st, c.at<int>(L.active), L.tp, c.at<int>(L.colmap));
   return hipGetLastError();
 }
 

@@ -113,6 +113,7 @@ struct TileArgs {
   int64_t n_valid;          // rows/columns >= n_valid carry zero operands
   int64_t cols_per_split;   // multiple of 32
   int tp;                   // leading dimension of the partial output
+  int ntt;                  // 16-column tiles of right-hand sides staged for this launch
   float s32;
   double s64;
 };
@@ -228,12 +229,19 @@ __global__ void k_stage_x_fp(const double* __restrict__ xs, int64_t n_pad, int d
   }
 }
 
-// V (rows < nrows, columns < ncols of an FP64 row-major array with leading
-// dimension ldv) -> fragment-major tile-precision copy; everything else zero.
+// V (rows < nrows of an FP64 row-major array with leading dimension ldv) ->
+// fragment-major tile-precision copy of ncols staged columns; staged column c
+// holds source column colmap[c] (c itself when colmap is null; nothing, i.e.
+// zeros, when the entry is negative).  Everything else is zero.
+__device__ inline int staged_source(const int* __restrict__ colmap, int col, int ncols) {
+  if (col >= ncols) return -1;
+  return colmap != nullptr ? colmap[col] : col;
+}
+
 // BF16: fragment (jb, tt, piece) lane l holds rows jb*32 + perm(l/16, s), s < 8,
 // perm(g, s) = 4g + s (s < 4) or 16 + 4g + s - 4, column tt*16 + l%16.
-__global__ void k_stage_v_bf16(const double* __restrict__ V, int64_t nrows, int ldv, int ncols, int64_t n_pad,
-                               int ntt, u32x4* __restrict__ vfrag) {
+__global__ void k_stage_v_bf16(const double* __restrict__ V, int64_t nrows, int ldv, int ncols,
+                               const int* __restrict__ colmap, int64_t n_pad, int ntt, u32x4* __restrict__ vfrag) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;  // (jb, tt, lane)
   const int64_t total = (n_pad / 32) * ntt * 64;
   if (e >= total) return;
@@ -241,13 +249,14 @@ __global__ void k_stage_v_bf16(const double* __restrict__ V, int64_t nrows, int 
   const int tt = (int)((e / 64) % ntt);
   const int64_t jb = e / (64 * ntt);
   const int g = lane / 16, col = tt * 16 + lane % 16;
+  const int src = staged_source(colmap, col, ncols);
   // FP64 -> hi + lo: hi = RNE(v), lo = RNE(v - hi) with v - hi taken in FP64
   uint32_t h[4], l[4];
   for (int w = 0; w < 4; ++w) {
     int64_t j0 = jb * 32 + (2 * w < 4 ? 4 * g + 2 * w : 16 + 4 * g + (2 * w - 4));
     int64_t j1 = j0 + 1;
-    double a = (j0 < nrows && col < ncols) ? V[j0 * ldv + col] : 0.0;
-    double b = (j1 < nrows && col < ncols) ? V[j1 * ldv + col] : 0.0;
+    double a = (j0 < nrows && src >= 0) ? V[j0 * ldv + src] : 0.0;
+    double b = (j1 < nrows && src >= 0) ? V[j1 * ldv + src] : 0.0;
     uint32_t hh = pack_bf16((float)a, (float)b);
     double ra = a - (double)bf16_lo_f(hh), rb = b - (double)bf16_hi_f(hh);
     h[w] = hh;
@@ -259,12 +268,14 @@ __global__ void k_stage_v_bf16(const double* __restrict__ V, int64_t nrows, int 
 
 // column maxima of |V| as float bit patterns (non-negative floats order like their
 // bits, so the integer maximum is exact and order-independent)
-__global__ void k_colmax(const double* __restrict__ V, int64_t nrows, int ldv, int ncols, uint32_t* __restrict__ cm) {
+__global__ void k_colmax(const double* __restrict__ V, int64_t nrows, int ldv, int ncols,
+                         const int* __restrict__ colmap, uint32_t* __restrict__ cm) {
   __shared__ uint32_t red[256];
   const int c = blockIdx.y;
+  const int src = staged_source(colmap, c, ncols);
   uint32_t m = 0;
-  for (int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x; r < nrows; r += (int64_t)gridDim.x * 256) {
-    const float v = fabsf((float)V[r * ldv + c]);
+  for (int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x; src >= 0 && r < nrows; r += (int64_t)gridDim.x * 256) {
+    const float v = fabsf((float)V[r * ldv + src]);
     const uint32_t b = __builtin_bit_cast(uint32_t, v);
     m = b > m ? b : m;
   }
@@ -292,8 +303,9 @@ __device__ __host__ inline float f16_col_scale(uint32_t maxbits) {
 }
 
 // as k_stage_v_bf16 with FP16 hi + lo of (scale_c * V)
-__global__ void k_stage_v_f16(const double* __restrict__ V, int64_t nrows, int ldv, int ncols, int64_t n_pad, int ntt,
-                              const uint32_t* __restrict__ cm, u32x4* __restrict__ vfrag) {
+__global__ void k_stage_v_f16(const double* __restrict__ V, int64_t nrows, int ldv, int ncols,
+                              const int* __restrict__ colmap, int64_t n_pad, int ntt, const uint32_t* __restrict__ cm,
+                              u32x4* __restrict__ vfrag) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;  // (jb, tt, lane)
   const int64_t total = (n_pad / 32) * ntt * 64;
   if (e >= total) return;
@@ -301,13 +313,14 @@ __global__ void k_stage_v_f16(const double* __restrict__ V, int64_t nrows, int l
   const int tt = (int)((e / 64) % ntt);
   const int64_t jb = e / (64 * ntt);
   const int g = lane / 16, col = tt * 16 + lane % 16;
+  const int src = staged_source(colmap, col, ncols);
   const double sc = (col < ncols) ? (double)f16_col_scale(cm[col]) : 1.0;
   uint32_t h[4], l[4];
   for (int w = 0; w < 4; ++w) {
     int64_t j0 = jb * 32 + (2 * w < 4 ? 4 * g + 2 * w : 16 + 4 * g + (2 * w - 4));
     int64_t j1 = j0 + 1;
-    double a = (j0 < nrows && col < ncols) ? sc * V[j0 * ldv + col] : 0.0;
-    double b = (j1 < nrows && col < ncols) ? sc * V[j1 * ldv + col] : 0.0;
+    double a = (j0 < nrows && src >= 0) ? sc * V[j0 * ldv + src] : 0.0;
+    double b = (j1 < nrows && src >= 0) ? sc * V[j1 * ldv + src] : 0.0;
     const uint32_t hh = pack_f16((float)a, (float)b);
     const f32x2 hf = __builtin_convertvector(__builtin_bit_cast(f16x2, hh), f32x2);
     h[w] = hh;
@@ -319,8 +332,8 @@ __global__ void k_stage_v_f16(const double* __restrict__ V, int64_t nrows, int l
 
 // FP32/FP64: fragment (j16, tt, v) lane l holds row j16*16 + acc_row(l/16, v), column tt*16 + l%16
 template <typename T>
-__global__ void k_stage_v_fp(const double* __restrict__ V, int64_t nrows, int ldv, int ncols, int64_t n_pad,
-                             int ntt, T* __restrict__ vfrag) {
+__global__ void k_stage_v_fp(const double* __restrict__ V, int64_t nrows, int ldv, int ncols,
+                             const int* __restrict__ colmap, int64_t n_pad, int ntt, T* __restrict__ vfrag) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;  // (j16, tt, v, lane)
   const int64_t total = (n_pad / 16) * ntt * 4 * 64;
   if (e >= total) return;
@@ -329,8 +342,8 @@ __global__ void k_stage_v_fp(const double* __restrict__ V, int64_t nrows, int ld
   const int tt = (int)((e / 256) % ntt);
   const int64_t j16 = e / (256 * ntt);
   const int64_t j = j16 * 16 + acc_row<T>(lane / 16, v);
-  const int col = tt * 16 + lane % 16;
-  vfrag[e] = (j < nrows && col < ncols) ? (T)V[j * ldv + col] : (T)0;
+  const int src = staged_source(colmap, tt * 16 + lane % 16, ncols);
+  vfrag[e] = (j < nrows && src >= 0) ? (T)V[j * ldv + src] : (T)0;
 }
 
 // W[i][c] = sum_s wpart[s][i][c] + sigma^2 V[i][c] (FP64, fixed order), rows < nrows,
@@ -339,34 +352,37 @@ __global__ void k_stage_v_fp(const double* __restrict__ V, int64_t nrows, int ld
 template <typename T>
 __global__ __launch_bounds__(256) void k_khat_reduce(const T* __restrict__ wpart, int nsplit, int64_t n_pad, int tp,
                                                      const double* __restrict__ V, int ldv, double* __restrict__ W,
-                                                     int ldw, int64_t nrows, int ncols, double s2,
-                                                     double* __restrict__ dot_part, const int* __restrict__ nactive,
+                                                     int ldw, int64_t nrows, int ncols, const int* __restrict__ colmap,
+                                                     int ldpart, double s2, double* __restrict__ dot_part,
+                                                     const int* __restrict__ nactive,
                                                      const uint32_t* __restrict__ colmax, double fac_s) {
   if (nactive != nullptr && *nactive == 0) return;
   __shared__ double red[4][64];
   const int cl = threadIdx.x % 64, lane4 = threadIdx.x / 64;
+  // staged column c carries source column src (results go back to that column)
   const int c = blockIdx.y * 64 + cl;
+  const int src = staged_source(colmap, c, ncols);
   const int64_t r0 = (int64_t)blockIdx.x * 64;
   double dot = 0.0;
   // FP16X3 partials carry the factors 2^15 / s (kernel values) and scale_c (column)
-  const double fac = (colmax != nullptr && c < ncols) ? fac_s / (double)f16_col_scale(colmax[c]) : 1.0;
-  if (c < ncols) {
+  const double fac = (colmax != nullptr && src >= 0) ? fac_s / (double)f16_col_scale(colmax[c]) : 1.0;
+  if (src >= 0) {
     for (int q = lane4; q < 64; q += 4) {
       const int64_t r = r0 + q;
       if (r >= nrows) break;
       double w = 0.0;
       for (int s = 0; s < nsplit; ++s) w += (double)wpart[((int64_t)s * n_pad + r) * tp + c];
-      const double v = V[r * ldv + c];
+      const double v = V[r * ldv + src];
       w = w * fac + s2 * v;
-      W[r * ldw + c] = w;
+      W[r * ldw + src] = w;
       dot += v * w;
     }
   }
   if (dot_part == nullptr) return;
   red[lane4][cl] = dot;
   __syncthreads();
-  if (lane4 == 0 && c < ncols)
-    dot_part[(int64_t)blockIdx.x * ncols + c] = red[0][cl] + red[1][cl] + red[2][cl] + red[3][cl];
+  if (lane4 == 0 && src >= 0)
+    dot_part[(int64_t)blockIdx.x * ldpart + src] = red[0][cl] + red[1][cl] + red[2][cl] + red[3][cl];
 }
 
 #endif  // part 0
@@ -766,7 +782,7 @@ hipError_t sel_bf16_ntt(const Ctx& c, const TileArgs& ta, const int* nact, int n
 template <int KIND, bool F16>
 hipError_t sel_bf16(const Ctx& c, const TileArgs& ta, const int* nact) {
   const Layout& L = *c.lay;
-  const int ntt = L.tp / 16;
+  const int ntt = ta.ntt;
   switch (L.kd / 32) {
     case 1: return sel_bf16_ntt<KIND, 1, F16>(c, ta, nact, ntt);
     case 2: return sel_bf16_ntt<KIND, 2, F16>(c, ta, nact, ntt);
@@ -814,7 +830,7 @@ hipError_t sel_fp_ntt(const Ctx& c, const TileArgs& ta, const int* nact, int ntt
 template <typename T, int KIND>
 hipError_t sel_fp(const Ctx& c, const TileArgs& ta, const int* nact, const ItemTable& it) {
   const Layout& L = *c.lay;
-  const int ntt = L.tp / 16;
+  const int ntt = ta.ntt;
   switch (L.kd / 4) {
     case 1: return sel_fp_ntt<T, KIND, 1>(c, ta, nact, ntt, it);
     case 2: return sel_fp_ntt<T, KIND, 2>(c, ta, nact, ntt, it);
@@ -882,41 +898,43 @@ hipError_t launch_stage_x_bwd(const Ctx& c, const Hyper& h) {
   return hipGetLastError();
 }
 
-hipError_t launch_stage_v(const Ctx& c, const double* V, int ldv, int ncols, const Hyper& h) {
+hipError_t launch_stage_v(const Ctx& c, const double* V, int ldv, int ncols, const Hyper& h, const int* colmap,
+                          int ntt) {
   const Layout& L = *c.lay;
   (void)h;
-  const int ntt = L.tp / 16;
+  if (ntt <= 0) ntt = L.tp / 16;
   if (L.prec == GP_PREC_FP16X3) {
     uint32_t* cm = c.at<uint32_t>(L.vscale);
     hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(256), 0, c.st, cm, L.tp);
     const unsigned gx = (unsigned)std::min<int64_t>(64, (L.n + 255) / 256);
-    hipLaunchKernelGGL(k_colmax, dim3(gx, (unsigned)ncols), dim3(256), 0, c.st, V, L.n, ldv, ncols, cm);
+    hipLaunchKernelGGL(k_colmax, dim3(gx, (unsigned)ncols), dim3(256), 0, c.st, V, L.n, ldv, ncols, colmap, cm);
     const int64_t total = (L.n_pad / 32) * ntt * 64;
     hipLaunchKernelGGL(k_stage_v_f16, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, c.st, V, L.n, ldv, ncols,
-                       L.n_pad, ntt, cm, c.at<u32x4>(L.vfrag));
+                       colmap, L.n_pad, ntt, cm, c.at<u32x4>(L.vfrag));
   } else if (L.prec == GP_PREC_BF16X3) {
     const int64_t total = (L.n_pad / 32) * ntt * 64;
     hipLaunchKernelGGL(k_stage_v_bf16, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, c.st, V, L.n, ldv,
-                       ncols, L.n_pad, ntt, c.at<u32x4>(L.vfrag));
+                       ncols, colmap, L.n_pad, ntt, c.at<u32x4>(L.vfrag));
   } else if (L.prec == GP_PREC_FP32) {
     const int64_t total = (L.n_pad / 16) * ntt * 256;
     hipLaunchKernelGGL(k_stage_v_fp<float>, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, c.st, V, L.n, ldv,
-                       ncols, L.n_pad, ntt, c.at<float>(L.vfrag));
+                       ncols, colmap, L.n_pad, ntt, c.at<float>(L.vfrag));
   } else {
     const int64_t total = (L.n_pad / 16) * ntt * 256;
     hipLaunchKernelGGL(k_stage_v_fp<double>, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, c.st, V, L.n,
-                       ldv, ncols, L.n_pad, ntt, c.at<double>(L.vfrag));
+                       ldv, ncols, colmap, L.n_pad, ntt, c.at<double>(L.vfrag));
   }
   return hipGetLastError();
 }
 
-hipError_t launch_khat_tiles(const Ctx& c, const Hyper& h, const int* nact) {
+hipError_t launch_khat_tiles(const Ctx& c, const Hyper& h, const int* nact, int ntt) {
   const Layout& L = *c.lay;
   TileArgs ta;
   ta.n_pad = L.n_pad;
   ta.n_valid = L.n;
   ta.cols_per_split = L.cols_per_split;
   ta.tp = L.tp;
+  ta.ntt = ntt > 0 ? ntt : L.tp / 16;
   ta.s32 = (float)h.s;
   ta.s64 = h.s;
   if (L.prec == GP_PREC_BF16X3 || L.prec == GP_PREC_FP16X3) {
@@ -936,6 +954,7 @@ hipError_t launch_khat_tiles_items(const Ctx& c, const Hyper& h, const ItemTable
   ta.n_valid = L.n;
   ta.cols_per_split = L.cols_per_split;
   ta.tp = L.tp;
+  ta.ntt = L.tp / 16;
   ta.s32 = 1.0f;
   ta.s64 = 1.0;
   if (L.prec == GP_PREC_FP32) return khat_tiles_fp32(c, h, ta, nact, it);
@@ -944,7 +963,8 @@ hipError_t launch_khat_tiles_items(const Ctx& c, const Hyper& h, const ItemTable
 }
 
 hipError_t launch_khat_reduce(const Ctx& c, const double* V, int ldv, double* W, int ldw, int ncols, const Hyper& h,
-                              double* dot_part, const int* nact) {
+                              double* dot_part, const int* nact, const int* colmap, int ldpart) {
+  if (ldpart <= 0) ldpart = ncols;
   const Layout& L = *c.lay;
   const dim3 nb((unsigned)((L.n + 63) / 64), (unsigned)((ncols + 63) / 64));
   const bool f16 = L.prec == GP_PREC_FP16X3;
@@ -952,10 +972,10 @@ hipError_t launch_khat_reduce(const Ctx& c, const double* V, int ldv, double* W,
   const double fac_s = f16 ? h.s / 32768.0 : 1.0;
   if (L.prec == GP_PREC_FP64)
     hipLaunchKernelGGL(k_khat_reduce<double>, nb, dim3(256), 0, c.st, c.at<double>(L.wpart), L.nsplit, L.n_pad,
-                       L.tp, V, ldv, W, ldw, L.n, ncols, h.s2, dot_part, nact, cm, fac_s);
+                       L.tp, V, ldv, W, ldw, L.n, ncols, colmap, ldpart, h.s2, dot_part, nact, cm, fac_s);
   else
     hipLaunchKernelGGL(k_khat_reduce<float>, nb, dim3(256), 0, c.st, c.at<float>(L.wpart), L.nsplit, L.n_pad,
-                       L.tp, V, ldv, W, ldw, L.n, ncols, h.s2, dot_part, nact, cm, fac_s);
+                       L.tp, V, ldv, W, ldw, L.n, ncols, colmap, ldpart, h.s2, dot_part, nact, cm, fac_s);
   return hipGetLastError();
 }
 
