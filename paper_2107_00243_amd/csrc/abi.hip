@@ -61,7 +61,9 @@ Layout make_layout(int64_t n, int d, int ard, int num_probes, int max_iters, int
   L.cols_per_split = cps;
   L.nsplit = (int)((L.n_pad + cps - 1) / cps);
   L.nchunk = (int)((n + kChunkRows - 1) / kChunkRows);
-  L.nchunk_ltr = (int)((n + kLtrRows - 1) / kLtrRows);
+  // L^T R: about 512 row chunks (two workgroups per CU per l-group), >= 64 rows each
+  L.ltr_rows = std::max<int64_t>(64, rup((n + 511) / 512, 16));
+  L.nchunk_ltr = (int)((n + L.ltr_rows - 1) / L.ltr_rows);
   L.nred = (int)std::min<int64_t>(256, (n + 255) / 256);
 
   const int64_t np = L.n_pad, tp = L.tp, k = rank;
@@ -103,7 +105,7 @@ Layout make_layout(int64_t n, int d, int ard, int num_probes, int max_iters, int
   L.Y = take(kk * tp * 8);
   L.ltr = take(kk * tp * 8);
   L.ltr_raw = take(kk * tp * 8);
-  L.ltr_part2 = take((size_t)L.nchunk_ltr * kk * tp * 8);
+  L.ltr_part2 = take((size_t)L.nchunk_ltr * rup(kk, 16) * tp * 8);
   L.Xs = take(np * tp * 8);
   L.R = take(np * tp * 8);
   L.Z0 = take(np * tp * 8);

@@ -23,7 +23,6 @@ constexpr int kRowBlock = 256;      // rows per workgroup of the tile kernels; n
 constexpr int kColChunk = 32;       // K-dimension of one tile-times-V step (MFMA K for BF16)
 constexpr int kRedBlock = 256;      // threads of the reduction kernels
 constexpr int kChunkRows = 2048;    // rows per partial of the Gram reduction L^T L
-constexpr int kLtrRows = 256;       // rows per partial of L^T R (many workgroups in flight)
 
 // Row groups of 16 rows per wave of the FP32 / FP64 tile kernels for NTT
 // 16-column tiles of right-hand sides; a workgroup covers 64 * RG rows.
@@ -81,6 +80,7 @@ struct Layout {
   int64_t cols_per_split;
   int nchunk;           // row chunks of the Gram reduction
   int nchunk_ltr;       // row chunks of the L^T R reduction
+  int64_t ltr_rows;     // rows per chunk of the L^T R reduction (multiple of 16)
   int nrb;              // row blocks of kRowBlock rows
   int nred;             // blocks of the row-parallel reductions (<= 256)
   // preconditioner block (offsets independent of the estimator options)

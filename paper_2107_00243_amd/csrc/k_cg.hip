@@ -186,140 +186,123 @@ __global__ void k_swap_count(int* __restrict__ nactive, int* __restrict__ nactiv
 }
 
 // ---------------------------------------------------------------------------
-// Woodbury apply Z = (R - L Y) / sigma^2 with Y = C^-1 L^T R, C^-1 = Rinv^T Rinv.
+// Woodbury apply Z = (R - L Y) / sigma^2 with Y = C^-1 L^T R, both products on
+// the FP64 matrix cores (v_mfma_f64_16x16x4f64: A lane l = (row l%16, k l/16),
+// B lane l = (k l/16, column l%16), D lane l = rows l/16 + 4v, column l%16).
 // ---------------------------------------------------------------------------
 
-// part[chunk][l][c] = sum_{i in chunk} L[l*n + i] R[i*tp + c]; 64 x 64 tiles, 4 x 4 per thread
-__global__ __launch_bounds__(256) void k_ltr_part(const double* __restrict__ L, const double* __restrict__ R, int64_t n,
-                                                  int k, int tp, int64_t chunk, double* __restrict__ part,
-                                                  const int* __restrict__ nactive) {
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+// part[chunk][l][c] = sum over the chunk's rows i of L[l][i] R[i][c], l < kpad,
+// c < tp.  Workgroup (chunk, group of 4 blocks of 16 l); wave w owns l-block
+// 4 * blockIdx.y + w and every 16-column tile of R.
+template <int NT>
+__global__ __launch_bounds__(256) void k_ltr_mfma(const double* __restrict__ L, const double* __restrict__ R,
+                                                  int64_t n, int k, int kpad, int tp, int64_t rows,
+                                                  double* __restrict__ part, const int* __restrict__ nactive) {
   if (nactive != nullptr && *nactive == 0) return;
-  __shared__ double As[16][65], Bs[16][65];
-  const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
-  const int l0 = blockIdx.y * 64, c0 = blockIdx.z * 64;
-  const int64_t r0 = (int64_t)blockIdx.x * chunk, r1 = min(n, r0 + chunk);
-  double acc[4][4] = {};
-  for (int64_t base = r0; base < r1; base += 16) {
-    for (int e = threadIdx.x; e < 16 * 64; e += 256) {
-      const int rr = e % 16, col = e / 16;
-      const int64_t i = base + rr;
-      As[rr][col] = (i < r1 && l0 + col < k) ? L[(int64_t)(l0 + col) * n + i] : 0.0;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int mb = blockIdx.y * 4 + wave;
+  if (mb * 16 >= kpad) return;
+  const int64_t i0 = (int64_t)blockIdx.x * rows, i1 = min(n, i0 + rows);
+  const int m = lane & 15, kq = lane >> 4;
+  const int l = mb * 16 + m;
+  const double* Lc = L + (int64_t)min(l, k - 1) * n;
+  f64x4 acc[NT];
+#pragma unroll
+  for (int nb = 0; nb < NT; ++nb) acc[nb] = f64x4{0.0, 0.0, 0.0, 0.0};
+  for (int64_t i = i0; i < i1; i += 4) {
+    const int64_t ir = i + kq;
+    const bool in = ir < i1;
+    const double av = (in && l < k) ? Lc[ir] : 0.0;
+    const double* Rr = R + (in ? ir : i0) * tp + m;
+#pragma unroll
+    for (int nb = 0; nb < NT; ++nb) {
+      const double bv = in ? Rr[nb * 16] : 0.0;
+      acc[nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[nb], 0, 0, 0);
     }
-    for (int e = threadIdx.x; e < 16 * 64; e += 256) {
-      const int rr = e / 64, col = e % 64;
-      const int64_t i = base + rr;
-      Bs[rr][col] = (i < r1 && c0 + col < tp) ? R[i * tp + c0 + col] : 0.0;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int rr = 0; rr < 16; ++rr) {
-      double av[4], bv[4];
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        av[q] = As[rr][ty * 4 + q];
-        bv[q] = Bs[rr][tx * 4 + q];
-      }
-#pragma unroll
-      for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int b = 0; b < 4; ++b) acc[a][b] += av[a] * bv[b];
-    }
-    __syncthreads();
   }
+  double* out = part + ((int64_t)blockIdx.x * kpad + mb * 16) * tp;
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
+  for (int nb = 0; nb < NT; ++nb)
 #pragma unroll
-    for (int b = 0; b < 4; ++b) {
-      const int l = l0 + ty * 4 + a, c = c0 + tx * 4 + b;
-      if (l < k && c < tp) part[((int64_t)blockIdx.x * k + l) * tp + c] = acc[a][b];
-    }
+    for (int v = 0; v < 4; ++v) out[(int64_t)(kq + 4 * v) * tp + nb * 16 + m] = acc[nb][v];
 }
 
-__global__ void k_ltr_final(const double* __restrict__ part, int nchunk, int k, int tp, double* __restrict__ out,
-                            const int* __restrict__ nactive) {
-  if (nactive != nullptr && *nactive == 0) return;
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= k * tp) return;
-  double s = 0.0;
-  for (int q = 0; q < nchunk; ++q) s += part[(int64_t)q * k * tp + e];
-  out[e] = s;
-}
-
-// out[l][c] = sum_m M[l][m] in[m][c] with M = Rinv (lower, trans = 0) or Rinv^T (upper, trans = 1)
-__global__ void k_tri_apply(const double* __restrict__ Rinv, const double* __restrict__ in, int k, int tp, int trans,
-                            double* __restrict__ out, const int* __restrict__ nactive) {
+// T[l][c] = sum over chunks of part (fixed order), l < k
+__global__ void k_ltr_sum(const double* __restrict__ part, int nchunk, int k, int kpad, int tp,
+                          double* __restrict__ T, const int* __restrict__ nactive) {
   if (nactive != nullptr && *nactive == 0) return;
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= k * tp) return;
   const int l = e / tp, c = e % tp;
   double s = 0.0;
-  if (!trans)
-    for (int m = 0; m <= l; ++m) s += Rinv[l * k + m] * in[m * tp + c];
-  else
-    for (int m = l; m < k; ++m) s += Rinv[m * k + l] * in[m * tp + c];
-  out[e] = s;
+  for (int q = 0; q < nchunk; ++q) s += part[((int64_t)q * kpad + l) * tp + c];
+  T[e] = s;
 }
 
-// Z = (R - L Y) / sigma^2 on a 64 x 64 tile, plus partial r.z per column
-__global__ __launch_bounds__(256) void k_z_apply(const double* __restrict__ L, const double* __restrict__ Y,
-                                                 const double* __restrict__ R, int64_t n, int k, int tp,
-                                                 double inv_s2, double* __restrict__ Z, double* __restrict__ part,
-                                                 const int* __restrict__ nactive) {
+// Y = C^-1 T (k x k times k x tp)
+__global__ void k_cinv_apply(const double* __restrict__ Cinv, const double* __restrict__ T, int k, int tp,
+                             double* __restrict__ Y, const int* __restrict__ nactive) {
   if (nactive != nullptr && *nactive == 0) return;
-  __shared__ double As[16][65], Bs[16][65];
-  __shared__ double red[16][64];
-  const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
-  const int64_t i0 = (int64_t)blockIdx.x * 64;
-  const int c0 = blockIdx.y * 64;
-  double acc[4][4] = {};
-  for (int lb = 0; lb < k; lb += 16) {
-    for (int e = threadIdx.x; e < 16 * 64; e += 256) {
-      const int ll = e / 64, rr = e % 64;
-      const int64_t i = i0 + rr;
-      As[ll][rr] = (i < n && lb + ll < k) ? L[(int64_t)(lb + ll) * n + i] : 0.0;
-      const int c = c0 + rr;
-      Bs[ll][rr] = (lb + ll < k && c < tp) ? Y[(lb + ll) * tp + c] : 0.0;
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= k * tp) return;
+  const int l = e / tp, c = e % tp;
+  double s = 0.0;
+  for (int m = 0; m < k; ++m) s += Cinv[l * k + m] * T[m * tp + c];
+  Y[e] = s;
+}
+
+// Z = (R - L Y) / sigma^2 on 64 rows per workgroup (16 per wave), plus the
+// per-block partial r.z of every column
+template <int NT>
+__global__ __launch_bounds__(256) void k_zapply_mfma(const double* __restrict__ L, const double* __restrict__ Y,
+                                                     const double* __restrict__ R, int64_t n, int k, int tp,
+                                                     double inv_s2, double* __restrict__ Z, double* __restrict__ part,
+                                                     const int* __restrict__ nactive) {
+  if (nactive != nullptr && *nactive == 0) return;
+  __shared__ double red[16][16 * NT];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int m = lane & 15, kq = lane >> 4;
+  const int64_t r0 = (int64_t)blockIdx.x * 64 + wave * 16;
+  const int64_t ra = r0 + m;
+  f64x4 acc[NT];
+#pragma unroll
+  for (int nb = 0; nb < NT; ++nb) acc[nb] = f64x4{0.0, 0.0, 0.0, 0.0};
+  for (int l0 = 0; l0 < k; l0 += 4) {
+    const int l = l0 + kq;
+    const bool in = l < k;
+    const double av = (in && ra < n) ? L[(int64_t)l * n + ra] : 0.0;
+    const double* Yr = Y + (int64_t)(in ? l : 0) * tp + m;
+#pragma unroll
+    for (int nb = 0; nb < NT; ++nb) {
+      const double bv = in ? Yr[nb * 16] : 0.0;
+      acc[nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[nb], 0, 0, 0);
     }
-    __syncthreads();
-#pragma unroll
-    for (int ll = 0; ll < 16; ++ll) {
-      double av[4], bv[4];
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        av[q] = As[ll][ty * 4 + q];
-        bv[q] = Bs[ll][tx * 4 + q];
-      }
-#pragma unroll
-      for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int b = 0; b < 4; ++b) acc[a][b] += av[a] * bv[b];
-    }
-    __syncthreads();
   }
-  double rz[4] = {0.0, 0.0, 0.0, 0.0};
+  // lane holds rows r0 + kq + 4v, column nb * 16 + m
 #pragma unroll
-  for (int a = 0; a < 4; ++a) {
-    const int64_t i = i0 + ty * 4 + a;
-    if (i >= n) continue;
+  for (int nb = 0; nb < NT; ++nb) {
+    double rz = 0.0;
 #pragma unroll
-    for (int b = 0; b < 4; ++b) {
-      const int c = c0 + tx * 4 + b;
-      if (c >= tp) continue;
-      const double r = R[i * tp + c];
-      const double z = (r - acc[a][b]) * inv_s2;
-      Z[i * tp + c] = z;
-      rz[b] += r * z;
+    for (int v = 0; v < 4; ++v) {
+      const int64_t r = r0 + kq + 4 * v;
+      if (r < n) {
+        const int64_t e = r * tp + nb * 16 + m;
+        const double rv = R[e];
+        const double z = (rv - acc[nb][v]) * inv_s2;
+        Z[e] = z;
+        rz += rv * z;
+      }
     }
+    red[wave * 4 + kq][nb * 16 + m] = rz;
   }
   if (part == nullptr) return;
-#pragma unroll
-  for (int b = 0; b < 4; ++b) red[ty][tx * 4 + b] = rz[b];
   __syncthreads();
-  if (threadIdx.x < 64) {
+  for (int c = threadIdx.x; c < 16 * NT; c += 256) {
     double s = 0.0;
-    for (int q = 0; q < 16; ++q) s += red[q][threadIdx.x];
-    const int c = c0 + threadIdx.x;
-    if (c < tp) part[(int64_t)blockIdx.x * tp + c] = s;
+    for (int q = 0; q < 16; ++q) s += red[q][c];
+    part[(int64_t)blockIdx.x * tp + c] = s;
   }
 }
 
@@ -329,30 +312,55 @@ __global__ __launch_bounds__(256) void k_z_apply(const double* __restrict__ L, c
 
 static unsigned nb_for(int64_t count, int bs) { return (unsigned)((count + bs - 1) / bs); }
 
+template <int NT>
+static void ltr_launch(const Ctx& c, const double* Rsrc, double* part, const int* nact) {
+  const Layout& L = *c.lay;
+  const int kpad = (L.k + 15) / 16 * 16;
+  hipLaunchKernelGGL((k_ltr_mfma<NT>), dim3(L.nchunk_ltr, (kpad / 16 + 3) / 4), dim3(256), 0, c.st, c.at<double>(L.L),
+                     Rsrc, L.n, L.k, kpad, L.tp, L.ltr_rows, part, nact);
+}
+
+template <int NT>
+static void zapply_launch(const Ctx& c, const Hyper& h, const double* Rsrc, double* Zdst, double* rz_part,
+                          const int* nact) {
+  const Layout& L = *c.lay;
+  hipLaunchKernelGGL((k_zapply_mfma<NT>), dim3(nb_for(L.n, 64)), dim3(256), 0, c.st, c.at<double>(L.L),
+                     c.at<double>(L.Y), Rsrc, L.n, L.k, L.tp, 1.0 / h.s2, Zdst, rz_part, nact);
+}
+
+#define GPMLL_TP_CASES(M) M(1) M(2) M(3) M(4) M(5) M(6) M(8) M(12) M(16)
+
 // dst (k x tp) = L^T Rsrc
 hipError_t launch_ltr(const Ctx& c, const double* Rsrc, double* dst, const int* nact) {
   const Layout& L = *c.lay;
-  hipLaunchKernelGGL(k_ltr_part, dim3(L.nchunk_ltr, (L.k + 63) / 64, (L.tp + 63) / 64), dim3(256), 0, c.st,
-                     c.at<double>(L.L), Rsrc, L.n, L.k, L.tp, (int64_t)kLtrRows, c.at<double>(L.ltr_part2), nact);
-  hipLaunchKernelGGL(k_ltr_final, dim3(nb_for((int64_t)L.k * L.tp, 256)), dim3(256), 0, c.st,
-                     c.at<double>(L.ltr_part2), L.nchunk_ltr, L.k, L.tp, dst, nact);
+  const int kpad = (L.k + 15) / 16 * 16;
+  double* part = c.at<double>(L.ltr_part2);
+  switch (L.tp / 16) {
+#define CASE(N) case N: ltr_launch<N>(c, Rsrc, part, nact); break;
+    GPMLL_TP_CASES(CASE)
+#undef CASE
+    default: return hipErrorInvalidValue;
+  }
+  hipLaunchKernelGGL(k_ltr_sum, dim3(nb_for((int64_t)L.k * L.tp, 256)), dim3(256), 0, c.st, part, L.nchunk_ltr, L.k,
+                     kpad, L.tp, dst, nact);
   return hipGetLastError();
 }
 
 hipError_t launch_woodbury(const Ctx& c, const Hyper& h, const double* Rsrc, double* Zdst, const int* nact,
                            double* rz_part) {
   const Layout& L = *c.lay;
-  const double inv_s2 = 1.0 / h.s2;
   if (L.k > 0) {
     hipError_t e = launch_ltr(c, Rsrc, c.at<double>(L.ltr), nact);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_tri_apply, dim3(nb_for((int64_t)L.k * L.tp, 256)), dim3(256), 0, c.st, c.at<double>(L.Rinv),
-                       c.at<double>(L.ltr), L.k, L.tp, 0, c.at<double>(L.Y), nact);
-    hipLaunchKernelGGL(k_tri_apply, dim3(nb_for((int64_t)L.k * L.tp, 256)), dim3(256), 0, c.st, c.at<double>(L.Rinv),
-                       c.at<double>(L.Y), L.k, L.tp, 1, c.at<double>(L.ltr), nact);
+    hipLaunchKernelGGL(k_cinv_apply, dim3(nb_for((int64_t)L.k * L.tp, 256)), dim3(256), 0, c.st,
+                       c.at<double>(L.Cinv), c.at<double>(L.ltr), L.k, L.tp, c.at<double>(L.Y), nact);
   }
-  hipLaunchKernelGGL(k_z_apply, dim3(nb_for(L.n, 64), (L.tp + 63) / 64), dim3(256), 0, c.st, c.at<double>(L.L),
-                     c.at<double>(L.ltr), Rsrc, L.n, L.k, L.tp, inv_s2, Zdst, rz_part, nact);
+  switch (L.tp / 16) {
+#define CASE(N) case N: zapply_launch<N>(c, h, Rsrc, Zdst, rz_part, nact); break;
+    GPMLL_TP_CASES(CASE)
+#undef CASE
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 
