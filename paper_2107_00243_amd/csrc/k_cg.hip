@@ -211,16 +211,23 @@ __global__ __launch_bounds__(256) void k_ltr_mfma(const double* __restrict__ L, 
   f64x4 acc[NT];
 #pragma unroll
   for (int nb = 0; nb < NT; ++nb) acc[nb] = f64x4{0.0, 0.0, 0.0, 0.0};
-  for (int64_t i = i0; i < i1; i += 4) {
-    const int64_t ir = i + kq;
-    const bool in = ir < i1;
-    const double av = (in && l < k) ? Lc[ir] : 0.0;
-    const double* Rr = R + (in ? ir : i0) * tp + m;
+  // four K-steps of operands are loaded before their MFMAs (loads in flight together)
+  constexpr int U = 4;
+  for (int64_t i = i0; i < i1; i += 4 * U) {
+    double av[U], bv[U][NT];
 #pragma unroll
-    for (int nb = 0; nb < NT; ++nb) {
-      const double bv = in ? Rr[nb * 16] : 0.0;
-      acc[nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[nb], 0, 0, 0);
+    for (int u = 0; u < U; ++u) {
+      const int64_t ir = i + 4 * u + kq;
+      const bool in = ir < i1;
+      av[u] = (in && l < k) ? Lc[ir] : 0.0;
+      const double* Rr = R + (in ? ir : i0) * tp + m;
+#pragma unroll
+      for (int nb = 0; nb < NT; ++nb) bv[u][nb] = in ? Rr[nb * 16] : 0.0;
     }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int nb = 0; nb < NT; ++nb) acc[nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u], bv[u][nb], acc[nb], 0, 0, 0);
   }
   double* out = part + ((int64_t)blockIdx.x * kpad + mb * 16) * tp;
 #pragma unroll
@@ -229,16 +236,28 @@ __global__ __launch_bounds__(256) void k_ltr_mfma(const double* __restrict__ L, 
     for (int v = 0; v < 4; ++v) out[(int64_t)(kq + 4 * v) * tp + nb * 16 + m] = acc[nb][v];
 }
 
-// T[l][c] = sum over chunks of part (fixed order), l < k
-__global__ void k_ltr_sum(const double* __restrict__ part, int nchunk, int k, int kpad, int tp,
-                          double* __restrict__ T, const int* __restrict__ nactive) {
+// T[l][c] = sum over chunks of part, l < k: 64 entries per workgroup, its 16
+// waves take chunks q = wave (mod 16), then a fixed-order sum over the waves
+__global__ __launch_bounds__(1024) void k_ltr_sum(const double* __restrict__ part, int nchunk, int k, int kpad, int tp,
+                                                  double* __restrict__ T, const int* __restrict__ nactive) {
   if (nactive != nullptr && *nactive == 0) return;
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= k * tp) return;
-  const int l = e / tp, c = e % tp;
+  __shared__ double red[16][64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int e = blockIdx.x * 64 + lane;
+  const bool in = e < k * tp;
+  const int l = in ? e / tp : 0, c = in ? e % tp : 0;
   double s = 0.0;
-  for (int q = 0; q < nchunk; ++q) s += part[((int64_t)q * kpad + l) * tp + c];
-  T[e] = s;
+  if (in) {
+#pragma unroll 4
+    for (int q = wave; q < nchunk; q += 16) s += part[((int64_t)q * kpad + l) * tp + c];
+  }
+  red[wave][lane] = s;
+  __syncthreads();
+  if (wave == 0 && in) {
+    double t = 0.0;
+    for (int w = 0; w < 16; ++w) t += red[w][lane];
+    T[e] = t;
+  }
 }
 
 // Y = C^-1 T (k x k times k x tp)
@@ -269,16 +288,22 @@ __global__ __launch_bounds__(256) void k_zapply_mfma(const double* __restrict__ 
   f64x4 acc[NT];
 #pragma unroll
   for (int nb = 0; nb < NT; ++nb) acc[nb] = f64x4{0.0, 0.0, 0.0, 0.0};
-  for (int l0 = 0; l0 < k; l0 += 4) {
-    const int l = l0 + kq;
-    const bool in = l < k;
-    const double av = (in && ra < n) ? L[(int64_t)l * n + ra] : 0.0;
-    const double* Yr = Y + (int64_t)(in ? l : 0) * tp + m;
+  constexpr int U = 4;
+  for (int l0 = 0; l0 < k; l0 += 4 * U) {
+    double av[U], bv[U][NT];
 #pragma unroll
-    for (int nb = 0; nb < NT; ++nb) {
-      const double bv = in ? Yr[nb * 16] : 0.0;
-      acc[nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[nb], 0, 0, 0);
+    for (int u = 0; u < U; ++u) {
+      const int l = l0 + 4 * u + kq;
+      const bool in = l < k;
+      av[u] = (in && ra < n) ? L[(int64_t)l * n + ra] : 0.0;
+      const double* Yr = Y + (int64_t)(in ? l : 0) * tp + m;
+#pragma unroll
+      for (int nb = 0; nb < NT; ++nb) bv[u][nb] = in ? Yr[nb * 16] : 0.0;
     }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int nb = 0; nb < NT; ++nb) acc[nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u], bv[u][nb], acc[nb], 0, 0, 0);
   }
   // lane holds rows r0 + kq + 4v, column nb * 16 + m
 #pragma unroll
@@ -341,7 +366,7 @@ hipError_t launch_ltr(const Ctx& c, const double* Rsrc, double* dst, const int* 
 #undef CASE
     default: return hipErrorInvalidValue;
   }
-  hipLaunchKernelGGL(k_ltr_sum, dim3(nb_for((int64_t)L.k * L.tp, 256)), dim3(256), 0, c.st, part, L.nchunk_ltr, L.k,
+  hipLaunchKernelGGL(k_ltr_sum, dim3(nb_for((int64_t)L.k * L.tp, 64)), dim3(1024), 0, c.st, part, L.nchunk_ltr, L.k,
                      kpad, L.tp, dst, nact);
   return hipGetLastError();
 }
