@@ -368,24 +368,23 @@ struct BwdBfArgs {
 
 template <int KIND>
 __device__ inline void bw_map(float q, float s, float rbf_sg, float rbf_kap, float* kap, float* sg) {
-  const float log2e = 1.4426950408889634f;
   if (KIND == GP_KERNEL_RBF) {
     const float k = __builtin_amdgcn_exp2f(q);  // q: log2 of the staged kernel value
     *sg = k * rbf_sg;
     *kap = k * rbf_kap;
-  } else if (KIND == GP_KERNEL_MATERN32) {
-    const float a = 1.7320508075688772f;
-    const float r = __builtin_sqrtf(fmaxf(q, 0.0f));
-    const float e = __builtin_amdgcn_exp2f(-a * log2e * r);
-    *kap = fmaf(a, r, 1.0f) * e;
-    *sg = s * 3.0f * e;
   } else {
-    const float a = 2.23606797749979f;
-    const float q0 = fmaxf(q, 0.0f);
-    const float r = __builtin_sqrtf(q0);
-    const float e = __builtin_amdgcn_exp2f(-a * log2e * r);
-    *kap = fmaf(5.0f / 3.0f, q0, fmaf(a, r, 1.0f)) * e;
-    *sg = s * (5.0f / 3.0f) * fmaf(a, r, 1.0f) * e;
+    // split-precision staging: q = rho^2 with rho = a log2(e) r, a r = ln2 rho
+    const float ln2 = 0.6931471805599453f;
+    const float rho = __builtin_sqrtf(fabsf(q));
+    const float e = __builtin_amdgcn_exp2f(-rho);
+    const float ar = ln2 * rho;
+    if (KIND == GP_KERNEL_MATERN32) {
+      *kap = (1.0f + ar) * e;
+      *sg = s * 3.0f * e;
+    } else {
+      *kap = fmaf(ar * ar, 1.0f / 3.0f, 1.0f + ar) * e;
+      *sg = s * (5.0f / 3.0f) * (1.0f + ar) * e;
+    }
   }
 }
 

@@ -79,6 +79,26 @@ __device__ inline void split_pair_f16(float a, float b, uint32_t* hi, uint32_t* 
 __device__ inline float bf16_lo_f(uint32_t w) { return __builtin_bit_cast(float, w << 16); }
 __device__ inline float bf16_hi_f(uint32_t w) { return __builtin_bit_cast(float, w & 0xffff0000u); }
 
+// kernel value of the split-precision tiles from the MFMA argument q: RBF
+// q = log2 k; Matern q = rho^2 with rho = a log2(e) r (a = sqrt3, sqrt5), so
+// exp(-a r) = exp2(-rho) and a r = ln2 rho:
+//   3/2: s (1 + ln2 rho) exp2(-rho),  5/2: s (1 + ln2 rho + (ln2 rho)^2 / 3) exp2(-rho)
+// (|q| guards the rounding of q = 0 to a tiny negative number)
+template <int KIND>
+__device__ inline float map_split(float q, float s) {
+  if (KIND == GP_KERNEL_RBF) {
+    return __builtin_amdgcn_exp2f(q);
+  } else {
+    const float ln2 = 0.6931471805599453f;
+    const float rho = __builtin_sqrtf(fabsf(q));
+    const float e = __builtin_amdgcn_exp2f(-rho);
+    float poly;
+    if (KIND == GP_KERNEL_MATERN32) poly = fmaf(s * ln2, rho, s);
+    else poly = fmaf(fmaf(s * (ln2 * ln2 / 3.0f), rho, s * ln2), rho, s);
+    return poly * e;
+  }
+}
+
 // kernel value from the MFMA argument q (FP32 tiles): RBF q = log2 k; Matern q = r^2
 template <int KIND>
 __device__ inline float map32(float q, float s) {
@@ -136,7 +156,9 @@ __device__ inline void copy_units(u32x4* dst, const u32x4* a, int na, const u32x
 // Staging of the inputs x~ into the MFMA fragment layouts, and the row and
 // column terms of the distance expansion.  RBF: x' = sqrt(log2 e) x~ on both
 // sides, q = x'_i.x'_j - |x'_i|^2/2 - |x'_j|^2/2 + log2 s = log2 k.  Matern:
-// x'_B = sqrt2 x~, x'_A = -x'_B, q = |x'_i|^2/2 + |x'_j|^2/2 - x'_i.x'_j = r^2.
+// x'_B = sqrt2 x~, x'_A = -x'_B, q = |x'_i|^2/2 + |x'_j|^2/2 - x'_i.x'_j = r^2;
+// the split-precision tiles stage x' = sqrt2 a log2(e) x~ instead (a = sqrt3 or
+// sqrt5), so that sqrt(q) = a log2(e) r is directly the exponent of exp2.
 // FP64 and the derivative sweep: as Matern, q = r^2.  Norms are those of the
 // represented (rounded) operands, so q is a true squared distance of slightly
 // perturbed points.
@@ -150,7 +172,10 @@ __global__ void k_stage_x_bf16(const double* __restrict__ xs, int64_t n_pad, int
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n_pad) return;
   const bool rbf = kind == GP_KERNEL_RBF;
-  const double scale = rbf ? 1.2011224087864498 /* sqrt(log2 e) */ : 1.4142135623730951;
+  // RBF: sqrt(log2 e); Matern: sqrt2 * a * log2 e with a = sqrt3 (3/2) or sqrt5 (5/2)
+  const double scale = rbf ? 1.2011224087864498
+                           : 1.4142135623730951 * 1.4426950408889634 *
+                                 (kind == GP_KERNEL_MATERN32 ? 1.7320508075688772 : 2.23606797749979);
   uint16_t hi[GP_MAX_D], lo[GP_MAX_D];
   double nrm = 0.0;
   for (int q = 0; q < dq; ++q) {
@@ -430,7 +455,7 @@ __device__ __forceinline__ void bf16_map(const f32x4 (&dd)[RG][2], const float* 
       const f32x4 ctv = js ? ct1 : ct0;
       float kv[4];
 #pragma unroll
-      for (int v = 0; v < 4; ++v) kv[v] = map32<KIND>(dd[rg][js][v] + ctv[v], s32);
+      for (int v = 0; v < 4; ++v) kv[v] = map_split<KIND>(dd[rg][js][v] + ctv[v], s32);
       if constexpr (DIAG) {
         const int64_t i = row0 + rg * 16 + li;
 #pragma unroll
