@@ -198,6 +198,7 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-problem ragged batch")
+    ap.add_argument("--batch-only", action="store_true", help="only the 64-problem ragged batch (one JSON line)")
     ap.add_argument("--n", type=int, default=100000)
     ap.add_argument("--tiles-only", action="store_true",
                     help="only the BF16x3 tile kernel (10 launches) and a 1 GiB elementwise copy, for counters")
@@ -210,6 +211,9 @@ def main():
     import torch
     import synthgp
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.batch_only:
+        print(json.dumps(run_batched(args.steps, args.warmup)))
+        return
     pr = synthgp.rbf_ard_100k(n=args.n)
     n, d, t = pr.n, pr.d, 1 + pr.num_probes
     log(f"[bench] workload rbf_ard_100k n={n} d={d} t={t} rank={pr.rank}")

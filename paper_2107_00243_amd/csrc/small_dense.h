@@ -164,29 +164,39 @@ inline __device__ void tridiag_eig_first_row(double* a, double* b, double* z, in
     // Wilkinson shift: eigenvalue of the trailing 2 x 2 closer to a[hi]
     const double dl = 0.5 * (a[hi - 1] - a[hi]);
     const double bb = b[hi - 1];
-    const double den = dl + copysign(hypot(dl, bb), dl == 0.0 ? 1.0 : dl);
+    const double den = dl + copysign(sqrt(dl * dl + bb * bb), dl == 0.0 ? 1.0 : dl);
     const double mu = a[hi] - bb * bb / den;
+    // one implicit QR sweep over [lo, hi]; the entries of row / column k travel in
+    // registers from one rotation to the next (ak, bk, zk are a[k], b[k], z[k])
     double x = a[lo] - mu, y = b[lo];
+    double ak = a[lo], bk = b[lo], zk = z[lo];
     for (int k = lo; k < hi; ++k) {
-      const double r = hypot(x, y);
-      const double cs = (r == 0.0) ? 1.0 : x / r;
-      const double sn = (r == 0.0) ? 0.0 : y / r;
+      const double r = sqrt(x * x + y * y);
+      const double inv = r > 0.0 ? 1.0 / r : 0.0;
+      const double cs = r > 0.0 ? x * inv : 1.0;
+      const double sn = y * inv;
       if (k > lo) b[k - 1] = r;
-      const double ak = a[k], ak1 = a[k + 1], bk = b[k];
-      a[k] = cs * cs * ak + 2.0 * cs * sn * bk + sn * sn * ak1;
-      a[k + 1] = sn * sn * ak - 2.0 * cs * sn * bk + cs * cs * ak1;
-      b[k] = cs * sn * (ak1 - ak) + (cs * cs - sn * sn) * bk;
-      double bulge = 0.0;
+      const double ak1 = a[k + 1], zk1 = z[k + 1];
+      const double c2 = cs * cs, s2 = sn * sn, csn = cs * sn;
+      a[k] = c2 * ak + 2.0 * csn * bk + s2 * ak1;
+      const double nak1 = s2 * ak - 2.0 * csn * bk + c2 * ak1;
+      const double nbk = csn * (ak1 - ak) + (c2 - s2) * bk;
+      double bulge = 0.0, bk1 = 0.0;
       if (k + 1 < hi) {
-        bulge = sn * b[k + 1];
-        b[k + 1] = cs * b[k + 1];
+        const double bn = b[k + 1];
+        bulge = sn * bn;
+        bk1 = cs * bn;
       }
-      const double zk = z[k], zk1 = z[k + 1];
       z[k] = cs * zk + sn * zk1;
-      z[k + 1] = -sn * zk + cs * zk1;
-      x = b[k];
+      zk = -sn * zk + cs * zk1;
+      ak = nak1;
+      bk = bk1;
+      x = nbk;
       y = bulge;
     }
+    a[hi] = ak;
+    z[hi] = zk;
+    b[hi - 1] = x;
     ++sweeps;
   }
 }
