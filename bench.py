@@ -33,9 +33,11 @@ PEAK_FP64_TFLOPS = 78.6
 # FETCH_SIZE, then WRITE_SIZE, KiB per dispatch, over `bench.py --tiles-only`),
 # each scaled by what the same counter reads for a 1 GiB elementwise copy, and the
 # MFMA counters of the same launches.  They describe the kernel source whose hash
-# is given; once that source changes they are stale and are not reported.
+# is given, launched on the given grid; once either changes they are stale and are
+# not reported.
 TILE_COUNTERS = {
     "kernel_source_sha256_16": "74d4d05e074c0c18",
+    "grid": [391, 6],
     "fetch_kib": 333810.6, "fetch_scale": 1048576.0 / 524307.1,
     "write_kib": 187680.0, "write_scale": 1.0,
     "mfma_insts": 3.718e8, "mfma_busy_cycles": 5.949e9, "gui_active_per_xcd": 8.113e7 / 8,
@@ -241,7 +243,8 @@ def main():
                 "kernel": "k_khat_bf16 (K_hat V tile, BF16x3)", "launch_grid": bf["tile_grid"],
                 "algorithmic_flops_per_launch": flops, "avg_launch_ms": bf["tile_ms"]}
     tc = TILE_COUNTERS
-    if n == 100000 and bf16_tile_source_hash() == tc["kernel_source_sha256_16"]:
+    if (n == 100000 and bf16_tile_source_hash() == tc["kernel_source_sha256_16"]
+            and list(bf["tile_grid"]) == tc["grid"]):
         roofline["traffic"] = 1024.0 * (tc["fetch_kib"] * tc["fetch_scale"] + tc["write_kib"] * tc["write_scale"])
         roofline["traffic_unit"] = "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)"
         roofline["traffic_gbps"] = roofline["traffic"] / (bf["tile_ms"] * 1e-3) / 1e9

@@ -52,10 +52,30 @@ Layout make_layout(int64_t n, int d, int ard, int num_probes, int max_iters, int
   L.bkd = (int)rup(d, 4);
   L.bow = (2 * d + 1 + 15) / 16 * 16 + 16;
   L.nrb = (int)(L.n_pad / kRowBlock);
-  // split the columns so that the tile grid has >= ~2048 workgroups (8 per CU) even
-  // with 256-row workgroups; every split is non-empty
-  int64_t want = (2048 + L.nrb - 1) / L.nrb;
-  if (want < 1) want = 1;
+  // Column splits: the tile grid (row blocks x splits) runs in rounds of
+  // kWgSlots resident workgroups (two per CU on the 256 CUs); take the fewest
+  // splits that give at least two rounds with the last round >= 95 % full, else
+  // the best-filled count (every split non-empty, >= 256 columns).
+  const int ntt_full = L.tp / 16;
+  const int64_t rows_wg = (prec == GP_PREC_BF16X3 || prec == GP_PREC_FP16X3)
+                              ? kRowBlock
+                              : 64 * fp_row_groups(prec == GP_PREC_FP64 ? 8 : 4, ntt_full);
+  const int64_t nrbk = L.n_pad / rows_wg;
+  const int64_t smax = std::max<int64_t>(1, std::min<int64_t>(32, L.n_pad / 256));
+  int64_t want = smax;
+  double best = -1.0;
+  for (int64_t s = 1; s <= smax; ++s) {
+    const double rounds = (double)(nrbk * s) / kWgSlots;
+    const double eff = rounds / std::ceil(rounds);
+    if (rounds >= 2.0 && eff >= 0.95) {
+      want = s;
+      break;
+    }
+    if (eff > best + 1e-12 && rounds >= 1.0) {
+      best = eff;
+      want = s;
+    }
+  }
   int64_t cps = rup((L.n_pad + want - 1) / want, 256);
   if (cps < 256) cps = 256;
   L.cols_per_split = cps;

@@ -20,6 +20,7 @@
 namespace gpmll {
 
 constexpr int kRowBlock = 256;      // rows per workgroup of the tile kernels; n is padded to this
+constexpr int kWgSlots = 512;       // resident tile workgroups on MI355X: 2 per CU x 256 CUs
 constexpr int kColChunk = 32;       // K-dimension of one tile-times-V step (MFMA K for BF16)
 constexpr int kRedBlock = 256;      // threads of the reduction kernels
 constexpr int kChunkRows = 2048;    // rows per partial of the Gram reduction L^T L
