@@ -37,10 +37,10 @@ PEAK_FP64_TFLOPS = 78.6
 # not reported.
 TILE_COUNTERS = {
     "kernel_source_sha256_16": "74d4d05e074c0c18",
-    "grid": [391, 6],
-    "fetch_kib": 333810.6, "fetch_scale": 1048576.0 / 524307.1,
-    "write_kib": 187680.0, "write_scale": 1.0,
-    "mfma_insts": 3.718e8, "mfma_busy_cycles": 5.949e9, "gui_active_per_xcd": 8.113e7 / 8,
+    "grid": [391, 5],
+    "fetch_kib": 322434.8, "fetch_scale": 1048576.0 / 524306.8,
+    "write_kib": 156400.2, "write_scale": 1.0,
+    "mfma_insts": 3.718e8, "mfma_busy_cycles": 5.949e9, "gui_active_per_xcd": 7.8599e7 / 8,
 }
 
 
