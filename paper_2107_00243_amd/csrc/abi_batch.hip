@@ -167,7 +167,7 @@ BLayout make_blayout(const gp_batch* bp, const gp_options* o, int32_t rank, cons
   L.H = take(B * K * L.ell * 8);
   L.Tb = take(B * K * tp * 8);
   L.Y = take(B * K * tp * 8);
-  L.ltr_part = take((size_t)nblk * K * tp * 8);
+  L.ltr_part = take((size_t)nblk * rup(K, 16) * tp * 8);
   L.R = take(N * tp * 8);
   L.Xs = take(N * tp * 8);
   L.Z0 = take(N * tp * 8);

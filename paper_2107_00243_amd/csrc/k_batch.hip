@@ -236,31 +236,134 @@ __global__ __launch_bounds__(256) void kb_probes(const BDesc* __restrict__ desc,
 // Woodbury apply Z = (R - L C^-1 L^T R) / sigma^2 per problem
 // ---------------------------------------------------------------------------
 
-// part[blk][l][c] = sum over the block's rows of L[i][l] R[i][c]
-__global__ __launch_bounds__(256) void kb_ltr_part(const BDesc* __restrict__ desc, const int32_t* __restrict__ blkprob,
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+// part[blk][l][c] = sum over the block's rows of L[i][l] R[i][c] on the FP64
+// matrix cores (v_mfma_f64_16x16x4f64; A lane = (l, 4 rows), B lane = (4 rows,
+// column)); wave w of workgroup (blk, y) owns the 16 l of block 4 y + w
+template <int NT>
+__global__ __launch_bounds__(256) void kb_ltr_mfma(const BDesc* __restrict__ desc, const int32_t* __restrict__ blkprob,
                                                    const double* __restrict__ Lall, const double* __restrict__ R,
-                                                   int K, int tp, double* __restrict__ part,
+                                                   int KP, int tp, double* __restrict__ part,
                                                    const int* __restrict__ nactive, const int* __restrict__ pact) {
   if (nactive != nullptr && *nactive == 0) return;
   const int b = blkprob[blockIdx.x];
   if (pact != nullptr && pact[b] == 0) return;
   const BDesc& D = desc[b];
   const int k = D.k;
-  if (k == 0) return;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int mb = blockIdx.y * 4 + wave;
+  if (mb * 16 >= k) return;
   const int64_t i0 = (int64_t)(blockIdx.x - D.blk0) * kBRows;
-  const int64_t i1 = min((int64_t)kBRows, D.n - i0);
+  const int64_t i1 = i0 + min((int64_t)kBRows, D.n - i0);
+  const int m = lane & 15, kq = lane >> 4;
+  const int l = mb * 16 + m;
+  const double* Lc = Lall + D.loff + (int64_t)min(l, k - 1) * D.n_pad;
+  const double* Rb = R + D.off * tp;
+  f64x4 acc[NT];
+#pragma unroll
+  for (int nb = 0; nb < NT; ++nb) acc[nb] = f64x4{0.0, 0.0, 0.0, 0.0};
+  constexpr int U = 4;
+  for (int64_t i = i0; i < i1; i += 4 * U) {
+    double av[U], bv[U][NT];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t ir = i + 4 * u + kq;
+      const bool in = ir < i1;
+      av[u] = (in && l < k) ? Lc[ir] : 0.0;
+      const double* Rr = Rb + (in ? ir : i0) * tp + m;
+#pragma unroll
+      for (int nb = 0; nb < NT; ++nb) bv[u][nb] = in ? Rr[nb * 16] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int nb = 0; nb < NT; ++nb) acc[nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u], bv[u][nb], acc[nb], 0, 0, 0);
+  }
+  double* out = part + ((int64_t)blockIdx.x * KP + mb * 16) * tp;
+#pragma unroll
+  for (int nb = 0; nb < NT; ++nb)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) out[(int64_t)(kq + 4 * v) * tp + nb * 16 + m] = acc[nb][v];
+}
+
+// Z = (R - L Y) / sigma^2 on the block's rows (four 16-row tiles per wave, FP64
+// MFMA over the rank), padding rows zero; partial r.z per column
+template <int NT>
+__global__ __launch_bounds__(256) void kb_zapply_mfma(const BDesc* __restrict__ desc,
+                                                      const int32_t* __restrict__ blkprob,
+                                                      const double* __restrict__ Lall, const double* __restrict__ Y,
+                                                      const double* __restrict__ R, int K, int tp,
+                                                      double* __restrict__ Z, double* __restrict__ part,
+                                                      const int* __restrict__ nactive, const int* __restrict__ pact) {
+  if (nactive != nullptr && *nactive == 0) return;
+  __shared__ double red[16][16 * NT];
+  const int b = blkprob[blockIdx.x];
+  if (pact != nullptr && pact[b] == 0) return;
+  const BDesc& D = desc[b];
+  const int k = D.k;
+  const double inv_s2 = 1.0 / D.s2;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int m = lane & 15, kq = lane >> 4;
   const double* Lb = Lall + D.loff;
-  for (int e = threadIdx.x; e < k * tp; e += 256) {
-    const int l = e / tp, c = e % tp;
+  const double* Yb = Y + (int64_t)b * K * tp;
+  const int64_t ib = (int64_t)(blockIdx.x - D.blk0) * kBRows + wave * 64;
+  double rzs[NT];
+#pragma unroll
+  for (int nb = 0; nb < NT; ++nb) rzs[nb] = 0.0;
+  for (int rt = 0; rt < 4; ++rt) {
+    const int64_t r0 = ib + rt * 16;
+    const int64_t ra = r0 + m;
+    f64x4 acc[NT];
+#pragma unroll
+    for (int nb = 0; nb < NT; ++nb) acc[nb] = f64x4{0.0, 0.0, 0.0, 0.0};
+    constexpr int U = 4;
+    for (int l0 = 0; l0 < k; l0 += 4 * U) {
+      double av[U], bv[U][NT];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int l = l0 + 4 * u + kq;
+        const bool in = l < k;
+        av[u] = (in && ra < D.n) ? Lb[(int64_t)l * D.n_pad + ra] : 0.0;
+        const double* Yr = Yb + (int64_t)(in ? l : 0) * tp + m;
+#pragma unroll
+        for (int nb = 0; nb < NT; ++nb) bv[u][nb] = in ? Yr[nb * 16] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int nb = 0; nb < NT; ++nb)
+          acc[nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u], bv[u][nb], acc[nb], 0, 0, 0);
+    }
+#pragma unroll
+    for (int nb = 0; nb < NT; ++nb)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t r = r0 + kq + 4 * v;
+        const int64_t e = (D.off + r) * tp + nb * 16 + m;
+        if (r < D.n) {
+          const double rv = R[e];
+          const double z = (rv - acc[nb][v]) * inv_s2;
+          Z[e] = z;
+          rzs[nb] += rv * z;
+        } else {
+          Z[e] = 0.0;
+        }
+      }
+  }
+#pragma unroll
+  for (int nb = 0; nb < NT; ++nb) red[wave * 4 + kq][nb * 16 + m] = rzs[nb];
+  __syncthreads();
+  for (int c = threadIdx.x; c < 16 * NT; c += 256) {
     double s = 0.0;
-    for (int64_t q = 0; q < i1; ++q) s += Lb[(int64_t)l * D.n_pad + i0 + q] * R[(D.off + i0 + q) * tp + c];
-    part[((int64_t)blockIdx.x * K + l) * tp + c] = s;
+    for (int q = 0; q < 16; ++q) s += red[q][c];
+    part[(int64_t)blockIdx.x * tp + c] = s;
   }
 }
 
 // Y = C^-1 (sum of the problem's partials of L^T R)
 __global__ __launch_bounds__(256) void kb_wood_y(const BDesc* __restrict__ desc, const double* __restrict__ part,
-                                                 const double* __restrict__ Cinv, int K, int tp,
+                                                 const double* __restrict__ Cinv, int K, int KP, int tp,
                                                  double* __restrict__ Tb, double* __restrict__ Y,
                                                  const int* __restrict__ nactive) {
   if (nactive != nullptr && *nactive == 0) return;
@@ -272,7 +375,7 @@ __global__ __launch_bounds__(256) void kb_wood_y(const BDesc* __restrict__ desc,
   for (int e = threadIdx.x; e < k * tp; e += 256) {
     const int l = e / tp, c = e % tp;
     double s = 0.0;
-    for (int q = 0; q < D.nblk; ++q) s += part[((int64_t)(D.blk0 + q) * K + l) * tp + c];
+    for (int q = 0; q < D.nblk; ++q) s += part[((int64_t)(D.blk0 + q) * KP + l) * tp + c];
     T[l * tp + c] = s;
   }
   __syncthreads();
@@ -283,49 +386,6 @@ __global__ __launch_bounds__(256) void kb_wood_y(const BDesc* __restrict__ desc,
     double s = 0.0;
     for (int m = 0; m < k; ++m) s += Ci[l * k + m] * T[m * tp + c];
     Yb[l * tp + c] = s;
-  }
-}
-
-// Z = (R - L Y) / sigma^2 on the block's rows; partial r.z per column
-__global__ __launch_bounds__(256) void kb_zapply(const BDesc* __restrict__ desc, const int32_t* __restrict__ blkprob,
-                                                 const double* __restrict__ Lall, const double* __restrict__ Y,
-                                                 const double* __restrict__ R, int K, int tp, double* __restrict__ Z,
-                                                 double* __restrict__ part, const int* __restrict__ nactive,
-                                                 const int* __restrict__ pact) {
-  if (nactive != nullptr && *nactive == 0) return;
-  __shared__ double red[256];
-  const int b = blkprob[blockIdx.x];
-  if (pact != nullptr && pact[b] == 0) return;
-  const BDesc& D = desc[b];
-  const int G = 256 / tp;
-  const int c = threadIdx.x % tp, rg = threadIdx.x / tp;
-  const int64_t i0 = (int64_t)(blockIdx.x - D.blk0) * kBRows;
-  const double* Lb = Lall + D.loff;
-  const double* Yb = Y + (int64_t)b * K * tp;
-  const double inv_s2 = 1.0 / D.s2;
-  double rz = 0.0;
-  if (rg < G) {
-    for (int q = rg; q < kBRows; q += G) {
-      const int64_t i = i0 + q;
-      const int64_t e = (D.off + i) * tp + c;
-      if (i >= D.n) {
-        Z[e] = 0.0;
-        continue;
-      }
-      double ly = 0.0;
-      for (int l = 0; l < D.k; ++l) ly += Lb[(int64_t)l * D.n_pad + i] * Yb[l * tp + c];
-      const double rv = R[e];
-      const double z = (rv - ly) * inv_s2;
-      Z[e] = z;
-      rz += rv * z;
-    }
-  }
-  red[threadIdx.x] = rg < G ? rz : 0.0;
-  __syncthreads();
-  if ((int)threadIdx.x < tp) {
-    double s = 0.0;
-    for (int q = 0; q < G; ++q) s += red[q * tp + threadIdx.x];
-    part[(int64_t)blockIdx.x * tp + threadIdx.x] = s;
   }
 }
 
@@ -891,14 +951,37 @@ hipError_t run_bwd_nt(const BLayout& L, char* ws, hipStream_t st) {
 // pact: per-problem active-column counts (rows of finished problems are skipped), or NULL
 hipError_t bl_woodbury(const BLayout& L, char* ws, hipStream_t st, const double* Rsrc, double* Zdst, double* part,
                        const int* nact, const int* pact) {
+  const int KP = (L.K + 15) / 16 * 16;
   if (L.K > 0) {
-    hipLaunchKernelGGL(kb_ltr_part, dim3(L.nblk), dim3(256), 0, st, at<BDesc>(ws, L.desc), at<int32_t>(ws, L.blkprob),
-                       at<double>(ws, L.L), Rsrc, L.K, L.tp, at<double>(ws, L.ltr_part), nact, pact);
+    const dim3 g(L.nblk, (KP / 16 + 3) / 4);
+#define BLTR(NT)                                                                                                  \
+  hipLaunchKernelGGL((kb_ltr_mfma<NT>), g, dim3(256), 0, st, at<BDesc>(ws, L.desc), at<int32_t>(ws, L.blkprob),   \
+                     at<double>(ws, L.L), Rsrc, KP, L.tp, at<double>(ws, L.ltr_part), nact, pact)
+    switch (L.tp / 16) {
+      case 1: BLTR(1); break;
+      case 2: BLTR(2); break;
+      case 3: BLTR(3); break;
+      case 4: BLTR(4); break;
+      case 5: BLTR(5); break;
+      default: return hipErrorInvalidValue;
+    }
+#undef BLTR
     hipLaunchKernelGGL(kb_wood_y, dim3(L.B), dim3(256), 0, st, at<BDesc>(ws, L.desc), at<double>(ws, L.ltr_part),
-                       at<double>(ws, L.Cinv), L.K, L.tp, at<double>(ws, L.Tb), at<double>(ws, L.Y), nact);
+                       at<double>(ws, L.Cinv), L.K, KP, L.tp, at<double>(ws, L.Tb), at<double>(ws, L.Y), nact);
   }
-  hipLaunchKernelGGL(kb_zapply, dim3(L.nblk), dim3(256), 0, st, at<BDesc>(ws, L.desc), at<int32_t>(ws, L.blkprob),
-                     at<double>(ws, L.L), at<double>(ws, L.Y), Rsrc, L.K, L.tp, Zdst, part, nact, pact);
+#define BZAP(NT)                                                                                                   \
+  hipLaunchKernelGGL((kb_zapply_mfma<NT>), dim3(L.nblk), dim3(256), 0, st, at<BDesc>(ws, L.desc),                  \
+                     at<int32_t>(ws, L.blkprob), at<double>(ws, L.L), at<double>(ws, L.Y), Rsrc, L.K, L.tp, Zdst, part, \
+                     nact, pact)
+  switch (L.tp / 16) {
+    case 1: BZAP(1); break;
+    case 2: BZAP(2); break;
+    case 3: BZAP(3); break;
+    case 4: BZAP(4); break;
+    case 5: BZAP(5); break;
+    default: return hipErrorInvalidValue;
+  }
+#undef BZAP
   return hipGetLastError();
 }
 
