@@ -43,7 +43,7 @@ int check_batch_options(const gp_options* o, int32_t rank) {
   if (!o) return GP_EINVAL;
   if (o->precision < 0 || o->precision > 3) return GP_EINVAL;
   if (o->num_probes < 1 || o->num_probes > GP_MAX_PROBES) return GP_EINVAL;
-  if (o->max_iters < 1 || o->max_iters > 2730) return GP_EINVAL;  // tridiagonal in 64 KB of LDS
+  if (o->max_iters < 1 || o->max_iters > 2645) return GP_EINVAL;  // tridiagonal + 256 doubles in 64 KB of LDS
   if (!(o->cg_tol >= 0.0) || !std::isfinite(o->cg_tol)) return GP_EINVAL;
   if (o->precond_grad != 0 && o->precond_grad != 1) return GP_EINVAL;
   if (o->sync_every < 0) return GP_EINVAL;

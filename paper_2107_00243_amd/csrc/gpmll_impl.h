@@ -20,6 +20,7 @@
 namespace gpmll {
 
 constexpr int kRowBlock = 256;      // rows per workgroup of the tile kernels; n is padded to this
+constexpr int kSlqQrMax = 128;      // longest Lanczos tridiagonal diagonalised by QR; longer: quadrature
 constexpr int kWgSlots = 512;       // resident tile workgroups on MI355X: 2 per CU x 256 CUs
 constexpr int kColChunk = 32;       // K-dimension of one tile-times-V step (MFMA K for BF16)
 constexpr int kRedBlock = 256;      // threads of the reduction kernels

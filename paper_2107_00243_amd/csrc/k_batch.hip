@@ -604,28 +604,43 @@ __global__ void kb_swap(int* __restrict__ nactive, int* __restrict__ nactive_nex
 // ---------------------------------------------------------------------------
 // Lanczos quadrature and log p per problem
 // ---------------------------------------------------------------------------
-__global__ void kb_slq(const double* __restrict__ alog, const double* __restrict__ blog, const int* __restrict__ iters,
-                       const double* __restrict__ rho0, int ell, int tp, int max_iters, double* __restrict__ gamma,
-                       int* __restrict__ flags) {
+// one workgroup per (problem, probe), as k_slq (QR up to kSlqQrMax steps, else the
+// quadrature of tridiag_log_e1 with the problem's spectral lower bound)
+__global__ __launch_bounds__(256) void kb_slq(const BDesc* __restrict__ desc, const double* __restrict__ alog,
+                                              const double* __restrict__ blog, const int* __restrict__ iters,
+                                              const double* __restrict__ rho0, int ell, int tp, int max_iters,
+                                              double* __restrict__ gamma, int* __restrict__ flags) {
   extern __shared__ double sm_tri[];
-  if (threadIdx.x != 0) return;
+  __shared__ int bad;
   const int b = blockIdx.x / ell, i = blockIdx.x % ell;
   const int e = b * tp + 1 + i;
   const int m = iters[e];
+  if (m == 0) {
+    if (threadIdx.x == 0) gamma[b * ell + i] = 0.0;
+    return;
+  }
+  const BDesc& D = desc[b];
   double* a = sm_tri;
   double* bb = a + max_iters;
   double* z = bb + max_iters;
-  if (m == 0) {
-    gamma[b * ell + i] = 0.0;
-    return;
-  }
+  double* red = z + max_iters;
   const double* al = alog + (int64_t)e * max_iters;
   const double* be = blog + (int64_t)e * max_iters;
-  a[0] = 1.0 / al[0];
-  for (int j = 1; j < m; ++j) {
-    a[j] = 1.0 / al[j] + be[j - 1] / al[j - 1];
-    bb[j - 1] = sqrt(be[j - 1]) / al[j - 1];
+  for (int j = threadIdx.x; j < m; j += blockDim.x) {
+    a[j] = 1.0 / al[j] + (j > 0 ? be[j - 1] / al[j - 1] : 0.0);
+    if (j + 1 < m) bb[j] = be[j] / (al[j] * al[j]);
   }
+  __syncthreads();
+  if (m > kSlqQrMax) {
+    double v;
+    const double lam_lo = D.s2 / (D.s2 + (double)D.n * D.s);
+    if (tridiag_log_e1(a, bb, m, lam_lo, red, &bad, &v)) {
+      if (threadIdx.x == 0) gamma[b * ell + i] = rho0[e] * v;
+      return;
+    }
+  }
+  if (threadIdx.x != 0) return;
+  for (int j = 0; j + 1 < m; ++j) bb[j] = sqrt(bb[j]);
   tridiag_eig_first_row(a, bb, z, m);
   double s = 0.0;
   int cl = 0;
@@ -1075,11 +1090,11 @@ hipError_t bl_cg_after_product(const BLayout& L, char* ws, hipStream_t st, int i
 }
 
 hipError_t bl_slq_logp(const BLayout& L, char* ws, hipStream_t st, const double* y, double* logp) {
-  const size_t smem = (size_t)3 * L.max_iters * sizeof(double);
+  const size_t smem = ((size_t)3 * L.max_iters + 256) * sizeof(double);
   if (smem > 64 * 1024) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(kb_slq, dim3(L.B * L.ell), dim3(64), smem, st, at<double>(ws, L.alog), at<double>(ws, L.blog),
-                     at<int>(ws, L.iters), at<double>(ws, L.rho0), L.ell, L.tp, L.max_iters, at<double>(ws, L.gamma),
-                     at<int>(ws, L.flags));
+  hipLaunchKernelGGL(kb_slq, dim3(L.B * L.ell), dim3(256), smem, st, at<BDesc>(ws, L.desc), at<double>(ws, L.alog),
+                     at<double>(ws, L.blog), at<int>(ws, L.iters), at<double>(ws, L.rho0), L.ell, L.tp, L.max_iters,
+                     at<double>(ws, L.gamma), at<int>(ws, L.flags));
   hipLaunchKernelGGL(kb_logp, dim3(L.B), dim3(256), 0, st, at<BDesc>(ws, L.desc), y, at<double>(ws, L.Xs), L.tp, L.t,
                      L.ell, at<double>(ws, L.gamma), at<double>(ws, L.logdetP), at<int>(ws, L.active),
                      at<int32_t>(ws, L.stop), at<int>(ws, L.flags), at<double>(ws, L.logp_aux), logp);

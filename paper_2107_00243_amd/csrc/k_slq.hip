@@ -16,30 +16,47 @@
 
 namespace gpmll {
 
-// one workgroup per probe column c = 1 + blockIdx.x; the eigen-solve runs on one
-// lane with the tridiagonal in LDS (3 * max_iters doubles of dynamic shared memory)
-__global__ void k_slq(const double* __restrict__ alog, const double* __restrict__ blog,
-                      const int* __restrict__ iters, const double* __restrict__ rho0, int ell, int max_iters,
-                      double* __restrict__ gamma, int* __restrict__ clamp) {
+// one workgroup of 256 threads per probe column c = 1 + blockIdx.x, tridiagonal in
+// LDS (dynamic shared memory: 3 max_iters + 256 doubles).  Up to kSlqQrMax Lanczos
+// steps one lane diagonalises T (QR, first row of the eigenvectors); longer T take
+// e1^T log(T) e1 from the quadrature of tridiag_log_e1 over the whole workgroup,
+// with lam_lo a lower bound of the preconditioned spectrum, and fall back to the
+// QR if T is not numerically positive definite.
+__global__ __launch_bounds__(256) void k_slq(const double* __restrict__ alog, const double* __restrict__ blog,
+                                             const int* __restrict__ iters, const double* __restrict__ rho0, int ell,
+                                             int max_iters, double lam_lo, double* __restrict__ gamma,
+                                             int* __restrict__ clamp) {
   extern __shared__ double sm_tri[];
+  __shared__ int bad;
   const int i = blockIdx.x;
-  if (i >= ell || threadIdx.x != 0) return;
+  if (i >= ell) return;
   const int c = 1 + i;
   const int m = iters[c];
+  if (m == 0) {
+    if (threadIdx.x == 0) gamma[i] = 0.0;
+    return;
+  }
   double* a = sm_tri;
   double* b = a + max_iters;
   double* z = b + max_iters;
+  double* red = z + max_iters;
   const double* al = alog + (int64_t)c * max_iters;
   const double* be = blog + (int64_t)c * max_iters;
-  if (m == 0) {
-    gamma[i] = 0.0;
-    return;
+  // T_11 = 1/alpha_0, T_jj = 1/alpha_j + beta_{j-1}/alpha_{j-1}, T_{j,j+1}^2 = beta_j / alpha_j^2
+  for (int j = threadIdx.x; j < m; j += blockDim.x) {
+    a[j] = 1.0 / al[j] + (j > 0 ? be[j - 1] / al[j - 1] : 0.0);
+    if (j + 1 < m) b[j] = be[j] / (al[j] * al[j]);
   }
-  a[0] = 1.0 / al[0];
-  for (int j = 1; j < m; ++j) {
-    a[j] = 1.0 / al[j] + be[j - 1] / al[j - 1];
-    b[j - 1] = sqrt(be[j - 1]) / al[j - 1];
+  __syncthreads();
+  if (m > kSlqQrMax) {
+    double v;
+    if (tridiag_log_e1(a, b, m, lam_lo, red, &bad, &v)) {
+      if (threadIdx.x == 0) gamma[i] = rho0[c] * v;
+      return;
+    }
   }
+  if (threadIdx.x != 0) return;
+  for (int j = 0; j + 1 < m; ++j) b[j] = sqrt(b[j]);
   tridiag_eig_first_row(a, b, z, m);
   double s = 0.0;
   int cl = 0;
@@ -55,7 +72,7 @@ __global__ void k_slq(const double* __restrict__ alog, const double* __restrict_
   if (cl) atomicAdd(clamp, cl);
 }
 
-// the same with the tridiagonal in global memory (iteration caps above 2730)
+// the same with the tridiagonal in global memory (iteration caps above 2645)
 __global__ void k_slq_global(const double* __restrict__ alog, const double* __restrict__ blog,
                              const int* __restrict__ iters, const double* __restrict__ rho0, int ell, int max_iters,
                              double* __restrict__ work, double* __restrict__ gamma, int* __restrict__ clamp) {
@@ -137,13 +154,15 @@ __global__ void k_logp(const double* __restrict__ part, int nblk, const double* 
 }
 
 hipError_t launch_slq_logp(const Ctx& c, const Hyper& h, const double* y, double* logp) {
-  (void)h;
   const Layout& L = *c.lay;
   double* sl = c.at<double>(L.gamma);  // gamma[ell] | datafit | logdet_est
-  const size_t smem = (size_t)3 * L.max_iters * sizeof(double);
+  const size_t smem = ((size_t)3 * L.max_iters + 256) * sizeof(double);
+  // lower bound of the spectrum of P^-1/2 K_hat P^-1/2: sigma^2 / (sigma^2 + tr L L^T), tr L L^T <= n s
+  const double lam_lo = h.s2 / (h.s2 + (double)L.n * h.s);
   if (smem <= 64 * 1024)
-    hipLaunchKernelGGL(k_slq, dim3(L.ell), dim3(64), smem, c.st, c.at<double>(L.alog), c.at<double>(L.blog),
-                       c.at<int>(L.iters), c.at<double>(L.rho0), L.ell, L.max_iters, sl, c.at<int>(L.flags) + 2);
+    hipLaunchKernelGGL(k_slq, dim3(L.ell), dim3(256), smem, c.st, c.at<double>(L.alog), c.at<double>(L.blog),
+                       c.at<int>(L.iters), c.at<double>(L.rho0), L.ell, L.max_iters, lam_lo, sl,
+                       c.at<int>(L.flags) + 2);
   else
     hipLaunchKernelGGL(k_slq_global, dim3((L.ell + 63) / 64), dim3(64), 0, c.st, c.at<double>(L.alog),
                        c.at<double>(L.blog), c.at<int>(L.iters), c.at<double>(L.rho0), L.ell, L.max_iters,

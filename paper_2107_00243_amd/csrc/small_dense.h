@@ -201,4 +201,69 @@ inline __device__ void tridiag_eig_first_row(double* a, double* b, double* z, in
   }
 }
 
+// e1^T log(T) e1 of a symmetric positive definite tridiagonal T (diagonal a,
+// squared off-diagonal bb, order m, both readable by the whole workgroup), by the
+// trapezoidal rule on
+//   log x = int_R ( e^u / (1 + e^u) - e^u / (x + e^u) ) du,
+// whose integrand is analytic in |Im u| < pi: with step h = 1/2 the rule's error
+// is about exp(-2 pi^2 / h) ~ 1e-17, and u runs from log(min(lam_lo, 1)) - 40 to
+// log(max(Gershgorin bound, 1)) + 40 (tails below 4e-18).  At each node
+// e1^T (T + t I)^-1 e1 = 1 / f_0 with the continued fraction
+//   f_{m-1} = a_{m-1} + t,  f_k = a_k + t - bb_k / f_{k+1},
+// and the integrand t (f_0 - 1 - t) / ((1 + t) f_0) uses f_0 - 1 - t formed without
+// t, free of cancellation.  Returns false on every thread if some f_k <= 0 (T not
+// numerically positive definite).  red: blockDim.x doubles of shared memory.
+inline __device__ bool tridiag_log_e1(const double* a, const double* bb, int m, double lam_lo, double* red,
+                                      int* bad, double* result) {
+  // Gershgorin upper bound of the spectrum
+  double g = 0.0;
+  for (int k = threadIdx.x; k < m; k += blockDim.x) {
+    double r = a[k];
+    if (k > 0) r += sqrt(bb[k - 1]);
+    if (k + 1 < m) r += sqrt(bb[k]);
+    g = fmax(g, r);
+  }
+  red[threadIdx.x] = g;
+  if (threadIdx.x == 0) *bad = 0;
+  __syncthreads();
+  for (int off = blockDim.x / 2; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + off]);
+    __syncthreads();
+  }
+  const double hi = red[0];
+  __syncthreads();
+  const double h = 0.5;
+  const double u0 = log(fmin(lam_lo, 1.0)) - 40.0;
+  const double u1 = log(fmax(hi, 1.0)) + 40.0;
+  const int nodes = (int)ceil((u1 - u0) / h) + 1;
+  double acc = 0.0;
+  int mybad = 0;
+  for (int q = threadIdx.x; q < nodes; q += blockDim.x) {
+    const double t = exp(u0 + h * q);
+    double f = a[m - 1] + t;
+    mybad |= !(f > 0.0);
+    for (int k = m - 2; k >= 1; --k) {
+      f = a[k] + t - bb[k] / f;
+      mybad |= !(f > 0.0);
+    }
+    // f0 - 1 - t and f0
+    const double fm = (m >= 2) ? (a[0] - 1.0 - bb[0] / f) : (a[0] - 1.0);
+    const double f0 = fm + 1.0 + t;
+    mybad |= !(f0 > 0.0);
+    acc += t * fm / ((1.0 + t) * f0);
+  }
+  if (mybad) atomicOr(bad, 1);
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int off = blockDim.x / 2; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+    __syncthreads();
+  }
+  const double total = red[0];
+  const bool ok = *bad == 0;
+  __syncthreads();
+  *result = h * total;
+  return ok;
+}
+
 }  // namespace gpmll

@@ -309,3 +309,15 @@ def test_adam_on_the_autograd_function_follows_the_oracle_trajectory():
         opt.step()
     np.testing.assert_allclose(theta, np.exp(lt.detach().numpy()), rtol=1e-6)
     assert hist[-1]["logp"] > hist[0]["logp"]
+
+
+def test_long_lanczos_runs_take_the_quadrature_path_and_match_the_oracle():
+    # ~470 CG steps per probe, beyond the tridiagonals diagonalised by QR: the
+    # log-determinant quadrature e1^T log(T) e1 comes from the integral form
+    pr = synthgp.random_problem(600, 3, "rbf", True, rank=0, num_probes=6, seed=11, sigma2=1e-4,
+                                ls_range=(0.5, 2.0), tol=1e-10, max_iters=600)
+    out = run_estimator(pr, "fp64", rank=0)
+    ref = oracle(pr, rank=0)
+    assert out["stats"].iters_max > 128
+    _check_tight(out, ref, FP64_LP, FP64_G)
+    np.testing.assert_allclose(out["stats"].gammas, ref["gammas"], rtol=1e-7)
