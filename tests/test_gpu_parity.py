@@ -321,3 +321,58 @@ def test_long_lanczos_runs_take_the_quadrature_path_and_match_the_oracle():
     assert out["stats"].iters_max > 128
     _check_tight(out, ref, FP64_LP, FP64_G)
     np.testing.assert_allclose(out["stats"].gammas, ref["gammas"], rtol=1e-7)
+
+
+# ---------------------------------------------------------------- full-size workloads
+
+@pytest.mark.parametrize("workload,precisions", [
+    ("rbf_ard_100k", ["bf16x3", "fp16x3", "fp64"]),
+    ("matern52_ard_20k", ["fp32", "fp64"]),
+    ("gmm_matern32_300k", ["bf16x3", "fp16x3"]),
+])
+def test_full_size_khat_rows_match_the_oracle(workload, precisions):
+    # the product of every CG iteration at the workload's full size, in the launch
+    # configuration of the estimator; the oracle computes 48 sampled rows one by one
+    pr = getattr(synthgp, workload)()
+    n, t = pr.n, 1 + pr.num_probes
+    rng = np.random.default_rng(3)
+    rows = np.unique(np.concatenate([[0, n - 1], rng.choice(n, 46, replace=False)]))
+    V = rng.standard_normal((n, t))
+    ref = go.khat_matvec(pr.X, pr.theta, pr.kernel, pr.ard, V, rows=rows)
+    scale = go.khat_matvec(pr.X, pr.theta, pr.kernel, pr.ard, np.abs(V), rows=rows)  # K_hat >= 0 entrywise
+    dev = torch.device("cuda:0")
+    X = torch.tensor(pr.X, device=dev)
+    y = torch.tensor(pr.y, device=dev)
+    prob = B.make_problem(X, y, pr.kernel, pr.ard)
+    Vd = torch.tensor(V, device=dev)
+    for prec in precisions:
+        say(f"[gpu] full-size khat rows {workload} n={n} t={t} {prec}")
+        opt = B.make_options(prec, pr.num_probes, 1)
+        ws = B.alloc_workspace(B.gp_workspace_size(prob, opt, 0))
+        Wd = torch.zeros_like(Vd)
+        B.gp_khat_matvec(prob, pr.theta, prec, Vd, Wd, ws)
+        W = Wd[torch.tensor(rows, device=dev)].cpu().numpy()
+        err = np.max(np.abs(W - ref) / scale)
+        say(f"    max scaled error {err:.3e}")
+        assert err < MATVEC_TOL[prec]
+        del ws, Wd
+        torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("workload,precision,lp_tol,g_tol", [
+    ("rbf_ard_100k", "bf16x3", 1e-5, 1e-3),
+    ("rbf_ard_100k", "fp16x3", 1e-5, 1e-3),
+    ("matern52_ard_20k", "fp32", 1e-4, 1e-2),
+])
+def test_full_size_estimator_against_the_fp64_tiles(workload, precision, lp_tol, g_tol):
+    # property that holds at any size: the split / single precision estimate tracks
+    # the FP64-tile estimate of the same probes (the full-size oracle is out of reach)
+    pr = getattr(synthgp, workload)()
+    lo = run_estimator(pr, precision)
+    hi = run_estimator(pr, "fp64")
+    say(f"    logp {lo['logp']:.10g} vs {hi['logp']:.10g}: rel {rel(lo['logp'], hi['logp']):.2e}; "
+        f"grad rel {relvec(lo['grad'], hi['grad']):.2e}")
+    # (FP32 tiles can leave a column just above the CG tolerance at the iteration cap;
+    # the estimate is still within the bar)
+    assert rel(lo["logp"], hi["logp"]) < lp_tol
+    assert relvec(lo["grad"], hi["grad"]) < g_tol
