@@ -19,7 +19,8 @@ Two parts:
   coefficients (supplement S1.2), Lanczos quadrature for the log (Section 2.2,
   SLQ), the log-determinant decomposition (Section 3) and the derivative
   decomposition (Section 3.3) with the trace of P^-1 dP computed by the matrix
-  inversion lemma (supplement S3.3).
+  inversion lemma (supplement S3.3).  The random Fourier feature preconditioner
+  of Table 1 (reading R-rff) can replace the pivoted Cholesky one.
 
 Readings taken where the paper is silent or loose (each is listed with its reason
 in the design notes):
@@ -48,6 +49,12 @@ R-cg     x0 = 0; a column stops after the iteration whose updated recurrence
 R-kern   k(x, x') = s * kappa(r), r^2 = sum_j ((x_j - x'_j) / ls_j)^2, noise
          sigma^2 on the diagonal; theta = [ls | s | sigma^2] natural parameters.
 R-ritz   Ritz values below 1e-300 are clamped to 1e-300 before the log.
+R-rff    Random Fourier feature preconditioner (Table 1, "RFF"): m = k/2 frequency
+         samples w_j of the kernel's spectral density at unit lengthscale are an
+         input; Z = sqrt(s/m) [cos(Phi) | sin(Phi)] with Phi = X~ W^T and
+         X~ = (X - column mean) / ls, so Z Z^T = (s/m) sum_j cos(w_j.(x~_a - x~_b))
+         (the origin of the phases is invisible in Z Z^T; the data mean fixes Z).
+         dP/dtheta holds the frequencies fixed.
 """
 from __future__ import annotations
 
@@ -320,6 +327,46 @@ class Preconditioner:
 
 
 # ----------------------------------------------------------------------------
+# Random Fourier feature preconditioner P = sigma^2 I + Z Z^T (Table 1, "RFF";
+# supplement S5, RFF approximation quality; Rahimi & Recht 2007), reading R-rff
+# ----------------------------------------------------------------------------
+
+def _rff_phases(X, theta, ard, freqs):
+    n, d = X.shape
+    ls, s, _ = split_theta(theta, d, ard)
+    freqs = np.asarray(freqs, dtype=np.float64)
+    if freqs.ndim != 2 or freqs.shape[1] != d:
+        raise ValueError("freqs must be (m, d)")
+    Xt = (X - X.mean(axis=0)) / ls
+    return Xt, ls, s, Xt @ freqs.T
+
+
+def rff_features(X, theta, ard, freqs):
+    """Z (n, 2m): columns 0..m-1 are sqrt(s/m) cos(Phi), columns m..2m-1 sqrt(s/m) sin(Phi)."""
+    _, _, s, Phi = _rff_phases(X, theta, ard, freqs)
+    a = math.sqrt(s / Phi.shape[1])
+    return a * np.concatenate([np.cos(Phi), np.sin(Phi)], axis=1)
+
+
+def rff_feature_derivatives(X, theta, ard, freqs):
+    """dZ/dtheta for the kernel parameters in theta order (lengthscales, then s),
+    frequencies held fixed: dPhi_ij/dls_q = -w_jq x~_iq / ls_q, d cos = -sin dPhi,
+    d sin = cos dPhi, dZ/ds = Z / (2 s)."""
+    n, d = X.shape
+    Xt, ls, s, Phi = _rff_phases(X, theta, ard, freqs)
+    m = Phi.shape[1]
+    a = math.sqrt(s / m)
+    C, S = np.cos(Phi), np.sin(Phi)
+    per_dim = []
+    for q in range(d):
+        dPhi = -np.outer(Xt[:, q], freqs[:, q]) / ls[q]
+        per_dim.append(a * np.concatenate([-S * dPhi, C * dPhi], axis=1))
+    out = per_dim if ard else [sum(per_dim)]
+    out.append(a * np.concatenate([C, S], axis=1) / (2.0 * s))
+    return out
+
+
+# ----------------------------------------------------------------------------
 # Preconditioned CG, one column at a time (R-cg), and the Lanczos tridiagonal
 # ----------------------------------------------------------------------------
 
@@ -476,14 +523,39 @@ def _precond_terms(X, theta, kind, ard, L, piv, kp, P, Cs, mode):
     return tr, ctrl
 
 
+def _precond_terms_rff(X, theta, ard, freqs, Z, P, Cs, mode):
+    """tr(P^-1 dP/dtheta) and the control variates c_i^T dP c_i for the RFF
+    preconditioner, dP = dZ Z^T + Z dZ^T, with P^-1 = sigma^-2 (I - Z C^-1 Z^T)
+    (matrix inversion lemma, as in supplement S3.3)."""
+    n, d = X.shape
+    _, _, s2 = split_theta(theta, d, ard)
+    p = d if ard else 1
+    ell = Cs.shape[1]
+    tr = np.zeros(p + 2)
+    ctrl = np.zeros((p + 2, ell))
+    ZCinv = P.Cinv(Z.T).T
+    tr[p + 1] = (n - np.sum(ZCinv * Z)) / s2
+    ctrl[p + 1] = np.sum(Cs * Cs, axis=0)
+    ZtC = Z.T @ Cs
+    ZtZ = Z.T @ Z
+    for idx, dZ in enumerate(rff_feature_derivatives(X, theta, ard, freqs)):
+        if mode == 1 and idx < p:
+            continue
+        dP_Z = dZ @ ZtZ + Z @ (dZ.T @ Z)                         # dP Z
+        tr[idx] = (2.0 * np.sum(dZ * Z) - np.sum(ZCinv * dP_Z)) / s2
+        ctrl[idx] = 2.0 * np.sum(ZtC * (dZ.T @ Cs), axis=0)
+    return tr, ctrl
+
+
 def estimate_mll(X, y, theta, kind, ard, rank, num_probes, tol, max_iters, seed,
-                 grad=True, precond_grad=0, signs=None, dense=None):
+                 grad=True, precond_grad=0, signs=None, dense=None, precond="pivchol", freqs=None):
     """Preconditioned estimate of log p (Algorithm 1) and, if grad, of its
     derivative (Algorithm 2) under the readings in the module docstring.
 
     signs: optional (E, H) Rademacher arrays of shapes (n, ell), (rank, ell)
     replacing the SplitMix64 stream.  dense: force (True) or forbid (False) a
-    dense K_hat; default dense for n <= 20000."""
+    dense K_hat; default dense for n <= 20000.  precond: "pivchol" (partial
+    pivoted Cholesky of the given rank) or "rff" (R-rff; freqs (rank/2, d))."""
     X = np.ascontiguousarray(X, dtype=np.float64)
     y = np.asarray(y, dtype=np.float64)
     n, d = X.shape
@@ -495,8 +567,16 @@ def estimate_mll(X, y, theta, kind, ard, rank, num_probes, tol, max_iters, seed,
     def matvec(V):
         return Kh @ V if dense else khat_matvec(X, theta, kind, ard, V)
 
-    # preconditioner (pivoted Cholesky) and log det P
-    L, piv, kp = pivoted_cholesky(X, theta, kind, ard, rank)
+    # preconditioner (pivoted Cholesky or random Fourier features) and log det P
+    if precond == "rff":
+        if freqs is None or 2 * len(freqs) != rank:
+            raise ValueError("the RFF preconditioner needs rank / 2 frequency rows")
+        L = rff_features(X, theta, ard, freqs)
+        piv, kp = np.full(rank, -1, dtype=np.int64), rank
+    elif precond == "pivchol":
+        L, piv, kp = pivoted_cholesky(X, theta, kind, ard, rank)
+    else:
+        raise ValueError(precond)
     P = Preconditioner(L[:, :kp], s2)
 
     # probes b_i = sigma eps_i + L eta_i (R-probe)
@@ -536,7 +616,10 @@ def estimate_mll(X, y, theta, kind, ard, rank, num_probes, tol, max_iters, seed,
     A1 = Xs
     C1 = np.concatenate([0.5 * u[:, None], -Cs / (2.0 * ell)], axis=1)
     bil = dkhat_contract(X, theta, kind, ard, lambda r: A1[r] @ C1.T)
-    tr, ctrl = _precond_terms(X, theta, kind, ard, L, piv, kp, P, Cs, precond_grad)
+    if precond == "rff":
+        tr, ctrl = _precond_terms_rff(X, theta, ard, freqs, L, P, Cs, precond_grad)
+    else:
+        tr, ctrl = _precond_terms(X, theta, kind, ard, L, piv, kp, P, Cs, precond_grad)
     g = bil - 0.5 * tr + ctrl.sum(axis=1) / (2.0 * ell)
     out.update({"grad": g, "bilinear": bil, "tr_precond": tr, "ctrl": ctrl, "precond_solves": Cs})
     return out

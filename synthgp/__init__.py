@@ -77,6 +77,20 @@ def rff_targets(rng, X, ls, s, sigma2, kernel, num_features=4096):
     return f + np.sqrt(sigma2) * rng.standard_normal(n)
 
 
+def spectral_frequencies(kernel, m, d, seed=0):
+    """m samples (m, d) of the kernel's spectral density at unit lengthscale, the
+    random input of the random Fourier feature preconditioner: N(0, I) for the
+    RBF kernel, z * sqrt(2 nu / u) with z ~ N(0, I), u ~ chi^2(2 nu) for Matern-nu
+    (module docstring)."""
+    rng = np.random.default_rng(np.random.SeedSequence([int(seed), 0x52FF]))
+    z = rng.standard_normal((m, d))
+    if kernel == "rbf":
+        return z
+    nu = {"matern32": 1.5, "matern52": 2.5}[kernel]
+    u = rng.chisquare(2.0 * nu, size=(m, 1))
+    return z * np.sqrt(2.0 * nu / u)
+
+
 def plain_rbf_1000(n=1000, seed=0):
     """Uniform[0,1]^3 inputs, isotropic RBF (ls 0.3, s 1, sigma^2 0.1), FP64 tiles."""
     rng = np.random.default_rng(seed)
