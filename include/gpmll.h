@@ -155,6 +155,30 @@ int gp_workspace_size(const gp_problem* prob, const gp_options* opt, int32_t ran
 int gp_precond_build(const gp_problem* prob, const double* theta_host, int32_t rank,
                      void* ws_dev, size_t ws_bytes, hipStream_t stream, gp_precond** out);
 
+/*
+ * gp_precond_build_rff — random Fourier feature preconditioner
+ * P_hat = sigma^2 I + Z Z^T (Table 1, "RFF"; supplement S5, RFF approximation
+ * quality), an alternative to gp_precond_build with the same handle, workspace
+ * layout and later use:
+ *   Z = sqrt(s / m) [cos(Phi) | sin(Phi)]   (n x rank, rank = 2m, column-major),
+ *   Phi = X~ W^T,  X~ = (X - column mean) / ls,
+ * so that Z Z^T = (s/m) sum_j cos(w_j . (x~_a - x~_b)), whose expectation over w_j
+ * drawn from the kernel's spectral density is K.  Then C, its factors and
+ * log det P_hat as in gp_precond_build.  freq_dev is a device array of m x d
+ * FP64 (row-major, row j = w_j): samples of the kernel's spectral density at
+ * unit lengthscale (RBF: standard normal; Matern-nu: multivariate Student t
+ * with 2 nu degrees of freedom).  They are copied into the workspace in stream
+ * order, so freq_dev may be released once the stream has passed this call.
+ * gp_mll_grad with this handle differentiates P_hat with the frequencies held
+ * fixed (precond_grad = 1 keeps only the s and sigma^2 terms, as for the
+ * pivoted Cholesky).  The pivots of the view read -1.
+ * Errors: GP_EINVAL for an odd rank, rank < 2, a null freq_dev, or as
+ * gp_precond_build; GP_EWORKSPACE; GP_EHIP.
+ */
+int gp_precond_build_rff(const gp_problem* prob, const double* theta_host, int32_t rank,
+                         const double* freq_dev, void* ws_dev, size_t ws_bytes, hipStream_t stream,
+                         gp_precond** out);
+
 /* gp_precond_view_of — device views of a built preconditioner. */
 int gp_precond_view_of(const gp_precond* P, gp_precond_view* view);
 

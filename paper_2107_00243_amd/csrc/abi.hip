@@ -14,7 +14,7 @@ hipError_t launch_stage_x(const Ctx& c, const Hyper& h);
 hipError_t launch_stage_x_bwd(const Ctx& c, const Hyper& h);
 hipError_t launch_cg_after_product(const Ctx& c, const Hyper& h, int it, double tol);
 hipError_t launch_slq_logp(const Ctx& c, const Hyper& h, const double* y, double* logp);
-hipError_t launch_backward(const Ctx& c, const Hyper& h, int ard, int precond_grad, double* grad);
+hipError_t launch_backward(const Ctx& c, const Hyper& h, int ard, int precond_grad, int precond_kind, double* grad);
 
 static size_t al(size_t x) { return (x + 255) / 256 * 256; }
 static int64_t rup(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
@@ -115,6 +115,7 @@ Layout make_layout(int64_t n, int d, int ard, int num_probes, int max_iters, int
   L.scal_small = take(64);
   L.flags = take(64);
   L.ltr_part = take((size_t)L.nchunk * kk * kk * 8);
+  L.freq = take((size_t)(kk / 2 + 1) * GP_MAX_D * 8);
   L.precond_end = off;
   // estimator block
   L.xfa = take(np * L.kd * esz);
@@ -175,6 +176,7 @@ struct gp_precond {
   char* ws;
   std::vector<double> theta;
   gp_problem prob;
+  int kind = kPivChol;
 };
 
 static thread_local int g_last_hip = 0;
@@ -310,6 +312,39 @@ extern "C" int gp_precond_build(const gp_problem* prob, const double* theta_host
   return GP_OK;
 }
 
+extern "C" int gp_precond_build_rff(const gp_problem* prob, const double* theta_host, int32_t rank,
+                                    const double* freq_dev, void* ws_dev, size_t ws_bytes, hipStream_t stream,
+                                    gp_precond** out) {
+  if (!out) return GP_EINVAL;
+  *out = nullptr;
+  RET_IF(check_problem(prob));
+  RET_IF(check_rank(prob, rank));
+  if (rank < 2 || rank % 2 != 0 || !freq_dev) return GP_EINVAL;
+  Hyper h;
+  RET_IF(make_hyper(prob, theta_host, &h));
+  RET_IF(check_device());
+  Layout L = make_layout(prob->n, prob->d, prob->ard, 1, 1, rank, GP_PREC_FP64);
+  if (!ws_dev || (reinterpret_cast<uintptr_t>(ws_dev) & 255) != 0) return GP_EINVAL;
+  if (ws_bytes < L.precond_end) return GP_EWORKSPACE;
+  Ctx c{&L, (char*)ws_dev, stream};
+  HIPCHK(hipMemsetAsync(c.at<int>(L.flags), 0, 64, stream));
+  // the samples are copied into the workspace, so the handle does not keep freq_dev
+  HIPCHK(hipMemcpyAsync(c.at<double>(L.freq), freq_dev, (size_t)(rank / 2) * prob->d * sizeof(double),
+                        hipMemcpyDeviceToDevice, stream));
+  HIPCHK(launch_prep(c, prob->X_dev, h));
+  HIPCHK(launch_rff(c, h));
+  HIPCHK(launch_precond_finish(c, h));
+  gp_precond* P = new gp_precond;
+  P->lay = L;
+  P->ws = (char*)ws_dev;
+  P->prob = *prob;
+  P->kind = kRff;
+  const int p = prob->ard ? prob->d : 1;
+  P->theta.assign(theta_host, theta_host + p + 2);
+  *out = P;
+  return GP_OK;
+}
+
 extern "C" int gp_precond_view_of(const gp_precond* P, gp_precond_view* view) {
   if (!P || !view) return GP_EINVAL;
   view->L_dev = reinterpret_cast<const double*>(P->ws + P->lay.L);
@@ -382,7 +417,7 @@ static int run_estimator(const gp_problem* prob, const double* theta_host, const
   HIPCHK(launch_slq_logp(c, h, prob->y_dev, logp_dev));
   if (grad_dev) {
     HIPCHK(launch_stage_x_bwd(c, h));
-    HIPCHK(launch_backward(c, h, prob->ard, opt->precond_grad, grad_dev));
+    HIPCHK(launch_backward(c, h, prob->ard, opt->precond_grad, P ? P->kind : kPivChol, grad_dev));
   }
   if (stats) {
     int flags[4];

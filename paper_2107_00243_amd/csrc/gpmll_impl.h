@@ -87,6 +87,7 @@ struct Layout {
   int nred;             // blocks of the row-parallel reductions (<= 256)
   // preconditioner block (offsets independent of the estimator options)
   size_t xs, mean, mean_part, L, diag, ispiv, piv, amax, C, Rc, Rinv, Cinv, logdetP, scal_small, flags, ltr_part;
+  size_t freq;          // m x d spectral samples of the random Fourier feature preconditioner
   size_t precond_end;
   // estimator block
   size_t xfa, xfb, rowterm, colterm, H, Y, ltr, ltr_raw, ltr_part2;
@@ -124,6 +125,11 @@ struct Ctx {
 hipError_t launch_prep(const Ctx& c, const double* X, const Hyper& h);
 hipError_t launch_pivchol(const Ctx& c, const Hyper& h);
 hipError_t launch_precond_finish(const Ctx& c, const Hyper& h);
+// random Fourier features from the samples at lay.freq into the L slot (rank 2m)
+hipError_t launch_rff(const Ctx& c, const Hyper& h);
+
+// preconditioner families: the low-rank factor in the L slot comes from
+enum PrecondKind { kPivChol = 0, kRff = 1 };
 hipError_t launch_probes(const Ctx& c, const double* y, const Hyper& h, uint64_t seed);
 hipError_t launch_cg_init(const Ctx& c, const Hyper& h);
 

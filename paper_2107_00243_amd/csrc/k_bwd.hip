@@ -633,6 +633,46 @@ __global__ void k_pg_contract(const double* __restrict__ xs, const int32_t* __re
   }
 }
 
+// Random Fourier feature preconditioner: sum over rows p and features of
+// Omega * dZ with the frequencies W fixed.  For lengthscale q,
+//   d cos(Phi_pj) = Z_{p,m+j} w_jq x~_pq / ls_q,  d sin(Phi_pj) = -Z_{p,j} w_jq x~_pq / ls_q
+// (dPhi_pj / dls_q = -w_jq x~_pq / ls_q, amplitude folded into Z), so the term is
+// (x~_pq / ls_q) sum_j w_jq (Omega_pj Z_{p,m+j} - Omega_{p,m+j} Z_pj); the outputscale
+// term is sum_j Omega_pj Z_pj / (2 s).  part[b][q] (q < d) and part[b][d] as k_pg_contract.
+__global__ void k_rff_contract(const double* __restrict__ xs, int64_t n, int m, const double* __restrict__ W,
+                               const double* __restrict__ Omega, const double* __restrict__ Z, Hyper h, int mode,
+                               double* __restrict__ part) {
+  __shared__ double red[256];
+  const int d = h.d;
+  const int64_t row = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  double acc[GP_MAX_D + 1];
+  for (int j = 0; j <= d; ++j) acc[j] = 0.0;
+  if (row < n) {
+    double os = 0.0;
+    for (int j = 0; j < m; ++j) {
+      const double oc = Omega[(int64_t)j * n + row], osn = Omega[(int64_t)(m + j) * n + row];
+      const double zc = Z[(int64_t)j * n + row], zs = Z[(int64_t)(m + j) * n + row];
+      os += oc * zc + osn * zs;
+      if (mode == 0) {
+        const double hj = oc * zs - osn * zc;
+        for (int q = 0; q < d; ++q) acc[q] = fma(hj, W[j * d + q], acc[q]);
+      }
+    }
+    for (int q = 0; q < d; ++q) acc[q] *= xs[row * d + q] * h.inv_ls[q];
+    acc[d] = os / (2.0 * h.s);
+  }
+  for (int j = 0; j <= d; ++j) {
+    red[threadIdx.x] = acc[j];
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+      if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) part[(int64_t)blockIdx.x * (GP_MAX_D + 1) + j] = red[0];
+    __syncthreads();
+  }
+}
+
 // gradient assembly (natural parameters [ls | s | sigma^2]); one workgroup,
 // fixed-order tree reductions
 __device__ double block_sum256(double v) {
@@ -803,7 +843,7 @@ hipError_t launch_bwd_bf16(const Ctx& c, const Hyper& h) {
   }
 }
 
-hipError_t launch_backward(const Ctx& c, const Hyper& h, int ard, int precond_grad, double* grad) {
+hipError_t launch_backward(const Ctx& c, const Hyper& h, int ard, int precond_grad, int precond_kind, double* grad) {
   const Layout& L = *c.lay;
   const int tp = L.tp;
   // (1) C' and the staged operands of the derivative sweep
@@ -866,7 +906,22 @@ hipError_t launch_backward(const Ctx& c, const Hyper& h, int ard, int precond_gr
   // (3) preconditioner terms
   double* pg_part = c.at<double>(L.pg_part);
   unsigned nb_pg = 1;
-  if (L.k > 0) {
+  if (L.k > 0 && precond_kind == kRff) {
+    // Z^T [c_i] into ltr_raw (columns 1..ell); Omega = -Z C^-1 + (1/ell) [c_i] (Z^T [c_i])^T
+    e = launch_ltr(c, c.at<double>(L.Z0), c.at<double>(L.ltr_raw), nullptr);
+    if (e != hipSuccess) return e;
+    double* Om = c.at<double>(L.omega);
+    dim3 gg(nbk(L.n, 64), (L.k + 63) / 64);
+    hipLaunchKernelGGL(k_gemm64, gg, dim3(256), 0, c.st, L.n, L.k, L.k, c.at<double>(L.L), (int64_t)1, (int64_t)L.n,
+                       c.at<double>(L.Cinv), (int64_t)L.k, (int64_t)1, Om, (int64_t)1, (int64_t)L.n, -1.0, 0.0,
+                       (const int*)nullptr, (const int*)nullptr);
+    hipLaunchKernelGGL(k_gemm64, gg, dim3(256), 0, c.st, L.n, L.k, L.ell, c.at<double>(L.Z0) + 1, (int64_t)tp,
+                       (int64_t)1, c.at<double>(L.ltr_raw) + 1, (int64_t)1, (int64_t)tp, Om, (int64_t)1, (int64_t)L.n,
+                       1.0 / L.ell, 1.0, (const int*)nullptr, (const int*)nullptr);
+    nb_pg = nbk(L.n, 256);
+    hipLaunchKernelGGL(k_rff_contract, dim3(nb_pg), dim3(256), 0, c.st, c.at<double>(L.xs), L.n, L.k / 2,
+                       c.at<double>(L.freq), Om, c.at<double>(L.L), h, precond_grad, pg_part);
+  } else if (L.k > 0) {
     // L^T [c_i] into ltr_raw (columns 1..ell)
     e = launch_ltr(c, c.at<double>(L.Z0), c.at<double>(L.ltr_raw), nullptr);
     if (e != hipSuccess) return e;

@@ -153,6 +153,19 @@ def test_null_pointers_and_rank_bounds_are_rejected(lib):
                               1 << 30, None) == B.GP_EINVAL
 
 
+def test_rff_build_rejects_odd_or_small_rank_and_null_frequencies(lib):
+    theta = np.array([0.5, 0.5, 0.5, 1.0, 0.1])
+    tp = theta.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    p = _fake_problem()
+    ws = ctypes.c_void_p(0x10000)
+    h = ctypes.c_void_p()
+    for rank, freq in ((3, 0x6000), (0, 0x6000), (4, 0), (102, 0x6000)):
+        assert lib.gp_precond_build_rff(ctypes.byref(p), tp, rank, ctypes.c_void_p(freq), ws, 1 << 30, None,
+                                        ctypes.byref(h)) == B.GP_EINVAL
+    assert lib.gp_precond_build_rff(ctypes.byref(p), tp, 4, ctypes.c_void_p(0x6000), ws, 1 << 30, None,
+                                    None) == B.GP_EINVAL
+
+
 def test_strerror_covers_every_status(lib):
     for code in (0, -1, -2, -3, -4, -5):
         assert B.gp_strerror(code) and B.gp_strerror(code) != "unknown status"

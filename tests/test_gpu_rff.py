@@ -1,0 +1,147 @@
+"""Parity of the random Fourier feature preconditioner (Table 1, "RFF") on the
+HIP path against the CPU oracle, through the C-ABI.  Marked gpu."""
+import sys
+
+import numpy as np
+import pytest
+
+import synthgp
+from oracle import gp_oracle as go
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from paper_2107_00243_amd import binding as B  # noqa: E402
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    if not torch.cuda.is_available():
+        pytest.fail("no GPU visible")
+    B.load()
+    return torch.device("cuda:0")
+
+
+def rel(a, b):
+    return abs(a - b) / max(abs(b), 1e-300)
+
+
+def relvec(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / max(np.linalg.norm(b), 1e-300))
+
+
+def run_rff(pr, precision, rank, W, num_probes=None, tol=None, max_iters=None, precond_grad=0, grad=True):
+    num_probes = pr.num_probes if num_probes is None else num_probes
+    tol = pr.tol if tol is None else tol
+    max_iters = pr.max_iters if max_iters is None else max_iters
+    say(f"[gpu] rff estimator {pr.name} n={pr.n} d={pr.d} {pr.kernel} ard={pr.ard} prec={precision} "
+        f"k={rank} ell={num_probes} mode={precond_grad}")
+    dev = torch.device("cuda:0")
+    X = torch.tensor(pr.X, device=dev)
+    y = torch.tensor(pr.y, device=dev)
+    Wd = torch.tensor(np.ascontiguousarray(W), device=dev)
+    prob = B.make_problem(X, y, pr.kernel, pr.ard)
+    opt = B.make_options(precision, num_probes, max_iters, tol, pr.probe_seed, precond_grad, 1)
+    ws = B.alloc_workspace(B.gp_workspace_size(prob, opt, rank))
+    h = B.gp_precond_build_rff(prob, pr.theta, rank, Wd, ws)
+    logp = torch.zeros(1, dtype=torch.float64, device=dev)
+    g = torch.zeros(len(pr.theta), dtype=torch.float64, device=dev)
+    st = B.Stats(num_probes, rank)
+    try:
+        if grad:
+            B.gp_mll_grad(prob, pr.theta, opt, rank, h, ws, logp, g, st)
+        else:
+            B.gp_mll_eval(prob, pr.theta, opt, rank, h, ws, logp, st)
+        torch.cuda.synchronize()
+        v = B.gp_precond_view_of(h)
+        n = pr.n
+        Wg = np.frombuffer(ws.cpu().numpy().tobytes(), dtype=np.uint8)  # whole workspace on host
+        base = ws.data_ptr()
+        Z = Wg[v.L_dev - base: v.L_dev - base + n * rank * 8].view(np.float64).reshape(rank, n).T
+        piv = Wg[v.pivots_dev - base: v.pivots_dev - base + rank * 4].view(np.int32)
+        ldp = float(Wg[v.logdet_dev - base: v.logdet_dev - base + 8].view(np.float64)[0])
+    finally:
+        B.gp_precond_free(h)
+    return {"logp": float(logp.cpu()[0]), "grad": g.cpu().numpy(), "stats": st, "Z": Z,
+            "piv": piv, "logdet_P": ldp}
+
+
+# RFF preconditioners of small rank are weak (Table 1: error rate k^-1/2), so
+# the cases keep CG well inside its cap: a column that stops at the cap leaves
+# a finite-precision Lanczos run whose rounding the two sides do not share.
+CASES = [
+    # name, n, d, kernel, ard, rank, sigma^2, CG iterations of the oracle
+    ("rbf_1d", 1500, 1, "rbf", False, 64, 0.05),          # 17
+    ("rbf_ard_2d", 1500, 2, "rbf", True, 64, 0.05),       # 138 (quadrature path)
+    ("matern32_ard_6d", 1100, 6, "matern32", True, 24, 0.5),  # 175
+    ("matern52_iso_3d", 900, 3, "matern52", False, 10, 0.5),  # 116
+]
+
+
+def _case(n, d, kernel, ard, rank, s2, seed):
+    ls = (0.5, 1.0) if d == 1 else ((0.5, 1.5) if d == 2 else (0.4, 1.5))
+    pr = synthgp.random_problem(n, d, kernel, ard=ard, rank=rank, num_probes=8, seed=seed,
+                                ls_range=ls, sigma2=s2, dist="normal", tol=1e-8, max_iters=400)
+    W = synthgp.spectral_frequencies(kernel, rank // 2, d, seed=seed)
+    return pr, W
+
+
+@pytest.mark.parametrize("name,n,d,kernel,ard,rank,s2", CASES)
+def test_rff_features_and_logdet_match_oracle(name, n, d, kernel, ard, rank, s2):
+    pr, W = _case(n, d, kernel, ard, rank, s2, seed=32)
+    out = run_rff(pr, "fp64", rank, W, grad=False)
+    Zr = go.rff_features(pr.X, pr.theta, ard, W)
+    np.testing.assert_allclose(out["Z"], Zr, rtol=0, atol=1e-12 * np.sqrt(pr.theta[-2]))
+    ldp = go.Preconditioner(Zr, pr.theta[-1]).logdet
+    assert rel(out["logdet_P"], ldp) < 1e-11
+    assert np.all(out["piv"] == -1)
+    assert out["stats"].rank_achieved == rank
+    assert out["stats"].flags & B.FLAG_RANK_DEFICIENT == 0
+
+
+@pytest.mark.parametrize("precision,lp_tol,g_tol", [("fp64", 1e-7, 1e-5), ("bf16x3", 1e-3, 1e-2),
+                                                     ("fp32", 1e-3, 1e-2)])
+@pytest.mark.parametrize("name,n,d,kernel,ard,rank,s2", CASES)
+def test_rff_estimator_matches_oracle(name, n, d, kernel, ard, rank, s2, precision, lp_tol, g_tol):
+    pr, W = _case(n, d, kernel, ard, rank, s2, seed=32)
+    out = run_rff(pr, precision, rank, W)
+    ref = go.estimate_mll(pr.X, pr.y, pr.theta, kernel, ard, rank, pr.num_probes, pr.tol, pr.max_iters,
+                          pr.probe_seed, grad=True, precond="rff", freqs=W)
+    say(f"    logp {out['logp']:.12e} oracle {ref['logp']:.12e} rel {rel(out['logp'], ref['logp']):.2e}; "
+        f"grad rel {relvec(out['grad'], ref['grad']):.2e}")
+    assert rel(out["logp"], ref["logp"]) < lp_tol
+    assert relvec(out["grad"], ref["grad"]) < g_tol
+    assert out["stats"].flags & B.FLAG_NOT_CONVERGED == 0
+    if precision == "fp64":
+        # past the loss of orthogonality the step at which the recurrence residual
+        # crosses the tolerance depends on rounding order (the results above do not)
+        assert abs(out["stats"].iters_max - int(ref["iters"].max())) <= 1 + 0.05 * int(ref["iters"].max())
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_rff_precond_grad_modes_match_oracle(mode):
+    pr, W = _case(1100, 6, "matern32", True, 24, 0.5, seed=33)   # 129 CG iterations
+    out = run_rff(pr, "fp64", 24, W, precond_grad=mode)
+    ref = go.estimate_mll(pr.X, pr.y, pr.theta, "matern32", True, 24, pr.num_probes, pr.tol, pr.max_iters,
+                          pr.probe_seed, grad=True, precond_grad=mode, precond="rff", freqs=W)
+    assert relvec(out["grad"], ref["grad"]) < 1e-5
+    assert rel(out["logp"], ref["logp"]) < 1e-7
+
+
+def test_rff_rejects_bad_arguments():
+    pr, W = _case(200, 2, "rbf", True, 8, 0.1, seed=34)
+    dev = torch.device("cuda:0")
+    X = torch.tensor(pr.X, device=dev)
+    y = torch.tensor(pr.y, device=dev)
+    prob = B.make_problem(X, y, "rbf", True)
+    opt = B.make_options("fp64", 4, 50)
+    ws = B.alloc_workspace(B.gp_workspace_size(prob, opt, 8))
+    Wd = torch.tensor(W, device=dev)
+    for rank in (7, 0):
+        with pytest.raises(B.GPError):
+            B.gp_precond_build_rff(prob, pr.theta, rank, Wd, ws)
