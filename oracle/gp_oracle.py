@@ -49,6 +49,13 @@ R-cg     x0 = 0; a column stops after the iteration whose updated recurrence
 R-kern   k(x, x') = s * kappa(r), r^2 = sum_j ((x_j - x'_j) / ls_j)^2, noise
          sigma^2 on the diagonal; theta = [ls | s | sigma^2] natural parameters.
 R-ritz   Ritz values below 1e-300 are clamped to 1e-300 before the log.
+R-nys    Randomized Nystrom preconditioner (Table 1; supplement S5, randomized
+         Nystrom approximation quality): the landmark rows S are an input, drawn
+         with probabilities proportional to K_ii^2 (uniform for a stationary
+         kernel) without replacement and with s = k landmarks, so no rank-k
+         truncation of K_SS^+ is needed: P = sigma^2 I + K_{:S} K_SS^-1 K_{S:}, the
+         partial Cholesky with the pivots prescribed in the order of S.  Its
+         derivative holds S fixed, exactly as R-dP.
 R-rff    Random Fourier feature preconditioner (Table 1, "RFF"): m = k/2 frequency
          samples w_j of the kernel's spectral density at unit lengthscale are an
          input; Z = sqrt(s/m) [cos(Phi) | sin(Phi)] with Phi = X~ W^T and
@@ -276,16 +283,22 @@ def probe_signs(seed, n, k, ell):
 # Partial pivoted Cholesky and the diagonal-plus-low-rank preconditioner
 # ----------------------------------------------------------------------------
 
-def pivoted_cholesky(X, theta, kind, ard, k):
+def pivoted_cholesky(X, theta, kind, ard, k, order=None):
     """Greedy partial pivoted Cholesky of K (noise excluded), R-chol.
-    Returns L (n, k) with zero columns after an early stop, pivots, achieved rank."""
+    Returns L (n, k) with zero columns after an early stop, pivots, achieved rank.
+    order: k distinct rows taken as the pivots in that order instead of the
+    greedy choice (the randomized Nystrom preconditioner, reading R-nys)."""
     n, d = X.shape
     ls, s, _ = split_theta(theta, d, ard)
+    if order is not None:
+        order = np.asarray(order, dtype=np.int64)
+        if order.shape != (k,) or len(set(order.tolist())) != k or order.min() < 0 or order.max() >= n:
+            raise ValueError("order must hold k distinct rows")
     L = np.zeros((n, k))
     diag = np.full(n, s)
     piv = []
     for j in range(k):
-        i = int(np.argmax(diag))
+        i = int(np.argmax(diag)) if order is None else int(order[j])
         if not diag[i] > PIVOT_BREAKDOWN * s:
             break
         piv.append(i)
@@ -548,7 +561,8 @@ def _precond_terms_rff(X, theta, ard, freqs, Z, P, Cs, mode):
 
 
 def estimate_mll(X, y, theta, kind, ard, rank, num_probes, tol, max_iters, seed,
-                 grad=True, precond_grad=0, signs=None, dense=None, precond="pivchol", freqs=None):
+                 grad=True, precond_grad=0, signs=None, dense=None, precond="pivchol", freqs=None,
+                 landmarks=None):
     """Preconditioned estimate of log p (Algorithm 1) and, if grad, of its
     derivative (Algorithm 2) under the readings in the module docstring.
 
@@ -573,6 +587,8 @@ def estimate_mll(X, y, theta, kind, ard, rank, num_probes, tol, max_iters, seed,
             raise ValueError("the RFF preconditioner needs rank / 2 frequency rows")
         L = rff_features(X, theta, ard, freqs)
         piv, kp = np.full(rank, -1, dtype=np.int64), rank
+    elif precond == "nystrom":
+        L, piv, kp = pivoted_cholesky(X, theta, kind, ard, rank, order=landmarks)
     elif precond == "pivchol":
         L, piv, kp = pivoted_cholesky(X, theta, kind, ard, rank)
     else:

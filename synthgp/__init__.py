@@ -91,6 +91,14 @@ def spectral_frequencies(kernel, m, d, seed=0):
     return z * np.sqrt(2.0 * nu / u)
 
 
+def uniform_landmarks(n, k, seed=0):
+    """k distinct rows of n drawn uniformly without replacement, the random input of
+    the randomized Nystrom preconditioner (column probabilities proportional to
+    K_ii^2 are uniform for a stationary kernel)."""
+    rng = np.random.default_rng(np.random.SeedSequence([int(seed), 0x4E59]))
+    return rng.choice(n, size=k, replace=False).astype(np.int32)
+
+
 def plain_rbf_1000(n=1000, seed=0):
     """Uniform[0,1]^3 inputs, isotropic RBF (ls 0.3, s 1, sigma^2 0.1), FP64 tiles."""
     rng = np.random.default_rng(seed)

@@ -479,3 +479,69 @@ def test_rff_estimators_are_unbiased_over_all_sign_patterns():
     np.testing.assert_allclose(grads.mean(axis=0), ex["grad"], rtol=1e-8, atol=1e-9)
     assert vals.std() > 1e-6
     assert es["rank"] == 2 and np.all(es["piv"] == -1)
+
+
+# ------------------------------------------------ randomized Nystrom (Table 1)
+
+def test_nystrom_landmarks_reproduce_the_nystrom_formula():
+    X, _, theta = _problem(40, 3, "matern52", True, seed=26)
+    S = synthgp.uniform_landmarks(40, 9, seed=1)
+    L, piv, kp = go.pivoted_cholesky(X, theta, "matern52", True, 9, order=S)
+    assert kp == 9 and list(piv) == list(S)
+    K = go.kernel_matrix(X, X, theta, "matern52", True)
+    KS = K[:, S]
+    np.testing.assert_allclose(L @ L.T, KS @ np.linalg.solve(K[np.ix_(S, S)], KS.T), rtol=0, atol=1e-12)
+    LS = L[S, :]
+    np.testing.assert_allclose(LS, np.tril(LS), atol=0)
+    np.testing.assert_allclose(LS, np.linalg.cholesky(K[np.ix_(S, S)]), rtol=1e-12, atol=1e-14)
+
+
+def test_nystrom_landmarks_stop_on_a_duplicate_point():
+    X, _, theta = _problem(12, 2, "rbf", True, seed=27)
+    X[5] = X[2]
+    L, piv, kp = go.pivoted_cholesky(X, theta, "rbf", True, 4, order=[2, 5, 7, 9])
+    assert kp == 1 and list(piv) == [2]
+    assert np.all(L[:, 1:] == 0.0)
+
+
+def test_nystrom_precond_terms_match_dense_finite_differences():
+    X, y, theta = _problem(25, 2, "matern32", True, seed=28, sigma2=0.05)
+    S = synthgp.uniform_landmarks(25, 5, seed=2)
+    L, piv, kp = go.pivoted_cholesky(X, theta, "matern32", True, 5, order=S)
+    P = go.Preconditioner(L[:, :kp], 0.05)
+    Cs = np.random.default_rng(9).standard_normal((25, 3))
+    tr, ctrl = go._precond_terms(X, theta, "matern32", True, L, piv, kp, P, Cs, 0)
+
+    def dense_P(th):
+        K = go.kernel_matrix(X, X, th, "matern32", True)
+        KS = K[:, S]
+        return th[-1] * np.eye(25) + KS @ np.linalg.solve(K[np.ix_(S, S)], KS.T)
+
+    for i in range(len(theta)):
+        h = 1e-6 * theta[i]
+        tp, tm = theta.copy(), theta.copy()
+        tp[i] += h
+        tm[i] -= h
+        Pp, Pm = dense_P(tp), dense_P(tm)
+        ref_tr = (np.linalg.slogdet(Pp)[1] - np.linalg.slogdet(Pm)[1]) / (2 * h)
+        ref_ctrl = (np.einsum("pi,pq,qi->i", Cs, Pp, Cs) - np.einsum("pi,pq,qi->i", Cs, Pm, Cs)) / (2 * h)
+        assert abs(tr[i] - ref_tr) <= 1e-6 * max(1.0, abs(ref_tr)), (i, tr[i], ref_tr)
+        np.testing.assert_allclose(ctrl[i], ref_ctrl, rtol=1e-6, atol=1e-6)
+
+
+def test_nystrom_estimators_are_unbiased_over_all_sign_patterns():
+    X, y, theta = _problem(7, 2, "rbf", True, seed=29, sigma2=0.1, ls=(0.3, 0.6))
+    S = np.array([4, 1], dtype=np.int32)
+    n, k = 7, 2
+    vals, grads = [], []
+    for bits in itertools.product((-1.0, 1.0), repeat=n + k):
+        xi = np.array(bits)
+        es = go.estimate_mll(X, y, theta, "rbf", True, k, 1, 1e-13, n, 0, grad=True,
+                             signs=(xi[:n, None], xi[n:, None]), precond="nystrom", landmarks=S)
+        vals.append(es["logdet_est"])
+        grads.append(es["grad"])
+    vals, grads = np.array(vals), np.array(grads)
+    ex = go.exact_mll(X, y, theta, "rbf", True)
+    assert abs(vals.mean() - ex["logdet"]) <= 1e-9 * abs(ex["logdet"])
+    np.testing.assert_allclose(grads.mean(axis=0), ex["grad"], rtol=1e-8, atol=1e-9)
+    assert list(es["piv"]) == [4, 1]
