@@ -156,6 +156,26 @@ int gp_precond_build(const gp_problem* prob, const double* theta_host, int32_t r
                      void* ws_dev, size_t ws_bytes, hipStream_t stream, gp_precond** out);
 
 /*
+ * gp_precond_build_nystrom — randomized Nystrom preconditioner
+ * P_hat = sigma^2 I + K_{:S} K_SS^-1 K_{S:} (Table 1, "randomized Nystrom";
+ * supplement S5, randomized Nystrom approximation quality) on `rank` landmark
+ * rows S given by the caller (drawn with probabilities proportional to K_ii^2,
+ * which is uniform for these stationary kernels).  With as many landmarks as
+ * the rank, no truncation of K_SS^+ is needed and the factor is the partial
+ * Cholesky of gp_precond_build with its pivots prescribed in the order of S:
+ * same handle, view (the pivots read S), breakdown rule (a landmark whose
+ * residual diagonal is <= 1e-12 * s stops the factor, GP_FLAG_RANK_DEFICIENT)
+ * and derivative (landmarks held fixed; precond_grad as for the pivoted
+ * Cholesky).  landmarks_host: host int32[rank], distinct rows in [0, n); it is
+ * copied before the call returns (the call waits for that copy).
+ * Errors: GP_EINVAL for rank < 1, a null, repeated or out-of-range landmark, or
+ * as gp_precond_build; GP_EWORKSPACE; GP_EHIP.
+ */
+int gp_precond_build_nystrom(const gp_problem* prob, const double* theta_host, int32_t rank,
+                             const int32_t* landmarks_host, void* ws_dev, size_t ws_bytes,
+                             hipStream_t stream, gp_precond** out);
+
+/*
  * gp_precond_build_rff — random Fourier feature preconditioner
  * P_hat = sigma^2 I + Z Z^T (Table 1, "RFF"; supplement S5, RFF approximation
  * quality), an alternative to gp_precond_build with the same handle, workspace

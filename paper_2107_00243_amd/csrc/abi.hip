@@ -1,5 +1,6 @@
 // C-ABI entry points: argument validation, workspace carving and launch
 // sequencing of the preconditioned log-likelihood estimator (Algorithms 1 and 2).
+#include <algorithm>
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
@@ -116,6 +117,7 @@ Layout make_layout(int64_t n, int d, int ard, int num_probes, int max_iters, int
   L.flags = take(64);
   L.ltr_part = take((size_t)L.nchunk * kk * kk * 8);
   L.freq = take((size_t)(kk / 2 + 1) * GP_MAX_D * 8);
+  L.landmarks = take(kk * 4);
   L.precond_end = off;
   // estimator block
   L.xfa = take(np * L.kd * esz);
@@ -339,6 +341,45 @@ extern "C" int gp_precond_build_rff(const gp_problem* prob, const double* theta_
   P->ws = (char*)ws_dev;
   P->prob = *prob;
   P->kind = kRff;
+  const int p = prob->ard ? prob->d : 1;
+  P->theta.assign(theta_host, theta_host + p + 2);
+  *out = P;
+  return GP_OK;
+}
+
+extern "C" int gp_precond_build_nystrom(const gp_problem* prob, const double* theta_host, int32_t rank,
+                                        const int32_t* landmarks_host, void* ws_dev, size_t ws_bytes,
+                                        hipStream_t stream, gp_precond** out) {
+  if (!out) return GP_EINVAL;
+  *out = nullptr;
+  RET_IF(check_problem(prob));
+  RET_IF(check_rank(prob, rank));
+  if (rank < 1 || !landmarks_host) return GP_EINVAL;
+  {
+    std::vector<int32_t> s(landmarks_host, landmarks_host + rank);
+    std::sort(s.begin(), s.end());
+    if (s.front() < 0 || (int64_t)s.back() >= prob->n) return GP_EINVAL;
+    if (std::adjacent_find(s.begin(), s.end()) != s.end()) return GP_EINVAL;
+  }
+  Hyper h;
+  RET_IF(make_hyper(prob, theta_host, &h));
+  RET_IF(check_device());
+  Layout L = make_layout(prob->n, prob->d, prob->ard, 1, 1, rank, GP_PREC_FP64);
+  if (!ws_dev || (reinterpret_cast<uintptr_t>(ws_dev) & 255) != 0) return GP_EINVAL;
+  if (ws_bytes < L.precond_end) return GP_EWORKSPACE;
+  Ctx c{&L, (char*)ws_dev, stream};
+  HIPCHK(hipMemsetAsync(c.at<int>(L.flags), 0, 64, stream));
+  // the landmark table comes from pageable host memory: wait for the copy once
+  HIPCHK(hipMemcpyAsync(c.at<int32_t>(L.landmarks), landmarks_host, (size_t)rank * sizeof(int32_t),
+                        hipMemcpyHostToDevice, stream));
+  HIPCHK(hipStreamSynchronize(stream));
+  HIPCHK(launch_prep(c, prob->X_dev, h));
+  HIPCHK(launch_pivchol(c, h, c.at<int32_t>(L.landmarks)));
+  HIPCHK(launch_precond_finish(c, h));
+  gp_precond* P = new gp_precond;
+  P->lay = L;
+  P->ws = (char*)ws_dev;
+  P->prob = *prob;
   const int p = prob->ard ? prob->d : 1;
   P->theta.assign(theta_host, theta_host + p + 2);
   *out = P;

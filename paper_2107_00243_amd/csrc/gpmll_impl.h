@@ -88,6 +88,7 @@ struct Layout {
   // preconditioner block (offsets independent of the estimator options)
   size_t xs, mean, mean_part, L, diag, ispiv, piv, amax, C, Rc, Rinv, Cinv, logdetP, scal_small, flags, ltr_part;
   size_t freq;          // m x d spectral samples of the random Fourier feature preconditioner
+  size_t landmarks;     // k prescribed pivot rows of the Nystrom preconditioner
   size_t precond_end;
   // estimator block
   size_t xfa, xfb, rowterm, colterm, H, Y, ltr, ltr_raw, ltr_part2;
@@ -123,7 +124,8 @@ struct Ctx {
 // flags[0] GP_FLAG_* bits, [1] deferred gp_status, [2] clamped Ritz values.
 
 hipError_t launch_prep(const Ctx& c, const double* X, const Hyper& h);
-hipError_t launch_pivchol(const Ctx& c, const Hyper& h);
+// greedy pivots, or (forced != null) the k prescribed distinct rows in that order
+hipError_t launch_pivchol(const Ctx& c, const Hyper& h, const int32_t* forced = nullptr);
 hipError_t launch_precond_finish(const Ctx& c, const Hyper& h);
 // random Fourier features from the samples at lay.freq into the L slot (rank 2m)
 hipError_t launch_rff(const Ctx& c, const Hyper& h);

@@ -62,6 +62,10 @@ __global__ void k_scale(const double* __restrict__ X, const double* __restrict__
 //   3. updates the residual diagonal and emits this block's maximum for step j+1.
 // A step whose largest residual is <= 1e-12 * s stops the factorisation: it and
 // all later steps leave their columns zero and record pivot -1.
+// With prescribed pivots (the randomized Nystrom preconditioner of Table 1 on
+// given landmark rows) step 1 takes the next landmark instead; the factor is then
+// K_{:S} K_SS^-1 K_{S:} on those rows, and the same breakdown rule applies to the
+// landmark's residual diagonal.
 // ---------------------------------------------------------------------------
 
 struct ArgMax {
@@ -119,7 +123,8 @@ __global__ void k_pivchol_init(int64_t n, int k, double s, double* __restrict__ 
 __global__ void k_pivchol_step(int j, int64_t n, int k, int nblk, Hyper h, const double* __restrict__ xs,
                                double* __restrict__ L, double* __restrict__ diag, int8_t* __restrict__ ispiv,
                                int32_t* __restrict__ piv, const ArgMax* __restrict__ amax_in,
-                               ArgMax* __restrict__ amax_out, int* __restrict__ stop) {
+                               ArgMax* __restrict__ amax_out, int* __restrict__ stop,
+                               const int32_t* __restrict__ forced) {
   __shared__ double Lp[GP_MAX_RANK];
   __shared__ double xp[GP_MAX_D];
   __shared__ ArgMax pivot;
@@ -127,11 +132,19 @@ __global__ void k_pivchol_step(int j, int64_t n, int k, int nblk, Hyper h, const
   if (threadIdx.x == 0) halted = *stop;
   __syncthreads();
   if (halted) return;
-  // 1. pivot of this step
-  ArgMax loc{-1.0, (int64_t)n};
-  for (int b = threadIdx.x; b < nblk; b += blockDim.x) loc = amax_better(loc, amax_in[b]);
-  ArgMax best = block_argmax(loc);
-  if (threadIdx.x == 0) pivot = best;
+  // 1. pivot of this step: the largest residual diagonal, or the prescribed row
+  // (its residual diagonal is left in place below, so every block reads the same value)
+  if (forced) {
+    if (threadIdx.x == 0) {
+      const int64_t f = forced[j];
+      pivot = ArgMax{diag[f], f};
+    }
+  } else {
+    ArgMax loc{-1.0, (int64_t)n};
+    for (int b = threadIdx.x; b < nblk; b += blockDim.x) loc = amax_better(loc, amax_in[b]);
+    ArgMax best = block_argmax(loc);
+    if (threadIdx.x == 0) pivot = best;
+  }
   __syncthreads();
   const double dpiv = pivot.v;
   const int64_t ip = pivot.i;
@@ -175,10 +188,12 @@ __global__ void k_pivchol_step(int j, int64_t n, int k, int nblk, Hyper h, const
       dn = diag[i] - lij * lij;
       mine = ArgMax{dn, i};
     }
-    diag[i] = dn;
+    if (!(forced && i == ip)) diag[i] = dn;
   }
-  ArgMax bm = block_argmax(mine);
-  if (threadIdx.x == 0) amax_out[blockIdx.x] = bm;
+  if (!forced) {
+    ArgMax bm = block_argmax(mine);
+    if (threadIdx.x == 0) amax_out[blockIdx.x] = bm;
+  }
   if (i == ip) ispiv[i] = 1;
   if (blockIdx.x == 0 && threadIdx.x == 0) piv[j] = (int32_t)ip;
 }
@@ -313,7 +328,7 @@ hipError_t launch_prep(const Ctx& c, const double* X, const Hyper& h) {
   return hipGetLastError();
 }
 
-hipError_t launch_pivchol(const Ctx& c, const Hyper& h) {
+hipError_t launch_pivchol(const Ctx& c, const Hyper& h, const int32_t* forced) {
   const Layout& L = *c.lay;
   const int nblk = (int)((L.n + kRedBlock - 1) / kRedBlock);
   ArgMax* am = c.at<ArgMax>(L.amax);
@@ -325,7 +340,7 @@ hipError_t launch_pivchol(const Ctx& c, const Hyper& h) {
     ArgMax* out = am + ((j + 1) % 2) * nblk;
     hipLaunchKernelGGL(k_pivchol_step, dim3(nblk), dim3(kRedBlock), 0, c.st, j, L.n, L.k, nblk, h,
                        c.at<double>(L.xs), c.at<double>(L.L), c.at<double>(L.diag), c.at<int8_t>(L.ispiv),
-                       c.at<int32_t>(L.piv), in, out, stop);
+                       c.at<int32_t>(L.piv), in, out, stop, forced);
   }
   return hipGetLastError();
 }

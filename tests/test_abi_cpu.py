@@ -166,6 +166,20 @@ def test_rff_build_rejects_odd_or_small_rank_and_null_frequencies(lib):
                                     None) == B.GP_EINVAL
 
 
+def test_nystrom_build_rejects_bad_landmarks_before_any_device_call(lib):
+    theta = np.array([0.5, 0.5, 0.5, 1.0, 0.1])
+    tp = theta.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    p = _fake_problem()
+    ws = ctypes.c_void_p(0x10000)
+    h = ctypes.c_void_p()
+    for lm in ([1, 2, 2, 3], [1, 2, 3, 100], [-1, 2, 3, 4]):
+        a = np.array(lm, dtype=np.int32)
+        assert lib.gp_precond_build_nystrom(ctypes.byref(p), tp, 4, a.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                            ws, 1 << 30, None, ctypes.byref(h)) == B.GP_EINVAL
+    assert lib.gp_precond_build_nystrom(ctypes.byref(p), tp, 4, None, ws, 1 << 30, None,
+                                        ctypes.byref(h)) == B.GP_EINVAL
+
+
 def test_strerror_covers_every_status(lib):
     for code in (0, -1, -2, -3, -4, -5):
         assert B.gp_strerror(code) and B.gp_strerror(code) != "unknown status"

@@ -1,5 +1,6 @@
-"""Parity of the random Fourier feature preconditioner (Table 1, "RFF") on the
-HIP path against the CPU oracle, through the C-ABI.  Marked gpu."""
+"""Parity of the other diagonal-plus-low-rank preconditioners of Table 1 on the
+HIP path against the CPU oracle, through the C-ABI: random Fourier features
+("RFF") and the randomized Nystrom approximation on given landmarks.  Marked gpu."""
 import sys
 
 import numpy as np
@@ -145,3 +146,118 @@ def test_rff_rejects_bad_arguments():
     for rank in (7, 0):
         with pytest.raises(B.GPError):
             B.gp_precond_build_rff(prob, pr.theta, rank, Wd, ws)
+
+
+# ---------------------------------------------------------------- randomized Nystrom
+
+NYS_CASES = [
+    # name, n, d, kernel, ard, rank, sigma^2, CG iterations of the oracle
+    ("rbf_ard_4d", 1500, 4, "rbf", True, 40, 0.02),            # 208 (quadrature path)
+    ("matern32_ard_6d", 1100, 6, "matern32", True, 24, 0.1),   # 48
+    ("matern52_iso_3d", 900, 3, "matern52", False, 16, 0.05),  # 139
+]
+
+
+def _nys_case(n, d, kernel, ard, rank, s2, seed=35):
+    pr = synthgp.random_problem(n, d, kernel, ard=ard, rank=rank, num_probes=8, seed=seed,
+                                ls_range=(0.4, 1.5), sigma2=s2, dist="normal", tol=1e-8, max_iters=400)
+    return pr, synthgp.uniform_landmarks(n, rank, seed=seed)
+
+
+def run_nystrom(pr, precision, rank, S, precond_grad=0, grad=True):
+    say(f"[gpu] nystrom estimator {pr.name} n={pr.n} d={pr.d} {pr.kernel} ard={pr.ard} prec={precision} "
+        f"k={rank} mode={precond_grad}")
+    dev = torch.device("cuda:0")
+    X = torch.tensor(pr.X, device=dev)
+    y = torch.tensor(pr.y, device=dev)
+    prob = B.make_problem(X, y, pr.kernel, pr.ard)
+    opt = B.make_options(precision, pr.num_probes, pr.max_iters, pr.tol, pr.probe_seed, precond_grad, 1)
+    ws = B.alloc_workspace(B.gp_workspace_size(prob, opt, rank))
+    h = B.gp_precond_build_nystrom(prob, pr.theta, rank, S, ws)
+    logp = torch.zeros(1, dtype=torch.float64, device=dev)
+    g = torch.zeros(len(pr.theta), dtype=torch.float64, device=dev)
+    st = B.Stats(pr.num_probes, rank)
+    try:
+        if grad:
+            B.gp_mll_grad(prob, pr.theta, opt, rank, h, ws, logp, g, st)
+        else:
+            B.gp_mll_eval(prob, pr.theta, opt, rank, h, ws, logp, st)
+        torch.cuda.synchronize()
+        v = B.gp_precond_view_of(h)
+        n = pr.n
+        Wg = np.frombuffer(ws.cpu().numpy().tobytes(), dtype=np.uint8)
+        base = ws.data_ptr()
+        L = Wg[v.L_dev - base: v.L_dev - base + n * rank * 8].view(np.float64).reshape(rank, n).T
+        piv = Wg[v.pivots_dev - base: v.pivots_dev - base + rank * 4].view(np.int32)
+        ldp = float(Wg[v.logdet_dev - base: v.logdet_dev - base + 8].view(np.float64)[0])
+    finally:
+        B.gp_precond_free(h)
+    return {"logp": float(logp.cpu()[0]), "grad": g.cpu().numpy(), "stats": st, "L": L, "piv": piv,
+            "logdet_P": ldp}
+
+
+@pytest.mark.parametrize("name,n,d,kernel,ard,rank,s2", NYS_CASES)
+def test_nystrom_factor_matches_oracle(name, n, d, kernel, ard, rank, s2):
+    pr, S = _nys_case(n, d, kernel, ard, rank, s2)
+    out = run_nystrom(pr, "fp64", rank, S, grad=False)
+    Lr, pivr, kp = go.pivoted_cholesky(pr.X, pr.theta, kernel, ard, rank, order=S)
+    assert kp == rank
+    np.testing.assert_array_equal(out["piv"], S)
+    np.testing.assert_allclose(out["L"], Lr, rtol=1e-9, atol=1e-11)
+    assert rel(out["logdet_P"], go.Preconditioner(Lr, pr.theta[-1]).logdet) < 1e-11
+    assert out["stats"].rank_achieved == rank
+
+
+@pytest.mark.parametrize("precision,lp_tol,g_tol", [("fp64", 1e-7, 1e-5), ("bf16x3", 1e-3, 1e-2),
+                                                     ("fp32", 1e-3, 1e-2)])
+@pytest.mark.parametrize("name,n,d,kernel,ard,rank,s2", NYS_CASES)
+def test_nystrom_estimator_matches_oracle(name, n, d, kernel, ard, rank, s2, precision, lp_tol, g_tol):
+    pr, S = _nys_case(n, d, kernel, ard, rank, s2)
+    out = run_nystrom(pr, precision, rank, S)
+    ref = go.estimate_mll(pr.X, pr.y, pr.theta, kernel, ard, rank, pr.num_probes, pr.tol, pr.max_iters,
+                          pr.probe_seed, grad=True, precond="nystrom", landmarks=S)
+    say(f"    logp {out['logp']:.12e} oracle {ref['logp']:.12e} rel {rel(out['logp'], ref['logp']):.2e}; "
+        f"grad rel {relvec(out['grad'], ref['grad']):.2e}")
+    assert rel(out["logp"], ref["logp"]) < lp_tol
+    assert relvec(out["grad"], ref["grad"]) < g_tol
+    assert out["stats"].flags & B.FLAG_NOT_CONVERGED == 0
+    if precision == "fp64":
+        assert abs(out["stats"].iters_max - int(ref["iters"].max())) <= 1 + 0.05 * int(ref["iters"].max())
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_nystrom_precond_grad_modes_match_oracle(mode):
+    pr, S = _nys_case(1100, 6, "matern32", True, 24, 0.1, seed=36)
+    out = run_nystrom(pr, "fp64", 24, S, precond_grad=mode)
+    ref = go.estimate_mll(pr.X, pr.y, pr.theta, "matern32", True, 24, pr.num_probes, pr.tol, pr.max_iters,
+                          pr.probe_seed, grad=True, precond_grad=mode, precond="nystrom", landmarks=S)
+    assert relvec(out["grad"], ref["grad"]) < 1e-5
+    assert rel(out["logp"], ref["logp"]) < 1e-7
+
+
+def test_nystrom_stops_on_a_duplicate_landmark_point():
+    pr, _ = _nys_case(600, 2, "rbf", True, 4, 0.1, seed=37)
+    pr.X[5] = pr.X[2]
+    S = np.array([2, 5, 7, 9], dtype=np.int32)
+    out = run_nystrom(pr, "fp64", 4, S)
+    ref = go.estimate_mll(pr.X, pr.y, pr.theta, "rbf", True, 4, pr.num_probes, pr.tol, pr.max_iters,
+                          pr.probe_seed, grad=True, precond="nystrom", landmarks=S)
+    assert ref["rank"] == 1
+    assert out["stats"].rank_achieved == 1
+    assert out["stats"].flags & B.FLAG_RANK_DEFICIENT
+    np.testing.assert_array_equal(out["piv"], [2, -1, -1, -1])
+    assert rel(out["logp"], ref["logp"]) < 1e-7
+    assert relvec(out["grad"], ref["grad"]) < 1e-5
+
+
+def test_nystrom_rejects_bad_landmarks():
+    pr, _ = _nys_case(200, 2, "rbf", True, 4, 0.1, seed=38)
+    dev = torch.device("cuda:0")
+    X = torch.tensor(pr.X, device=dev)
+    y = torch.tensor(pr.y, device=dev)
+    prob = B.make_problem(X, y, "rbf", True)
+    opt = B.make_options("fp64", 4, 50)
+    ws = B.alloc_workspace(B.gp_workspace_size(prob, opt, 4))
+    for S in ([1, 2, 2, 3], [1, 2, 3, 200], [-1, 2, 3, 4]):
+        with pytest.raises(B.GPError):
+            B.gp_precond_build_nystrom(prob, pr.theta, 4, S, ws)
