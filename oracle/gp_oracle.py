@@ -56,6 +56,11 @@ R-nys    Randomized Nystrom preconditioner (Table 1; supplement S5, randomized
          truncation of K_SS^+ is needed: P = sigma^2 I + K_{:S} K_SS^-1 K_{S:}, the
          partial Cholesky with the pivots prescribed in the order of S.  Its
          derivative holds S fixed, exactly as R-dP.
+R-qff    Quadrature Fourier features (Table 1, "QFF", RBF kernel): the frequencies
+         of R-rff are the nodes of a tensor Gauss-Hermite rule with q (even)
+         points per dimension for the standard normal spectral density; of each
+         +-pair of nodes one is kept with its weight doubled, and feature j has
+         amplitude sqrt(s w_j) instead of sqrt(s/m).  Rank q^d.
 R-rff    Random Fourier feature preconditioner (Table 1, "RFF"): m = k/2 frequency
          samples w_j of the kernel's spectral density at unit lengthscale are an
          input; Z = sqrt(s/m) [cos(Phi) | sin(Phi)] with Phi = X~ W^T and
@@ -65,6 +70,7 @@ R-rff    Random Fourier feature preconditioner (Table 1, "RFF"): m = k/2 frequen
 """
 from __future__ import annotations
 
+import itertools
 import math
 from fractions import Fraction
 
@@ -354,29 +360,53 @@ def _rff_phases(X, theta, ard, freqs):
     return Xt, ls, s, Xt @ freqs.T
 
 
-def rff_features(X, theta, ard, freqs):
-    """Z (n, 2m): columns 0..m-1 are sqrt(s/m) cos(Phi), columns m..2m-1 sqrt(s/m) sin(Phi)."""
+def rff_features(X, theta, ard, freqs, weights=None):
+    """Z (n, 2m): column j is sqrt(s w_j) cos(Phi_j), column m + j is sqrt(s w_j) sin(Phi_j),
+    w_j = 1/m for random features (R-rff) or the quadrature weights (R-qff)."""
     _, _, s, Phi = _rff_phases(X, theta, ard, freqs)
-    a = math.sqrt(s / Phi.shape[1])
-    return a * np.concatenate([np.cos(Phi), np.sin(Phi)], axis=1)
+    a = _feature_amplitudes(s, Phi.shape[1], weights)
+    return np.concatenate([a * np.cos(Phi), a * np.sin(Phi)], axis=1)
 
 
-def rff_feature_derivatives(X, theta, ard, freqs):
+def _feature_amplitudes(s, m, weights):
+    w = np.full(m, 1.0 / m) if weights is None else np.asarray(weights, dtype=np.float64)
+    if w.shape != (m,):
+        raise ValueError("one weight per frequency")
+    return np.sqrt(s * w)
+
+
+def rff_feature_derivatives(X, theta, ard, freqs, weights=None):
     """dZ/dtheta for the kernel parameters in theta order (lengthscales, then s),
-    frequencies held fixed: dPhi_ij/dls_q = -w_jq x~_iq / ls_q, d cos = -sin dPhi,
-    d sin = cos dPhi, dZ/ds = Z / (2 s)."""
+    frequencies and weights held fixed: dPhi_ij/dls_q = -w_jq x~_iq / ls_q,
+    d cos = -sin dPhi, d sin = cos dPhi, dZ/ds = Z / (2 s)."""
     n, d = X.shape
     Xt, ls, s, Phi = _rff_phases(X, theta, ard, freqs)
-    m = Phi.shape[1]
-    a = math.sqrt(s / m)
+    a = _feature_amplitudes(s, Phi.shape[1], weights)
     C, S = np.cos(Phi), np.sin(Phi)
     per_dim = []
     for q in range(d):
         dPhi = -np.outer(Xt[:, q], freqs[:, q]) / ls[q]
-        per_dim.append(a * np.concatenate([-S * dPhi, C * dPhi], axis=1))
+        per_dim.append(np.concatenate([-a * S * dPhi, a * C * dPhi], axis=1))
     out = per_dim if ard else [sum(per_dim)]
-    out.append(a * np.concatenate([C, S], axis=1) / (2.0 * s))
+    out.append(np.concatenate([a * C, a * S], axis=1) / (2.0 * s))
     return out
+
+
+def qff_frequencies(d, q):
+    """Quadrature Fourier features of the RBF kernel (Table 1, "QFF"; Mutny & Krause
+    2018), reading R-qff: the q-point Gauss-Hermite rule of N(0, 1) (probabilists'
+    Hermite nodes, weights normalised to sum 1) in every dimension, tensor product,
+    one frequency of each +-pair (first coordinate among the q/2 negative nodes),
+    lexicographic order, weight doubled.  Returns (freqs (q^d/2, d), weights)."""
+    if q < 2 or q % 2:
+        raise ValueError("q must be even")
+    x, w = np.polynomial.hermite_e.hermegauss(q)
+    w = w / math.sqrt(2.0 * math.pi)
+    freqs, weights = [], []
+    for J in itertools.product(range(q // 2), *([range(q)] * (d - 1))):
+        freqs.append([x[j] for j in J])
+        weights.append(2.0 * float(np.prod([w[j] for j in J])))
+    return np.array(freqs, dtype=np.float64).reshape(-1, d), np.array(weights)
 
 
 # ----------------------------------------------------------------------------
@@ -536,7 +566,7 @@ def _precond_terms(X, theta, kind, ard, L, piv, kp, P, Cs, mode):
     return tr, ctrl
 
 
-def _precond_terms_rff(X, theta, ard, freqs, Z, P, Cs, mode):
+def _precond_terms_rff(X, theta, ard, freqs, Z, P, Cs, mode, weights=None):
     """tr(P^-1 dP/dtheta) and the control variates c_i^T dP c_i for the RFF
     preconditioner, dP = dZ Z^T + Z dZ^T, with P^-1 = sigma^-2 (I - Z C^-1 Z^T)
     (matrix inversion lemma, as in supplement S3.3)."""
@@ -551,7 +581,7 @@ def _precond_terms_rff(X, theta, ard, freqs, Z, P, Cs, mode):
     ctrl[p + 1] = np.sum(Cs * Cs, axis=0)
     ZtC = Z.T @ Cs
     ZtZ = Z.T @ Z
-    for idx, dZ in enumerate(rff_feature_derivatives(X, theta, ard, freqs)):
+    for idx, dZ in enumerate(rff_feature_derivatives(X, theta, ard, freqs, weights)):
         if mode == 1 and idx < p:
             continue
         dP_Z = dZ @ ZtZ + Z @ (dZ.T @ Z)                         # dP Z
@@ -562,7 +592,7 @@ def _precond_terms_rff(X, theta, ard, freqs, Z, P, Cs, mode):
 
 def estimate_mll(X, y, theta, kind, ard, rank, num_probes, tol, max_iters, seed,
                  grad=True, precond_grad=0, signs=None, dense=None, precond="pivchol", freqs=None,
-                 landmarks=None):
+                 landmarks=None, qff_nodes=None):
     """Preconditioned estimate of log p (Algorithm 1) and, if grad, of its
     derivative (Algorithm 2) under the readings in the module docstring.
 
@@ -582,10 +612,17 @@ def estimate_mll(X, y, theta, kind, ard, rank, num_probes, tol, max_iters, seed,
         return Kh @ V if dense else khat_matvec(X, theta, kind, ard, V)
 
     # preconditioner (pivoted Cholesky or random Fourier features) and log det P
-    if precond == "rff":
+    weights = None
+    if precond == "qff":
+        if kind != "rbf":
+            raise ValueError("quadrature Fourier features are built for the RBF kernel")
+        freqs, weights = qff_frequencies(d, qff_nodes)
+        if 2 * len(freqs) != rank:
+            raise ValueError("the QFF preconditioner has rank q^d")
+    if precond in ("rff", "qff"):
         if freqs is None or 2 * len(freqs) != rank:
             raise ValueError("the RFF preconditioner needs rank / 2 frequency rows")
-        L = rff_features(X, theta, ard, freqs)
+        L = rff_features(X, theta, ard, freqs, weights)
         piv, kp = np.full(rank, -1, dtype=np.int64), rank
     elif precond == "nystrom":
         L, piv, kp = pivoted_cholesky(X, theta, kind, ard, rank, order=landmarks)
@@ -632,8 +669,8 @@ def estimate_mll(X, y, theta, kind, ard, rank, num_probes, tol, max_iters, seed,
     A1 = Xs
     C1 = np.concatenate([0.5 * u[:, None], -Cs / (2.0 * ell)], axis=1)
     bil = dkhat_contract(X, theta, kind, ard, lambda r: A1[r] @ C1.T)
-    if precond == "rff":
-        tr, ctrl = _precond_terms_rff(X, theta, ard, freqs, L, P, Cs, precond_grad)
+    if precond in ("rff", "qff"):
+        tr, ctrl = _precond_terms_rff(X, theta, ard, freqs, L, P, Cs, precond_grad, weights)
     else:
         tr, ctrl = _precond_terms(X, theta, kind, ard, L, piv, kp, P, Cs, precond_grad)
     g = bil - 0.5 * tr + ctrl.sum(axis=1) / (2.0 * ell)

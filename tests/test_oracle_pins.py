@@ -545,3 +545,75 @@ def test_nystrom_estimators_are_unbiased_over_all_sign_patterns():
     assert abs(vals.mean() - ex["logdet"]) <= 1e-9 * abs(ex["logdet"])
     np.testing.assert_allclose(grads.mean(axis=0), ex["grad"], rtol=1e-8, atol=1e-9)
     assert list(es["piv"]) == [4, 1]
+
+
+# ------------------------------------------------ quadrature Fourier features (Table 1)
+
+def test_qff_rule_integrates_gaussian_moments_exactly():
+    # a q-point Gauss rule integrates polynomials up to degree 2q - 1 exactly:
+    # E[w^2k] = (2k - 1)!! for the standard normal; degree 2q is not exact
+    q = 6
+    f, wt = go.qff_frequencies(1, q)
+    x = np.concatenate([f[:, 0], -f[:, 0]])
+    v = np.concatenate([wt, wt]) / 2.0
+    assert abs(v.sum() - 1.0) < 1e-14
+    for k in range(1, q):
+        dfact = float(np.prod(np.arange(2 * k - 1, 0, -2)))
+        assert abs(np.sum(v * x ** (2 * k)) - dfact) <= 1e-12 * dfact
+    assert abs(np.sum(v * x ** (2 * q)) - float(np.prod(np.arange(2 * q - 1, 0, -2)))) > 1.0
+    # every frequency of the half grid has its first coordinate negative (one of each pair)
+    f2, w2 = go.qff_frequencies(3, 4)
+    assert f2.shape == (32, 3) and np.all(f2[:, 0] < 0) and abs(w2.sum() - 1.0) < 1e-14
+
+
+def test_qff_gram_converges_exponentially_to_the_rbf_kernel():
+    X, _, theta = _problem(30, 2, "rbf", True, seed=40, ls=(0.5, 1.5))
+    K = go.kernel_matrix(X, X, theta, "rbf", True)
+    errs = []
+    for q in (2, 4, 8, 12):
+        f, w = go.qff_frequencies(2, q)
+        Z = go.rff_features(X, theta, True, f, w)
+        assert Z.shape == (30, q * q)
+        errs.append(np.max(np.abs(Z @ Z.T - K)))
+    assert errs[0] > 1e2 * errs[1] and errs[1] > 1e5 * errs[2]
+    assert errs[3] < 1e-12
+
+
+def test_qff_precond_terms_match_dense_finite_differences():
+    X, _, theta = _problem(25, 2, "rbf", True, seed=41, sigma2=0.05)
+    f, w = go.qff_frequencies(2, 4)
+    Z = go.rff_features(X, theta, True, f, w)
+    P = go.Preconditioner(Z, 0.05)
+    Cs = np.random.default_rng(11).standard_normal((25, 3))
+    tr, ctrl = go._precond_terms_rff(X, theta, True, f, Z, P, Cs, 0, w)
+
+    def dense_P(th):
+        Zt = go.rff_features(X, th, True, f, w)
+        return th[-1] * np.eye(25) + Zt @ Zt.T
+
+    for i in range(len(theta)):
+        h = 1e-6 * theta[i]
+        tp, tm = theta.copy(), theta.copy()
+        tp[i] += h
+        tm[i] -= h
+        Pp, Pm = dense_P(tp), dense_P(tm)
+        ref_tr = (np.linalg.slogdet(Pp)[1] - np.linalg.slogdet(Pm)[1]) / (2 * h)
+        ref_ctrl = (np.einsum("pi,pq,qi->i", Cs, Pp, Cs) - np.einsum("pi,pq,qi->i", Cs, Pm, Cs)) / (2 * h)
+        assert abs(tr[i] - ref_tr) <= 1e-6 * max(1.0, abs(ref_tr)), (i, tr[i], ref_tr)
+        np.testing.assert_allclose(ctrl[i], ref_ctrl, rtol=1e-6, atol=1e-6)
+
+
+def test_qff_estimators_are_unbiased_over_all_sign_patterns():
+    X, y, theta = _problem(7, 1, "rbf", False, seed=42, sigma2=0.1, ls=(0.3, 0.6))
+    n, k = 7, 2
+    vals, grads = [], []
+    for bits in itertools.product((-1.0, 1.0), repeat=n + k):
+        xi = np.array(bits)
+        es = go.estimate_mll(X, y, theta, "rbf", False, k, 1, 1e-13, n, 0, grad=True,
+                             signs=(xi[:n, None], xi[n:, None]), precond="qff", qff_nodes=2)
+        vals.append(es["logdet_est"])
+        grads.append(es["grad"])
+    vals, grads = np.array(vals), np.array(grads)
+    ex = go.exact_mll(X, y, theta, "rbf", False)
+    assert abs(vals.mean() - ex["logdet"]) <= 1e-9 * abs(ex["logdet"])
+    np.testing.assert_allclose(grads.mean(axis=0), ex["grad"], rtol=1e-8, atol=1e-9)
