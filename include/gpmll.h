@@ -199,6 +199,23 @@ int gp_precond_build_rff(const gp_problem* prob, const double* theta_host, int32
                          const double* freq_dev, void* ws_dev, size_t ws_bytes, hipStream_t stream,
                          gp_precond** out);
 
+/*
+ * gp_precond_build_qff — quadrature Fourier feature preconditioner of the RBF
+ * kernel (Table 1, "QFF"; Mutny & Krause 2018): the form of
+ * gp_precond_build_rff with deterministic frequencies and weights, the tensor
+ * Gauss rule of the standard normal spectral density with q = nodes_per_dim
+ * points per dimension (probabilists' Hermite nodes, weights summing to 1).
+ * Of each +-pair of grid nodes one is kept, with its weight doubled, so the
+ * rank is q^d: Z = sqrt(s) [sqrt(w_j) cos(Phi_j) | sqrt(w_j) sin(Phi_j)] and
+ * Z Z^T -> K exponentially fast in q.  The workspace and later gp_mll_* calls
+ * use rank = q^d.  Derivatives hold nodes and weights fixed.
+ * Errors: GP_EINVAL for odd q, q < 2, q > 64, q^d > min(n, GP_MAX_RANK), or as
+ * gp_precond_build; GP_EUNSUPPORTED for a kernel other than GP_KERNEL_RBF;
+ * GP_EWORKSPACE; GP_EHIP.  The call waits for its small host-to-device copy.
+ */
+int gp_precond_build_qff(const gp_problem* prob, const double* theta_host, int32_t nodes_per_dim,
+                         void* ws_dev, size_t ws_bytes, hipStream_t stream, gp_precond** out);
+
 /* gp_precond_view_of — device views of a built preconditioner. */
 int gp_precond_view_of(const gp_precond* P, gp_precond_view* view);
 

@@ -24,7 +24,7 @@ MAX_D, MAX_PROBES, MAX_RANK = 32, 255, 1024
 BATCH_MAX_RANK, BATCH_MAX_PROBES = 256, 64
 
 EXPORTS = ("gp_workspace_size", "gp_precond_build", "gp_precond_build_nystrom", "gp_precond_build_rff",
-           "gp_precond_view_of",
+           "gp_precond_build_qff", "gp_precond_view_of",
            "gp_precond_free",
            "gp_mll_eval", "gp_mll_grad", "gp_khat_matvec", "gp_khat_profile", "gp_batch_workspace_size",
            "gp_batch_mll_eval", "gp_batch_mll_grad", "gp_strerror", "gp_last_hip_error")
@@ -92,6 +92,7 @@ def load(path: str = LIB_PATH):
     lib.gp_workspace_size.argtypes = [P, O, i32, szp]
     lib.gp_precond_build.argtypes = [P, dp, i32, vp, ctypes.c_size_t, vp, ctypes.POINTER(vp)]
     lib.gp_precond_build_rff.argtypes = [P, dp, i32, vp, vp, ctypes.c_size_t, vp, ctypes.POINTER(vp)]
+    lib.gp_precond_build_qff.argtypes = [P, dp, i32, vp, ctypes.c_size_t, vp, ctypes.POINTER(vp)]
     lib.gp_precond_build_nystrom.argtypes = [P, dp, i32, ctypes.POINTER(ctypes.c_int32), vp, ctypes.c_size_t, vp,
                                              ctypes.POINTER(vp)]
     lib.gp_precond_view_of.argtypes = [vp, ctypes.POINTER(gp_precond_view)]
@@ -110,7 +111,8 @@ def load(path: str = LIB_PATH):
     lib.gp_strerror.restype = ctypes.c_char_p
     lib.gp_last_hip_error.argtypes = []
     for name in ("gp_workspace_size", "gp_precond_build", "gp_precond_build_nystrom", "gp_precond_build_rff",
-                 "gp_precond_view_of", "gp_mll_eval", "gp_mll_grad", "gp_khat_matvec", "gp_khat_profile",
+                 "gp_precond_build_qff", "gp_precond_view_of", "gp_mll_eval", "gp_mll_grad", "gp_khat_matvec",
+                 "gp_khat_profile",
                  "gp_batch_workspace_size", "gp_batch_mll_eval", "gp_batch_mll_grad", "gp_last_hip_error"):
         getattr(lib, name).restype = ctypes.c_int
     del u64
@@ -208,6 +210,15 @@ def gp_precond_build_nystrom(prob, theta, rank, landmarks, ws, stream=None):
                                            lm.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
                                            ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream(stream),
                                            ctypes.byref(h)), "gp_precond_build_nystrom")
+    return h
+
+
+def gp_precond_build_qff(prob, theta, nodes_per_dim, ws, stream=None):
+    """RBF kernel only; the preconditioner rank is nodes_per_dim ** d."""
+    arr, tp = _theta(theta)
+    h = ctypes.c_void_p()
+    _check(load().gp_precond_build_qff(ctypes.byref(prob), tp, nodes_per_dim, ctypes.c_void_p(ws.data_ptr()),
+                                       ws.numel(), _stream(stream), ctypes.byref(h)), "gp_precond_build_qff")
     return h
 
 

@@ -118,6 +118,7 @@ Layout make_layout(int64_t n, int d, int ard, int num_probes, int max_iters, int
   L.ltr_part = take((size_t)L.nchunk * kk * kk * 8);
   L.freq = take((size_t)(kk / 2 + 1) * GP_MAX_D * 8);
   L.landmarks = take(kk * 4);
+  L.famp = take((kk / 2 + 1) * 8);
   L.precond_end = off;
   // estimator block
   L.xfa = take(np * L.kd * esz);
@@ -380,6 +381,118 @@ extern "C" int gp_precond_build_nystrom(const gp_problem* prob, const double* th
   P->lay = L;
   P->ws = (char*)ws_dev;
   P->prob = *prob;
+  const int p = prob->ard ? prob->d : 1;
+  P->theta.assign(theta_host, theta_host + p + 2);
+  *out = P;
+  return GP_OK;
+}
+
+// Gauss rule of the standard normal with q points (probabilists' Hermite
+// polynomials He_0 = 1, He_1 = x, He_{k+1} = x He_k - k He_{k-1}): nodes are the
+// eigenvalues of the Jacobi matrix (zero diagonal, off-diagonal sqrt(k)), found by
+// Sturm-sequence bisection and polished by Newton steps on He_q; weights
+// q! / (q He_{q-1}(x))^2 (Christoffel numbers, summing to 1).  Nodes ascending.
+static void hermite_pair(int q, double x, double* hq, double* hq1) {
+  double a = 1.0, b = x;  // He_0, He_1
+  for (int k = 1; k < q; ++k) {
+    const double c = x * b - k * a;
+    a = b;
+    b = c;
+  }
+  *hq = b;   // He_q
+  *hq1 = a;  // He_{q-1}
+}
+
+static void gauss_hermite_normal(int q, std::vector<double>& x, std::vector<double>& w) {
+  x.assign(q, 0.0);
+  w.assign(q, 0.0);
+  // eigenvalues below t = negative pivots of the LDL^T factorisation of J - t I
+  // (an exact zero pivot is taken as -0, i.e. t as slightly larger)
+  auto below = [q](double t) {
+    int cnt = 0;
+    double dk = -t;
+    for (int k = 0;; ++k) {
+      if (dk == 0.0) dk = -1e-300;
+      if (dk < 0.0) ++cnt;
+      if (k + 1 == q) break;
+      dk = -t - (double)(k + 1) / dk;
+    }
+    return cnt;
+  };
+  const double bound = 2.0 * std::sqrt((double)q) + 2.0;
+  for (int i = 0; i < q; ++i) {
+    double lo = -bound, hi = bound;  // below(lo) <= i < below(hi)
+    for (int it = 0; it < 200 && hi - lo > 1e-15 * std::max(1.0, std::fabs(lo)); ++it) {
+      const double mid = 0.5 * (lo + hi);
+      if (below(mid) <= i) lo = mid;
+      else hi = mid;
+    }
+    double xi = 0.5 * (lo + hi);
+    for (int it = 0; it < 3; ++it) {
+      double hq, hq1;
+      hermite_pair(q, xi, &hq, &hq1);
+      if (hq1 != 0.0) xi -= hq / (q * hq1);
+    }
+    double hq, hq1;
+    hermite_pair(q, xi, &hq, &hq1);
+    x[i] = xi;
+    w[i] = std::exp(std::lgamma(q + 1.0) - 2.0 * std::log((double)q) - 2.0 * std::log(std::fabs(hq1)));
+  }
+}
+
+extern "C" int gp_precond_build_qff(const gp_problem* prob, const double* theta_host, int32_t nodes_per_dim,
+                                    void* ws_dev, size_t ws_bytes, hipStream_t stream, gp_precond** out) {
+  if (!out) return GP_EINVAL;
+  *out = nullptr;
+  RET_IF(check_problem(prob));
+  const int q = nodes_per_dim;
+  if (q < 2 || q % 2 != 0 || q > 64) return GP_EINVAL;  // He_{q-1} stays in range up to q = 64
+  int64_t rank64 = 1;
+  for (int j = 0; j < prob->d; ++j) {
+    rank64 *= q;
+    if (rank64 > GP_MAX_RANK) return GP_EINVAL;
+  }
+  const int rank = (int)rank64;
+  RET_IF(check_rank(prob, rank));
+  if (prob->kernel != GP_KERNEL_RBF) return GP_EUNSUPPORTED;
+  Hyper h;
+  RET_IF(make_hyper(prob, theta_host, &h));
+  RET_IF(check_device());
+  Layout L = make_layout(prob->n, prob->d, prob->ard, 1, 1, rank, GP_PREC_FP64);
+  if (!ws_dev || (reinterpret_cast<uintptr_t>(ws_dev) & 255) != 0) return GP_EINVAL;
+  if (ws_bytes < L.precond_end) return GP_EWORKSPACE;
+  // tensor grid, first coordinate over the q/2 negative nodes (one of each +- pair,
+  // weight doubled), lexicographic with the first coordinate slowest
+  std::vector<double> gx, gw;
+  gauss_hermite_normal(q, gx, gw);
+  const int m = rank / 2, d = prob->d;
+  std::vector<double> W((size_t)m * d), amp(m);
+  for (int r = 0; r < m; ++r) {
+    int rem = r;
+    double wt = 2.0;
+    for (int j = d - 1; j >= 0; --j) {
+      const int base = (j == 0) ? q / 2 : q;
+      const int idx = rem % base;
+      rem /= base;
+      W[(size_t)r * d + j] = gx[idx];
+      wt *= gw[idx];
+    }
+    amp[r] = std::sqrt(h.s * wt);
+  }
+  Ctx c{&L, (char*)ws_dev, stream};
+  HIPCHK(hipMemsetAsync(c.at<int>(L.flags), 0, 64, stream));
+  HIPCHK(hipMemcpyAsync(c.at<double>(L.freq), W.data(), W.size() * sizeof(double), hipMemcpyHostToDevice, stream));
+  HIPCHK(hipMemcpyAsync(c.at<double>(L.famp), amp.data(), amp.size() * sizeof(double), hipMemcpyHostToDevice,
+                        stream));
+  HIPCHK(hipStreamSynchronize(stream));  // the host tables are locals
+  HIPCHK(launch_prep(c, prob->X_dev, h));
+  HIPCHK(launch_rff(c, h, true));
+  HIPCHK(launch_precond_finish(c, h));
+  gp_precond* P = new gp_precond;
+  P->lay = L;
+  P->ws = (char*)ws_dev;
+  P->prob = *prob;
+  P->kind = kRff;
   const int p = prob->ard ? prob->d : 1;
   P->theta.assign(theta_host, theta_host + p + 2);
   *out = P;

@@ -89,6 +89,7 @@ struct Layout {
   size_t xs, mean, mean_part, L, diag, ispiv, piv, amax, C, Rc, Rinv, Cinv, logdetP, scal_small, flags, ltr_part;
   size_t freq;          // m x d spectral samples of the random Fourier feature preconditioner
   size_t landmarks;     // k prescribed pivot rows of the Nystrom preconditioner
+  size_t famp;          // m per-frequency amplitudes of weighted Fourier features
   size_t precond_end;
   // estimator block
   size_t xfa, xfb, rowterm, colterm, H, Y, ltr, ltr_raw, ltr_part2;
@@ -127,8 +128,9 @@ hipError_t launch_prep(const Ctx& c, const double* X, const Hyper& h);
 // greedy pivots, or (forced != null) the k prescribed distinct rows in that order
 hipError_t launch_pivchol(const Ctx& c, const Hyper& h, const int32_t* forced = nullptr);
 hipError_t launch_precond_finish(const Ctx& c, const Hyper& h);
-// random Fourier features from the samples at lay.freq into the L slot (rank 2m)
-hipError_t launch_rff(const Ctx& c, const Hyper& h);
+// Fourier features from the frequencies at lay.freq into the L slot (rank 2m), with
+// amplitude sqrt(s/m) (random features) or the amplitudes at lay.famp (weighted)
+hipError_t launch_rff(const Ctx& c, const Hyper& h, bool weighted = false);
 
 // preconditioner families: the low-rank factor in the L slot comes from
 enum PrecondKind { kPivChol = 0, kRff = 1 };

@@ -252,14 +252,16 @@ __global__ void k_logdet_noprecond(int64_t n, double s2, double* logdetP) {
 // ---------------------------------------------------------------------------
 // Random Fourier feature preconditioner (Table 1, "RFF"): Z = sqrt(s/m)
 // [cos(Phi) | sin(Phi)] with Phi = x~ W^T, x~ the centred scaled inputs and W the
-// m x d spectral samples at unit lengthscale.  One thread per row; Z is written
+// m x d spectral samples at unit lengthscale.  Quadrature Fourier features (Table
+// 1, "QFF") use the same form with quadrature nodes as W and per-frequency
+// amplitudes sqrt(s w_j) (amps; null: sqrt(s/m) for all).  One thread per row; Z is written
 // column-major n x 2m in the slot of the pivoted Cholesky factor, the pivots read
 // -1 and the achieved rank is 2m.
 // ---------------------------------------------------------------------------
 
 __global__ void k_rff_features(const double* __restrict__ xs, int64_t n, int d, int m,
-                               const double* __restrict__ W, double amp, double* __restrict__ Z,
-                               int32_t* __restrict__ piv, int* __restrict__ small) {
+                               const double* __restrict__ W, const double* __restrict__ amps, double amp0,
+                               double* __restrict__ Z, int32_t* __restrict__ piv, int* __restrict__ small) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < 2 * m) piv[i] = -1;
   if (i == 0) {
@@ -274,6 +276,7 @@ __global__ void k_rff_features(const double* __restrict__ xs, int64_t n, int d, 
     for (int q = 0; q < d; ++q) ph = fma(W[j * d + q], x[q], ph);
     double sn, cs;
     sincos(ph, &sn, &cs);
+    const double amp = amps ? amps[j] : amp0;
     Z[(int64_t)j * n + i] = amp * cs;
     Z[(int64_t)(m + j) * n + i] = amp * sn;
   }
@@ -345,13 +348,13 @@ hipError_t launch_pivchol(const Ctx& c, const Hyper& h, const int32_t* forced) {
   return hipGetLastError();
 }
 
-hipError_t launch_rff(const Ctx& c, const Hyper& h) {
+hipError_t launch_rff(const Ctx& c, const Hyper& h, bool weighted) {
   const Layout& L = *c.lay;
   const int m = L.k / 2;
   const int64_t cnt = std::max<int64_t>(L.n, L.k);
   hipLaunchKernelGGL(k_rff_features, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, c.st, c.at<double>(L.xs),
-                     L.n, L.d, m, c.at<double>(L.freq), sqrt(h.s / m), c.at<double>(L.L), c.at<int32_t>(L.piv),
-                     c.at<int>(L.scal_small));
+                     L.n, L.d, m, c.at<double>(L.freq), weighted ? c.at<double>(L.famp) : nullptr, sqrt(h.s / m),
+                     c.at<double>(L.L), c.at<int32_t>(L.piv), c.at<int>(L.scal_small));
   return hipGetLastError();
 }
 

@@ -180,6 +180,21 @@ def test_nystrom_build_rejects_bad_landmarks_before_any_device_call(lib):
                                         ctypes.byref(h)) == B.GP_EINVAL
 
 
+def test_qff_build_rejects_bad_node_counts_and_kernels(lib):
+    theta = np.array([0.5, 0.5, 0.5, 1.0, 0.1])
+    tp = theta.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    ws = ctypes.c_void_p(0x10000)
+    h = ctypes.c_void_p()
+    p = _fake_problem(n=10000, d=3)
+    for q in (3, 0, 66, 12):   # odd, too small, above 64, 12^3 > GP_MAX_RANK
+        assert lib.gp_precond_build_qff(ctypes.byref(p), tp, q, ws, 1 << 30, None, ctypes.byref(h)) == B.GP_EINVAL
+    p_small = _fake_problem(n=50, d=3)   # 4^3 = 64 > n
+    assert lib.gp_precond_build_qff(ctypes.byref(p_small), tp, 4, ws, 1 << 30, None, ctypes.byref(h)) == B.GP_EINVAL
+    p_mat = _fake_problem(n=10000, d=3, kernel=1)
+    assert lib.gp_precond_build_qff(ctypes.byref(p_mat), tp, 4, ws, 1 << 30, None,
+                                    ctypes.byref(h)) == B.GP_EUNSUPPORTED
+
+
 def test_strerror_covers_every_status(lib):
     for code in (0, -1, -2, -3, -4, -5):
         assert B.gp_strerror(code) and B.gp_strerror(code) != "unknown status"

@@ -261,3 +261,90 @@ def test_nystrom_rejects_bad_landmarks():
     for S in ([1, 2, 2, 3], [1, 2, 3, 200], [-1, 2, 3, 4]):
         with pytest.raises(B.GPError):
             B.gp_precond_build_nystrom(prob, pr.theta, 4, S, ws)
+
+
+# ---------------------------------------------------------------- quadrature Fourier features
+
+# A q-point rule resolves cos(w . delta) only for |delta| up to about sqrt(q), so
+# the cases keep the scaled inputs compact (longer lengthscales in 2-D and 3-D).
+# Noise levels keep K_hat's condition number within what BF16x3 tiles resolve
+# (their relative product error ~1e-5 times the condition number bounds the
+# solves; a 1-D set of 1500 points at sigma^2 = 0.01 exceeds the gradient bar).
+QFF_CASES = [
+    # name, n, d, ard, q (rank q^d), sigma^2, lengthscale range; CG iterations of the oracle
+    ("rbf_1d", 1500, 1, False, 8, 0.05, (0.4, 1.5)),      # 27
+    ("rbf_ard_2d", 1200, 2, True, 6, 0.05, (1.0, 2.0)),   # 25
+    ("rbf_ard_3d", 900, 3, True, 4, 0.1, (1.0, 2.0)),     # 77
+]
+
+
+def run_qff(pr, precision, q, precond_grad=0, grad=True):
+    rank = q ** pr.d
+    say(f"[gpu] qff estimator {pr.name} n={pr.n} d={pr.d} ard={pr.ard} prec={precision} q={q} rank={rank}")
+    dev = torch.device("cuda:0")
+    X = torch.tensor(pr.X, device=dev)
+    y = torch.tensor(pr.y, device=dev)
+    prob = B.make_problem(X, y, "rbf", pr.ard)
+    opt = B.make_options(precision, pr.num_probes, pr.max_iters, pr.tol, pr.probe_seed, precond_grad, 1)
+    ws = B.alloc_workspace(B.gp_workspace_size(prob, opt, rank))
+    h = B.gp_precond_build_qff(prob, pr.theta, q, ws)
+    logp = torch.zeros(1, dtype=torch.float64, device=dev)
+    g = torch.zeros(len(pr.theta), dtype=torch.float64, device=dev)
+    st = B.Stats(pr.num_probes, rank)
+    try:
+        if grad:
+            B.gp_mll_grad(prob, pr.theta, opt, rank, h, ws, logp, g, st)
+        else:
+            B.gp_mll_eval(prob, pr.theta, opt, rank, h, ws, logp, st)
+        torch.cuda.synchronize()
+        v = B.gp_precond_view_of(h)
+        n = pr.n
+        Wg = np.frombuffer(ws.cpu().numpy().tobytes(), dtype=np.uint8)
+        base = ws.data_ptr()
+        Z = Wg[v.L_dev - base: v.L_dev - base + n * rank * 8].view(np.float64).reshape(rank, n).T
+        ldp = float(Wg[v.logdet_dev - base: v.logdet_dev - base + 8].view(np.float64)[0])
+    finally:
+        B.gp_precond_free(h)
+    return {"logp": float(logp.cpu()[0]), "grad": g.cpu().numpy(), "stats": st, "Z": Z, "logdet_P": ldp}
+
+
+def _qff_case(n, d, ard, q, s2, ls, seed=39):
+    return synthgp.random_problem(n, d, "rbf", ard=ard, rank=q ** d, num_probes=8, seed=seed,
+                                  ls_range=ls, sigma2=s2, dist="normal", tol=1e-8, max_iters=400)
+
+
+@pytest.mark.parametrize("name,n,d,ard,q,s2,ls", QFF_CASES)
+def test_qff_features_match_oracle(name, n, d, ard, q, s2, ls):
+    pr = _qff_case(n, d, ard, q, s2, ls)
+    out = run_qff(pr, "fp64", q, grad=False)
+    f, w = go.qff_frequencies(d, q)
+    Zr = go.rff_features(pr.X, pr.theta, ard, f, w)
+    np.testing.assert_allclose(out["Z"], Zr, rtol=0, atol=1e-12)
+    assert rel(out["logdet_P"], go.Preconditioner(Zr, pr.theta[-1]).logdet) < 1e-11
+
+
+@pytest.mark.parametrize("precision,lp_tol,g_tol", [("fp64", 1e-7, 1e-5), ("bf16x3", 1e-3, 1e-2)])
+@pytest.mark.parametrize("name,n,d,ard,q,s2,ls", QFF_CASES)
+def test_qff_estimator_matches_oracle(name, n, d, ard, q, s2, ls, precision, lp_tol, g_tol):
+    pr = _qff_case(n, d, ard, q, s2, ls)
+    out = run_qff(pr, precision, q)
+    ref = go.estimate_mll(pr.X, pr.y, pr.theta, "rbf", ard, q ** d, pr.num_probes, pr.tol, pr.max_iters,
+                          pr.probe_seed, grad=True, precond="qff", qff_nodes=q)
+    say(f"    logp {out['logp']:.12e} oracle {ref['logp']:.12e} rel {rel(out['logp'], ref['logp']):.2e}; "
+        f"grad rel {relvec(out['grad'], ref['grad']):.2e}; iters {out['stats'].iters_max} / {ref['iters'].max()}")
+    assert rel(out["logp"], ref["logp"]) < lp_tol
+    assert relvec(out["grad"], ref["grad"]) < g_tol
+    assert out["stats"].flags & B.FLAG_NOT_CONVERGED == 0
+
+
+def test_qff_rejects_bad_arguments():
+    pr = _qff_case(300, 2, True, 4, 0.1, (1.0, 2.0))
+    dev = torch.device("cuda:0")
+    X = torch.tensor(pr.X, device=dev)
+    y = torch.tensor(pr.y, device=dev)
+    ws = B.alloc_workspace(B.gp_workspace_size(B.make_problem(X, y, "rbf", True), B.make_options("fp64", 4, 50), 64))
+    for q in (3, 0, 66):
+        with pytest.raises(B.GPError):
+            B.gp_precond_build_qff(B.make_problem(X, y, "rbf", True), pr.theta, q, ws)
+    with pytest.raises(B.GPError):
+        B.gp_precond_build_qff(B.make_problem(X, y, "matern32", True), pr.theta, 4, ws)
