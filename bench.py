@@ -9,7 +9,8 @@ HBM.  Prints one JSON line.
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-fp64] [--no-cpu] [--no-batch]
 
 Besides the headline line it reports the FP16X3 and FP64 tile precisions on the same
-workload and the 64-problem ragged batch (gp_batch_mll_grad) as extra fields.
+workload, the randomized Nystrom and random Fourier feature preconditioners at the
+same rank, and the 64-problem ragged batch (gp_batch_mll_grad) as extra fields.
 """
 from __future__ import annotations
 
@@ -138,6 +139,57 @@ def run_batched(steps, warmup):
             "flags_any": int(st.flags_any)}
 
 
+def run_preconditioners(pr, steps, ref):
+    """The other diagonal-plus-low-rank preconditioners of Table 1 on the headline
+    workload at the same rank and tile precision (BF16x3): randomized Nystrom on
+    uniform landmarks and random Fourier features.  A step is the preconditioner
+    build plus one gp_mll_grad with that handle.  `ref` is the pivoted-Cholesky
+    run, whose log p the estimates are compared with (both are stochastic
+    estimates of the same quantity)."""
+    import torch
+    import synthgp
+    from paper_2107_00243_amd import binding as B
+    dev = torch.device("cuda:0")
+    X = torch.tensor(pr.X, device=dev)
+    y = torch.tensor(pr.y, device=dev)
+    prob = B.make_problem(X, y, pr.kernel, pr.ard)
+    opt = B.make_options("bf16x3", pr.num_probes, pr.max_iters, pr.tol, pr.probe_seed, 0, 1)
+    ws = B.alloc_workspace(B.gp_workspace_size(prob, opt, pr.rank))
+    logp = torch.zeros(1, dtype=torch.float64, device=dev)
+    grad = torch.zeros(len(pr.theta), dtype=torch.float64, device=dev)
+    S = synthgp.uniform_landmarks(pr.n, pr.rank, seed=1)
+    Wd = torch.tensor(synthgp.spectral_frequencies(pr.kernel, pr.rank // 2, pr.d, seed=1), device=dev)
+    builders = {
+        "nystrom_uniform_landmarks": lambda: B.gp_precond_build_nystrom(prob, pr.theta, pr.rank, S, ws),
+        "random_fourier_features": lambda: B.gp_precond_build_rff(prob, pr.theta, pr.rank, Wd, ws),
+    }
+    out = {}
+    for name, build in builders.items():
+        st = B.Stats(pr.num_probes, pr.rank)
+        h = build()
+        B.gp_mll_grad(prob, pr.theta, opt, pr.rank, h, ws, logp, grad, st)
+        B.gp_precond_free(h)
+        torch.cuda.synchronize()
+        lp = float(logp.cpu()[0])
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            h = build()
+            B.gp_mll_grad(prob, pr.theta, opt, pr.rank, h, ws, logp, grad)
+            B.gp_precond_free(h)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / steps
+        out[name] = {"evals_per_s": 1.0 / dt, "ms_per_step": 1e3 * dt, "steps": steps,
+                     "cg_iters_max": int(st.iters_max), "cg_iters_mean": float(np.mean(st.col_iters)),
+                     "flags": int(st.flags), "logp": lp,
+                     "rel_logp_vs_pivoted_cholesky": abs(lp - ref["logp"]) / abs(ref["logp"])}
+        log(f"[bench] {name}: {1e3 * dt:.1f} ms/eval, iters {st.iters_max}")
+    out["pivoted_cholesky"] = {"evals_per_s": ref["evals_per_s"], "cg_iters_max": ref["iters_max"],
+                               "cg_iters_mean": ref["iters_mean"], "logp": ref["logp"]}
+    del ws
+    torch.cuda.empty_cache()
+    return out
+
+
 def tiles_only(pr, reps=10, copy_bytes=1 << 30):
     """The tile kernel alone in the bench's launch configuration, then a plain
     elementwise copy of copy_bytes (read copy_bytes, write copy_bytes) whose
@@ -201,6 +253,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-problem ragged batch")
     ap.add_argument("--batch-only", action="store_true", help="only the 64-problem ragged batch (one JSON line)")
+    ap.add_argument("--no-precond", action="store_true", help="skip the Nystrom / RFF preconditioner leg")
     ap.add_argument("--n", type=int, default=100000)
     ap.add_argument("--tiles-only", action="store_true",
                     help="only the BF16x3 tile kernel (10 launches) and a 1 GiB elementwise copy, for counters")
@@ -252,6 +305,10 @@ def main():
         roofline["issued_mfma_flops_per_launch"] = issued
         roofline["issued_mfma_frac_of_peak"] = issued / (bf["tile_ms"] * 1e-3) / 1e12 / PEAK_BF16_TFLOPS
         roofline["mfma_busy_frac"] = tc["mfma_busy_cycles"] / (tc["gui_active_per_xcd"] * 1024)
+    precs = None
+    if not args.no_precond:
+        log("[bench] other preconditioners of Table 1 (BF16x3)")
+        precs = run_preconditioners(pr, 2, bf)
     batched = None
     if not args.no_batch:
         log("[bench] 64-problem ragged batch")
@@ -275,6 +332,7 @@ def main():
         "fp64_gpu": out_fp64,
         "speedup_vs_fp64_gpu": (bf["evals_per_s"] / out_fp64["value"]) if out_fp64 else None,
         "batched_rbf_64": batched,
+        "preconditioners_bf16x3": precs,
         "fp16x3_gpu": {"value": h16["evals_per_s"], "ms_per_step": h16["ms_per_step"],
                        "iters_max": h16["iters_max"], "tile_ms": h16["tile_ms"],
                        "tile_tflops": tile_flops(n, d, t) / (h16["tile_ms"] * 1e-3) / 1e12,

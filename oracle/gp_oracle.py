@@ -212,8 +212,8 @@ def dkernel_cols(X, theta, kind, ard, cols):
 # Exact targets: Eq. (1) and Eq. (2) via dense Cholesky
 # ----------------------------------------------------------------------------
 
-def exact_mll(X, y, theta, kind, ard):
-    """Exact log p(y | theta) (Eq. 1) and its gradient (Eq. 2) in FP64."""
+def exact_mll(X, y, theta, kind, ard, grad=True):
+    """Exact log p(y | theta) (Eq. 1) and, if grad, its gradient (Eq. 2) in FP64."""
     n, d = X.shape
     Kh = khat_dense(X, theta, kind, ard)
     R = sla.cholesky(Kh, lower=True, overwrite_a=False, check_finite=True)
@@ -221,6 +221,8 @@ def exact_mll(X, y, theta, kind, ard):
     u = sla.cho_solve((R, True), y)
     datafit = float(y @ u)
     logp = -0.5 * (datafit + logdet + n * LOG2PI)
+    if not grad:
+        return {"logp": logp, "logdet": logdet, "datafit": datafit, "u": u}
     Kinv = sla.cho_solve((R, True), np.eye(n))
     del Kh, R
     # dL/dtheta = sum_pq dK_hat_pq (u_p u_q / 2 - Kinv_pq / 2)

@@ -311,6 +311,39 @@ def test_adam_on_the_autograd_function_follows_the_oracle_trajectory():
     assert hist[-1]["logp"] > hist[0]["logp"]
 
 
+class _OracleModel:
+    """The oracle's estimate behind the model interface of the optimiser drivers."""
+
+    def __init__(self, pr, rank, ell, tol, max_iters):
+        self.pr, self.args = pr, (rank, ell, tol, max_iters)
+        self.want_stats, self.last_stats = False, None
+
+    def evaluate(self, theta, with_grad=True, stats=False):
+        import torch as T
+        rank, ell, tol, max_iters = self.args
+        ref = go.estimate_mll(self.pr.X, self.pr.y, np.asarray(theta), self.pr.kernel, self.pr.ard, rank, ell, tol,
+                              max_iters, self.pr.probe_seed)
+        return T.tensor([ref["logp"]]), T.tensor(ref["grad"])
+
+
+def test_lbfgs_on_the_autograd_function_follows_the_oracle_trajectory():
+    # three L-BFGS iterations (strong Wolfe line search) through GPMLL and through
+    # the oracle's estimate (same probes): same evaluations, same iterates
+    from paper_2107_00243_amd.model import GPMarginalLikelihood
+    from paper_2107_00243_amd.train import lbfgs_fit
+    pr = synthgp.matern52_ard_20k(n=1200)
+    say(f"[gpu] lbfgs driver n={pr.n} d={pr.d}")
+    model = GPMarginalLikelihood(pr.X, pr.y, pr.kernel, pr.ard, 30, 16, 400, 1e-8, "fp64", pr.probe_seed)
+    hist, theta = lbfgs_fit(model, pr.theta, steps=3, log=say)
+    ref_hist, ref_theta = lbfgs_fit(_OracleModel(pr, 30, 16, 1e-8, 400), pr.theta, steps=3, log=say)
+    assert [h["evaluations"] for h in hist] == [h["evaluations"] for h in ref_hist]
+    for h, r in zip(hist, ref_hist):
+        for e, f in zip(h["evals"], r["evals"]):
+            assert rel(e["logp"], f["logp"]) < 1e-7
+    np.testing.assert_allclose(theta, ref_theta, rtol=1e-5)
+    assert hist[-1]["logp"] > hist[0]["logp"]
+
+
 def test_long_lanczos_runs_take_the_quadrature_path_and_match_the_oracle():
     # ~470 CG steps per probe, beyond the tridiagonals diagonalised by QR: the
     # log-determinant quadrature e1^T log(T) e1 comes from the integral form
