@@ -9,7 +9,8 @@ use it.  It shares no code with the HIP path.
 Two parts:
 
 * exact_mll: the exact targets, Eq. (1) (log marginal likelihood) and Eq. (2)
-  (its derivative), by a dense FP64 Cholesky factorisation (LAPACK potrf).
+  (its derivative), by a dense FP64 Cholesky factorisation (LAPACK potrf);
+  predict: the posterior mean and latent variance at test points, likewise.
 * estimate_mll: the stochastic estimator of Algorithms 1 and 2 (Section 4.4),
   step by step in the paper's order, with dense or row-blocked matrix products:
   partial pivoted Cholesky preconditioner P = sigma^2 I + L L^T (Section 2.2,
@@ -229,6 +230,20 @@ def exact_mll(X, y, theta, kind, ard, grad=True):
     grad = dkhat_contract(X, theta, kind, ard,
                           lambda r: 0.5 * np.outer(u[r], u) - 0.5 * Kinv[r])
     return {"logp": logp, "grad": grad, "logdet": logdet, "datafit": datafit, "u": u}
+
+
+def predict(X, y, theta, kind, ard, Xstar):
+    """GP posterior at test points (Sec. 2.1: the posterior of f given y under the
+    zero-mean prior): mean k(X*, X) K_hat^-1 y and latent variance
+    k(x*, x*) - k(x*, X) K_hat^-1 k(X, x*) (noise not added), by a dense FP64
+    Cholesky factorisation of K_hat."""
+    Kh = khat_dense(X, theta, kind, ard)
+    R = sla.cholesky(Kh, lower=True)
+    Ks = kernel_matrix(X, np.asarray(Xstar, dtype=np.float64), theta, kind, ard)   # n x n*
+    u = sla.cho_solve((R, True), y)
+    A = sla.cho_solve((R, True), Ks)
+    _, s, _ = split_theta(theta, X.shape[1], ard)
+    return Ks.T @ u, s - np.sum(Ks * A, axis=0)
 
 
 def bareiss_det(A):

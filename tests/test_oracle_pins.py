@@ -617,3 +617,34 @@ def test_qff_estimators_are_unbiased_over_all_sign_patterns():
     ex = go.exact_mll(X, y, theta, "rbf", False)
     assert abs(vals.mean() - ex["logdet"]) <= 1e-9 * abs(ex["logdet"])
     np.testing.assert_allclose(grads.mean(axis=0), ex["grad"], rtol=1e-8, atol=1e-9)
+
+
+# ------------------------------------------------ posterior prediction (Sec. 2.1)
+
+@pytest.mark.parametrize("kind,nu", [("rbf", None), ("matern32", 1.5), ("matern52", 2.5)])
+def test_predict_matches_scikit_learn_gaussian_process_regressor(kind, nu):
+    from sklearn.gaussian_process import GaussianProcessRegressor
+    from sklearn.gaussian_process.kernels import RBF, ConstantKernel, Matern
+    X, y, theta = _problem(60, 3, kind, True, seed=50, sigma2=0.05)
+    Xs = np.random.default_rng(51).uniform(-0.2, 1.2, size=(25, 3))
+    ls, s, s2 = theta[:3], theta[3], theta[4]
+    base = RBF(length_scale=ls, length_scale_bounds="fixed") if kind == "rbf" else \
+        Matern(length_scale=ls, length_scale_bounds="fixed", nu=nu)
+    gpr = GaussianProcessRegressor(ConstantKernel(s, constant_value_bounds="fixed") * base, alpha=s2,
+                                   optimizer=None, normalize_y=False).fit(X, y)
+    mu_ref, sd_ref = gpr.predict(Xs, return_std=True)
+    mu, var = go.predict(X, y, theta, kind, True, Xs)
+    np.testing.assert_allclose(mu, mu_ref, rtol=1e-9, atol=1e-10)
+    np.testing.assert_allclose(np.sqrt(np.maximum(var, 0.0)), sd_ref, rtol=1e-7, atol=1e-8)
+
+
+def test_predict_single_point_closed_form_and_limits():
+    X = np.array([[0.3, -0.1]])
+    y = np.array([1.7])
+    theta = np.array([0.8, 1.3, 0.1])            # isotropic ls, s, sigma^2
+    Xs = np.array([[0.3, -0.1], [1.0, 0.5], [30.0, 30.0]])
+    mu, var = go.predict(X, y, theta, "rbf", False, Xs)
+    k = 1.3 * np.exp(-0.5 * np.sum((Xs - X) ** 2, axis=1) / 0.8 ** 2)
+    np.testing.assert_allclose(mu, k * 1.7 / (1.3 + 0.1), rtol=1e-14)
+    np.testing.assert_allclose(var, 1.3 - k * k / (1.3 + 0.1), rtol=1e-14)
+    assert abs(mu[2]) < 1e-100 and abs(var[2] - 1.3) < 1e-14   # far away: the prior
