@@ -254,6 +254,26 @@ int gp_mll_grad(const gp_problem* prob, const double* theta_host, const gp_optio
                 hipStream_t stream, double* logp_dev, double* grad_dev, gp_stats* stats);
 
 /*
+ * gp_predict — GP posterior at test points (Sec. 2.1: the posterior of f under
+ * the zero-mean prior given y): for each test point x*_j
+ *   mean_j = k(x*_j, X) K_hat^-1 y,
+ *   var_j  = s - k(x*_j, X) K_hat^-1 k(X, x*_j)   (latent f; add sigma^2 for y*),
+ * from preconditioned CG on [y | k(X, x*_j) for a chunk of test points] with the
+ * same on-the-fly K_hat tiles, preconditioner and stopping rule as gp_mll_eval.
+ * Test points go in chunks of opt->num_probes per CG call, so the workspace of
+ * gp_workspace_size(prob, opt, rank) serves any nstar.  Xstar_dev: nstar x d
+ * row-major FP64 device array; mean_dev: FP64[nstar]; var_dev: FP64[nstar] or
+ * NULL.  opt->seed and precond_grad are unused.  P: NULL or a preconditioner
+ * built in ws_dev for the same problem, theta and rank.  The call waits for
+ * the stream at its end to report deferred errors (GP_ENOTSPD).
+ * Errors: GP_EINVAL (null pointers, nstar < 1, bad shapes or theta),
+ * GP_EWORKSPACE, GP_ENOTSPD, GP_EHIP.
+ */
+int gp_predict(const gp_problem* prob, const double* theta_host, const gp_options* opt, int32_t rank,
+               gp_precond* P, const double* Xstar_dev, int64_t nstar, void* ws_dev, size_t ws_bytes,
+               hipStream_t stream, double* mean_dev, double* var_dev);
+
+/*
  * gp_khat_matvec — W = K_hat V (the product inside every CG iteration) with
  * tiles of the given precision: V_dev and W_dev are n x num_rhs row-major FP64
  * (1 <= num_rhs <= 1 + GP_MAX_PROBES).  Uses the workspace for staging.

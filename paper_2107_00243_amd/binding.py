@@ -24,7 +24,7 @@ MAX_D, MAX_PROBES, MAX_RANK = 32, 255, 1024
 BATCH_MAX_RANK, BATCH_MAX_PROBES = 256, 64
 
 EXPORTS = ("gp_workspace_size", "gp_precond_build", "gp_precond_build_nystrom", "gp_precond_build_rff",
-           "gp_precond_build_qff", "gp_precond_view_of",
+           "gp_precond_build_qff", "gp_precond_view_of", "gp_predict",
            "gp_precond_free",
            "gp_mll_eval", "gp_mll_grad", "gp_khat_matvec", "gp_khat_profile", "gp_batch_workspace_size",
            "gp_batch_mll_eval", "gp_batch_mll_grad", "gp_strerror", "gp_last_hip_error")
@@ -101,6 +101,7 @@ def load(path: str = LIB_PATH):
     lib.gp_mll_eval.argtypes = [P, dp, O, i32, vp, vp, ctypes.c_size_t, vp, vp, S]
     lib.gp_mll_grad.argtypes = [P, dp, O, i32, vp, vp, ctypes.c_size_t, vp, vp, vp, S]
     lib.gp_khat_matvec.argtypes = [P, dp, i32, vp, i32, vp, vp, ctypes.c_size_t, vp]
+    lib.gp_predict.argtypes = [P, dp, O, i32, vp, vp, ctypes.c_int64, vp, ctypes.c_size_t, vp, vp, vp]
     lib.gp_khat_profile.argtypes = [P, dp, O, i32, vp, ctypes.c_size_t, vp, dp, ctypes.POINTER(ctypes.c_int64),
                                     ctypes.POINTER(ctypes.c_int64)]
     BP, BS = ctypes.POINTER(gp_batch), ctypes.POINTER(gp_batch_stats)
@@ -112,6 +113,7 @@ def load(path: str = LIB_PATH):
     lib.gp_last_hip_error.argtypes = []
     for name in ("gp_workspace_size", "gp_precond_build", "gp_precond_build_nystrom", "gp_precond_build_rff",
                  "gp_precond_build_qff", "gp_precond_view_of", "gp_mll_eval", "gp_mll_grad", "gp_khat_matvec",
+                 "gp_predict",
                  "gp_khat_profile",
                  "gp_batch_workspace_size", "gp_batch_mll_eval", "gp_batch_mll_grad", "gp_last_hip_error"):
         getattr(lib, name).restype = ctypes.c_int
@@ -256,6 +258,16 @@ def gp_mll_grad(prob, theta, opt, rank, precond, ws, logp, grad, stats: Stats | 
                               ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream(stream),
                               ctypes.c_void_p(logp.data_ptr()), ctypes.c_void_p(grad.data_ptr()),
                               ctypes.byref(stats.raw) if stats is not None else None), "gp_mll_grad")
+
+
+def gp_predict(prob, theta, opt, rank, precond, Xstar, ws, mean, var=None, stream=None):
+    """Posterior mean (and latent variance if var is given) at the rows of the
+    device tensor Xstar (nstar x d FP64)."""
+    arr, tp = _theta(theta)
+    _check(load().gp_predict(ctypes.byref(prob), tp, ctypes.byref(opt), rank, precond,
+                             ctypes.c_void_p(Xstar.data_ptr()), Xstar.shape[0], ctypes.c_void_p(ws.data_ptr()),
+                             ws.numel(), _stream(stream), ctypes.c_void_p(mean.data_ptr()),
+                             ctypes.c_void_p(var.data_ptr()) if var is not None else None), "gp_predict")
 
 
 def gp_khat_matvec(prob, theta, precision, V, W, ws, stream=None):

@@ -511,48 +511,21 @@ extern "C" int gp_precond_view_of(const gp_precond* P, gp_precond_view* view) {
 
 extern "C" void gp_precond_free(gp_precond* P) { delete P; }
 
-static int run_estimator(const gp_problem* prob, const double* theta_host, const gp_options* opt, int32_t rank,
-                         gp_precond* P, void* ws_dev, size_t ws_bytes, hipStream_t stream, double* logp_dev,
-                         double* grad_dev, gp_stats* stats) {
-  RET_IF(check_problem(prob));
-  RET_IF(check_options(opt));
-  RET_IF(check_rank(prob, rank));
-  if (!logp_dev) return GP_EINVAL;
-  Hyper h;
-  RET_IF(make_hyper(prob, theta_host, &h));
-  RET_IF(check_device());
-  Layout L = make_layout(prob->n, prob->d, prob->ard, opt->num_probes, opt->max_iters, rank, opt->precision);
-  RET_IF(check_ws(ws_dev, ws_bytes, L));
-  Ctx c{&L, (char*)ws_dev, stream};
-  const int p = prob->ard ? prob->d : 1;
-  if (P) {
-    // a prebuilt preconditioner must come from the same problem, theta, rank and workspace
-    if (P->ws != (char*)ws_dev || P->lay.k != rank || P->lay.n != prob->n || P->lay.d != prob->d ||
-        P->lay.L != L.L || P->lay.Cinv != L.Cinv || P->prob.X_dev != prob->X_dev)
-      return GP_EINVAL;
-    for (int i = 0; i < p + 2; ++i)
-      if (P->theta[i] != theta_host[i]) return GP_EINVAL;
-    // keep flags[1] (a build-time status); clear the per-evaluation flags
-    HIPCHK(hipMemsetAsync(c.at<int>(L.flags), 0, 4, stream));
-    HIPCHK(hipMemsetAsync(c.at<int>(L.flags) + 2, 0, 56, stream));
-  } else {
-    HIPCHK(hipMemsetAsync(c.at<int>(L.flags), 0, 64, stream));
-    RET_IF(build_precond(prob, h, c));
-  }
-  HIPCHK(launch_stage_x(c, h));
-  HIPCHK(launch_probes(c, prob->y_dev, h, opt->seed));
-  HIPCHK(launch_cg_init(c, h));
+// The CG iterations of one call on the right-hand sides already in R (one CG run
+// with many right-hand sides, footnote to Section 4.4).  With the host polling the
+// active-column count, the product of an iteration runs only over the active
+// columns, packed to the fewest 16-column tiles (the count read last is an upper
+// bound: columns only ever stop).
+static int run_cg(const Ctx& c, const Hyper& h, const gp_options* opt) {
+  const Layout& L = *c.lay;
   int* nact = c.at<int>(L.nactive);
   const int q = opt->sync_every;
-  // With the host polling the active-column count, the product of an iteration
-  // runs only over the active columns, packed to the fewest 16-column tiles
-  // (the count read last is an upper bound: columns only ever stop).
   const int full_ntt = L.tp / 16;
   int host_nact = L.t;
   for (int it = 0; it < opt->max_iters; ++it) {
     if (q > 0 && it > 0 && it % q == 0) {
-      HIPCHK(hipMemcpyAsync(&host_nact, nact, sizeof(int), hipMemcpyDeviceToHost, stream));
-      HIPCHK(hipStreamSynchronize(stream));
+      HIPCHK(hipMemcpyAsync(&host_nact, nact, sizeof(int), hipMemcpyDeviceToHost, c.st));
+      HIPCHK(hipStreamSynchronize(c.st));
       if (host_nact == 0) break;
     }
     int ntt = full_ntt;
@@ -568,6 +541,49 @@ static int run_estimator(const gp_problem* prob, const double* theta_host, const
                               c.at<double>(L.dot_part), nact, cmap, L.tp));
     HIPCHK(launch_cg_after_product(c, h, it, opt->cg_tol));
   }
+  return GP_OK;
+}
+
+// A prebuilt preconditioner must come from the same problem, theta, rank and
+// workspace; then only the per-evaluation flags are cleared.  Otherwise the
+// pivoted Cholesky preconditioner is built in the workspace.
+static int use_or_build_precond(const gp_problem* prob, const double* theta_host, int32_t rank, gp_precond* P,
+                                const Hyper& h, const Ctx& c) {
+  const Layout& L = *c.lay;
+  const int p = prob->ard ? prob->d : 1;
+  if (P) {
+    if (P->ws != c.ws || P->lay.k != rank || P->lay.n != prob->n || P->lay.d != prob->d || P->lay.L != L.L ||
+        P->lay.Cinv != L.Cinv || P->prob.X_dev != prob->X_dev)
+      return GP_EINVAL;
+    for (int i = 0; i < p + 2; ++i)
+      if (P->theta[i] != theta_host[i]) return GP_EINVAL;
+    // keep flags[1] (a build-time status); clear the per-evaluation flags
+    HIPCHK(hipMemsetAsync(c.at<int>(L.flags), 0, 4, c.st));
+    HIPCHK(hipMemsetAsync(c.at<int>(L.flags) + 2, 0, 56, c.st));
+    return GP_OK;
+  }
+  HIPCHK(hipMemsetAsync(c.at<int>(L.flags), 0, 64, c.st));
+  return build_precond(prob, h, c);
+}
+
+static int run_estimator(const gp_problem* prob, const double* theta_host, const gp_options* opt, int32_t rank,
+                         gp_precond* P, void* ws_dev, size_t ws_bytes, hipStream_t stream, double* logp_dev,
+                         double* grad_dev, gp_stats* stats) {
+  RET_IF(check_problem(prob));
+  RET_IF(check_options(opt));
+  RET_IF(check_rank(prob, rank));
+  if (!logp_dev) return GP_EINVAL;
+  Hyper h;
+  RET_IF(make_hyper(prob, theta_host, &h));
+  RET_IF(check_device());
+  Layout L = make_layout(prob->n, prob->d, prob->ard, opt->num_probes, opt->max_iters, rank, opt->precision);
+  RET_IF(check_ws(ws_dev, ws_bytes, L));
+  Ctx c{&L, (char*)ws_dev, stream};
+  RET_IF(use_or_build_precond(prob, theta_host, rank, P, h, c));
+  HIPCHK(launch_stage_x(c, h));
+  HIPCHK(launch_probes(c, prob->y_dev, h, opt->seed));
+  HIPCHK(launch_cg_init(c, h));
+  RET_IF(run_cg(c, h, opt));
   HIPCHK(launch_slq_logp(c, h, prob->y_dev, logp_dev));
   if (grad_dev) {
     HIPCHK(launch_stage_x_bwd(c, h));
@@ -625,6 +641,36 @@ extern "C" int gp_mll_grad(const gp_problem* prob, const double* theta_host, con
                            double* grad_dev, gp_stats* stats) {
   if (!grad_dev) return GP_EINVAL;
   return run_estimator(prob, theta_host, opt, rank, P, ws_dev, ws_bytes, stream, logp_dev, grad_dev, stats);
+}
+
+extern "C" int gp_predict(const gp_problem* prob, const double* theta_host, const gp_options* opt, int32_t rank,
+                          gp_precond* P, const double* Xstar_dev, int64_t nstar, void* ws_dev, size_t ws_bytes,
+                          hipStream_t stream, double* mean_dev, double* var_dev) {
+  RET_IF(check_problem(prob));
+  RET_IF(check_options(opt));
+  RET_IF(check_rank(prob, rank));
+  if (!Xstar_dev || !mean_dev || nstar < 1 || nstar > ((int64_t)1 << 31)) return GP_EINVAL;
+  Hyper h;
+  RET_IF(make_hyper(prob, theta_host, &h));
+  RET_IF(check_device());
+  Layout L = make_layout(prob->n, prob->d, prob->ard, opt->num_probes, opt->max_iters, rank, opt->precision);
+  RET_IF(check_ws(ws_dev, ws_bytes, L));
+  Ctx c{&L, (char*)ws_dev, stream};
+  RET_IF(use_or_build_precond(prob, theta_host, rank, P, h, c));
+  HIPCHK(launch_stage_x(c, h));
+  // test points in chunks of num_probes: one CG call on [y | k(X, x*_j)] per chunk
+  for (int64_t j0 = 0; j0 < nstar; j0 += L.ell) {
+    const int m = (int)std::min<int64_t>(L.ell, nstar - j0);
+    HIPCHK(launch_pred_rhs(c, h, prob->y_dev, Xstar_dev + j0 * prob->d, m));
+    HIPCHK(launch_cg_init(c, h));
+    RET_IF(run_cg(c, h, opt));
+    HIPCHK(launch_pred_finish(c, h, m, mean_dev + j0, var_dev ? var_dev + j0 : nullptr));
+  }
+  int flags[2];
+  HIPCHK(hipMemcpyAsync(flags, c.at<int>(L.flags), sizeof(flags), hipMemcpyDeviceToHost, stream));
+  HIPCHK(hipStreamSynchronize(stream));
+  if (flags[1] != 0) return flags[1];
+  return GP_OK;
 }
 
 extern "C" int gp_khat_matvec(const gp_problem* prob, const double* theta_host, int32_t precision, const double* V_dev,

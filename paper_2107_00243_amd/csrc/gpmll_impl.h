@@ -137,6 +137,11 @@ enum PrecondKind { kPivChol = 0, kRff = 1 };
 hipError_t launch_probes(const Ctx& c, const double* y, const Hyper& h, uint64_t seed);
 hipError_t launch_cg_init(const Ctx& c, const Hyper& h);
 
+// posterior prediction: right-hand sides [y | k(X, x*_j), j < ncols] (and their copy
+// kept through CG), then mean_j and latent var_j from the solutions
+hipError_t launch_pred_rhs(const Ctx& c, const Hyper& h, const double* y, const double* xstar, int ncols);
+hipError_t launch_pred_finish(const Ctx& c, const Hyper& h, int ncols, double* mean, double* var);
+
 // GP_OK when the current device is gfx950 (cached per device); records the HIP
 // error behind a GP_EHIP for gp_last_hip_error.
 int gpmll_check_device();

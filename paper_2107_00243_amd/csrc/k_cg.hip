@@ -445,6 +445,92 @@ hipError_t launch_colmap(const Ctx& c) {
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// Posterior prediction (Sec. 2.1): one CG call on [y | k(X, x*_1) .. k(X, x*_m)]
+// gives u = K_hat^-1 y and a_j = K_hat^-1 k(X, x*_j); the mean is a_j^T y and the
+// latent variance s - k(X, x*_j)^T a_j.
+// ---------------------------------------------------------------------------
+
+// R = [y | s kappa(x~_i, x~*_j) for the chunk's test points | 0], the cross
+// covariances also into Bk (kept through CG), Xs = 0; padding rows zero
+__global__ void k_pred_rhs(const double* __restrict__ y, const double* __restrict__ xs,
+                           const double* __restrict__ xstar, const double* __restrict__ mean, int64_t n,
+                           int64_t n_pad, int tp, int ncols, Hyper h, double* __restrict__ R, double* __restrict__ Bk,
+                           double* __restrict__ Xs) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_pad) return;
+  double* row = R + i * tp;
+  double* brow = Bk + i * tp;
+  double* xrow = Xs + i * tp;
+  for (int c = 0; c < tp; ++c) {
+    row[c] = 0.0;
+    brow[c] = 0.0;
+    xrow[c] = 0.0;
+  }
+  if (i >= n) return;
+  const int d = h.d;
+  double xi[GP_MAX_D];
+  for (int q = 0; q < d; ++q) xi[q] = xs[i * d + q];
+  row[0] = y[i];
+  brow[0] = y[i];
+  for (int j = 0; j < ncols; ++j) {
+    double r2 = 0.0;
+    for (int q = 0; q < d; ++q) {
+      const double df = xi[q] - (xstar[(int64_t)j * d + q] - mean[q]) * h.inv_ls[q];
+      r2 = fma(df, df, r2);
+    }
+    const double kv = h.s * kappa64(h.kind, r2);
+    row[1 + j] = kv;
+    brow[1 + j] = kv;
+  }
+}
+
+// dst[i][c] = src[i][0] for every column c
+__global__ void k_bcast_col0(const double* __restrict__ src, double* __restrict__ dst, int64_t n, int tp) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n * tp) return;
+  dst[e] = src[(e / tp) * tp];
+}
+
+// mean_j = sum_i Xs[i][1+j] y_i and var_j = s - sum_i Bk[i][1+j] Xs[i][1+j] from the
+// per-block partials; one workgroup per test point
+__global__ void k_pred_final(const double* __restrict__ part_mean, const double* __restrict__ part_var, int nblk,
+                             int tp, double s, double* __restrict__ mean, double* __restrict__ var) {
+  const int j = blockIdx.x;
+  const double m = column_total(part_mean, nblk, tp, 1 + j);
+  const double v = column_total(part_var, nblk, tp, 1 + j);
+  if (threadIdx.x == 0) {
+    mean[j] = m;
+    if (var) var[j] = s - v;
+  }
+}
+
+hipError_t launch_pred_rhs(const Ctx& c, const Hyper& h, const double* y, const double* xstar, int ncols) {
+  const Layout& L = *c.lay;
+  hipLaunchKernelGGL(k_pred_rhs, dim3(nb_for(L.n_pad, 256)), dim3(256), 0, c.st, y, c.at<double>(L.xs), xstar,
+                     c.at<double>(L.mean), L.n, L.n_pad, L.tp, ncols, h, c.at<double>(L.R), c.at<double>(L.cprime),
+                     c.at<double>(L.Xs));
+  return hipGetLastError();
+}
+
+hipError_t launch_coldot(const Ctx& c, const double* A, const double* B, double* part);
+
+hipError_t launch_pred_finish(const Ctx& c, const Hyper& h, int ncols, double* mean, double* var) {
+  const Layout& L = *c.lay;
+  double* part_mean = c.at<double>(L.dot_part);
+  double* part_var = part_mean + (int64_t)L.nred * L.tp;
+  // y in every column of W (free after CG), then column dots with the solutions
+  hipLaunchKernelGGL(k_bcast_col0, dim3(nb_for(L.n * L.tp, 256)), dim3(256), 0, c.st, c.at<double>(L.cprime),
+                     c.at<double>(L.W), L.n, L.tp);
+  hipError_t e = launch_coldot(c, c.at<double>(L.Xs), c.at<double>(L.W), part_mean);
+  if (e != hipSuccess) return e;
+  e = launch_coldot(c, c.at<double>(L.cprime), c.at<double>(L.Xs), part_var);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_pred_final, dim3(ncols), dim3(256), 0, c.st, part_mean, part_var, L.nred, L.tp, h.s, mean,
+                     var);
+  return hipGetLastError();
+}
+
 hipError_t launch_coldot(const Ctx& c, const double* A, const double* B, double* part) {
   const Layout& L = *c.lay;
   const int64_t rpb = (L.n + L.nred - 1) / L.nred;

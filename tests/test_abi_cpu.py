@@ -195,6 +195,18 @@ def test_qff_build_rejects_bad_node_counts_and_kernels(lib):
                                     ctypes.byref(h)) == B.GP_EUNSUPPORTED
 
 
+def test_predict_rejects_null_outputs_and_empty_test_sets(lib):
+    theta = np.array([0.5, 0.5, 0.5, 1.0, 0.1])
+    tp = theta.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    o = B.make_options("fp64", 4, 10)
+    p = _fake_problem()
+    ws = ctypes.c_void_p(0x10000)
+    xs, mean = ctypes.c_void_p(0x7000), ctypes.c_void_p(0x8000)
+    for xs_, n_, m_ in ((None, 5, mean), (xs, 0, mean), (xs, 5, None)):
+        assert lib.gp_predict(ctypes.byref(p), tp, ctypes.byref(o), 2, None, xs_, n_, ws, 1 << 30, None, m_,
+                              None) == B.GP_EINVAL
+
+
 def test_strerror_covers_every_status(lib):
     for code in (0, -1, -2, -3, -4, -5):
         assert B.gp_strerror(code) and B.gp_strerror(code) != "unknown status"
