@@ -10,7 +10,8 @@ HBM.  Prints one JSON line.
 
 Besides the headline line it reports the FP16X3 and FP64 tile precisions on the same
 workload, the randomized Nystrom and random Fourier feature preconditioners at the
-same rank, and the 64-problem ragged batch (gp_batch_mll_grad) as extra fields.
+same rank, posterior prediction at 256 test points (gp_predict) and the 64-problem
+ragged batch (gp_batch_mll_grad) as extra fields.
 """
 from __future__ import annotations
 
@@ -37,11 +38,11 @@ PEAK_FP64_TFLOPS = 78.6
 # is given, launched on the given grid; once either changes they are stale and are
 # not reported.
 TILE_COUNTERS = {
-    "kernel_source_sha256_16": "74d4d05e074c0c18",
+    "kernel_source_sha256_16": "73e86300af830d79",
     "grid": [391, 5],
-    "fetch_kib": 322434.8, "fetch_scale": 1048576.0 / 524306.8,
-    "write_kib": 156400.2, "write_scale": 1.0,
-    "mfma_insts": 3.718e8, "mfma_busy_cycles": 5.949e9, "gui_active_per_xcd": 7.8599e7 / 8,
+    "fetch_kib": 321794.4, "fetch_scale": 1048576.0 / 524307.2,
+    "write_kib": 156400.1, "write_scale": 1.0,
+    "mfma_insts": 3.71807e8, "mfma_busy_cycles": 5.9489e9, "gui_active_per_xcd": 7.87557e7 / 8,
 }
 
 
@@ -190,6 +191,38 @@ def run_preconditioners(pr, steps, ref):
     return out
 
 
+def run_predict(pr, nstar=256):
+    """Posterior mean and latent variance at nstar test points drawn like the
+    training inputs (gp_predict, BF16x3 tiles, chunks of 64 test points per CG
+    call); the FP64-tile run of the same call gives the accuracy."""
+    import torch
+    from paper_2107_00243_amd import binding as B
+    dev = torch.device("cuda:0")
+    X = torch.tensor(pr.X, device=dev)
+    y = torch.tensor(pr.y, device=dev)
+    Xs = torch.tensor(np.random.default_rng(7).uniform(0.0, 1.0, size=(nstar, pr.d)), device=dev)
+    prob = B.make_problem(X, y, pr.kernel, pr.ard)
+    out = {}
+    for prec in ("bf16x3", "fp64"):
+        opt = B.make_options(prec, pr.num_probes, pr.max_iters, pr.tol, pr.probe_seed, 0, 1)
+        ws = B.alloc_workspace(B.gp_workspace_size(prob, opt, pr.rank))
+        mean = torch.zeros(nstar, dtype=torch.float64, device=dev)
+        var = torch.zeros(nstar, dtype=torch.float64, device=dev)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        B.gp_predict(prob, pr.theta, opt, pr.rank, None, Xs, ws, mean, var)
+        torch.cuda.synchronize()
+        out[prec] = (time.perf_counter() - t0, mean.cpu().numpy(), var.cpu().numpy())
+        del ws
+        torch.cuda.empty_cache()
+    dt, mb, vb = out["bf16x3"]
+    _, m64, v64 = out["fp64"]
+    return {"test_points": nstar, "seconds": dt, "test_points_per_s": nstar / dt, "precision": "bf16x3",
+            "fp64_seconds": out["fp64"][0],
+            "mean_err_vs_fp64": float(np.max(np.abs(mb - m64)) / np.max(np.abs(m64))),
+            "var_err_vs_fp64_of_s": float(np.max(np.abs(vb - v64)) / pr.theta[-2])}
+
+
 def tiles_only(pr, reps=10, copy_bytes=1 << 30):
     """The tile kernel alone in the bench's launch configuration, then a plain
     elementwise copy of copy_bytes (read copy_bytes, write copy_bytes) whose
@@ -253,7 +286,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-problem ragged batch")
     ap.add_argument("--batch-only", action="store_true", help="only the 64-problem ragged batch (one JSON line)")
-    ap.add_argument("--no-precond", action="store_true", help="skip the Nystrom / RFF preconditioner leg")
+    ap.add_argument("--no-precond", action="store_true",
+                    help="skip the Nystrom / RFF preconditioner and posterior prediction legs")
     ap.add_argument("--n", type=int, default=100000)
     ap.add_argument("--tiles-only", action="store_true",
                     help="only the BF16x3 tile kernel (10 launches) and a 1 GiB elementwise copy, for counters")
@@ -305,6 +339,11 @@ def main():
         roofline["issued_mfma_flops_per_launch"] = issued
         roofline["issued_mfma_frac_of_peak"] = issued / (bf["tile_ms"] * 1e-3) / 1e12 / PEAK_BF16_TFLOPS
         roofline["mfma_busy_frac"] = tc["mfma_busy_cycles"] / (tc["gui_active_per_xcd"] * 1024)
+    pred = None
+    if not args.no_precond:
+        log("[bench] posterior prediction at 256 test points")
+        pred = run_predict(pr)
+        log(f"[bench] predict: {pred['seconds']:.2f} s for {pred['test_points']} test points")
     precs = None
     if not args.no_precond:
         log("[bench] other preconditioners of Table 1 (BF16x3)")
@@ -333,6 +372,7 @@ def main():
         "speedup_vs_fp64_gpu": (bf["evals_per_s"] / out_fp64["value"]) if out_fp64 else None,
         "batched_rbf_64": batched,
         "preconditioners_bf16x3": precs,
+        "predict": pred,
         "fp16x3_gpu": {"value": h16["evals_per_s"], "ms_per_step": h16["ms_per_step"],
                        "iters_max": h16["iters_max"], "tile_ms": h16["tile_ms"],
                        "tile_tflops": tile_flops(n, d, t) / (h16["tile_ms"] * 1e-3) / 1e12,
