@@ -47,6 +47,10 @@ R-chol   Greedy pivoting on the residual diagonal, ties to the lowest index; run
          is <= 1e-12 * s; L factors K without the noise term.
 R-cg     x0 = 0; a column stops after the iteration whose updated recurrence
          residual satisfies ||r|| <= tol * ||b||; its alpha/beta stream ends there.
+R-rq     Rational quadratic kernel (used with the RBF and Matern-3/2 kernels in
+         Table S1): kappa = (1 + r^2 / (2 alpha))^-alpha with the shape alpha a
+         fixed kernel constant (kind "ratquad:<alpha>"), not a hyperparameter
+         of theta; the paper does not optimise it.
 R-kern   k(x, x') = s * kappa(r), r^2 = sum_j ((x_j - x'_j) / ls_j)^2, noise
          sigma^2 on the diagonal; theta = [ls | s | sigma^2] natural parameters.
 R-ritz   Ritz values below 1e-300 are clamped to 1e-300 before the log.
@@ -110,10 +114,23 @@ def sqdist(X1, X2, ls):
     return np.einsum("pqj,pqj->pq", D, D)
 
 
+def ratquad_shape(kind):
+    """alpha of a rational quadratic kind "ratquad:<alpha>" (None for other kinds)."""
+    if not kind.startswith("ratquad"):
+        return None
+    alpha = float(kind.split(":", 1)[1]) if ":" in kind else 1.0
+    if not alpha > 0.0:
+        raise ValueError(kind)
+    return alpha
+
+
 def kappa(kind, r2):
     """Correlation kappa(r) of the stationary kernel, k = s * kappa."""
     if kind == "rbf":
         return np.exp(-0.5 * r2)
+    alpha = ratquad_shape(kind)
+    if alpha is not None:
+        return (1.0 + r2 / (2.0 * alpha)) ** (-alpha)
     r = np.sqrt(r2)
     if kind == "matern32":
         return (1.0 + SQRT3 * r) * np.exp(-SQRT3 * r)
@@ -126,6 +143,9 @@ def gfun(kind, r2):
     """g(r) with d kappa / d ls_j = g(r) * dtilde_j^2 / ls_j (dtilde = scaled diff)."""
     if kind == "rbf":
         return np.exp(-0.5 * r2)
+    alpha = ratquad_shape(kind)
+    if alpha is not None:
+        return (1.0 + r2 / (2.0 * alpha)) ** (-alpha - 1.0)
     r = np.sqrt(r2)
     if kind == "matern32":
         return 3.0 * np.exp(-SQRT3 * r)

@@ -12,7 +12,9 @@ has covariance s * kappa(r) up to O(F^-1/2); y = f + sigma * N(0, 1).
 The spectral density of the RBF kernel with lengthscales ls is N(0, diag(ls)^-2);
 that of a Matern-nu kernel is a multivariate t with 2 nu degrees of freedom,
     w = z * sqrt(2 nu / u) / ls,  z ~ N(0, I),  u ~ chi^2(2 nu)
-(Rasmussen & Williams 2006, Sec. 4.2).
+(Rasmussen & Williams 2006, Sec. 4.2); the rational quadratic kernel with shape
+alpha is a Gamma(alpha, rate alpha) scale mixture of RBF kernels, so
+    w = z * sqrt(tau) / ls,  tau ~ Gamma(alpha, rate alpha).
 
 Theta layout everywhere: [ls_1 .. ls_p | s | sigma^2] with p = d for ARD
 kernels and p = 1 for isotropic ones; all entries are natural (positive)
@@ -23,7 +25,7 @@ from __future__ import annotations
 import dataclasses
 import numpy as np
 
-KERNELS = ("rbf", "matern32", "matern52")
+KERNELS = ("rbf", "matern32", "matern52", "ratquad:<alpha>")
 PRECISIONS = ("fp64", "fp32", "bf16x3")
 
 
@@ -63,6 +65,10 @@ def rff_targets(rng, X, ls, s, sigma2, kernel, num_features=4096):
     z = rng.standard_normal((num_features, d))
     if kernel == "rbf":
         w = z / ls
+    elif kernel.startswith("ratquad"):
+        alpha = float(kernel.split(":", 1)[1]) if ":" in kernel else 1.0
+        tau = rng.gamma(alpha, 1.0 / alpha, size=(num_features, 1))
+        w = z * np.sqrt(tau) / ls
     else:
         nu = {"matern32": 1.5, "matern52": 2.5}[kernel]
         u = rng.chisquare(2.0 * nu, size=(num_features, 1))
@@ -80,12 +86,16 @@ def rff_targets(rng, X, ls, s, sigma2, kernel, num_features=4096):
 def spectral_frequencies(kernel, m, d, seed=0):
     """m samples (m, d) of the kernel's spectral density at unit lengthscale, the
     random input of the random Fourier feature preconditioner: N(0, I) for the
-    RBF kernel, z * sqrt(2 nu / u) with z ~ N(0, I), u ~ chi^2(2 nu) for Matern-nu
+    RBF kernel, z * sqrt(2 nu / u) with z ~ N(0, I), u ~ chi^2(2 nu) for Matern-nu,
+    z * sqrt(tau), tau ~ Gamma(alpha, rate alpha) for the rational quadratic
     (module docstring)."""
     rng = np.random.default_rng(np.random.SeedSequence([int(seed), 0x52FF]))
     z = rng.standard_normal((m, d))
     if kernel == "rbf":
         return z
+    if kernel.startswith("ratquad"):
+        alpha = float(kernel.split(":", 1)[1]) if ":" in kernel else 1.0
+        return z * np.sqrt(rng.gamma(alpha, 1.0 / alpha, size=(m, 1)))
     nu = {"matern32": 1.5, "matern52": 2.5}[kernel]
     u = rng.chisquare(2.0 * nu, size=(m, 1))
     return z * np.sqrt(2.0 * nu / u)

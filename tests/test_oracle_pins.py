@@ -71,7 +71,7 @@ def test_rbf_is_matern_limit():
     np.testing.assert_allclose(go.kappa("rbf", r * r), mat, rtol=2e-2)
 
 
-@pytest.mark.parametrize("kind", ["rbf", "matern32", "matern52"])
+@pytest.mark.parametrize("kind", ["rbf", "matern32", "matern52", "ratquad:0.8"])
 @pytest.mark.parametrize("ard", [True, False])
 def test_kernel_derivative_entries_match_finite_differences(kind, ard):
     X, _, theta = _problem(12, 3, kind, ard, seed=1)
@@ -648,3 +648,53 @@ def test_predict_single_point_closed_form_and_limits():
     np.testing.assert_allclose(mu, k * 1.7 / (1.3 + 0.1), rtol=1e-14)
     np.testing.assert_allclose(var, 1.3 - k * k / (1.3 + 0.1), rtol=1e-14)
     assert abs(mu[2]) < 1e-100 and abs(var[2] - 1.3) < 1e-14   # far away: the prior
+
+
+# ------------------------------------------------ rational quadratic kernel (Table S1)
+
+def test_ratquad_matches_scikit_learn_and_tends_to_rbf():
+    from sklearn.gaussian_process.kernels import RationalQuadratic
+    X, _, _ = _problem(30, 3, "rbf", False, seed=70)
+    for alpha in (0.5, 1.0, 3.0):
+        theta = np.array([0.7, 1.0, 0.1])
+        K = go.kernel_matrix(X, X, theta, f"ratquad:{alpha}", False)
+        ref = RationalQuadratic(length_scale=0.7, alpha=alpha)(X)
+        np.testing.assert_allclose(K, ref, rtol=1e-13, atol=1e-15)
+    theta = np.array([0.7, 1.0, 0.1])
+    Krbf = go.kernel_matrix(X, X, theta, "rbf", False)
+    Kbig = go.kernel_matrix(X, X, theta, "ratquad:1e7", False)
+    assert np.max(np.abs(Kbig - Krbf)) < 1e-6
+
+
+def test_ratquad_derivatives_and_gradient_match_finite_differences():
+    X, y, theta = _problem(12, 2, "rbf", True, seed=71)
+    kind = "ratquad:1.7"
+    ex = go.exact_mll(X, y, theta, kind, True)
+    for i in range(len(theta)):
+        h = 1e-6 * theta[i]
+        tp, tm = theta.copy(), theta.copy()
+        tp[i] += h
+        tm[i] -= h
+        fd = (go.exact_mll(X, y, tp, kind, True)["logp"] - go.exact_mll(X, y, tm, kind, True)["logp"]) / (2 * h)
+        assert abs(ex["grad"][i] - fd) <= 1e-6 * max(1.0, abs(fd)), (i, ex["grad"][i], fd)
+
+
+def test_ratquad_spectral_samples_reproduce_the_kernel():
+    X, _, theta = _problem(25, 2, "rbf", True, seed=72, ls=(0.5, 1.5))
+    W = synthgp.spectral_frequencies("ratquad:2.0", 40000, 2, seed=9)
+    Z = go.rff_features(X, theta, True, W)
+    assert np.max(np.abs(Z @ Z.T - go.kernel_matrix(X, X, theta, "ratquad:2.0", True))) < 0.03
+
+
+def test_ratquad_predict_matches_scikit_learn():
+    from sklearn.gaussian_process import GaussianProcessRegressor
+    from sklearn.gaussian_process.kernels import ConstantKernel, RationalQuadratic
+    X, y, theta = _problem(50, 2, "rbf", False, seed=73, sigma2=0.05)
+    Xs = np.random.default_rng(74).uniform(-0.2, 1.2, size=(20, 2))
+    kern = ConstantKernel(theta[1], constant_value_bounds="fixed") * RationalQuadratic(
+        length_scale=theta[0], alpha=2.5, length_scale_bounds="fixed", alpha_bounds="fixed")
+    gpr = GaussianProcessRegressor(kern, alpha=theta[2], optimizer=None).fit(X, y)
+    mu_ref, sd_ref = gpr.predict(Xs, return_std=True)
+    mu, var = go.predict(X, y, theta, "ratquad:2.5", False, Xs)
+    np.testing.assert_allclose(mu, mu_ref, rtol=1e-9, atol=1e-10)
+    np.testing.assert_allclose(np.sqrt(np.maximum(var, 0.0)), sd_ref, rtol=1e-7, atol=1e-8)
