@@ -57,7 +57,9 @@ typedef enum gp_status {
 typedef enum gp_kernel {
   GP_KERNEL_RBF = 0,        /* kappa = exp(-r^2 / 2) */
   GP_KERNEL_MATERN32 = 1,   /* kappa = (1 + sqrt3 r) exp(-sqrt3 r) */
-  GP_KERNEL_MATERN52 = 2    /* kappa = (1 + sqrt5 r + 5 r^2 / 3) exp(-sqrt5 r) */
+  GP_KERNEL_MATERN52 = 2,   /* kappa = (1 + sqrt5 r + 5 r^2 / 3) exp(-sqrt5 r) */
+  GP_KERNEL_RATQUAD = 3     /* kappa = (1 + r^2 / (2 alpha))^-alpha, alpha = gp_problem.kernel_shape
+                               (a fixed constant of the kernel, not part of theta) */
 } gp_kernel;
 
 typedef enum gp_precision {
@@ -87,6 +89,7 @@ typedef struct gp_problem {
   int32_t d;             /* input dimension, 1 .. GP_MAX_D */
   int32_t kernel;        /* gp_kernel */
   int32_t ard;           /* 1: d lengthscales; 0: one shared lengthscale */
+  double kernel_shape;   /* GP_KERNEL_RATQUAD: alpha > 0; ignored by the other kernels */
 } gp_problem;
 
 /* Estimator options (Algorithms 1 and 2). */

@@ -16,7 +16,15 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libgpmll.so")
 
 GP_OK, GP_EINVAL, GP_EWORKSPACE, GP_ENOTSPD, GP_EHIP, GP_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
-KERNELS = {"rbf": 0, "matern32": 1, "matern52": 2}
+KERNELS = {"rbf": 0, "matern32": 1, "matern52": 2, "ratquad": 3}
+
+
+def kernel_id(kernel: str):
+    """gp_kernel id and shape of a kernel name ("ratquad:<alpha>" carries the shape)."""
+    name, _, shape = kernel.partition(":")
+    if name not in KERNELS:
+        raise ValueError(f"unknown kernel {kernel!r}")
+    return KERNELS[name], (float(shape) if shape else 1.0)
 PRECISIONS = {"fp64": 0, "fp32": 1, "bf16x3": 2, "fp16x3": 3}
 FLAG_NOT_CONVERGED, FLAG_RANK_DEFICIENT, FLAG_RITZ_CLAMPED = 1, 2, 4
 MAX_D, MAX_PROBES, MAX_RANK = 32, 255, 1024
@@ -32,7 +40,8 @@ EXPORTS = ("gp_workspace_size", "gp_precond_build", "gp_precond_build_nystrom", 
 
 class gp_problem(ctypes.Structure):
     _fields_ = [("X_dev", ctypes.c_void_p), ("y_dev", ctypes.c_void_p), ("n", ctypes.c_int64),
-                ("d", ctypes.c_int32), ("kernel", ctypes.c_int32), ("ard", ctypes.c_int32)]
+                ("d", ctypes.c_int32), ("kernel", ctypes.c_int32), ("ard", ctypes.c_int32),
+                ("kernel_shape", ctypes.c_double)]
 
 
 class gp_options(ctypes.Structure):
@@ -152,7 +161,8 @@ def make_problem(X, y, kernel: str, ard: bool) -> gp_problem:
         raise ValueError("X and y must be FP64 CUDA tensors")
     if not X.is_contiguous() or not y.is_contiguous() or X.dim() != 2 or y.shape != (X.shape[0],):
         raise ValueError("X must be a contiguous (n, d) tensor and y a contiguous (n,) tensor")
-    return gp_problem(X.data_ptr(), y.data_ptr(), X.shape[0], X.shape[1], KERNELS[kernel], 1 if ard else 0)
+    kid, shape = kernel_id(kernel)
+    return gp_problem(X.data_ptr(), y.data_ptr(), X.shape[0], X.shape[1], kid, 1 if ard else 0, shape)
 
 
 def make_options(precision="fp64", num_probes=16, max_iters=200, cg_tol=1e-6, seed=1, precond_grad=0,
@@ -304,7 +314,7 @@ class Batch:
             raise ValueError("the sizes must add up to the rows of X")
         self.X, self.y = X, y
         self.raw = gp_batch(X.data_ptr(), y.data_ptr(), self.offsets.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
-                            len(sizes), X.shape[1], KERNELS[kernel], 1 if ard else 0)
+                            len(sizes), X.shape[1], kernel_id(kernel)[0], 1 if ard else 0)
 
     @property
     def batch(self) -> int:

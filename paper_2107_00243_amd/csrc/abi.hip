@@ -222,7 +222,9 @@ static int compact_ntt(int nact, int full) {
 static int check_problem(const gp_problem* prob) {
   if (!prob || !prob->X_dev || !prob->y_dev) return GP_EINVAL;
   if (prob->n < 1 || prob->d < 1 || prob->d > GP_MAX_D) return GP_EINVAL;
-  if (prob->kernel < 0 || prob->kernel > 2) return GP_EINVAL;
+  if (prob->kernel < 0 || prob->kernel > 3) return GP_EINVAL;
+  if (prob->kernel == GP_KERNEL_RATQUAD && !(prob->kernel_shape > 0.0 && std::isfinite(prob->kernel_shape)))
+    return GP_EINVAL;
   if (prob->ard != 0 && prob->ard != 1) return GP_EINVAL;
   if (prob->n > ((int64_t)1 << 31) - 256) return GP_EINVAL;
   return GP_OK;
@@ -256,6 +258,7 @@ static int make_hyper(const gp_problem* prob, const double* theta, Hyper* h) {
   h->s = theta[p];
   h->s2 = theta[p + 1];
   h->log2s = std::log2(h->s);
+  h->alpha = prob->kernel == GP_KERNEL_RATQUAD ? prob->kernel_shape : 1.0;
   return GP_OK;
 }
 

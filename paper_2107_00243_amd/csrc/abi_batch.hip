@@ -26,6 +26,7 @@ int check_batch(const gp_batch* bp) {
   if (!bp || !bp->offsets_host) return GP_EINVAL;
   if (bp->batch < 1 || bp->batch > 65536) return GP_EINVAL;
   if (bp->d < 1 || bp->d > GP_MAX_D) return GP_EINVAL;
+  if (bp->kernel == GP_KERNEL_RATQUAD) return GP_EUNSUPPORTED;  // batches: RBF and Matern kernels
   if (bp->kernel < 0 || bp->kernel > 2) return GP_EINVAL;
   if (bp->ard != 0 && bp->ard != 1) return GP_EINVAL;
   if (bp->offsets_host[0] != 0) return GP_EINVAL;
@@ -272,6 +273,7 @@ int run_batch(const gp_batch* bp, const double* theta_host, const gp_options* op
   h.d = bp->d;
   h.s = 1.0;
   h.log2s = 0.0;
+  h.alpha = 1.0;
   BHIP(bl_zero_flags(L, ws, stream));
   BHIP(bl_prep(L, ws, stream, bp->X_dev));
   BHIP(bl_precond(L, ws, stream));

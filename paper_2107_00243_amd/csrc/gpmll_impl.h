@@ -40,17 +40,24 @@ struct Hyper {
   double s;      // outputscale
   double s2;     // noise variance
   double log2s;  // log2(s)
+  double alpha;  // rational quadratic shape (1 for the other kernels)
 };
 
 // Kernel correlation kappa(r^2) and the derivative factor g(r^2) with
 // d kappa / d ls_j = g * dtilde_j^2 / ls_j (FP64, used by the FP64 tiles, the
 // pivoted Cholesky and the preconditioner derivative).
-__device__ inline void kappa_g64(int kind, double r2, double* kap, double* g) {
+__device__ inline void kappa_g64(int kind, double r2, double* kap, double* g, double alpha) {
   const double sqrt3 = 1.7320508075688772, sqrt5 = 2.23606797749979;
   if (kind == GP_KERNEL_RBF) {
     double e = exp(-0.5 * r2);
     *kap = e;
     *g = e;
+  } else if (kind == GP_KERNEL_RATQUAD) {
+    // kappa = b^-alpha with b = 1 + r^2 / (2 alpha); -2 d kappa / d r^2 = b^(-alpha-1)
+    const double b = 1.0 + r2 / (2.0 * alpha);
+    const double k = exp(-alpha * log(b));
+    *kap = k;
+    *g = k / b;
   } else if (kind == GP_KERNEL_MATERN32) {
     double r = sqrt(r2);
     double e = exp(-sqrt3 * r);
@@ -64,9 +71,9 @@ __device__ inline void kappa_g64(int kind, double r2, double* kap, double* g) {
   }
 }
 
-__device__ inline double kappa64(int kind, double r2) {
+__device__ inline double kappa64(int kind, double r2, double alpha) {
   double k, g;
-  kappa_g64(kind, r2, &k, &g);
+  kappa_g64(kind, r2, &k, &g, alpha);
   return k;
 }
 

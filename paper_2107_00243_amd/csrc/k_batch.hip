@@ -149,7 +149,7 @@ __global__ __launch_bounds__(1024) void kb_pivchol(const BDesc* __restrict__ des
           const double df = xb[i * d + q] - xp[q];
           r2 += df * df;
         }
-        const double kv = D.s * kappa64(kind, r2);
+        const double kv = D.s * kappa64(kind, r2, 1.0);  // batches take no rational quadratic kernel
         double dot = 0.0;
         for (int l = 0; l < j; ++l) dot += Lb[(int64_t)l * np + i] * Lp[l];
         lij = (kv - dot) * inv;
@@ -752,7 +752,7 @@ __global__ __launch_bounds__(256) void kb_bwd(const BDesc* __restrict__ desc, co
 #pragma unroll
         for (int c = 0; c < TP; ++c) m += ap[c] * cq[q][c];
         double kap, g;
-        kappa_g64(KIND, r2, &kap, &g);
+        kappa_g64(KIND, r2, &kap, &g, 1.0);
         const double wg = D.s * g * m;
 #pragma unroll
         for (int j = 0; j < DM; ++j) acc[j] += wg * df2[j];
@@ -819,7 +819,7 @@ __global__ __launch_bounds__(1024) void kb_pg_small(const BDesc* __restrict__ de
       r2 += df2[j];
     }
     double kap, g;
-    kappa_g64(kind, r2, &kap, &g);
+    kappa_g64(kind, r2, &kap, &g, 1.0);
     if (mode == 0)
       for (int j = 0; j < d; ++j) acc[j] += w * D.s * g * df2[j];
     acc[d] += w * kap;
@@ -868,7 +868,7 @@ __global__ __launch_bounds__(256) void kb_pg_rows(const BDesc* __restrict__ desc
         r2 += df2[j];
       }
       double kap, g;
-      kappa_g64(kind, r2, &kap, &g);
+      kappa_g64(kind, r2, &kap, &g, 1.0);
       if (mode == 0)
         for (int j = 0; j < d; ++j) acc[j] += om * D.s * g * df2[j];
       acc[d] += om * kap;

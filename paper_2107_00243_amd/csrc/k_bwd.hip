@@ -108,19 +108,25 @@ struct BwdArgs {
   int64_t cols_per_split;
   int nk4, nkt, nbt, ow;  // distance K/4, t/4, [1|x|x^2] tiles, output row width
   double s;
+  double alpha;           // rational quadratic shape
 };
 
 template <typename T>
-__device__ inline void kappa_g_t(int kind, T q, T s, T* kap, T* sg) {
+__device__ inline void kappa_g_t(int kind, T q, T s, T alpha, T* kap, T* sg) {
   if constexpr (sizeof(T) == 8) {
     double k, g;
-    kappa_g64(kind, q > 0.0 ? q : 0.0, &k, &g);
+    kappa_g64(kind, q > 0.0 ? q : 0.0, &k, &g, alpha);
     *kap = k;
     *sg = s * g;
   } else {
     const float log2e = 1.4426950408889634f;
     const float q0 = fmaxf(q, 0.0f);
-    if (kind == GP_KERNEL_RBF) {
+    if (kind == GP_KERNEL_RATQUAD) {
+      const float b = fmaf(q0, 0.5f / alpha, 1.0f);
+      const float k = __builtin_amdgcn_exp2f(-alpha * __builtin_amdgcn_logf(b));
+      *kap = k;
+      *sg = s * k / b;
+    } else if (kind == GP_KERNEL_RBF) {
       const float e = __builtin_amdgcn_exp2f(-0.5f * log2e * q0);
       *kap = e;
       *sg = s * e;
@@ -193,7 +199,7 @@ __global__ __launch_bounds__(256) void k_bwd_tiles(const T* __restrict__ xfa, co
     for (int v = 0; v < 4; ++v) {
       const int64_t q = c + acc_row_b<T>(g, v);
       T kap, sg;
-      kappa_g_t<T>(KIND, dd[v] + ct[acc_row_b<T>(g, v)], (T)a.s, &kap, &sg);
+      kappa_g_t<T>(KIND, dd[v] + ct[acc_row_b<T>(g, v)], (T)a.s, (T)a.alpha, &kap, &sg);
       if (p == q) {
         kap = (T)1;
         sg = (T)0;  // the scaled difference is exactly zero on the diagonal
@@ -364,11 +370,18 @@ struct BwdBfArgs {
   int ow, nbt;
   float s, inv_s;
   float rbf_sg, rbf_kap;  // RBF: s g = rbf_sg * exp2(q), kappa = rbf_kap * exp2(q)
+  float alpha;            // rational quadratic shape
 };
 
 template <int KIND>
-__device__ inline void bw_map(float q, float s, float rbf_sg, float rbf_kap, float* kap, float* sg) {
-  if (KIND == GP_KERNEL_RBF) {
+__device__ inline void bw_map(float q, float s, float rbf_sg, float rbf_kap, float alpha, float* kap, float* sg) {
+  if (KIND == GP_KERNEL_RATQUAD) {
+    // split-precision staging: q = r^2 / (2 alpha); kappa = b^-alpha, g = b^(-alpha-1), b = 1 + q
+    const float b = 1.0f + fabsf(q);
+    const float k = __builtin_amdgcn_exp2f(-alpha * __builtin_amdgcn_logf(b));
+    *kap = k;
+    *sg = s * k / b;
+  } else if (KIND == GP_KERNEL_RBF) {
     const float k = __builtin_amdgcn_exp2f(q);  // q: log2 of the staged kernel value
     *sg = k * rbf_sg;
     *kap = k * rbf_kap;
@@ -467,7 +480,7 @@ __global__ __launch_bounds__(256, 2) void k_bwd_bf16(const u32x4* __restrict__ x
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           float kap, sg;
-          bw_map<KIND>(dd[v] + ctv[v], a.s, a.rbf_sg, a.rbf_kap, &kap, &sg);
+          bw_map<KIND>(dd[v] + ctv[v], a.s, a.rbf_sg, a.rbf_kap, a.alpha, &kap, &sg);
           if (diag && row0 + rg * 16 + li == c + js * 16 + 4 * g + v) {
             kap = 1.0f;
             sg = 0.0f;
@@ -613,7 +626,7 @@ __global__ void k_pg_contract(const double* __restrict__ xs, const int32_t* __re
         r2 += df2[j];
       }
       double kap, g;
-      kappa_g64(h.kind, r2, &kap, &g);
+      kappa_g64(h.kind, r2, &kap, &g, h.alpha);
       const double wg = w * h.s * g;
       if (mode == 0)
         for (int j = 0; j < d; ++j) acc[j] += wg * df2[j];
@@ -755,6 +768,10 @@ static hipError_t run_bwd_tiles(const Ctx& c, const Hyper& h, BwdArgs ba, const 
       hipLaunchKernelGGL((k_bwd_tiles<T, GP_KERNEL_MATERN32>), grid, dim3(256), smem, c.st, xfa, xfb, rt, ct, afr, cfr,
                          xau, rows, ba);
       break;
+    case GP_KERNEL_RATQUAD:
+      hipLaunchKernelGGL((k_bwd_tiles<T, GP_KERNEL_RATQUAD>), grid, dim3(256), smem, c.st, xfa, xfb, rt, ct, afr, cfr,
+                         xau, rows, ba);
+      break;
     default:
       hipLaunchKernelGGL((k_bwd_tiles<T, GP_KERNEL_MATERN52>), grid, dim3(256), smem, c.st, xfa, xfb, rt, ct, afr, cfr,
                          xau, rows, ba);
@@ -829,6 +846,7 @@ hipError_t launch_bwd_bf16(const Ctx& c, const Hyper& h) {
   ba.nbt = (2 * L.d + 1 + 15) / 16;
   ba.s = (float)h.s;
   ba.inv_s = (float)(1.0 / h.s);
+  ba.alpha = (float)h.alpha;
   if (L.prec == GP_PREC_FP16X3) {  // staged RBF values are 2^15 kappa
     ba.rbf_sg = (float)(h.s / 32768.0);
     ba.rbf_kap = 1.0f / 32768.0f;
@@ -839,6 +857,7 @@ hipError_t launch_bwd_bf16(const Ctx& c, const Hyper& h) {
   switch (h.kind) {
     case GP_KERNEL_RBF: return sel_bwd<GP_KERNEL_RBF>(c, ba, nkc, nkm, nxt);
     case GP_KERNEL_MATERN32: return sel_bwd<GP_KERNEL_MATERN32>(c, ba, nkc, nkm, nxt);
+    case GP_KERNEL_RATQUAD: return sel_bwd<GP_KERNEL_RATQUAD>(c, ba, nkc, nkm, nxt);
     default: return sel_bwd<GP_KERNEL_MATERN52>(c, ba, nkc, nkm, nxt);
   }
 }
@@ -858,6 +877,7 @@ hipError_t launch_backward(const Ctx& c, const Hyper& h, int ard, int precond_gr
   ba.nbt = (2 * L.d + 1 + 15) / 16;
   ba.ow = L.bow;
   ba.s = h.s;
+  ba.alpha = h.alpha;
   const int64_t nfr_t = (L.n_pad / 16) * ba.nkt * 64;
   const int64_t nfr_x = (L.n_pad / 16) * ba.nbt * 256;
   const bool f64 = L.bprec == GP_PREC_FP64;

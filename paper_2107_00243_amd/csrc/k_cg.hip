@@ -479,7 +479,7 @@ __global__ void k_pred_rhs(const double* __restrict__ y, const double* __restric
       const double df = xi[q] - (xstar[(int64_t)j * d + q] - mean[q]) * h.inv_ls[q];
       r2 = fma(df, df, r2);
     }
-    const double kv = h.s * kappa64(h.kind, r2);
+    const double kv = h.s * kappa64(h.kind, r2, h.alpha);
     row[1 + j] = kv;
     brow[1 + j] = kv;
   }

@@ -83,11 +83,14 @@ __device__ inline float bf16_hi_f(uint32_t w) { return __builtin_bit_cast(float,
 // q = log2 k; Matern q = rho^2 with rho = a log2(e) r (a = sqrt3, sqrt5), so
 // exp(-a r) = exp2(-rho) and a r = ln2 rho:
 //   3/2: s (1 + ln2 rho) exp2(-rho),  5/2: s (1 + ln2 rho + (ln2 rho)^2 / 3) exp2(-rho)
-// (|q| guards the rounding of q = 0 to a tiny negative number)
+// (|q| guards the rounding of q = 0 to a tiny negative number).  Rational
+// quadratic: q = r^2 / (2 alpha) (x staged times 1/sqrt(alpha)), s (1 + q)^-alpha.
 template <int KIND>
-__device__ inline float map_split(float q, float s) {
+__device__ inline float map_split(float q, float s, float alpha) {
   if (KIND == GP_KERNEL_RBF) {
     return __builtin_amdgcn_exp2f(q);
+  } else if (KIND == GP_KERNEL_RATQUAD) {
+    return s * __builtin_amdgcn_exp2f(-alpha * __builtin_amdgcn_logf(1.0f + fabsf(q)));
   } else {
     const float ln2 = 0.6931471805599453f;
     const float rho = __builtin_sqrtf(fabsf(q));
@@ -99,11 +102,13 @@ __device__ inline float map_split(float q, float s) {
   }
 }
 
-// kernel value from the MFMA argument q (FP32 tiles): RBF q = log2 k; Matern q = r^2
+// kernel value from the MFMA argument q (FP32 tiles): RBF q = log2 k; otherwise q = r^2
 template <int KIND>
-__device__ inline float map32(float q, float s) {
+__device__ inline float map32(float q, float s, float alpha) {
   if (KIND == GP_KERNEL_RBF) {
     return __builtin_amdgcn_exp2f(q);
+  } else if (KIND == GP_KERNEL_RATQUAD) {
+    return s * __builtin_amdgcn_exp2f(-alpha * __builtin_amdgcn_logf(fmaf(fmaxf(q, 0.0f), 0.5f / alpha, 1.0f)));
   } else if (KIND == GP_KERNEL_MATERN32) {
     const float a = 1.7320508075688772f;
     float r = __builtin_sqrtf(fmaxf(q, 0.0f));
@@ -119,9 +124,9 @@ __device__ inline float map32(float q, float s) {
 }
 
 template <int KIND>
-__device__ inline double map64(double q, double s) {
+__device__ inline double map64(double q, double s, double alpha) {
   q = q > 0.0 ? q : 0.0;
-  return s * kappa64(KIND, q);
+  return s * kappa64(KIND, q, alpha);
 }
 
 // ---------------------------------------------------------------------------
@@ -136,6 +141,8 @@ struct TileArgs {
   int ntt;                  // 16-column tiles of right-hand sides staged for this launch
   float s32;
   double s64;
+  float alpha32;            // rational quadratic shape
+  double alpha64;
 };
 
 // cooperative copy of `count` 16-byte units from three contiguous sources into LDS
@@ -167,15 +174,18 @@ __device__ inline void copy_units(u32x4* dst, const u32x4* a, int na, const u32x
 // rbf_add: added to the RBF row term (log2 s for BF16X3 tiles; 15 for FP16X3 tiles,
 // whose kernel values are 2^15 kappa)
 __global__ void k_stage_x_bf16(const double* __restrict__ xs, int64_t n_pad, int d, int dq, int nkc, int kind,
-                               float rbf_add, u32x4* __restrict__ xfa, u32x4* __restrict__ xfb,
+                               double alpha, float rbf_add, u32x4* __restrict__ xfa, u32x4* __restrict__ xfb,
                                float* __restrict__ rowterm, float* __restrict__ colterm) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n_pad) return;
   const bool rbf = kind == GP_KERNEL_RBF;
-  // RBF: sqrt(log2 e); Matern: sqrt2 * a * log2 e with a = sqrt3 (3/2) or sqrt5 (5/2)
+  // RBF: sqrt(log2 e); Matern: sqrt2 * a * log2 e with a = sqrt3 (3/2) or sqrt5 (5/2);
+  // rational quadratic: 1/sqrt(alpha), so that q = r^2 / (2 alpha)
   const double scale = rbf ? 1.2011224087864498
-                           : 1.4142135623730951 * 1.4426950408889634 *
-                                 (kind == GP_KERNEL_MATERN32 ? 1.7320508075688772 : 2.23606797749979);
+                           : (kind == GP_KERNEL_RATQUAD
+                                  ? 1.0 / sqrt(alpha)
+                                  : 1.4142135623730951 * 1.4426950408889634 *
+                                        (kind == GP_KERNEL_MATERN32 ? 1.7320508075688772 : 2.23606797749979));
   uint16_t hi[GP_MAX_D], lo[GP_MAX_D];
   double nrm = 0.0;
   for (int q = 0; q < dq; ++q) {
@@ -444,7 +454,8 @@ __device__ __forceinline__ void bf16_distance(const u32x4* __restrict__ A, const
 // kernel map and hi/lo split of one step: dd -> (ph, pl); DIAG puts s on i == j
 template <int KIND, int RG, bool DIAG, bool F16>
 __device__ __forceinline__ void bf16_map(const f32x4 (&dd)[RG][2], const float* __restrict__ ct, u32x4 (&ph)[RG],
-                                         u32x4 (&pl)[RG], int lane, int64_t row0, int64_t c, float s32) {
+                                         u32x4 (&pl)[RG], int lane, int64_t row0, int64_t c, float s32,
+                                         float alpha) {
   const int g = lane >> 4, li = lane & 15;
   const f32x4 ct0 = *reinterpret_cast<const f32x4*>(ct + 4 * g);
   const f32x4 ct1 = *reinterpret_cast<const f32x4*>(ct + 16 + 4 * g);
@@ -455,7 +466,7 @@ __device__ __forceinline__ void bf16_map(const f32x4 (&dd)[RG][2], const float* 
       const f32x4 ctv = js ? ct1 : ct0;
       float kv[4];
 #pragma unroll
-      for (int v = 0; v < 4; ++v) kv[v] = map_split<KIND>(dd[rg][js][v] + ctv[v], s32);
+      for (int v = 0; v < 4; ++v) kv[v] = map_split<KIND>(dd[rg][js][v] + ctv[v], s32, alpha);
       if constexpr (DIAG) {
         const int64_t i = row0 + rg * 16 + li;
 #pragma unroll
@@ -588,8 +599,8 @@ __global__ __launch_bounds__(256, 2) void k_khat_bf16(const u32x4* __restrict__ 
     f32x4 dd[RG][2];
     bf16_distance<NKC, RG>(lds[0], xbv, rt, dd, lane);
     const float* ct = reinterpret_cast<const float*>(lds[0] + A_U + V_U);
-    if (is_diag(c_begin)) bf16_map<KIND, RG, true, F16>(dd, ct, ph, pl, lane, row0, c_begin, a.s32);
-    else bf16_map<KIND, RG, false, F16>(dd, ct, ph, pl, lane, row0, c_begin, a.s32);
+    if (is_diag(c_begin)) bf16_map<KIND, RG, true, F16>(dd, ct, ph, pl, lane, row0, c_begin, a.s32, a.alpha32);
+    else bf16_map<KIND, RG, false, F16>(dd, ct, ph, pl, lane, row0, c_begin, a.s32, a.alpha32);
   }
   int cur = 0;
   for (int j = 0; j + 1 < nsteps; ++j) {
@@ -603,10 +614,10 @@ __global__ __launch_bounds__(256, 2) void k_khat_bf16(const u32x4* __restrict__ 
     const float* ctn = reinterpret_cast<const float*>(lds[nxt] + A_U + V_U);
     if (is_diag(cn)) {
       bf16_tile_v<NTT, RG, F16>(lds[cur] + A_U, ph, pl, acc, lane);
-      bf16_map<KIND, RG, true, F16>(dd, ctn, nph, npl, lane, row0, cn, a.s32);
+      bf16_map<KIND, RG, true, F16>(dd, ctn, nph, npl, lane, row0, cn, a.s32, a.alpha32);
     } else {
       bf16_tile_v<NTT, RG, F16>(lds[cur] + A_U, ph, pl, acc, lane);
-      bf16_map<KIND, RG, false, F16>(dd, ctn, nph, npl, lane, row0, cn, a.s32);
+      bf16_map<KIND, RG, false, F16>(dd, ctn, nph, npl, lane, row0, cn, a.s32, a.alpha32);
     }
 #pragma unroll
     for (int rg = 0; rg < RG; ++rg) {
@@ -729,8 +740,8 @@ __global__ __launch_bounds__(256, 2) void k_khat_fp(const T* __restrict__ xfa, c
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         T q = dd[v] + ctv[v];
-        if constexpr (sizeof(T) == 4) kv[rg][v] = map32<KIND>(q, a.s32);
-        else kv[rg][v] = map64<KIND>(q, a.s64);
+        if constexpr (sizeof(T) == 4) kv[rg][v] = map32<KIND>(q, a.s32, a.alpha32);
+        else kv[rg][v] = map64<KIND>(q, a.s64, a.alpha64);
       }
       if (diag) {
         const int64_t i = row0 + rg * 16 + li;
@@ -824,6 +835,8 @@ hipError_t khat_tiles_bf16(const Ctx& c, const Hyper& h, const TileArgs& ta, con
       return f16 ? sel_bf16<GP_KERNEL_RBF, true>(c, ta, nact) : sel_bf16<GP_KERNEL_RBF, false>(c, ta, nact);
     case GP_KERNEL_MATERN32:
       return f16 ? sel_bf16<GP_KERNEL_MATERN32, true>(c, ta, nact) : sel_bf16<GP_KERNEL_MATERN32, false>(c, ta, nact);
+    case GP_KERNEL_RATQUAD:
+      return f16 ? sel_bf16<GP_KERNEL_RATQUAD, true>(c, ta, nact) : sel_bf16<GP_KERNEL_RATQUAD, false>(c, ta, nact);
     default:
       return f16 ? sel_bf16<GP_KERNEL_MATERN52, true>(c, ta, nact) : sel_bf16<GP_KERNEL_MATERN52, false>(c, ta, nact);
   }
@@ -869,6 +882,7 @@ hipError_t khat_tiles_fp(const Ctx& c, const Hyper& h, const TileArgs& ta, const
   switch (h.kind) {
     case GP_KERNEL_RBF: return sel_fp<T, GP_KERNEL_RBF>(c, ta, nact, it);
     case GP_KERNEL_MATERN32: return sel_fp<T, GP_KERNEL_MATERN32>(c, ta, nact, it);
+    case GP_KERNEL_RATQUAD: return sel_fp<T, GP_KERNEL_RATQUAD>(c, ta, nact, it);
     default: return sel_fp<T, GP_KERNEL_MATERN52>(c, ta, nact, it);
   }
 }
@@ -892,7 +906,7 @@ hipError_t launch_stage_x(const Ctx& c, const Hyper& h) {
     const int dq = (L.d + 7) / 8 * 8;
     const float rbf_add = L.prec == GP_PREC_FP16X3 ? 15.0f : (float)h.log2s;
     hipLaunchKernelGGL(k_stage_x_bf16, dim3(nb), dim3(256), 0, c.st, c.at<double>(L.xs), L.n_pad, L.d, dq,
-                       L.kd / 32, h.kind, rbf_add, c.at<u32x4>(L.xfa), c.at<u32x4>(L.xfb),
+                       L.kd / 32, h.kind, h.alpha, rbf_add, c.at<u32x4>(L.xfa), c.at<u32x4>(L.xfb),
                        c.at<float>(L.rowterm), c.at<float>(L.colterm));
   } else if (L.prec == GP_PREC_FP32) {
     hipLaunchKernelGGL(k_stage_x_fp<float>, dim3(nb), dim3(256), 0, c.st, c.at<double>(L.xs), L.n_pad, L.d,
@@ -962,6 +976,8 @@ hipError_t launch_khat_tiles(const Ctx& c, const Hyper& h, const int* nact, int 
   ta.ntt = ntt > 0 ? ntt : L.tp / 16;
   ta.s32 = (float)h.s;
   ta.s64 = h.s;
+  ta.alpha32 = (float)h.alpha;
+  ta.alpha64 = h.alpha;
   if (L.prec == GP_PREC_BF16X3 || L.prec == GP_PREC_FP16X3) {
     // FP16X3 kernel values are 2^15 kappa: the tile carries no outputscale
     if (L.prec == GP_PREC_FP16X3) ta.s32 = 32768.0f;
@@ -982,6 +998,8 @@ hipError_t launch_khat_tiles_items(const Ctx& c, const Hyper& h, const ItemTable
   ta.ntt = L.tp / 16;
   ta.s32 = 1.0f;
   ta.s64 = 1.0;
+  ta.alpha32 = (float)h.alpha;
+  ta.alpha64 = h.alpha;
   if (L.prec == GP_PREC_FP32) return khat_tiles_fp32(c, h, ta, nact, it);
   if (L.prec == GP_PREC_FP64) return khat_tiles_fp64(c, h, ta, nact, it);
   return hipErrorInvalidValue;

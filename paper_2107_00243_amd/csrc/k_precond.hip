@@ -175,7 +175,7 @@ __global__ void k_pivchol_step(int j, int64_t n, int k, int nblk, Hyper h, const
         double df = xs[i * h.d + q] - xp[q];
         r2 += df * df;
       }
-      double kv = h.s * kappa64(h.kind, r2);
+      double kv = h.s * kappa64(h.kind, r2, h.alpha);
       double dot = 0.0;
       for (int l = 0; l < j; ++l) dot += L[(int64_t)l * n + i] * Lp[l];
       lij = (kv - dot) * inv;

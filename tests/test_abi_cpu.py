@@ -56,7 +56,7 @@ int main(void) {
   printf("gp_batch_stats %zu\n", sizeof(gp_batch_stats));
   P(gp_batch, offsets_host); P(gp_batch, batch); P(gp_batch, ard);
   P(gp_batch_stats, flags_any); P(gp_batch_stats, iters_host); P(gp_batch_stats, rank_host);
-  P(gp_problem, n); P(gp_problem, d); P(gp_problem, ard);
+  P(gp_problem, n); P(gp_problem, d); P(gp_problem, ard); P(gp_problem, kernel_shape);
   P(gp_options, cg_tol); P(gp_options, seed); P(gp_options, precond_grad); P(gp_options, sync_every);
   P(gp_stats, logdet_precond); P(gp_stats, logdet_estimate); P(gp_stats, col_iters_host); P(gp_stats, pivots_host);
   P(gp_precond_view, n); P(gp_precond_view, rank);
@@ -94,7 +94,9 @@ def test_workspace_size_is_positive_and_grows(lib):
     lambda p, o: setattr(p, "n", 0),
     lambda p, o: setattr(p, "d", 0),
     lambda p, o: setattr(p, "d", 33),
-    lambda p, o: setattr(p, "kernel", 3),
+    lambda p, o: setattr(p, "kernel", 4),
+    lambda p, o: setattr(p, "kernel", 3),              # rational quadratic without a shape
+    lambda p, o: (setattr(p, "kernel", 3), setattr(p, "kernel_shape", float("nan"))),
     lambda p, o: setattr(p, "ard", 2),
     lambda p, o: setattr(o, "num_probes", 0),
     lambda p, o: setattr(o, "num_probes", 256),
@@ -207,6 +209,14 @@ def test_predict_rejects_null_outputs_and_empty_test_sets(lib):
                               None) == B.GP_EINVAL
 
 
+def test_batch_reports_the_rational_quadratic_kernel_unsupported(lib):
+    o = B.make_options("fp64", 4, 10)
+    offs = (ctypes.c_int64 * 3)(0, 100, 250)
+    b = B.gp_batch(0x1000, 0x2000, offs, 2, 3, 3, 1)
+    out = ctypes.c_size_t(0)
+    assert lib.gp_batch_workspace_size(ctypes.byref(b), ctypes.byref(o), 2, ctypes.byref(out)) == B.GP_EUNSUPPORTED
+
+
 def test_strerror_covers_every_status(lib):
     for code in (0, -1, -2, -3, -4, -5):
         assert B.gp_strerror(code) and B.gp_strerror(code) != "unknown status"
@@ -255,7 +265,7 @@ def test_batch_rejects_bad_shapes(lib, case):
     elif case == "d33":
         b.d = 33
     elif case == "kernel":
-        b.kernel = 3
+        b.kernel = 4
     elif case == "ard":
         b.ard = 2
     elif case == "rank_neg":
