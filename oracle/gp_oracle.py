@@ -31,6 +31,10 @@ R-probe  Probes for the preconditioned quadrature are b_i = sigma*eps_i + L*eta_
          Quadrature weight of probe i is rho0_i = b_i^T P^-1 b_i (the first r^T z
          of preconditioned CG): gamma_i = rho0_i * sum_j tau_1j^2 log(theta_j).
          This makes (1/ell) sum_i gamma_i unbiased for tr log(P^-1/2 K P^-T/2).
+R-sqrt   The alternative probe b_i = P^1/2 w_i with the symmetric square root of P
+         and Rademacher w_i (length n, the eps stream): E[b b^T] = P as under
+         R-probe, and rho0_i = w_i^T w_i = n exactly, the (n/ell) normalisation of
+         the paper's Hutchinson form.
 R-quad   The quadrature sums over the m Ritz values of the m x m tridiagonal
          produced by m CG steps (indices 1..m).
 R-grad   The derivative probes reuse the forward solves: with a_i = K^-1 b_i and
@@ -446,6 +450,19 @@ def qff_frequencies(d, q):
     return np.array(freqs, dtype=np.float64).reshape(-1, d), np.array(weights)
 
 
+def precond_sqrt_apply(L, sigma2, W):
+    """P^1/2 W for P = sigma^2 I + L L^T with the symmetric square root (R-sqrt):
+    P^1/2 = sigma I + L V D V^T L^T with L^T L = V diag(lam) V^T and
+    D = diag(1 / (sigma + sqrt(sigma^2 + lam)))."""
+    sigma = math.sqrt(sigma2)
+    if L.shape[1] == 0:
+        return sigma * W
+    lam, V = np.linalg.eigh(L.T @ L)
+    lam = np.maximum(lam, 0.0)
+    D = 1.0 / (sigma + np.sqrt(sigma2 + lam))
+    return sigma * W + L @ (V @ (D[:, None] * (V.T @ (L.T @ W))))
+
+
 # ----------------------------------------------------------------------------
 # Preconditioned CG, one column at a time (R-cg), and the Lanczos tridiagonal
 # ----------------------------------------------------------------------------
@@ -629,7 +646,7 @@ def _precond_terms_rff(X, theta, ard, freqs, Z, P, Cs, mode, weights=None):
 
 def estimate_mll(X, y, theta, kind, ard, rank, num_probes, tol, max_iters, seed,
                  grad=True, precond_grad=0, signs=None, dense=None, precond="pivchol", freqs=None,
-                 landmarks=None, qff_nodes=None):
+                 landmarks=None, qff_nodes=None, probe_mode=0):
     """Preconditioned estimate of log p (Algorithm 1) and, if grad, of its
     derivative (Algorithm 2) under the readings in the module docstring.
 
@@ -669,13 +686,16 @@ def estimate_mll(X, y, theta, kind, ard, rank, num_probes, tol, max_iters, seed,
         raise ValueError(precond)
     P = Preconditioner(L[:, :kp], s2)
 
-    # probes b_i = sigma eps_i + L eta_i (R-probe)
+    # probes b_i = sigma eps_i + L eta_i (R-probe), or P^1/2 w_i (R-sqrt)
     if signs is None:
         E, H = probe_signs(seed, n, rank, num_probes)
     else:
         E, H = signs
     ell = E.shape[1]
-    B = math.sqrt(s2) * E + L @ H[:rank] if rank else math.sqrt(s2) * E
+    if probe_mode == 1:
+        B = precond_sqrt_apply(L[:, :kp], s2, E)
+    else:
+        B = math.sqrt(s2) * E + L @ H[:rank] if rank else math.sqrt(s2) * E
     rhs = np.concatenate([y[:, None], B], axis=1)
 
     # one CG call over all right hand sides (footnote to Section 4.4)

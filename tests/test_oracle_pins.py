@@ -698,3 +698,31 @@ def test_ratquad_predict_matches_scikit_learn():
     mu, var = go.predict(X, y, theta, "ratquad:2.5", False, Xs)
     np.testing.assert_allclose(mu, mu_ref, rtol=1e-9, atol=1e-10)
     np.testing.assert_allclose(np.sqrt(np.maximum(var, 0.0)), sd_ref, rtol=1e-7, atol=1e-8)
+
+
+# ------------------------------------------------ symmetric-square-root probes (R-sqrt)
+
+def test_precond_sqrt_squares_to_the_preconditioner():
+    rng = np.random.default_rng(90)
+    L = rng.standard_normal((30, 5))
+    L[:, 4] = L[:, 3]                       # rank-deficient L^T L is allowed
+    S = go.precond_sqrt_apply(L, 0.07, np.eye(30))
+    np.testing.assert_allclose(S, S.T, atol=1e-13)
+    np.testing.assert_allclose(S @ S, 0.07 * np.eye(30) + L @ L.T, rtol=1e-12, atol=1e-12)
+    assert np.all(np.linalg.eigvalsh(S) > 0)
+
+
+def test_sqrt_probes_have_rho0_n_and_unbiased_estimators():
+    X, y, theta = _problem(7, 2, "rbf", True, seed=91, sigma2=0.1, ls=(0.3, 0.6))
+    n, k = 7, 2
+    vals, grads = [], []
+    for bits in itertools.product((-1.0, 1.0), repeat=n):
+        xi = np.array(bits)
+        es = go.estimate_mll(X, y, theta, "rbf", True, k, 1, 1e-13, n, 0, grad=True,
+                             signs=(xi[:, None], np.ones((k, 1))), probe_mode=1)
+        assert abs(es["rho0"][1] - n) < 1e-10
+        vals.append(es["logdet_est"])
+        grads.append(es["grad"])
+    ex = go.exact_mll(X, y, theta, "rbf", True)
+    assert abs(np.mean(vals) - ex["logdet"]) <= 1e-9 * abs(ex["logdet"])
+    np.testing.assert_allclose(np.mean(grads, axis=0), ex["grad"], rtol=1e-8, atol=1e-9)
