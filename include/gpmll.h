@@ -103,6 +103,9 @@ typedef struct gp_options {
   int32_t sync_every;    /* poll the convergence flag on the host every q iterations (q >= 1),
                             or 0 to enqueue all max_iters iterations without a host wait
                             (iterations after convergence exit at once on the device) */
+  int32_t probe_mode;    /* 0: b_i = sigma eps_i + L eta_i; 1: b_i = P_hat^1/2 w_i with the symmetric
+                            square root (rho0_i = n); both have E[b b^T] = P_hat.  Single
+                            problems only (batches: GP_EUNSUPPORTED) */
 } gp_options;
 
 /* Statistics copied to the host when a stats pointer is given (this waits for

@@ -47,7 +47,7 @@ class gp_problem(ctypes.Structure):
 class gp_options(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("num_probes", ctypes.c_int32), ("max_iters", ctypes.c_int32),
                 ("cg_tol", ctypes.c_double), ("seed", ctypes.c_uint64), ("precond_grad", ctypes.c_int32),
-                ("sync_every", ctypes.c_int32)]
+                ("sync_every", ctypes.c_int32), ("probe_mode", ctypes.c_int32)]
 
 
 class gp_stats(ctypes.Structure):
@@ -166,9 +166,9 @@ def make_problem(X, y, kernel: str, ard: bool) -> gp_problem:
 
 
 def make_options(precision="fp64", num_probes=16, max_iters=200, cg_tol=1e-6, seed=1, precond_grad=0,
-                 sync_every=1) -> gp_options:
+                 sync_every=1, probe_mode=0) -> gp_options:
     return gp_options(PRECISIONS[precision] if isinstance(precision, str) else int(precision), num_probes,
-                      max_iters, cg_tol, seed, precond_grad, sync_every)
+                      max_iters, cg_tol, seed, precond_grad, sync_every, probe_mode)
 
 
 def gp_workspace_size(prob: gp_problem, opt: gp_options, rank: int) -> int:

@@ -20,7 +20,7 @@ hipError_t launch_backward(const Ctx& c, const Hyper& h, int ard, int precond_gr
 static size_t al(size_t x) { return (x + 255) / 256 * 256; }
 static int64_t rup(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
 
-Layout make_layout(int64_t n, int d, int ard, int num_probes, int max_iters, int rank, int prec) {
+Layout make_layout(int64_t n, int d, int ard, int num_probes, int max_iters, int rank, int prec, int probe_mode) {
   Layout L{};
   L.n = n;
   L.n_pad = rup(n, kRowBlock);
@@ -166,6 +166,7 @@ Layout make_layout(int64_t n, int d, int ard, int num_probes, int max_iters, int
   L.pg_small = take((4 * kk * kk + kk * tp) * 8);
   L.omega = take(n * k * 8);
   L.pg_part = take(((n + k + 255) / 256 + 1) * (GP_MAX_D + 1) * 8);
+  L.sqrt_work = take(probe_mode == 1 ? 6 * kk * kk * 8 : 0);
   L.total = off;
   return L;
 }
@@ -238,6 +239,7 @@ static int check_options(const gp_options* o) {
   if (!(o->cg_tol >= 0.0) || !std::isfinite(o->cg_tol)) return GP_EINVAL;
   if (o->precond_grad != 0 && o->precond_grad != 1) return GP_EINVAL;
   if (o->sync_every < 0) return GP_EINVAL;
+  if (o->probe_mode != 0 && o->probe_mode != 1) return GP_EINVAL;
   return GP_OK;
 }
 
@@ -280,7 +282,8 @@ extern "C" int gp_workspace_size(const gp_problem* prob, const gp_options* opt, 
   if (!prob || prob->n < 1 || prob->d < 1 || prob->d > GP_MAX_D) return GP_EINVAL;
   RET_IF(check_options(opt));
   RET_IF(check_rank(prob, rank));
-  Layout L = make_layout(prob->n, prob->d, prob->ard, opt->num_probes, opt->max_iters, rank, opt->precision);
+  Layout L = make_layout(prob->n, prob->d, prob->ard, opt->num_probes, opt->max_iters, rank, opt->precision,
+                         opt->probe_mode);
   *bytes = L.total;
   return GP_OK;
 }
@@ -579,12 +582,14 @@ static int run_estimator(const gp_problem* prob, const double* theta_host, const
   Hyper h;
   RET_IF(make_hyper(prob, theta_host, &h));
   RET_IF(check_device());
-  Layout L = make_layout(prob->n, prob->d, prob->ard, opt->num_probes, opt->max_iters, rank, opt->precision);
+  Layout L = make_layout(prob->n, prob->d, prob->ard, opt->num_probes, opt->max_iters, rank, opt->precision,
+                         opt->probe_mode);
   RET_IF(check_ws(ws_dev, ws_bytes, L));
   Ctx c{&L, (char*)ws_dev, stream};
   RET_IF(use_or_build_precond(prob, theta_host, rank, P, h, c));
   HIPCHK(launch_stage_x(c, h));
-  HIPCHK(launch_probes(c, prob->y_dev, h, opt->seed));
+  if (opt->probe_mode == 1) HIPCHK(launch_probes_sqrt(c, prob->y_dev, h, opt->seed));
+  else HIPCHK(launch_probes(c, prob->y_dev, h, opt->seed));
   HIPCHK(launch_cg_init(c, h));
   RET_IF(run_cg(c, h, opt));
   HIPCHK(launch_slq_logp(c, h, prob->y_dev, logp_dev));

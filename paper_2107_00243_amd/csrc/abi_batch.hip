@@ -48,7 +48,9 @@ int check_batch_options(const gp_options* o, int32_t rank) {
   if (!(o->cg_tol >= 0.0) || !std::isfinite(o->cg_tol)) return GP_EINVAL;
   if (o->precond_grad != 0 && o->precond_grad != 1) return GP_EINVAL;
   if (o->sync_every < 0) return GP_EINVAL;
+  if (o->probe_mode != 0 && o->probe_mode != 1) return GP_EINVAL;
   if (rank < 0) return GP_EINVAL;
+  if (o->probe_mode != 0) return GP_EUNSUPPORTED;
   if (o->precision != GP_PREC_FP64 && o->precision != GP_PREC_FP32) return GP_EUNSUPPORTED;
   if (o->num_probes > GP_BATCH_MAX_PROBES || rank > GP_BATCH_MAX_RANK) return GP_EUNSUPPORTED;
   return GP_OK;

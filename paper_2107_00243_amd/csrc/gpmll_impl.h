@@ -104,10 +104,12 @@ struct Layout {
   size_t rho, rho0, bnorm, rnorm2, pw, active, nactive, iters, colmap, alog, blog;
   size_t dot_part, gamma, slq_work;
   size_t cprime, bxa, bxb, brt, bct, bafrag, bcfrag, bxaug, bwd_part, pg_small, omega, pg_part;
+  size_t sqrt_work;     // 6 k x k FP64 of the square-root probes (probe_mode 1 only)
   size_t total;
 };
 
-Layout make_layout(int64_t n, int d, int ard, int num_probes, int max_iters, int rank, int prec);
+Layout make_layout(int64_t n, int d, int ard, int num_probes, int max_iters, int rank, int prec,
+                   int probe_mode = 0);
 
 // 32-wide K chunks of the BF16x3 M-tile contraction over t columns split as
 // (hi, hi, lo) x (hi, lo, hi), rounded up to a compiled chunk count
@@ -142,6 +144,9 @@ hipError_t launch_rff(const Ctx& c, const Hyper& h, bool weighted = false);
 // preconditioner families: the low-rank factor in the L slot comes from
 enum PrecondKind { kPivChol = 0, kRff = 1 };
 hipError_t launch_probes(const Ctx& c, const double* y, const Hyper& h, uint64_t seed);
+// probes b_i = P_hat^1/2 w_i (symmetric square root; C^1/2 by a coupled Newton-Schulz
+// iteration on the k x k matrix C, then (C^1/2 + sigma I)^-1 by Cholesky)
+hipError_t launch_probes_sqrt(const Ctx& c, const double* y, const Hyper& h, uint64_t seed);
 hipError_t launch_cg_init(const Ctx& c, const Hyper& h);
 
 // posterior prediction: right-hand sides [y | k(X, x*_j), j < ncols] (and their copy

@@ -21,6 +21,8 @@
 //     and for sigma^2: -1/2 ((n - k)/sigma^2 + tr C^-1) + 1/(2 ell) sum_i |c_i|^2
 //     (trace of P_hat^-1 dP_hat by the matrix inversion lemma, supplement S3.3).
 #include "gpmll_impl.h"
+
+#include <utility>
 #include "small_dense.h"
 
 namespace gpmll {
@@ -860,6 +862,122 @@ hipError_t launch_bwd_bf16(const Ctx& c, const Hyper& h) {
     case GP_KERNEL_RATQUAD: return sel_bwd<GP_KERNEL_RATQUAD>(c, ba, nkc, nkm, nxt);
     default: return sel_bwd<GP_KERNEL_MATERN52>(c, ba, nkc, nkm, nxt);
   }
+}
+
+// ---------------------------------------------------------------------------
+// Probes through the symmetric square root of P_hat = sigma^2 I + L L^T:
+//   P_hat^1/2 w = sigma w + L M L^T w,  M = (C^1/2 + sigma I)^-1,  C = sigma^2 I + L^T L
+// (for L^T L = V diag(lam) V^T, M = V diag(1 / (sigma + sqrt(sigma^2 + lam))) V^T).
+// C^1/2 comes from the coupled Newton-Schulz iteration on A = C / tr(C) (spectrum in
+// (0, 1]): T = (3I - Z Y) / 2, Y <- Y T, Z <- T Z, with Y -> A^1/2 and Z -> A^-1/2
+// quadratically once close (Higham, "Functions of Matrices", Sec. 6.7); a fixed
+// count of steps covers condition numbers of C up to about 1e16.
+// ---------------------------------------------------------------------------
+
+constexpr int kSqrtSteps = 100;
+
+// R = [y | sigma w_1 .. sigma w_ell | 0] with w the Rademacher stream 0 (the eps of the
+// first probe form), Xs = 0; padding rows zero
+__global__ void k_probes_base(const double* __restrict__ y, int64_t n, int64_t n_pad, int ell, int tp, double sigma,
+                              uint64_t seed, double* __restrict__ R, double* __restrict__ Xs) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_pad) return;
+  double* row = R + i * tp;
+  double* xrow = Xs + i * tp;
+  for (int c = 0; c < tp; ++c) {
+    xrow[c] = 0.0;
+    row[c] = 0.0;
+  }
+  if (i >= n) return;
+  row[0] = y[i];
+  for (int c = 0; c < ell; ++c) row[1 + c] = sigma * rademacher(seed, 0, (uint64_t)c, (uint64_t)i);
+}
+
+// inverse of an SPD k x k matrix by the small Cholesky routine (logdet and status
+// outputs go to scratch / the deferred-status slot)
+__global__ void k_sqrt_inverse(int64_t n, int k, double s2, const double* __restrict__ Bm, double* __restrict__ Rc,
+                               double* __restrict__ Rinv, double* __restrict__ Binv, double* __restrict__ scratch,
+                               int* __restrict__ status) {
+  small_chol_body(n, k, s2, Bm, Rc, Rinv, Binv, scratch, status);
+}
+
+// A = C / tr(C), Y = A, Z = I; scal[0] = tr(C) (one workgroup)
+__global__ void k_sqrt_init(const double* __restrict__ C, int k, double* __restrict__ Y, double* __restrict__ Z,
+                            double* __restrict__ scal) {
+  __shared__ double red[256];
+  double s = 0.0;
+  for (int j = threadIdx.x; j < k; j += blockDim.x) s += C[(int64_t)j * k + j];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+    __syncthreads();
+  }
+  const double tr = red[0];
+  for (int e = threadIdx.x; e < k * k; e += blockDim.x) {
+    Y[e] = C[e] / tr;
+    Z[e] = (e / k == e % k) ? 1.0 : 0.0;
+  }
+  if (threadIdx.x == 0) scal[0] = tr;
+}
+
+// T = (3 I - P) / 2
+__global__ void k_sqrt_t(const double* __restrict__ P, int k, double* __restrict__ T) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= k * k) return;
+  T[e] = ((e / k == e % k) ? 1.5 : 0.0) - 0.5 * P[e];
+}
+
+// B = sqrt(tr C) Y + sigma I
+__global__ void k_sqrt_shift(const double* __restrict__ Y, const double* __restrict__ scal, int k, double sigma,
+                             double* __restrict__ Bm) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= k * k) return;
+  Bm[e] = sqrt(scal[0]) * Y[e] + ((e / k == e % k) ? sigma : 0.0);
+}
+
+hipError_t launch_probes_sqrt(const Ctx& c, const double* y, const Hyper& h, uint64_t seed) {
+  const Layout& L = *c.lay;
+  const double sigma = sqrt(h.s2);
+  // R = [y | sigma w] with w the Rademacher stream of the first probe form
+  hipLaunchKernelGGL(k_probes_base, dim3((unsigned)((L.n_pad + 255) / 256)), dim3(256), 0, c.st, y, L.n, L.n_pad,
+                     L.ell, L.tp, sigma, seed, c.at<double>(L.R), c.at<double>(L.Xs));
+  if (L.k == 0) return hipGetLastError();
+  const int k = L.k;
+  const int64_t kk = (int64_t)k * k;
+  double* w = c.at<double>(L.sqrt_work);
+  double *Y = w, *Z = w + kk, *P = w + 2 * kk, *T = w + 3 * kk, *Y2 = w + 4 * kk, *Z2 = w + 5 * kk;
+  double* scal = c.at<double>(L.pg_part);  // free until the derivative sweep
+  hipLaunchKernelGGL(k_sqrt_init, dim3(1), dim3(256), 0, c.st, c.at<double>(L.C), k, Y, Z, scal);
+  const dim3 gk(nbk(k, 64), (k + 63) / 64), bk(256);
+  const unsigned ne = nbk(kk, 256);
+  for (int it = 0; it < kSqrtSteps; ++it) {
+    hipLaunchKernelGGL(k_gemm64, gk, bk, 0, c.st, (int64_t)k, k, k, Z, (int64_t)k, (int64_t)1, Y, (int64_t)k,
+                       (int64_t)1, P, (int64_t)k, (int64_t)1, 1.0, 0.0, (const int*)nullptr, (const int*)nullptr);
+    hipLaunchKernelGGL(k_sqrt_t, dim3(ne), dim3(256), 0, c.st, P, k, T);
+    hipLaunchKernelGGL(k_gemm64, gk, bk, 0, c.st, (int64_t)k, k, k, Y, (int64_t)k, (int64_t)1, T, (int64_t)k,
+                       (int64_t)1, Y2, (int64_t)k, (int64_t)1, 1.0, 0.0, (const int*)nullptr, (const int*)nullptr);
+    hipLaunchKernelGGL(k_gemm64, gk, bk, 0, c.st, (int64_t)k, k, k, T, (int64_t)k, (int64_t)1, Z, (int64_t)k,
+                       (int64_t)1, Z2, (int64_t)k, (int64_t)1, 1.0, 0.0, (const int*)nullptr, (const int*)nullptr);
+    std::swap(Y, Y2);
+    std::swap(Z, Z2);
+  }
+  // M = (C^1/2 + sigma I)^-1 by the small Cholesky routine (its log-det output is a scratch slot)
+  hipLaunchKernelGGL(k_sqrt_shift, dim3(ne), dim3(256), 0, c.st, Y, scal, k, sigma, P);
+  double* M = T;
+  hipLaunchKernelGGL(k_sqrt_inverse, dim3(1), dim3(1024), 0, c.st, L.n, k, h.s2, P, Z2, Y2, M, scal + 1,
+                     c.at<int>(L.flags) + 1);
+  // U = L^T (sigma w) into ltr_raw ([k][tp]); V = M U / sigma; R[:, 1..ell] += L V
+  hipError_t e = launch_ltr(c, c.at<double>(L.R), c.at<double>(L.ltr_raw), nullptr);
+  if (e != hipSuccess) return e;
+  double* V = c.at<double>(L.ltr);
+  hipLaunchKernelGGL(k_gemm64, dim3(nbk(k, 64), (L.tp + 63) / 64), bk, 0, c.st, (int64_t)k, L.tp, k, M, (int64_t)k,
+                     (int64_t)1, c.at<double>(L.ltr_raw), (int64_t)L.tp, (int64_t)1, V, (int64_t)L.tp, (int64_t)1,
+                     1.0 / sigma, 0.0, (const int*)nullptr, (const int*)nullptr);
+  hipLaunchKernelGGL(k_gemm64, dim3(nbk(L.n, 64), (L.ell + 63) / 64), bk, 0, c.st, L.n, L.ell, k, c.at<double>(L.L),
+                     (int64_t)1, (int64_t)L.n, V + 1, (int64_t)L.tp, (int64_t)1, c.at<double>(L.R) + 1, (int64_t)L.tp,
+                     (int64_t)1, 1.0, 1.0, (const int*)nullptr, (const int*)nullptr);
+  return hipGetLastError();
 }
 
 hipError_t launch_backward(const Ctx& c, const Hyper& h, int ard, int precond_grad, int precond_kind, double* grad) {

@@ -58,6 +58,7 @@ int main(void) {
   P(gp_batch_stats, flags_any); P(gp_batch_stats, iters_host); P(gp_batch_stats, rank_host);
   P(gp_problem, n); P(gp_problem, d); P(gp_problem, ard); P(gp_problem, kernel_shape);
   P(gp_options, cg_tol); P(gp_options, seed); P(gp_options, precond_grad); P(gp_options, sync_every);
+  P(gp_options, probe_mode);
   P(gp_stats, logdet_precond); P(gp_stats, logdet_estimate); P(gp_stats, col_iters_host); P(gp_stats, pivots_host);
   P(gp_precond_view, n); P(gp_precond_view, rank);
   return 0;
@@ -106,6 +107,7 @@ def test_workspace_size_is_positive_and_grows(lib):
     lambda p, o: setattr(o, "precision", 4),
     lambda p, o: setattr(o, "precond_grad", 2),
     lambda p, o: setattr(o, "sync_every", -1),
+    lambda p, o: setattr(o, "probe_mode", 2),
 ])
 def test_invalid_shapes_and_options_are_rejected(lib, mutate):
     p, o = _fake_problem(), B.make_options("fp64", 4, 10)
@@ -215,6 +217,21 @@ def test_batch_reports_the_rational_quadratic_kernel_unsupported(lib):
     b = B.gp_batch(0x1000, 0x2000, offs, 2, 3, 3, 1)
     out = ctypes.c_size_t(0)
     assert lib.gp_batch_workspace_size(ctypes.byref(b), ctypes.byref(o), 2, ctypes.byref(out)) == B.GP_EUNSUPPORTED
+
+
+def test_batch_reports_square_root_probes_unsupported(lib):
+    o = B.make_options("fp64", 4, 10, probe_mode=1)
+    offs = (ctypes.c_int64 * 3)(0, 100, 250)
+    b = B.gp_batch(0x1000, 0x2000, offs, 2, 3, 0, 1)
+    out = ctypes.c_size_t(0)
+    assert lib.gp_batch_workspace_size(ctypes.byref(b), ctypes.byref(o), 2, ctypes.byref(out)) == B.GP_EUNSUPPORTED
+
+
+def test_square_root_probes_need_more_workspace(lib):
+    p = _fake_problem(n=5000, d=3)
+    s0 = B.gp_workspace_size(p, B.make_options("fp64", 8, 50), 200)
+    s1 = B.gp_workspace_size(p, B.make_options("fp64", 8, 50, probe_mode=1), 200)
+    assert s1 >= s0 + 6 * 200 * 200 * 8 - 256   # the empty slot of mode 0 still takes one 256-byte unit
 
 
 def test_strerror_covers_every_status(lib):

@@ -409,3 +409,60 @@ def test_full_size_estimator_against_the_fp64_tiles(workload, precision, lp_tol,
     # the estimate is still within the bar)
     assert rel(lo["logp"], hi["logp"]) < lp_tol
     assert relvec(lo["grad"], hi["grad"]) < g_tol
+
+
+# ---------------------------------------------------------------- square-root probes
+
+@pytest.mark.parametrize("kernel,ard,precision,lp_tol,g_tol,rank", [
+    ("rbf", True, "fp64", 1e-7, 1e-5, 40),
+    ("matern32", True, "fp64", 1e-7, 1e-5, 25),
+    ("matern52", False, "bf16x3", 1e-3, 1e-2, 30),
+    ("rbf", True, "fp64", 1e-7, 1e-5, 0),
+])
+def test_square_root_probes_match_oracle(kernel, ard, precision, lp_tol, g_tol, rank):
+    pr = synthgp.random_problem(1400, 4, kernel, ard=ard, rank=rank, num_probes=8, seed=95, ls_range=(0.4, 1.5),
+                                sigma2=0.02, dist="normal", tol=1e-8, max_iters=400)
+    say(f"[gpu] sqrt probes {kernel} ard={ard} {precision} rank={rank}")
+    dev = torch.device("cuda:0")
+    X = torch.tensor(pr.X, device=dev)
+    y = torch.tensor(pr.y, device=dev)
+    prob = B.make_problem(X, y, kernel, ard)
+    opt = B.make_options(precision, pr.num_probes, pr.max_iters, pr.tol, pr.probe_seed, 0, 1, probe_mode=1)
+    ws = B.alloc_workspace(B.gp_workspace_size(prob, opt, rank))
+    logp = torch.zeros(1, dtype=torch.float64, device=dev)
+    g = torch.zeros(len(pr.theta), dtype=torch.float64, device=dev)
+    st = B.Stats(pr.num_probes, rank)
+    B.gp_mll_grad(prob, pr.theta, opt, rank, None, ws, logp, g, st)
+    torch.cuda.synchronize()
+    ref = go.estimate_mll(pr.X, pr.y, pr.theta, kernel, ard, rank, pr.num_probes, pr.tol, pr.max_iters,
+                          pr.probe_seed, probe_mode=1)
+    lp, gr = float(logp.cpu()[0]), g.cpu().numpy()
+    say(f"    logp rel {rel(lp, ref['logp']):.2e}, grad rel {relvec(gr, ref['grad']):.2e}")
+    assert rel(lp, ref["logp"]) < lp_tol
+    assert relvec(gr, ref["grad"]) < g_tol
+    if precision == "fp64":
+        np.testing.assert_allclose(st.gammas, ref["gammas"], rtol=1e-6)
+
+
+def test_square_root_probes_with_a_fourier_feature_preconditioner():
+    pr = synthgp.random_problem(1200, 2, "rbf", ard=True, rank=32, num_probes=8, seed=96, ls_range=(0.5, 1.5),
+                                sigma2=0.05, dist="normal", tol=1e-8, max_iters=400)
+    W = synthgp.spectral_frequencies("rbf", 16, 2, seed=96)
+    dev = torch.device("cuda:0")
+    X = torch.tensor(pr.X, device=dev)
+    y = torch.tensor(pr.y, device=dev)
+    prob = B.make_problem(X, y, "rbf", True)
+    opt = B.make_options("fp64", 8, 400, 1e-8, pr.probe_seed, 0, 1, probe_mode=1)
+    ws = B.alloc_workspace(B.gp_workspace_size(prob, opt, 32))
+    h = B.gp_precond_build_rff(prob, pr.theta, 32, torch.tensor(W, device=dev), ws)
+    logp = torch.zeros(1, dtype=torch.float64, device=dev)
+    g = torch.zeros(len(pr.theta), dtype=torch.float64, device=dev)
+    try:
+        B.gp_mll_grad(prob, pr.theta, opt, 32, h, ws, logp, g)
+    finally:
+        B.gp_precond_free(h)
+    torch.cuda.synchronize()
+    ref = go.estimate_mll(pr.X, pr.y, pr.theta, "rbf", True, 32, 8, 1e-8, 400, pr.probe_seed, precond="rff",
+                          freqs=W, probe_mode=1)
+    assert rel(float(logp.cpu()[0]), ref["logp"]) < 1e-7
+    assert relvec(g.cpu().numpy(), ref["grad"]) < 1e-5
