@@ -4,6 +4,7 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <map>
 #include <mutex>
 #include <vector>
 
@@ -309,6 +310,7 @@ extern "C" int gp_precond_build(const gp_problem* prob, const double* theta_host
   if (!ws_dev || (reinterpret_cast<uintptr_t>(ws_dev) & 255) != 0) return GP_EINVAL;
   if (ws_bytes < L.precond_end) return GP_EWORKSPACE;
   Ctx c{&L, (char*)ws_dev, stream};
+  gpmll_forget_forward(ws_dev);
   HIPCHK(hipMemsetAsync(c.at<int>(L.flags), 0, 64, stream));
   RET_IF(build_precond(prob, h, c));
   gp_precond* P = new gp_precond;
@@ -336,6 +338,7 @@ extern "C" int gp_precond_build_rff(const gp_problem* prob, const double* theta_
   if (!ws_dev || (reinterpret_cast<uintptr_t>(ws_dev) & 255) != 0) return GP_EINVAL;
   if (ws_bytes < L.precond_end) return GP_EWORKSPACE;
   Ctx c{&L, (char*)ws_dev, stream};
+  gpmll_forget_forward(ws_dev);
   HIPCHK(hipMemsetAsync(c.at<int>(L.flags), 0, 64, stream));
   // the samples are copied into the workspace, so the handle does not keep freq_dev
   HIPCHK(hipMemcpyAsync(c.at<double>(L.freq), freq_dev, (size_t)(rank / 2) * prob->d * sizeof(double),
@@ -375,6 +378,7 @@ extern "C" int gp_precond_build_nystrom(const gp_problem* prob, const double* th
   if (!ws_dev || (reinterpret_cast<uintptr_t>(ws_dev) & 255) != 0) return GP_EINVAL;
   if (ws_bytes < L.precond_end) return GP_EWORKSPACE;
   Ctx c{&L, (char*)ws_dev, stream};
+  gpmll_forget_forward(ws_dev);
   HIPCHK(hipMemsetAsync(c.at<int>(L.flags), 0, 64, stream));
   // the landmark table comes from pageable host memory: wait for the copy once
   HIPCHK(hipMemcpyAsync(c.at<int32_t>(L.landmarks), landmarks_host, (size_t)rank * sizeof(int32_t),
@@ -486,6 +490,7 @@ extern "C" int gp_precond_build_qff(const gp_problem* prob, const double* theta_
     amp[r] = std::sqrt(h.s * wt);
   }
   Ctx c{&L, (char*)ws_dev, stream};
+  gpmll_forget_forward(ws_dev);
   HIPCHK(hipMemsetAsync(c.at<int>(L.flags), 0, 64, stream));
   HIPCHK(hipMemcpyAsync(c.at<double>(L.freq), W.data(), W.size() * sizeof(double), hipMemcpyHostToDevice, stream));
   HIPCHK(hipMemcpyAsync(c.at<double>(L.famp), amp.data(), amp.size() * sizeof(double), hipMemcpyHostToDevice,
@@ -515,7 +520,10 @@ extern "C" int gp_precond_view_of(const gp_precond* P, gp_precond_view* view) {
   return GP_OK;
 }
 
-extern "C" void gp_precond_free(gp_precond* P) { delete P; }
+extern "C" void gp_precond_free(gp_precond* P) {
+  if (P) gpmll_forget_forward(P->ws);  // a forward pass made with this handle is not reused after it
+  delete P;
+}
 
 // The CG iterations of one call on the right-hand sides already in R (one CG run
 // with many right-hand sides, footnote to Section 4.4).  With the host polling the
@@ -553,16 +561,23 @@ static int run_cg(const Ctx& c, const Hyper& h, const gp_options* opt) {
 // A prebuilt preconditioner must come from the same problem, theta, rank and
 // workspace; then only the per-evaluation flags are cleared.  Otherwise the
 // pivoted Cholesky preconditioner is built in the workspace.
+static int check_precond_handle(const gp_problem* prob, const double* theta_host, int32_t rank, const gp_precond* P,
+                                const Ctx& c) {
+  const Layout& L = *c.lay;
+  const int p = prob->ard ? prob->d : 1;
+  if (P->ws != c.ws || P->lay.k != rank || P->lay.n != prob->n || P->lay.d != prob->d || P->lay.L != L.L ||
+      P->lay.Cinv != L.Cinv || P->prob.X_dev != prob->X_dev)
+    return GP_EINVAL;
+  for (int i = 0; i < p + 2; ++i)
+    if (P->theta[i] != theta_host[i]) return GP_EINVAL;
+  return GP_OK;
+}
+
 static int use_or_build_precond(const gp_problem* prob, const double* theta_host, int32_t rank, gp_precond* P,
                                 const Hyper& h, const Ctx& c) {
   const Layout& L = *c.lay;
-  const int p = prob->ard ? prob->d : 1;
   if (P) {
-    if (P->ws != c.ws || P->lay.k != rank || P->lay.n != prob->n || P->lay.d != prob->d || P->lay.L != L.L ||
-        P->lay.Cinv != L.Cinv || P->prob.X_dev != prob->X_dev)
-      return GP_EINVAL;
-    for (int i = 0; i < p + 2; ++i)
-      if (P->theta[i] != theta_host[i]) return GP_EINVAL;
+    RET_IF(check_precond_handle(prob, theta_host, rank, P, c));
     // keep flags[1] (a build-time status); clear the per-evaluation flags
     HIPCHK(hipMemsetAsync(c.at<int>(L.flags), 0, 4, c.st));
     HIPCHK(hipMemsetAsync(c.at<int>(L.flags) + 2, 0, 56, c.st));
@@ -570,6 +585,61 @@ static int use_or_build_precond(const gp_problem* prob, const double* theta_host
   }
   HIPCHK(hipMemsetAsync(c.at<int>(L.flags), 0, 64, c.st));
   return build_precond(prob, h, c);
+}
+
+// The last forward pass completed on each workspace (host-side record).  A
+// gp_mll_grad with the same problem, theta, options, rank, preconditioner handle
+// and stream finds the solves, the CG coefficients and the preconditioner still in
+// the workspace and runs only the derivative part.  Every other call that writes
+// into a workspace forgets its record first.
+namespace {
+struct ForwardRecord {
+  gp_problem prob;
+  std::vector<double> theta;
+  gp_options opt;
+  int32_t rank;
+  const gp_precond* P;
+  hipStream_t stream;
+};
+std::mutex g_fwd_mu;
+std::map<const void*, ForwardRecord> g_fwd;
+
+bool same_options(const gp_options& a, const gp_options& b) {
+  return a.precision == b.precision && a.num_probes == b.num_probes && a.max_iters == b.max_iters &&
+         a.cg_tol == b.cg_tol && a.seed == b.seed && a.precond_grad == b.precond_grad &&
+         a.sync_every == b.sync_every && a.probe_mode == b.probe_mode;
+}
+
+bool same_problem(const gp_problem& a, const gp_problem& b) {
+  return a.X_dev == b.X_dev && a.y_dev == b.y_dev && a.n == b.n && a.d == b.d && a.kernel == b.kernel &&
+         a.ard == b.ard && (a.kernel != GP_KERNEL_RATQUAD || a.kernel_shape == b.kernel_shape);
+}
+
+bool forward_matches(const void* ws, const gp_problem* prob, const double* theta, const gp_options* opt,
+                     int32_t rank, const gp_precond* P, hipStream_t stream) {
+  std::lock_guard<std::mutex> lk(g_fwd_mu);
+  auto it = g_fwd.find(ws);
+  if (it == g_fwd.end()) return false;
+  const ForwardRecord& r = it->second;
+  if (!same_problem(r.prob, *prob) || !same_options(r.opt, *opt) || r.rank != rank || r.P != P ||
+      r.stream != stream)
+    return false;
+  for (size_t i = 0; i < r.theta.size(); ++i)
+    if (r.theta[i] != theta[i]) return false;
+  return true;
+}
+
+void forward_remember(const void* ws, const gp_problem* prob, const double* theta, const gp_options* opt,
+                      int32_t rank, const gp_precond* P, hipStream_t stream) {
+  const int p = prob->ard ? prob->d : 1;
+  std::lock_guard<std::mutex> lk(g_fwd_mu);
+  g_fwd[ws] = ForwardRecord{*prob, std::vector<double>(theta, theta + p + 2), *opt, rank, P, stream};
+}
+}  // namespace
+
+void gpmll::gpmll_forget_forward(const void* ws) {
+  std::lock_guard<std::mutex> lk(g_fwd_mu);
+  g_fwd.erase(ws);
 }
 
 static int run_estimator(const gp_problem* prob, const double* theta_host, const gp_options* opt, int32_t rank,
@@ -586,12 +656,19 @@ static int run_estimator(const gp_problem* prob, const double* theta_host, const
                          opt->probe_mode);
   RET_IF(check_ws(ws_dev, ws_bytes, L));
   Ctx c{&L, (char*)ws_dev, stream};
-  RET_IF(use_or_build_precond(prob, theta_host, rank, P, h, c));
-  HIPCHK(launch_stage_x(c, h));
-  if (opt->probe_mode == 1) HIPCHK(launch_probes_sqrt(c, prob->y_dev, h, opt->seed));
-  else HIPCHK(launch_probes(c, prob->y_dev, h, opt->seed));
-  HIPCHK(launch_cg_init(c, h));
-  RET_IF(run_cg(c, h, opt));
+  if (P) RET_IF(check_precond_handle(prob, theta_host, rank, P, c));
+  const bool resume = grad_dev && forward_matches(ws_dev, prob, theta_host, opt, rank, P, stream);
+  gpmll_forget_forward(ws_dev);
+  if (!resume) {
+    RET_IF(use_or_build_precond(prob, theta_host, rank, P, h, c));
+    HIPCHK(launch_stage_x(c, h));
+    if (opt->probe_mode == 1) HIPCHK(launch_probes_sqrt(c, prob->y_dev, h, opt->seed));
+    else HIPCHK(launch_probes(c, prob->y_dev, h, opt->seed));
+    HIPCHK(launch_cg_init(c, h));
+    RET_IF(run_cg(c, h, opt));
+  }
+  // (after a matching forward pass only log p is rewritten from the stored coefficients)
+  if (resume) HIPCHK(hipMemsetAsync(c.at<int>(L.flags) + 2, 0, 4, stream));  // the Ritz clamps are recounted
   HIPCHK(launch_slq_logp(c, h, prob->y_dev, logp_dev));
   if (grad_dev) {
     HIPCHK(launch_stage_x_bwd(c, h));
@@ -635,6 +712,7 @@ static int run_estimator(const gp_problem* prob, const double* theta_host, const
     if (stats->pivots_host)
       for (int i = 0; i < rank; ++i) stats->pivots_host[i] = pv[i];
   }
+  forward_remember(ws_dev, prob, theta_host, opt, rank, P, stream);
   return GP_OK;
 }
 
@@ -664,6 +742,7 @@ extern "C" int gp_predict(const gp_problem* prob, const double* theta_host, cons
   Layout L = make_layout(prob->n, prob->d, prob->ard, opt->num_probes, opt->max_iters, rank, opt->precision);
   RET_IF(check_ws(ws_dev, ws_bytes, L));
   Ctx c{&L, (char*)ws_dev, stream};
+  gpmll_forget_forward(ws_dev);
   RET_IF(use_or_build_precond(prob, theta_host, rank, P, h, c));
   HIPCHK(launch_stage_x(c, h));
   // test points in chunks of num_probes: one CG call on [y | k(X, x*_j)] per chunk
@@ -693,6 +772,7 @@ extern "C" int gp_khat_matvec(const gp_problem* prob, const double* theta_host, 
   Layout L = make_layout(prob->n, prob->d, prob->ard, std::max(1, num_rhs - 1), 1, 0, precision);
   RET_IF(check_ws(ws_dev, ws_bytes, L));
   Ctx c{&L, (char*)ws_dev, stream};
+  gpmll_forget_forward(ws_dev);
   HIPCHK(launch_prep(c, prob->X_dev, h));
   HIPCHK(launch_stage_x(c, h));
   HIPCHK(launch_stage_v(c, V_dev, num_rhs, num_rhs, h));
@@ -725,6 +805,7 @@ extern "C" int gp_khat_profile(const gp_problem* prob, const double* theta_host,
   Layout L = make_layout(prob->n, prob->d, prob->ard, opt->num_probes, opt->max_iters, 0, opt->precision);
   RET_IF(check_ws(ws_dev, ws_bytes, L));
   Ctx c{&L, (char*)ws_dev, stream};
+  gpmll_forget_forward(ws_dev);
   HIPCHK(launch_prep(c, prob->X_dev, h));
   HIPCHK(launch_stage_x(c, h));
   const int64_t cnt = L.n_pad * L.tp;

@@ -269,6 +269,7 @@ int run_batch(const gp_batch* bp, const double* theta_host, const gp_options* op
   BHIP(hipStreamSynchronize(stream));
 
   Ctx c{&L.view, ws, stream};
+  gpmll_forget_forward(ws);
   Hyper h;
   std::memset(&h, 0, sizeof(h));
   h.kind = bp->kernel;

@@ -154,6 +154,10 @@ hipError_t launch_cg_init(const Ctx& c, const Hyper& h);
 hipError_t launch_pred_rhs(const Ctx& c, const Hyper& h, const double* y, const double* xstar, int ncols);
 hipError_t launch_pred_finish(const Ctx& c, const Hyper& h, int ncols, double* mean, double* var);
 
+// forgets the forward pass recorded for a workspace (every call that writes into a
+// workspace other than the estimator itself calls this first)
+void gpmll_forget_forward(const void* ws);
+
 // GP_OK when the current device is gfx950 (cached per device); records the HIP
 // error behind a GP_EHIP for gp_last_hip_error.
 int gpmll_check_device();

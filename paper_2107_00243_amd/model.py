@@ -5,6 +5,7 @@ estimator options; GPMLL.apply(model, log_theta) returns the estimate of
 log p(y | theta) with theta = exp(log_theta), and its backward returns
 grad_log_theta = theta * d log p / d theta from the same library call (the
 forward solves are reused; the derivative sweep runs once per evaluation).
+When log_theta does not require a gradient, only the estimate is computed.
 """
 from __future__ import annotations
 
@@ -47,9 +48,13 @@ class GPMLL(torch.autograd.Function):
     @staticmethod
     def forward(ctx, model: GPMarginalLikelihood, log_theta: torch.Tensor):
         theta = torch.exp(log_theta.detach().to(torch.float64).cpu())
-        logp, grad = model.evaluate(theta.numpy(), with_grad=True, stats=model.want_stats)
-        g = grad.detach().cpu()
-        ctx.save_for_backward(theta * g)
+        if ctx.needs_input_grad[1]:
+            # log p and its gradient from one library call (the derivative sweep
+            # reuses the forward solves)
+            logp, grad = model.evaluate(theta.numpy(), with_grad=True, stats=model.want_stats)
+            ctx.save_for_backward(theta * grad.detach().cpu())
+        else:
+            logp, _ = model.evaluate(theta.numpy(), with_grad=False, stats=model.want_stats)
         return logp.detach().cpu().reshape(())
 
     @staticmethod

@@ -466,3 +466,62 @@ def test_square_root_probes_with_a_fourier_feature_preconditioner():
                           freqs=W, probe_mode=1)
     assert rel(float(logp.cpu()[0]), ref["logp"]) < 1e-7
     assert relvec(g.cpu().numpy(), ref["grad"]) < 1e-5
+
+
+# ---------------------------------------------------------------- reuse of a forward pass
+
+def test_grad_after_eval_reuses_the_forward_pass_bitwise():
+    import time
+    pr = synthgp.matern52_ard_20k(n=12000)
+    dev = torch.device("cuda:0")
+    X = torch.tensor(pr.X, device=dev)
+    y = torch.tensor(pr.y, device=dev)
+    prob = B.make_problem(X, y, pr.kernel, pr.ard)
+    opt = B.make_options("fp32", 16, 300, 1e-6, 1, 0, 1)
+    ws = B.alloc_workspace(B.gp_workspace_size(prob, opt, 40))
+    out = [torch.zeros(1, dtype=torch.float64, device=dev) for _ in range(3)]
+    grads = [torch.zeros(len(pr.theta), dtype=torch.float64, device=dev) for _ in range(2)]
+    say("[gpu] reuse: fresh gradient, then eval + gradient")
+    B.gp_mll_grad(prob, pr.theta, opt, 40, None, ws, out[0], grads[0])      # warm-up and reference
+    B.gp_khat_matvec(prob, pr.theta, "fp32", torch.zeros(pr.n, 2, dtype=torch.float64, device=dev),
+                     torch.zeros(pr.n, 2, dtype=torch.float64, device=dev), ws)   # ends the reuse
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    B.gp_mll_grad(prob, pr.theta, opt, 40, None, ws, out[0], grads[0])
+    torch.cuda.synchronize()
+    t_full = time.perf_counter() - t0
+    B.gp_mll_eval(prob, pr.theta, opt, 40, None, ws, out[1])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    B.gp_mll_grad(prob, pr.theta, opt, 40, None, ws, out[2], grads[1])
+    torch.cuda.synchronize()
+    t_reuse = time.perf_counter() - t0
+    say(f"    full {1e3 * t_full:.1f} ms, after eval {1e3 * t_reuse:.1f} ms")
+    assert float(out[0].cpu()[0]) == float(out[1].cpu()[0]) == float(out[2].cpu()[0])
+    assert torch.equal(grads[0], grads[1])
+    assert t_reuse < 0.6 * t_full
+
+
+def test_grad_after_eval_at_another_theta_or_after_other_work_recomputes():
+    pr = synthgp.random_problem(1500, 3, "rbf", ard=True, seed=97, sigma2=0.05, dist="normal")
+    dev = torch.device("cuda:0")
+    X = torch.tensor(pr.X, device=dev)
+    y = torch.tensor(pr.y, device=dev)
+    prob = B.make_problem(X, y, "rbf", True)
+    opt = B.make_options("fp64", 8, 300, 1e-8, 1, 0, 1)
+    ws = B.alloc_workspace(B.gp_workspace_size(prob, opt, 20))
+    th2 = pr.theta * 1.1
+    lp = torch.zeros(1, dtype=torch.float64, device=dev)
+    g_ref = torch.zeros(len(pr.theta), dtype=torch.float64, device=dev)
+    g = torch.zeros_like(g_ref)
+    B.gp_mll_grad(prob, th2, opt, 20, None, ws, lp, g_ref)
+    lp_ref = float(lp.cpu()[0])
+    B.gp_mll_eval(prob, pr.theta, opt, 20, None, ws, lp)     # another theta
+    B.gp_mll_grad(prob, th2, opt, 20, None, ws, lp, g)
+    assert float(lp.cpu()[0]) == lp_ref and torch.equal(g, g_ref)
+    B.gp_mll_eval(prob, th2, opt, 20, None, ws, lp)          # same theta, then other work
+    Xs = torch.tensor(pr.X[:10], device=dev)
+    m = torch.zeros(10, dtype=torch.float64, device=dev)
+    B.gp_predict(prob, th2, opt, 20, None, Xs, ws, m)
+    B.gp_mll_grad(prob, th2, opt, 20, None, ws, lp, g)
+    assert float(lp.cpu()[0]) == lp_ref and torch.equal(g, g_ref)
