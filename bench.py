@@ -387,7 +387,22 @@ def main():
             "rel_logp": abs(h16["logp"] - f64["logp"]) / abs(f64["logp"]),
             "rel_grad": float(np.linalg.norm(h16["grad"] - f64["grad"]) / np.linalg.norm(f64["grad"])),
         }
+    rec["env"] = run_environment()
     print(json.dumps(rec))
+
+
+def run_environment():
+    """GPU, HIP and host CPU the numbers were taken on."""
+    import platform
+    import torch
+    cpu = platform.processor()
+    try:
+        with open("/proc/cpuinfo") as f:
+            cpu = next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")), cpu)
+    except OSError:
+        pass
+    return {"gpu": torch.cuda.get_device_name(0), "hip": torch.version.hip, "torch": torch.__version__,
+            "host_cpu": cpu, "host_cpus": os.cpu_count()}
 
 
 if __name__ == "__main__":

@@ -88,3 +88,26 @@ def test_a_single_point_gives_the_exact_likelihood(rank):
     if rank == 1:
         assert rel(lp, exact) < 1e-12
     assert st.iters_max <= 1
+
+
+def test_workspace_one_byte_short_is_rejected():
+    pr = synthgp.random_problem(700, 3, "rbf", ard=True, seed=98, dist="normal")
+    dev = torch.device("cuda:0")
+    X = torch.tensor(pr.X, device=dev)
+    y = torch.tensor(pr.y, device=dev)
+    prob = B.make_problem(X, y, "rbf", True)
+    opt = B.make_options("fp64", 8, 100)
+    need = B.gp_workspace_size(prob, opt, 16)
+    ws = B.alloc_workspace(need - 1)
+    lp = torch.zeros(1, dtype=torch.float64, device=dev)
+    g = torch.zeros(len(pr.theta), dtype=torch.float64, device=dev)
+    for call in (lambda: B.gp_mll_grad(prob, pr.theta, opt, 16, None, ws, lp, g),
+                 lambda: B.gp_mll_eval(prob, pr.theta, opt, 16, None, ws, lp),
+                 lambda: B.gp_predict(prob, pr.theta, opt, 16, None, X[:4], ws, lp.repeat(4))):
+        with pytest.raises(B.GPError) as e:
+            call()
+        assert e.value.code == B.GP_EWORKSPACE
+    full = B.alloc_workspace(need)
+    B.gp_mll_grad(prob, pr.theta, opt, 16, None, full, lp, g)      # the exact size is enough
+    torch.cuda.synchronize()
+    assert np.isfinite(float(lp.cpu()[0]))
