@@ -261,7 +261,8 @@ int gp_mll_eval(const gp_problem* prob, const double* theta_host, const gp_optio
  * are computed (the results are bitwise those of a full call).  Any other call
  * on the workspace (preconditioner builds, gp_khat_matvec, gp_khat_profile,
  * gp_predict, batch calls) and gp_precond_free of the handle end the reuse; the
- * caller must not write into the workspace in between.
+ * caller must not change X, y or the workspace in between (the record compares
+ * pointers and values of the arguments, not the contents of device arrays).
  */
 int gp_mll_grad(const gp_problem* prob, const double* theta_host, const gp_options* opt,
                 int32_t rank, gp_precond* P, void* ws_dev, size_t ws_bytes,
