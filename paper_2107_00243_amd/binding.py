@@ -13,7 +13,8 @@ import os
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libgpmll.so")
+# GPMLL_LIB selects another build of the library (the host-sanitizer build, say)
+LIB_PATH = os.environ.get("GPMLL_LIB") or os.path.join(HERE, "libgpmll.so")
 
 GP_OK, GP_EINVAL, GP_EWORKSPACE, GP_ENOTSPD, GP_EHIP, GP_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
 KERNELS = {"rbf": 0, "matern32": 1, "matern52": 2, "ratquad": 3}

@@ -37,9 +37,17 @@ def sources():
     return sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".hip"))
 
 
-def build(verbose: bool = False, jobs: int | None = None) -> str:
+# host-side AddressSanitizer and UndefinedBehaviorSanitizer (device code is built as
+# usual); the library then needs the sanitizer runtime preloaded into the process
+SANITIZE_FLAGS = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+                  "-Xarch_host", "-fno-omit-frame-pointer"]
+
+
+def build(verbose: bool = False, jobs: int | None = None, sanitize: bool = False) -> str:
     cc = hipcc()
     srcs = sources()
+    extra = SANITIZE_FLAGS if sanitize else []
+    lib = LIB.replace(".so", "_san.so") if sanitize else LIB
     jobs = jobs or min(9, int(os.environ.get("MAX_JOBS", "8")))
     tmp = tempfile.mkdtemp(prefix="gpmll_build_")
     try:
@@ -54,18 +62,18 @@ def build(verbose: bool = False, jobs: int | None = None) -> str:
         for src, defs, tag in units:
             obj = os.path.join(tmp, os.path.basename(src) + tag + ".o")
             objs.append(obj)
-            cmd = [cc, *HIPCC_FLAGS, *defs, "-c", src, "-o", obj]
+            cmd = [cc, *HIPCC_FLAGS, *extra, *defs, "-c", src, "-o", obj]
             procs.append((cmd, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)))
             if len(procs) >= jobs:
                 _drain(procs, verbose)
         _drain(procs, verbose)
-        out_tmp = LIB + ".tmp"
-        cmd = [cc, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", out_tmp, *objs]
+        out_tmp = lib + ".tmp"
+        cmd = [cc, f"--offload-arch={ARCH}", "-shared", "-fPIC", *extra, "-o", out_tmp, *objs]
         _run(cmd, verbose)
-        os.replace(out_tmp, LIB)
+        os.replace(out_tmp, lib)
     finally:
         shutil.rmtree(tmp, ignore_errors=True)
-    return LIB
+    return lib
 
 
 def _run(cmd, verbose):
@@ -90,5 +98,5 @@ def _drain(procs, verbose):
 
 
 if __name__ == "__main__":
-    path = build(verbose="-v" in sys.argv)
+    path = build(verbose="-v" in sys.argv, sanitize="--sanitize" in sys.argv)
     print(path)
