@@ -525,3 +525,28 @@ def test_grad_after_eval_at_another_theta_or_after_other_work_recomputes():
     B.gp_predict(prob, th2, opt, 20, None, Xs, ws, m)
     B.gp_mll_grad(prob, th2, opt, 20, None, ws, lp, g)
     assert float(lp.cpu()[0]) == lp_ref and torch.equal(g, g_ref)
+
+
+def test_grad_after_eval_with_a_prebuilt_handle_reuses_and_a_freed_handle_does_not():
+    pr = synthgp.random_problem(1300, 3, "matern32", ard=True, seed=99, sigma2=0.05, dist="normal")
+    dev = torch.device("cuda:0")
+    X = torch.tensor(pr.X, device=dev)
+    y = torch.tensor(pr.y, device=dev)
+    prob = B.make_problem(X, y, "matern32", True)
+    opt = B.make_options("fp64", 8, 300, 1e-8, 1, 0, 1)
+    ws = B.alloc_workspace(B.gp_workspace_size(prob, opt, 24))
+    lp = torch.zeros(1, dtype=torch.float64, device=dev)
+    g_ref = torch.zeros(len(pr.theta), dtype=torch.float64, device=dev)
+    g = torch.zeros_like(g_ref)
+    S = synthgp.uniform_landmarks(pr.n, 24, seed=5)
+    h = B.gp_precond_build_nystrom(prob, pr.theta, 24, S, ws)
+    B.gp_mll_grad(prob, pr.theta, opt, 24, h, ws, lp, g_ref)
+    lp_ref = float(lp.cpu()[0])
+    B.gp_mll_eval(prob, pr.theta, opt, 24, h, ws, lp)
+    B.gp_mll_grad(prob, pr.theta, opt, 24, h, ws, lp, g)
+    assert float(lp.cpu()[0]) == lp_ref and torch.equal(g, g_ref)
+    B.gp_precond_free(h)
+    # without the handle the call builds the pivoted Cholesky: a different estimate
+    B.gp_mll_grad(prob, pr.theta, opt, 24, None, ws, lp, g)
+    ref = go.estimate_mll(pr.X, pr.y, pr.theta, "matern32", True, 24, 8, 1e-8, 300, 1)
+    assert rel(float(lp.cpu()[0]), ref["logp"]) < 1e-7
