@@ -254,11 +254,12 @@ int gp_mll_eval(const gp_problem* prob, const double* theta_host, const gp_optio
  * inversion lemma (supplement S3.3).  dP_hat holds the pivots fixed
  * (precond_grad = 0) or keeps only the s and sigma^2 terms (precond_grad = 1).
  * Writes one FP64 to logp_dev and p + 2 FP64 to grad_dev, ordered like theta.
- * Reuse: when the previous call on this workspace was a gp_mll_eval or
- * gp_mll_grad with the same problem, theta, options, rank, preconditioner
- * handle and stream, the forward pass is not repeated: its solves and CG
- * coefficients are read from the workspace and only log p and the derivative
- * are computed (the results are bitwise those of a full call).  Any other call
+ * Reuse: when the previous call on this workspace was a gp_mll_eval with the
+ * same problem, theta, options, rank, preconditioner handle and stream, the
+ * forward pass is not repeated: its solves and CG coefficients are read from
+ * the workspace and only log p and the derivative are computed (the results
+ * are bitwise those of a full call).  A gp_mll_grad after a gp_mll_grad always
+ * runs the whole evaluation.  Any other call
  * on the workspace (preconditioner builds, gp_khat_matvec, gp_khat_profile,
  * gp_predict, batch calls) and gp_precond_free of the handle end the reuse; the
  * caller must not change X, y or the workspace in between (the record compares

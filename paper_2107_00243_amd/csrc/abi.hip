@@ -587,11 +587,11 @@ static int use_or_build_precond(const gp_problem* prob, const double* theta_host
   return build_precond(prob, h, c);
 }
 
-// The last forward pass completed on each workspace (host-side record).  A
-// gp_mll_grad with the same problem, theta, options, rank, preconditioner handle
-// and stream finds the solves, the CG coefficients and the preconditioner still in
-// the workspace and runs only the derivative part.  Every other call that writes
-// into a workspace forgets its record first.
+// The last forward-only pass (gp_mll_eval) completed on each workspace (host-side
+// record).  A gp_mll_grad with the same problem, theta, options, rank,
+// preconditioner handle and stream finds the solves, the CG coefficients and the
+// preconditioner still in the workspace and runs only the derivative part.  Every
+// other call that writes into a workspace forgets its record first.
 namespace {
 struct ForwardRecord {
   gp_problem prob;
@@ -712,7 +712,9 @@ static int run_estimator(const gp_problem* prob, const double* theta_host, const
     if (stats->pivots_host)
       for (int i = 0; i < rank; ++i) stats->pivots_host[i] = pv[i];
   }
-  forward_remember(ws_dev, prob, theta_host, opt, rank, P, stream);
+  // only a forward-only call leaves a record: a gp_mll_grad always recomputes after
+  // another gp_mll_grad, so repeated identical calls each do the whole evaluation
+  if (!grad_dev) forward_remember(ws_dev, prob, theta_host, opt, rank, P, stream);
   return GP_OK;
 }
 

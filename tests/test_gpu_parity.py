@@ -550,3 +550,27 @@ def test_grad_after_eval_with_a_prebuilt_handle_reuses_and_a_freed_handle_does_n
     B.gp_mll_grad(prob, pr.theta, opt, 24, None, ws, lp, g)
     ref = go.estimate_mll(pr.X, pr.y, pr.theta, "matern32", True, 24, 8, 1e-8, 300, 1)
     assert rel(float(lp.cpu()[0]), ref["logp"]) < 1e-7
+
+
+def test_repeated_identical_grad_calls_each_do_the_whole_evaluation():
+    # only a forward-only call is reused: timing repeated gp_mll_grad calls measures
+    # full evaluations (a grad after a grad recomputes)
+    import time
+    pr = synthgp.matern52_ard_20k(n=12000)
+    dev = torch.device("cuda:0")
+    X = torch.tensor(pr.X, device=dev)
+    y = torch.tensor(pr.y, device=dev)
+    prob = B.make_problem(X, y, pr.kernel, pr.ard)
+    opt = B.make_options("fp32", 16, 300, 1e-6, 1, 0, 1)
+    ws = B.alloc_workspace(B.gp_workspace_size(prob, opt, 40))
+    lp = torch.zeros(1, dtype=torch.float64, device=dev)
+    g = torch.zeros(len(pr.theta), dtype=torch.float64, device=dev)
+    times = []
+    for _ in range(3):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        B.gp_mll_grad(prob, pr.theta, opt, 40, None, ws, lp, g)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+    say(f"    grad call times (ms): {[round(1e3 * x, 1) for x in times]}")
+    assert min(times[1:]) > 0.5 * times[0]
