@@ -80,7 +80,8 @@ def run_gpu(pr, precision, steps, warmup, sync_every=1):
     B.gp_mll_grad(prob, pr.theta, opt, pr.rank, None, ws, logp, grad, st)
     torch.cuda.synchronize()
     info = {"logp": float(logp.cpu()[0]), "grad": grad.cpu().numpy(), "iters_max": int(st.iters_max),
-            "iters_mean": float(np.mean(st.col_iters)), "flags": int(st.flags), "rank": int(st.rank_achieved)}
+            "iters_mean": float(np.mean(st.col_iters)), "iters_y": int(st.col_iters[0]),
+            "flags": int(st.flags), "rank": int(st.rank_achieved)}
     for _ in range(warmup):
         B.gp_mll_grad(prob, pr.theta, opt, pr.rank, None, ws, logp, grad)
     torch.cuda.synchronize()
@@ -365,7 +366,8 @@ def main():
                                f"rank {pr.rank} pivoted Cholesky, {pr.num_probes} probes, CG tol {pr.tol}, "
                                f"BF16x3 tiles, FP64 recurrences",
                    "n": n, "d": d, "num_probes": pr.num_probes, "rank": pr.rank, "precision": "bf16x3",
-                   "cg_iters_max": bf["iters_max"], "cg_iters_mean": bf["iters_mean"]},
+                   "cg_iters_max": bf["iters_max"], "cg_iters_mean": bf["iters_mean"],
+                   "cg_iters_y_column": bf["iters_y"]},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "fp64_gpu": out_fp64,
