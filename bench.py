@@ -102,10 +102,10 @@ def run_gpu(pr, precision, steps, warmup, sync_every=1):
     return info
 
 
-def run_batched(steps, warmup):
+def run_batched(steps, warmup, precision=None):
     """The 64-problem ragged batch (n_b ~ U{500..8000}, d 4, RBF, rank 20, 16 probes,
-    FP64 tiles): one gp_batch_mll_grad call evaluates log p and the gradient of all
-    64 problems."""
+    FP64 tiles unless precision is given): one gp_batch_mll_grad call evaluates log p
+    and the gradient of all 64 problems."""
     import torch
     import synthgp
     from paper_2107_00243_amd import binding as B
@@ -115,7 +115,8 @@ def run_batched(steps, warmup):
     X = torch.tensor(np.concatenate([p.X for p in probs]), device=dev)
     y = torch.tensor(np.concatenate([p.y for p in probs]), device=dev)
     bt = B.Batch(X, y, [p.n for p in probs], pr0.kernel, pr0.ard)
-    opt = B.make_options(pr0.precision, pr0.num_probes, pr0.max_iters, pr0.tol, pr0.probe_seed, 0, 1)
+    prec = precision or pr0.precision
+    opt = B.make_options(prec, pr0.num_probes, pr0.max_iters, pr0.tol, pr0.probe_seed, 0, 1)
     ws = B.alloc_workspace(B.gp_batch_workspace_size(bt, opt, pr0.rank))
     theta = np.stack([p.theta for p in probs])
     nb, P = len(probs), len(pr0.theta)
@@ -134,7 +135,8 @@ def run_batched(steps, warmup):
     n = np.array([p.n for p in probs], dtype=np.float64)
     pair_iters = float(np.sum(n * n * st.iters))
     return {"value": 1.0 / dt, "unit": "batch evals/s (64 problems, log p + gradient each)",
-            "problems_per_s": nb / dt, "ms_per_batch": 1e3 * dt, "steps": steps, "precision": pr0.precision,
+            "problems_per_s": nb / dt, "ms_per_batch": 1e3 * dt, "steps": steps, "precision": prec,
+            "logp": logp.cpu().numpy().tolist(), "grad": grad.cpu().numpy().reshape(nb, P).tolist(),
             "problems": nb, "n_min": int(n.min()), "n_max": int(n.max()), "sum_n": int(n.sum()),
             "cg_iters_max": int(st.iters_max), "cg_iters_median": float(np.median(st.iters)),
             "kernel_pair_evaluations_in_cg": pair_iters,
@@ -302,7 +304,10 @@ def main():
     import synthgp
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     if args.batch_only:
-        print(json.dumps(run_batched(args.steps, args.warmup)))
+        r = run_batched(args.steps, args.warmup)
+        r.pop("logp")
+        r.pop("grad")
+        print(json.dumps(r))
         return
     pr = synthgp.rbf_ard_100k(n=args.n)
     n, d, t = pr.n, pr.d, 1 + pr.num_probes
@@ -354,6 +359,16 @@ def main():
         log("[bench] 64-problem ragged batch")
         batched = run_batched(2, 1)
         log(f"[bench] batch: {batched['ms_per_batch']:.1f} ms per call, iters max {batched['cg_iters_max']}")
+        # FP32 tiles on the same batch: faster, and how far from the FP64-tile results
+        b32 = run_batched(1, 0, "fp32")
+        lp64, lp32 = np.array(batched.pop("logp")), np.array(b32.pop("logp"))
+        g64, g32 = np.array(batched.pop("grad")), np.array(b32.pop("grad"))
+        relg = np.linalg.norm(g32 - g64, axis=1) / np.linalg.norm(g64, axis=1)
+        batched["fp32_tiles"] = {"ms_per_batch": b32["ms_per_batch"], "cg_iters_max": b32["cg_iters_max"],
+                                 "max_rel_logp_vs_fp64": float(np.max(np.abs(lp32 - lp64) / np.abs(lp64))),
+                                 "max_rel_grad_vs_fp64": float(relg.max()),
+                                 "problems_within_1e-2_grad": int(np.sum(relg < 1e-2))}
+        log(f"[bench] batch fp32: {b32['ms_per_batch']:.1f} ms per call")
     cpu = None
     if not args.no_cpu:
         log("[bench] timing the CPU oracle sample")
