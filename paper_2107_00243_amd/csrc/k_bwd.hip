@@ -893,6 +893,29 @@ __global__ void k_probes_base(const double* __restrict__ y, int64_t n, int64_t n
   for (int c = 0; c < ell; ++c) row[1 + c] = sigma * rademacher(seed, 0, (uint64_t)c, (uint64_t)i);
 }
 
+// eta signs of the probes: H[l][c] for preconditioner column l and probe c (stream 1)
+__global__ void k_probe_eta(uint64_t seed, int k, int ell, double* __restrict__ H) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= k * ell) return;
+  const int l = e / ell, c = e % ell;
+  H[e] = rademacher(seed, 1, (uint64_t)c, (uint64_t)l);
+}
+
+// R = [y | sigma eps + L eta] (n_pad x tp row-major; the product L H as one tile GEMM)
+hipError_t launch_probes(const Ctx& c, const double* y, const Hyper& h, uint64_t seed) {
+  const Layout& L = *c.lay;
+  hipLaunchKernelGGL(k_probes_base, dim3((unsigned)((L.n_pad + 255) / 256)), dim3(256), 0, c.st, y, L.n, L.n_pad,
+                     L.ell, L.tp, sqrt(h.s2), seed, c.at<double>(L.R), c.at<double>(L.Xs));
+  if (L.k == 0) return hipGetLastError();
+  hipLaunchKernelGGL(k_probe_eta, dim3((L.k * L.ell + 255) / 256), dim3(256), 0, c.st, seed, L.k, L.ell,
+                     c.at<double>(L.H));
+  hipLaunchKernelGGL(k_gemm64, dim3(nbk(L.n, 64), (L.ell + 63) / 64), dim3(256), 0, c.st, L.n, L.ell, L.k,
+                     c.at<double>(L.L), (int64_t)1, (int64_t)L.n, c.at<double>(L.H), (int64_t)L.ell, (int64_t)1,
+                     c.at<double>(L.R) + 1, (int64_t)L.tp, (int64_t)1, 1.0, 1.0, (const int*)nullptr,
+                     (const int*)nullptr);
+  return hipGetLastError();
+}
+
 // inverse of an SPD k x k matrix by the small Cholesky routine (logdet and status
 // outputs go to scratch / the deferred-status slot)
 __global__ void k_sqrt_inverse(int64_t n, int k, double s2, const double* __restrict__ Bm, double* __restrict__ Rc,

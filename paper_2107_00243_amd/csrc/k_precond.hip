@@ -283,39 +283,6 @@ __global__ void k_rff_features(const double* __restrict__ xs, int64_t n, int d, 
 }
 
 // ---------------------------------------------------------------------------
-// Probes
-// ---------------------------------------------------------------------------
-
-__global__ void k_eta(uint64_t seed, int k, int ell, double* __restrict__ H) {
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= k * ell) return;
-  const int l = e / ell, c = e % ell;
-  H[e] = rademacher(seed, 1, (uint64_t)c, (uint64_t)l);
-}
-
-// R = [y | sigma eps + L eta] (n_pad x tp row-major), Xs = 0, padding zero
-__global__ void k_probes(const double* __restrict__ y, const double* __restrict__ L,
-                         const double* __restrict__ H, int64_t n, int64_t n_pad, int k, int ell, int tp,
-                         double sigma, uint64_t seed, double* __restrict__ R, double* __restrict__ Xs) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n_pad) return;
-  double* row = R + i * tp;
-  double* xrow = Xs + i * tp;
-  for (int c = 0; c < tp; ++c) xrow[c] = 0.0;
-  if (i >= n) {
-    for (int c = 0; c < tp; ++c) row[c] = 0.0;
-    return;
-  }
-  row[0] = y[i];
-  for (int c = 0; c < ell; ++c) {
-    double acc = sigma * rademacher(seed, 0, (uint64_t)c, (uint64_t)i);
-    for (int l = 0; l < k; ++l) acc += L[(int64_t)l * n + i] * H[l * ell + c];
-    row[1 + c] = acc;
-  }
-  for (int c = 1 + ell; c < tp; ++c) row[c] = 0.0;
-}
-
-// ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
 
@@ -375,15 +342,5 @@ hipError_t launch_precond_finish(const Ctx& c, const Hyper& h) {
   return hipGetLastError();
 }
 
-hipError_t launch_probes(const Ctx& c, const double* y, const Hyper& h, uint64_t seed) {
-  const Layout& L = *c.lay;
-  if (L.k > 0)
-    hipLaunchKernelGGL(k_eta, dim3((L.k * L.ell + 255) / 256), dim3(256), 0, c.st, seed, L.k, L.ell,
-                       c.at<double>(L.H));
-  hipLaunchKernelGGL(k_probes, dim3((unsigned)((L.n_pad + 255) / 256)), dim3(256), 0, c.st, y,
-                     c.at<double>(L.L), c.at<double>(L.H), L.n, L.n_pad, L.k, L.ell, L.tp, sqrt(h.s2), seed,
-                     c.at<double>(L.R), c.at<double>(L.Xs));
-  return hipGetLastError();
-}
 
 }  // namespace gpmll
