@@ -8,10 +8,13 @@ HBM.  Prints one JSON line.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-fp64] [--no-cpu] [--no-batch]
 
-Besides the headline line it reports the FP16X3 and FP64 tile precisions on the same
-workload, the randomized Nystrom and random Fourier feature preconditioners at the
-same rank, posterior prediction at 256 test points (gp_predict) and the 64-problem
-ragged batch (gp_batch_mll_grad) as extra fields.
+The headline runs the K_hat V tiles in split FP16 (FP16X3: hi + lo halves, three
+products, FP32 accumulation).  Beside it the line reports the BF16X3 and FP64 tile
+precisions on the same workload (BF16X3 tiles run at the same speed but their
+coarser split costs CG iterations at this tolerance), the randomized Nystrom and
+random Fourier feature preconditioners at the same rank, posterior prediction at 256
+test points (gp_predict) and the 64-problem ragged batch (gp_batch_mll_grad) as
+extra fields.
 """
 from __future__ import annotations
 
@@ -31,18 +34,27 @@ PEAK_BF16_TFLOPS = 2500.0   # MI355X dense BF16 MFMA
 PEAK_FP64_TFLOPS = 78.6
 
 
-# Counter readings of one k_khat_bf16 launch on this workload (rocprofv3 --pmc
-# FETCH_SIZE, then WRITE_SIZE, KiB per dispatch, over `bench.py --tiles-only`),
-# each scaled by what the same counter reads for a 1 GiB elementwise copy, and the
-# MFMA counters of the same launches.  They describe the kernel source whose hash
-# is given, launched on the given grid; once either changes they are stale and are
-# not reported.
+# Counter readings of one split-precision tile launch on this workload (rocprofv3
+# --pmc FETCH_SIZE, then WRITE_SIZE, KiB per dispatch, over `bench.py --tiles-only
+# --tile-precision P`), each scaled by what the same counter reads for a 1 GiB
+# elementwise copy, and the MFMA counters of the same launches.  They describe the
+# kernel source whose hash is given, launched on the given grid; once either changes
+# they are stale and are not reported.
 TILE_COUNTERS = {
-    "kernel_source_sha256_16": "2ad01f18215e8305",
-    "grid": [391, 5],
-    "fetch_kib": 321175.9, "fetch_scale": 1048576.0 / 524307.2,
-    "write_kib": 156400.0, "write_scale": 1.0,
-    "mfma_insts": 3.71807e8, "mfma_busy_cycles": 5.9489e9, "gui_active_per_xcd": 7.83262e7 / 8,
+    "fp16x3": {
+        "kernel_source_sha256_16": "2ad01f18215e8305",
+        "grid": [391, 5],
+        "fetch_kib": 419696.6, "fetch_scale": 1048576.0 / 524307.1,
+        "write_kib": 156400.0, "write_scale": 1.0,
+        "mfma_insts": 3.71807e8, "mfma_busy_cycles": 5.9489e9, "gui_active_per_xcd": 8.41555e7 / 8,
+    },
+    "bf16x3": {
+        "kernel_source_sha256_16": "2ad01f18215e8305",
+        "grid": [391, 5],
+        "fetch_kib": 321175.9, "fetch_scale": 1048576.0 / 524307.2,
+        "write_kib": 156400.0, "write_scale": 1.0,
+        "mfma_insts": 3.71807e8, "mfma_busy_cycles": 5.9489e9, "gui_active_per_xcd": 7.83262e7 / 8,
+    },
 }
 
 
@@ -226,17 +238,17 @@ def run_predict(pr, nstar=256):
             "var_err_vs_fp64_of_s": float(np.max(np.abs(vb - v64)) / pr.theta[-2])}
 
 
-def tiles_only(pr, reps=10, copy_bytes=1 << 30):
-    """The tile kernel alone in the bench's launch configuration, then a plain
-    elementwise copy of copy_bytes (read copy_bytes, write copy_bytes) whose
-    counter readings calibrate the HBM byte counters."""
+def tiles_only(pr, precision="fp16x3", reps=10, copy_bytes=1 << 30):
+    """The tile kernel of one split precision alone in the bench's launch
+    configuration, then a plain elementwise copy of copy_bytes (read copy_bytes,
+    write copy_bytes) whose counter readings calibrate the HBM byte counters."""
     import torch
     from paper_2107_00243_amd import binding as B
     dev = torch.device("cuda:0")
     X = torch.tensor(pr.X, device=dev)
     y = torch.tensor(pr.y, device=dev)
     prob = B.make_problem(X, y, pr.kernel, pr.ard)
-    opt = B.make_options("bf16x3", pr.num_probes, pr.max_iters, pr.tol, pr.probe_seed, 0, 1)
+    opt = B.make_options(precision, pr.num_probes, pr.max_iters, pr.tol, pr.probe_seed, 0, 1)
     ws = B.alloc_workspace(B.gp_workspace_size(prob, opt, pr.rank))
     ms, grid = B.gp_khat_profile(prob, pr.theta, opt, reps, ws)
     a = torch.ones(copy_bytes // 4, dtype=torch.float32, device=dev)
@@ -248,7 +260,8 @@ def tiles_only(pr, reps=10, copy_bytes=1 << 30):
     torch.mul(a, 1.0, out=c)
     e1.record()
     torch.cuda.synchronize()
-    return {"tile_ms": ms, "tile_grid": list(grid), "reps": reps, "copy_bytes_read": copy_bytes,
+    return {"precision": precision, "tile_ms": ms, "tile_grid": list(grid), "reps": reps,
+            "copy_bytes_read": copy_bytes,
             "copy_bytes_written": copy_bytes, "copy_ms": e0.elapsed_time(e1)}
 
 
@@ -279,6 +292,30 @@ def cpu_baseline(pr, iters, budget_s=12.0):
             "host_cpus": os.cpu_count()}
 
 
+def tile_roofline(n, d, t, run, precision):
+    """Roofline of the split-precision tile kernel from the run's HIP-event launch
+    time; traffic and MFMA counters only while the recorded readings still match
+    the kernel source and grid."""
+    flops = tile_flops(n, d, t)
+    achieved = flops / (run["tile_ms"] * 1e-3) / 1e12
+    name = {"fp16x3": "k_khat_bf16<RBF, 2, 5, 4, F16> (K_hat V tile, FP16x3)",
+            "bf16x3": "k_khat_bf16<RBF, 2, 5, 4, BF16> (K_hat V tile, BF16x3)"}[precision]
+    roof = {"bound": "mfma", "achieved": achieved, "peak": PEAK_BF16_TFLOPS, "unit": "TFLOP/s",
+            "frac": achieved / PEAK_BF16_TFLOPS, "traffic": None, "kernel": name,
+            "launch_grid": run["tile_grid"], "algorithmic_flops_per_launch": flops, "avg_launch_ms": run["tile_ms"]}
+    tc = TILE_COUNTERS.get(precision)
+    if (tc is not None and n == 100000 and bf16_tile_source_hash() == tc["kernel_source_sha256_16"]
+            and list(run["tile_grid"]) == tc["grid"]):
+        roof["traffic"] = 1024.0 * (tc["fetch_kib"] * tc["fetch_scale"] + tc["write_kib"] * tc["write_scale"])
+        roof["traffic_unit"] = "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)"
+        roof["traffic_gbps"] = roof["traffic"] / (run["tile_ms"] * 1e-3) / 1e9
+        issued = tc["mfma_insts"] * 16384.0
+        roof["issued_mfma_flops_per_launch"] = issued
+        roof["issued_mfma_frac_of_peak"] = issued / (run["tile_ms"] * 1e-3) / 1e12 / PEAK_BF16_TFLOPS
+        roof["mfma_busy_frac"] = tc["mfma_busy_cycles"] / (tc["gui_active_per_xcd"] * 1024)
+    return roof
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -293,7 +330,10 @@ def main():
                     help="skip the Nystrom / RFF preconditioner and posterior prediction legs")
     ap.add_argument("--n", type=int, default=100000)
     ap.add_argument("--tiles-only", action="store_true",
-                    help="only the BF16x3 tile kernel (10 launches) and a 1 GiB elementwise copy, for counters")
+                    help="only the split-precision tile kernel (10 launches) and a 1 GiB elementwise copy, "
+                         "for counters")
+    ap.add_argument("--tile-precision", default="fp16x3", choices=["fp16x3", "bf16x3"],
+                    help="tile precision of --tiles-only")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: there is no multi-GPU path "
@@ -313,13 +353,14 @@ def main():
     n, d, t = pr.n, pr.d, 1 + pr.num_probes
     log(f"[bench] workload rbf_ard_100k n={n} d={d} t={t} rank={pr.rank}")
     if args.tiles_only:
-        print(json.dumps(tiles_only(pr)))
+        print(json.dumps(tiles_only(pr, args.tile_precision)))
         return
 
-    bf = run_gpu(pr, "bf16x3", args.steps, args.warmup)
-    log(f"[bench] bf16x3: {bf['ms_per_step']:.2f} ms/eval, iters {bf['iters_max']}, tile {bf['tile_ms']:.3f} ms")
+    # headline: FP16X3 tiles; BF16X3 beside it (same tile kernel speed, more CG iterations)
     h16 = run_gpu(pr, "fp16x3", args.steps, args.warmup)
     log(f"[bench] fp16x3: {h16['ms_per_step']:.2f} ms/eval, iters {h16['iters_max']}, tile {h16['tile_ms']:.3f} ms")
+    bf = run_gpu(pr, "bf16x3", args.steps, args.warmup)
+    log(f"[bench] bf16x3: {bf['ms_per_step']:.2f} ms/eval, iters {bf['iters_max']}, tile {bf['tile_ms']:.3f} ms")
     out_fp64 = None
     if not args.no_fp64:
         f64 = run_gpu(pr, "fp64", args.fp64_steps, 0)
@@ -329,22 +370,7 @@ def main():
             "tile_ms": f64["tile_ms"], "tile_tflops": tile_flops(n, d, t) / (f64["tile_ms"] * 1e-3) / 1e12,
             "tile_frac_fp64_peak": tile_flops(n, d, t) / (f64["tile_ms"] * 1e-3) / 1e12 / PEAK_FP64_TFLOPS,
         }
-    flops = tile_flops(n, d, t)
-    achieved = flops / (bf["tile_ms"] * 1e-3) / 1e12
-    roofline = {"bound": "mfma", "achieved": achieved, "peak": PEAK_BF16_TFLOPS, "unit": "TFLOP/s",
-                "frac": achieved / PEAK_BF16_TFLOPS, "traffic": None,
-                "kernel": "k_khat_bf16 (K_hat V tile, BF16x3)", "launch_grid": bf["tile_grid"],
-                "algorithmic_flops_per_launch": flops, "avg_launch_ms": bf["tile_ms"]}
-    tc = TILE_COUNTERS
-    if (n == 100000 and bf16_tile_source_hash() == tc["kernel_source_sha256_16"]
-            and list(bf["tile_grid"]) == tc["grid"]):
-        roofline["traffic"] = 1024.0 * (tc["fetch_kib"] * tc["fetch_scale"] + tc["write_kib"] * tc["write_scale"])
-        roofline["traffic_unit"] = "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)"
-        roofline["traffic_gbps"] = roofline["traffic"] / (bf["tile_ms"] * 1e-3) / 1e9
-        issued = tc["mfma_insts"] * 16384.0
-        roofline["issued_mfma_flops_per_launch"] = issued
-        roofline["issued_mfma_frac_of_peak"] = issued / (bf["tile_ms"] * 1e-3) / 1e12 / PEAK_BF16_TFLOPS
-        roofline["mfma_busy_frac"] = tc["mfma_busy_cycles"] / (tc["gui_active_per_xcd"] * 1024)
+    roofline = tile_roofline(n, d, t, h16, "fp16x3")
     pred = None
     if not args.no_precond:
         log("[bench] posterior prediction at 256 test points")
@@ -372,37 +398,38 @@ def main():
     cpu = None
     if not args.no_cpu:
         log("[bench] timing the CPU oracle sample")
-        cpu = cpu_baseline(pr, bf["iters_max"])
+        cpu = cpu_baseline(pr, h16["iters_max"])
     rec = {
-        "metric": METRIC, "value": bf["evals_per_s"], "unit": "evals/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": bf["ms_per_step"], "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "bf16", "data": "synthetic",
+        "metric": METRIC, "value": h16["evals_per_s"], "unit": "evals/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": h16["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "fp16", "data": "synthetic",
         "config": {"workload": f"rbf_ard_100k: n={n}, d={d}, RBF ARD ls~LogU[0.1,1], sigma2=1e-3, "
                                f"rank {pr.rank} pivoted Cholesky, {pr.num_probes} probes, CG tol {pr.tol}, "
-                               f"BF16x3 tiles, FP64 recurrences",
-                   "n": n, "d": d, "num_probes": pr.num_probes, "rank": pr.rank, "precision": "bf16x3",
-                   "cg_iters_max": bf["iters_max"], "cg_iters_mean": bf["iters_mean"],
-                   "cg_iters_y_column": bf["iters_y"]},
+                               f"FP16x3 tiles (split FP16, FP32 accumulation), FP64 recurrences",
+                   "n": n, "d": d, "num_probes": pr.num_probes, "rank": pr.rank, "precision": "fp16x3",
+                   "cg_iters_max": h16["iters_max"], "cg_iters_mean": h16["iters_mean"],
+                   "cg_iters_y_column": h16["iters_y"]},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "fp64_gpu": out_fp64,
-        "speedup_vs_fp64_gpu": (bf["evals_per_s"] / out_fp64["value"]) if out_fp64 else None,
+        "speedup_vs_fp64_gpu": (h16["evals_per_s"] / out_fp64["value"]) if out_fp64 else None,
+        "bf16x3_gpu": {"value": bf["evals_per_s"], "ms_per_step": bf["ms_per_step"],
+                       "iters_max": bf["iters_max"], "iters_mean": bf["iters_mean"], "tile_ms": bf["tile_ms"],
+                       "tile_tflops": tile_flops(n, d, t) / (bf["tile_ms"] * 1e-3) / 1e12,
+                       "speedup_vs_fp64_gpu": (bf["evals_per_s"] / out_fp64["value"]) if out_fp64 else None,
+                       "roofline": tile_roofline(n, d, t, bf, "bf16x3")},
         "batched_rbf_64": batched,
         "preconditioners_bf16x3": precs,
         "predict": pred,
-        "fp16x3_gpu": {"value": h16["evals_per_s"], "ms_per_step": h16["ms_per_step"],
-                       "iters_max": h16["iters_max"], "tile_ms": h16["tile_ms"],
-                       "tile_tflops": tile_flops(n, d, t) / (h16["tile_ms"] * 1e-3) / 1e12,
-                       "speedup_vs_fp64_gpu": (h16["evals_per_s"] / out_fp64["value"]) if out_fp64 else None},
     }
     if out_fp64 is not None:
         rec["accuracy_vs_fp64_gpu"] = {
-            "rel_logp": abs(bf["logp"] - f64["logp"]) / abs(f64["logp"]),
-            "rel_grad": float(np.linalg.norm(bf["grad"] - f64["grad"]) / np.linalg.norm(f64["grad"])),
-        }
-        rec["fp16x3_gpu"]["accuracy_vs_fp64_gpu"] = {
             "rel_logp": abs(h16["logp"] - f64["logp"]) / abs(f64["logp"]),
             "rel_grad": float(np.linalg.norm(h16["grad"] - f64["grad"]) / np.linalg.norm(f64["grad"])),
+        }
+        rec["bf16x3_gpu"]["accuracy_vs_fp64_gpu"] = {
+            "rel_logp": abs(bf["logp"] - f64["logp"]) / abs(f64["logp"]),
+            "rel_grad": float(np.linalg.norm(bf["grad"] - f64["grad"]) / np.linalg.norm(f64["grad"])),
         }
     rec["env"] = run_environment()
     print(json.dumps(rec))
