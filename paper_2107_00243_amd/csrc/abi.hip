@@ -86,7 +86,8 @@ Layout make_layout(int64_t n, int d, int ard, int num_probes, int max_iters, int
   // L^T R: about 512 row chunks (two workgroups per CU per l-group), >= 64 rows each
   L.ltr_rows = std::max<int64_t>(64, rup((n + 511) / 512, 16));
   L.nchunk_ltr = (int)((n + L.ltr_rows - 1) / L.ltr_rows);
-  L.nred = (int)std::min<int64_t>(256, (n + 255) / 256);
+  // row-parallel reductions: about 128 rows per workgroup, at most 1024 workgroups
+  L.nred = (int)std::min<int64_t>(1024, (n + 127) / 128);
 
   const int64_t np = L.n_pad, tp = L.tp, k = rank;
   const int64_t kk = std::max<int64_t>(k, 1);

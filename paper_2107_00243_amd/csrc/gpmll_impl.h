@@ -91,7 +91,7 @@ struct Layout {
   int nchunk_ltr;       // row chunks of the L^T R reduction
   int64_t ltr_rows;     // rows per chunk of the L^T R reduction (multiple of 16)
   int nrb;              // row blocks of kRowBlock rows
-  int nred;             // blocks of the row-parallel reductions (<= 256)
+  int nred;             // blocks of the row-parallel reductions (<= 1024)
   // preconditioner block (offsets independent of the estimator options)
   size_t xs, mean, mean_part, L, diag, ispiv, piv, amax, C, Rc, Rinv, Cinv, logdetP, scal_small, flags, ltr_part;
   size_t freq;          // m x d spectral samples of the random Fourier feature preconditioner

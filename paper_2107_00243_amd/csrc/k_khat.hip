@@ -382,11 +382,8 @@ __global__ void k_stage_v_fp(const double* __restrict__ V, int64_t nrows, int ld
 }
 
 // W[i][c] = sum_s wpart[s][i][c] + sigma^2 V[i][c] (FP64, fixed order), rows < nrows,
-// columns < ncols; optionally per-block partial dots V[:,c].W[:,c].  Block: 64 rows x cb
-// columns (cb = the staged columns rounded up to 16, at most 256), grid
-// (ceil(nrows/64), ceil(ncols/cb)).  The partial dot of a block always sums the 16 row
-// groups {g, g+16, g+32, g+48} in group order, so it does not depend on cb: results are
-// the same however many columns are still active.
+// columns < ncols; optionally per-block partial dots V[:,c].W[:,c].  Block: 64 rows
+// x 64 columns (thread = column x 4 row lanes), grid (ceil(nrows/64), ceil(ncols/64)).
 template <typename T>
 __global__ __launch_bounds__(256) void k_khat_reduce(const T* __restrict__ wpart, int nsplit, int64_t n_pad, int tp,
                                                      const double* __restrict__ V, int ldv, double* __restrict__ W,
@@ -395,41 +392,32 @@ __global__ __launch_bounds__(256) void k_khat_reduce(const T* __restrict__ wpart
                                                      const int* __restrict__ nactive,
                                                      const uint32_t* __restrict__ colmax, double fac_s) {
   if (nactive != nullptr && *nactive == 0) return;
-  // cb consecutive threads take cb consecutive columns of one row, 256 / cb row lanes
-  // share the 16 row groups of the block
-  __shared__ double red[16 * 256];
-  const int cb = min(256, (ncols + 15) / 16 * 16);
-  const int nl = 256 / cb;
-  const int cl = threadIdx.x % cb, lane = threadIdx.x / cb;
+  __shared__ double red[4][64];
+  const int cl = threadIdx.x % 64, lane4 = threadIdx.x / 64;
   // staged column c carries source column src (results go back to that column)
-  const int c = blockIdx.y * cb + cl;
-  const int src = lane < nl ? staged_source(colmap, c, ncols) : -1;
+  const int c = blockIdx.y * 64 + cl;
+  const int src = staged_source(colmap, c, ncols);
   const int64_t r0 = (int64_t)blockIdx.x * 64;
+  double dot = 0.0;
   // FP16X3 partials carry the factors 2^15 / s (kernel values) and scale_c (column)
   const double fac = (colmax != nullptr && src >= 0) ? fac_s / (double)f16_col_scale(colmax[c]) : 1.0;
   if (src >= 0) {
-    for (int g = lane; g < 16; g += nl) {
-      double dot = 0.0;
-      for (int q = g; q < 64; q += 16) {
-        const int64_t r = r0 + q;
-        if (r >= nrows) break;
-        double w = 0.0;
-        for (int s = 0; s < nsplit; ++s) w += (double)wpart[((int64_t)s * n_pad + r) * tp + c];
-        const double v = V[r * ldv + src];
-        w = w * fac + s2 * v;
-        W[r * ldw + src] = w;
-        dot += v * w;
-      }
-      red[g * cb + cl] = dot;
+    for (int q = lane4; q < 64; q += 4) {
+      const int64_t r = r0 + q;
+      if (r >= nrows) break;
+      double w = 0.0;
+      for (int s = 0; s < nsplit; ++s) w += (double)wpart[((int64_t)s * n_pad + r) * tp + c];
+      const double v = V[r * ldv + src];
+      w = w * fac + s2 * v;
+      W[r * ldw + src] = w;
+      dot += v * w;
     }
   }
   if (dot_part == nullptr) return;
+  red[lane4][cl] = dot;
   __syncthreads();
-  if (lane == 0 && src >= 0) {
-    double s = 0.0;
-    for (int g = 0; g < 16; ++g) s += red[g * cb + cl];
-    dot_part[(int64_t)blockIdx.x * ldpart + src] = s;
-  }
+  if (lane4 == 0 && src >= 0)
+    dot_part[(int64_t)blockIdx.x * ldpart + src] = red[0][cl] + red[1][cl] + red[2][cl] + red[3][cl];
 }
 
 #endif  // part 0
@@ -1019,11 +1007,9 @@ hipError_t launch_khat_tiles_items(const Ctx& c, const Hyper& h, const ItemTable
 
 hipError_t launch_khat_reduce(const Ctx& c, const double* V, int ldv, double* W, int ldw, int ncols, const Hyper& h,
                               double* dot_part, const int* nact, const int* colmap, int ldpart) {
-  if (ncols <= 0) return hipSuccess;
   if (ldpart <= 0) ldpart = ncols;
   const Layout& L = *c.lay;
-  const int cb = std::min(256, (ncols + 15) / 16 * 16);  // columns per block, as in k_khat_reduce
-  const dim3 nb((unsigned)((L.n + 63) / 64), (unsigned)((ncols + cb - 1) / cb));
+  const dim3 nb((unsigned)((L.n + 63) / 64), (unsigned)((ncols + 63) / 64));
   const bool f16 = L.prec == GP_PREC_FP16X3;
   const uint32_t* cm = f16 ? c.at<uint32_t>(L.vscale) : nullptr;
   const double fac_s = f16 ? h.s / 32768.0 : 1.0;
