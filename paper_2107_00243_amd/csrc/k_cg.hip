@@ -110,6 +110,7 @@ __global__ void k_cg_update(double* __restrict__ X, double* __restrict__ R, cons
   double s = 0.0;
   if (rg < G && active[c]) {
     const double a = alpha[c];
+#pragma unroll 4
     for (int64_t r = r0 + rg; r < r1; r += G) {
       const int64_t e = r * tp + c;
       X[e] += a * P[e];
@@ -194,17 +195,18 @@ __global__ void k_swap_count(int* __restrict__ nactive, int* __restrict__ nactiv
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 
 // part[chunk][l][c] = sum over the chunk's rows i of L[l][i] R[i][c], l < kpad,
-// c < tp.  Workgroup (chunk, group of 4 blocks of 16 l); wave w owns l-block
-// 4 * blockIdx.y + w and every 16-column tile of R.
+// c < tp.  Workgroup (group of 4 blocks of 16 l, chunk); wave w owns l-block
+// 4 * blockIdx.x + w and every 16-column tile of R.  The l-groups of one chunk are
+// neighbours in launch order, so the chunk of R comes from HBM once.
 template <int NT>
 __global__ __launch_bounds__(256) void k_ltr_mfma(const double* __restrict__ L, const double* __restrict__ R,
                                                   int64_t n, int k, int kpad, int tp, int64_t rows,
                                                   double* __restrict__ part, const int* __restrict__ nactive) {
   if (nactive != nullptr && *nactive == 0) return;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int mb = blockIdx.y * 4 + wave;
+  const int mb = blockIdx.x * 4 + wave;
   if (mb * 16 >= kpad) return;
-  const int64_t i0 = (int64_t)blockIdx.x * rows, i1 = min(n, i0 + rows);
+  const int64_t i0 = (int64_t)blockIdx.y * rows, i1 = min(n, i0 + rows);
   const int m = lane & 15, kq = lane >> 4;
   const int l = mb * 16 + m;
   const double* Lc = L + (int64_t)min(l, k - 1) * n;
@@ -229,7 +231,7 @@ __global__ __launch_bounds__(256) void k_ltr_mfma(const double* __restrict__ L, 
 #pragma unroll
       for (int nb = 0; nb < NT; ++nb) acc[nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u], bv[u][nb], acc[nb], 0, 0, 0);
   }
-  double* out = part + ((int64_t)blockIdx.x * kpad + mb * 16) * tp;
+  double* out = part + ((int64_t)blockIdx.y * kpad + mb * 16) * tp;
 #pragma unroll
   for (int nb = 0; nb < NT; ++nb)
 #pragma unroll
@@ -268,6 +270,8 @@ __global__ void k_cinv_apply(const double* __restrict__ Cinv, const double* __re
   if (e >= k * tp) return;
   const int l = e / tp, c = e % tp;
   double s = 0.0;
+  // unrolled so that the loads of several terms are in flight together (same order)
+#pragma unroll 8
   for (int m = 0; m < k; ++m) s += Cinv[l * k + m] * T[m * tp + c];
   Y[e] = s;
 }
@@ -341,7 +345,7 @@ template <int NT>
 static void ltr_launch(const Ctx& c, const double* Rsrc, double* part, const int* nact) {
   const Layout& L = *c.lay;
   const int kpad = (L.k + 15) / 16 * 16;
-  hipLaunchKernelGGL((k_ltr_mfma<NT>), dim3(L.nchunk_ltr, (kpad / 16 + 3) / 4), dim3(256), 0, c.st, c.at<double>(L.L),
+  hipLaunchKernelGGL((k_ltr_mfma<NT>), dim3((kpad / 16 + 3) / 4, L.nchunk_ltr), dim3(256), 0, c.st, c.at<double>(L.L),
                      Rsrc, L.n, L.k, kpad, L.tp, L.ltr_rows, part, nact);
 }
 

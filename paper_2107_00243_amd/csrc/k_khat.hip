@@ -304,23 +304,24 @@ __global__ void k_stage_v_bf16(const double* __restrict__ V, int64_t nrows, int 
 // column maxima of |V| as float bit patterns (non-negative floats order like their
 // bits, so the integer maximum is exact and order-independent)
 __global__ void k_colmax(const double* __restrict__ V, int64_t nrows, int ldv, int ncols,
-                         const int* __restrict__ colmap, uint32_t* __restrict__ cm) {
-  __shared__ uint32_t red[256];
-  const int c = blockIdx.y;
+                         const int* __restrict__ colmap, uint32_t* __restrict__ cm, int64_t rows_per_block) {
+  // block: 64 staged columns x 4 row lanes over rows_per_block rows (each row's columns
+  // read together); blocks combine with atomicMax
+  __shared__ uint32_t red[4][64];
+  const int cl = threadIdx.x % 64, lane4 = threadIdx.x / 64;
+  const int c = blockIdx.y * 64 + cl;
   const int src = staged_source(colmap, c, ncols);
+  const int64_t r0 = (int64_t)blockIdx.x * rows_per_block, r1 = min(nrows, r0 + rows_per_block);
   uint32_t m = 0;
-  for (int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x; src >= 0 && r < nrows; r += (int64_t)gridDim.x * 256) {
-    const float v = fabsf((float)V[r * ldv + src]);
-    const uint32_t b = __builtin_bit_cast(uint32_t, v);
-    m = b > m ? b : m;
+  if (src >= 0) {
+    for (int64_t r = r0 + lane4; r < r1; r += 4) {
+      const uint32_t b = __builtin_bit_cast(uint32_t, fabsf((float)V[r * ldv + src]));
+      m = b > m ? b : m;
+    }
   }
-  red[threadIdx.x] = m;
+  red[lane4][cl] = m;
   __syncthreads();
-  for (int off = 128; off > 0; off >>= 1) {
-    if (threadIdx.x < off) red[threadIdx.x] = max(red[threadIdx.x], red[threadIdx.x + off]);
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) atomicMax(cm + c, red[0]);
+  if (lane4 == 0 && src >= 0) atomicMax(cm + c, max(max(red[0][cl], red[1][cl]), max(red[2][cl], red[3][cl])));
 }
 
 __global__ void k_zero_u32(uint32_t* p, int count) {
@@ -402,6 +403,7 @@ __global__ __launch_bounds__(256) void k_khat_reduce(const T* __restrict__ wpart
   // FP16X3 partials carry the factors 2^15 / s (kernel values) and scale_c (column)
   const double fac = (colmax != nullptr && src >= 0) ? fac_s / (double)f16_col_scale(colmax[c]) : 1.0;
   if (src >= 0) {
+#pragma unroll 4
     for (int q = lane4; q < 64; q += 4) {
       const int64_t r = r0 + q;
       if (r >= nrows) break;
@@ -945,8 +947,9 @@ hipError_t launch_stage_v(const Ctx& c, const double* V, int ldv, int ncols, con
   if (L.prec == GP_PREC_FP16X3) {
     uint32_t* cm = c.at<uint32_t>(L.vscale);
     hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(256), 0, c.st, cm, L.tp);
-    const unsigned gx = (unsigned)std::min<int64_t>(64, (L.n + 255) / 256);
-    hipLaunchKernelGGL(k_colmax, dim3(gx, (unsigned)ncols), dim3(256), 0, c.st, V, L.n, ldv, ncols, colmap, cm);
+    const int64_t rpb = 256;
+    hipLaunchKernelGGL(k_colmax, dim3((unsigned)((L.n + rpb - 1) / rpb), (unsigned)((ncols + 63) / 64)), dim3(256), 0,
+                       c.st, V, L.n, ldv, ncols, colmap, cm, rpb);
     const int64_t total = (L.n_pad / 32) * ntt * 64;
     hipLaunchKernelGGL(k_stage_v_f16, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, c.st, V, L.n, ldv, ncols,
                        colmap, L.n_pad, ntt, cm, c.at<u32x4>(L.vfrag));
