@@ -9,7 +9,7 @@ Typical use (device tensors X (n x d, FP64) and y (n,)):
 
     from paper_2107_00243_amd import binding as B
     prob = B.make_problem(X, y, "rbf", ard=True)          # or "matern32", "matern52", "ratquad:<alpha>"
-    opt = B.make_options("fp16x3", num_probes=64, max_iters=200, cg_tol=1e-6)  # or "bf16x3", "fp32", "fp64"
+    opt = B.make_options("bf16x3", num_probes=64, max_iters=200, cg_tol=1e-6)  # or "fp16x3", "fp32", "fp64"
     ws = B.alloc_workspace(B.gp_workspace_size(prob, opt, rank=100))
     logp = torch.zeros(1, dtype=torch.float64, device="cuda")
     grad = torch.zeros(len(theta), dtype=torch.float64, device="cuda")
