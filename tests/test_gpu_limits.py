@@ -1,6 +1,7 @@
 """The interface's limits and degenerate cases on the HIP path against the
-oracle: d = GP_MAX_D, ell = GP_MAX_PROBES and rank = GP_MAX_RANK together; a
-single point; rank 0 and full rank.  Marked gpu."""
+oracle: d = GP_MAX_D, ell = GP_MAX_PROBES and rank = GP_MAX_RANK together (FP64,
+BF16X3 and FP16X3 tiles); a single point (rank 0 and full rank in FP64, rank 0 in
+the split and FP32 tiles).  Marked gpu."""
 import sys
 
 import numpy as np
@@ -58,7 +59,8 @@ def max_case():
     return pr, ref
 
 
-@pytest.mark.parametrize("precision,lp_tol,g_tol", [("fp64", 1e-7, 1e-5), ("bf16x3", 1e-3, 1e-2)])
+@pytest.mark.parametrize("precision,lp_tol,g_tol", [("fp64", 1e-7, 1e-5), ("bf16x3", 1e-3, 1e-2),
+                                                    ("fp16x3", 1e-3, 1e-2)])
 def test_maximum_dimension_probes_and_rank_together(max_case, precision, lp_tol, g_tol):
     pr, ref = max_case
     say(f"[gpu] limits n=3000 d={B.MAX_D} ell={B.MAX_PROBES} rank={B.MAX_RANK} {precision}")
@@ -88,6 +90,23 @@ def test_a_single_point_gives_the_exact_likelihood(rank):
     if rank == 1:
         assert rel(lp, exact) < 1e-12
     assert st.iters_max <= 1
+
+
+@pytest.mark.parametrize("precision", ["bf16x3", "fp16x3", "fp32"])
+def test_a_single_point_in_split_and_single_precision_tiles(precision):
+    # n = 1 pads to a whole 256-row tile block of zero operands; the one kernel value is
+    # the exact diagonal s, so only the tile product's rounding separates the estimate
+    # from the FP64 oracle's
+    X = np.array([[0.3, -0.7]])
+    y = np.array([1.3])
+    theta = np.array([0.9, 1.1, 0.6, 0.2])
+    say(f"[gpu] single point, {precision} tiles")
+    lp, gr, st = run(synthgp.GPProblem("one_point", X, y, theta, "rbf", True, rank=0, num_probes=4, tol=1e-12,
+                                       max_iters=5, precision=precision), precision, 0, 4, 1e-12, 5)
+    ref = go.estimate_mll(X, y, theta, "rbf", True, 0, 4, 1e-12, 5, 1)
+    assert rel(lp, ref["logp"]) < 1e-4
+    assert relvec(gr, ref["grad"]) < 1e-3
+    assert st.iters_max <= 2
 
 
 def test_workspace_one_byte_short_is_rejected():
