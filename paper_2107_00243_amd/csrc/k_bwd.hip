@@ -607,33 +607,23 @@ __global__ __launch_bounds__(256) void k_gemm64(int64_t M, int N, int K, const d
 __global__ void k_pg_contract(const double* __restrict__ xs, const int32_t* __restrict__ piv,
                               const int* __restrict__ kpp, int64_t n, int k, const double* __restrict__ Omega,
                               const double* __restrict__ Psi, Hyper h, int mode, double* __restrict__ part) {
-  constexpr int QC = 64;  // pivot points staged in shared memory per pass
   __shared__ double red[256];
-  __shared__ double xq[QC * GP_MAX_D];
   const int kp = *kpp;
   const int d = h.d;
   const int64_t row = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  const bool live = row < n + kp;
   double acc[GP_MAX_D + 1];
   for (int j = 0; j <= d; ++j) acc[j] = 0.0;
-  double xp[GP_MAX_D];
-  if (live) {
+  if (row < n + kp) {
     const int64_t pi = row < n ? row : (int64_t)piv[row - n];
+    double xp[GP_MAX_D];
     for (int j = 0; j < d; ++j) xp[j] = xs[pi * d + j];
-  }
-  for (int q0 = 0; q0 < kp; q0 += QC) {
-    const int qn = min(QC, kp - q0);
-    __syncthreads();
-    for (int e = threadIdx.x; e < qn * d; e += 256) xq[e] = xs[(int64_t)piv[q0 + e / d] * d + e % d];
-    __syncthreads();
-    if (!live) continue;
-    for (int qq = 0; qq < qn; ++qq) {
-      const int q = q0 + qq;
+    for (int q = 0; q < kp; ++q) {
       const double w = row < n ? Omega[(int64_t)q * n + row] : Psi[(row - n) * k + q];
+      const int64_t sq = piv[q];
       double r2 = 0.0;
       double df2[GP_MAX_D];
       for (int j = 0; j < d; ++j) {
-        const double df = xp[j] - xq[qq * d + j];
+        const double df = xp[j] - xs[sq * d + j];
         df2[j] = df * df;
         r2 += df2[j];
       }
@@ -644,9 +634,8 @@ __global__ void k_pg_contract(const double* __restrict__ xs, const int32_t* __re
         for (int j = 0; j < d; ++j) acc[j] += wg * df2[j];
       acc[d] += w * kap;
     }
-  }
-  if (live)
     for (int j = 0; j < d; ++j) acc[j] *= h.inv_ls[j];
+  }
   for (int j = 0; j <= d; ++j) {
     red[threadIdx.x] = acc[j];
     __syncthreads();
