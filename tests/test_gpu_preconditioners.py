@@ -106,7 +106,7 @@ def test_rff_features_and_logdet_match_oracle(name, n, d, kernel, ard, rank, s2)
 
 
 @pytest.mark.parametrize("precision,lp_tol,g_tol", [("fp64", 1e-7, 1e-5), ("bf16x3", 1e-3, 1e-2),
-                                                     ("fp32", 1e-3, 1e-2)])
+                                                     ("fp16x3", 1e-3, 1e-2), ("fp32", 1e-3, 1e-2)])
 @pytest.mark.parametrize("name,n,d,kernel,ard,rank,s2", CASES)
 def test_rff_estimator_matches_oracle(name, n, d, kernel, ard, rank, s2, precision, lp_tol, g_tol):
     pr, W = _case(n, d, kernel, ard, rank, s2, seed=32)
@@ -209,7 +209,7 @@ def test_nystrom_factor_matches_oracle(name, n, d, kernel, ard, rank, s2):
 
 
 @pytest.mark.parametrize("precision,lp_tol,g_tol", [("fp64", 1e-7, 1e-5), ("bf16x3", 1e-3, 1e-2),
-                                                     ("fp32", 1e-3, 1e-2)])
+                                                     ("fp16x3", 1e-3, 1e-2), ("fp32", 1e-3, 1e-2)])
 @pytest.mark.parametrize("name,n,d,kernel,ard,rank,s2", NYS_CASES)
 def test_nystrom_estimator_matches_oracle(name, n, d, kernel, ard, rank, s2, precision, lp_tol, g_tol):
     pr, S = _nys_case(n, d, kernel, ard, rank, s2)
@@ -323,7 +323,8 @@ def test_qff_features_match_oracle(name, n, d, ard, q, s2, ls):
     assert rel(out["logdet_P"], go.Preconditioner(Zr, pr.theta[-1]).logdet) < 1e-11
 
 
-@pytest.mark.parametrize("precision,lp_tol,g_tol", [("fp64", 1e-7, 1e-5), ("bf16x3", 1e-3, 1e-2)])
+@pytest.mark.parametrize("precision,lp_tol,g_tol", [("fp64", 1e-7, 1e-5), ("bf16x3", 1e-3, 1e-2),
+                                                     ("fp16x3", 1e-3, 1e-2)])
 @pytest.mark.parametrize("name,n,d,ard,q,s2,ls", QFF_CASES)
 def test_qff_estimator_matches_oracle(name, n, d, ard, q, s2, ls, precision, lp_tol, g_tol):
     pr = _qff_case(n, d, ard, q, s2, ls)

@@ -56,7 +56,8 @@ CASES = [
 
 
 @pytest.mark.parametrize("kernel,ard,n,d", CASES)
-@pytest.mark.parametrize("precision,mtol,vtol", [("fp64", 1e-8, 1e-8), ("fp32", 1e-4, 1e-4), ("bf16x3", 1e-3, 1e-3)])
+@pytest.mark.parametrize("precision,mtol,vtol", [("fp64", 1e-8, 1e-8), ("fp32", 1e-4, 1e-4), ("bf16x3", 1e-3, 1e-3),
+                                                 ("fp16x3", 1e-3, 1e-3)])
 def test_predict_matches_the_dense_posterior(kernel, ard, n, d, precision, mtol, vtol):
     pr = synthgp.random_problem(n, d, kernel, ard=ard, seed=60 + d, ls_range=(0.4, 1.5), sigma2=0.05,
                                 dist="normal")
