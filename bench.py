@@ -369,6 +369,7 @@ def main():
             "value": f64["evals_per_s"], "ms_per_step": f64["ms_per_step"], "iters_max": f64["iters_max"],
             "tile_ms": f64["tile_ms"], "tile_tflops": tile_flops(n, d, t) / (f64["tile_ms"] * 1e-3) / 1e12,
             "tile_frac_fp64_peak": tile_flops(n, d, t) / (f64["tile_ms"] * 1e-3) / 1e12 / PEAK_FP64_TFLOPS,
+            "ms_per_cg_iteration": f64["ms_per_step"] / max(1, f64["iters_max"]),
         }
     roofline = tile_roofline(n, d, t, bf, "bf16x3")
     pred = None
@@ -413,10 +414,17 @@ def main():
         "cpu_baseline": cpu,
         "fp64_gpu": out_fp64,
         "speedup_vs_fp64_gpu": (bf["evals_per_s"] / out_fp64["value"]) if out_fp64 else None,
+        # the same comparison at equal iteration count: evaluation time per CG iteration
+        # (the longest column's count), which also carries the fixed per-evaluation work
+        "ms_per_cg_iteration": bf["ms_per_step"] / max(1, bf["iters_max"]),
+        "speedup_vs_fp64_gpu_per_iteration": ((out_fp64["ms_per_cg_iteration"]
+                                               / (bf["ms_per_step"] / max(1, bf["iters_max"])))
+                                              if out_fp64 else None),
         "fp16x3_gpu": {"value": h16["evals_per_s"], "ms_per_step": h16["ms_per_step"],
                        "iters_max": h16["iters_max"], "iters_mean": h16["iters_mean"], "tile_ms": h16["tile_ms"],
                        "tile_tflops": tile_flops(n, d, t) / (h16["tile_ms"] * 1e-3) / 1e12,
                        "speedup_vs_fp64_gpu": (h16["evals_per_s"] / out_fp64["value"]) if out_fp64 else None,
+                       "ms_per_cg_iteration": h16["ms_per_step"] / max(1, h16["iters_max"]),
                        "roofline": tile_roofline(n, d, t, h16, "fp16x3")},
         "batched_rbf_64": batched,
         "preconditioners_bf16x3": precs,
