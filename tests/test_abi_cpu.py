@@ -80,6 +80,50 @@ int main(void) {
             assert ctypes.sizeof(types[key]) == int(val), key
 
 
+def test_a_plain_c_program_links_and_calls_the_library(tmp_path, lib):
+    # the boundary needs nothing but the header and the shared library: a C program
+    # linked against them sizes the workspace of the n = 100,000 bench shape and gets
+    # the argument errors back, without a GPU (no call here reaches the device)
+    prog = tmp_path / "consumer.c"
+    prog.write_text(r"""
+#define __HIP_PLATFORM_AMD__ 1
+#include <stdio.h>
+#include "gpmll.h"
+int main(void) {
+  gp_problem prob = {(const double*)0x1000, (const double*)0x2000, 100000, 16, GP_KERNEL_RBF, 1, 0.0};
+  gp_options opt = {GP_PREC_BF16X3, 64, 200, 1e-6, 1, 0, 1, 0};
+  size_t bytes = 0;
+  int st = gp_workspace_size(&prob, &opt, 100, &bytes);
+  printf("size %d %zu\n", st, bytes);
+  prob.d = GP_MAX_D + 1;
+  printf("bad_d %d\n", gp_workspace_size(&prob, &opt, 100, &bytes));
+  prob.d = 16;
+  double theta[18];
+  for (int j = 0; j < 18; ++j) theta[j] = 1.0;
+  printf("null_ws %d\n", gp_mll_grad(&prob, theta, &opt, 100, NULL, NULL, 0, NULL, NULL, NULL, NULL));
+  printf("msg %s\n", gp_strerror(GP_EINVAL));
+  return 0;
+}
+""")
+    exe = tmp_path / "consumer"
+    libdir = os.path.dirname(B.LIB_PATH)
+    r = subprocess.run(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), "-I", "/opt/rocm/include", str(prog),
+                        "-o", str(exe), "-L", libdir, "-l:" + os.path.basename(B.LIB_PATH),
+                        "-Wl,-rpath," + libdir, "-L/opt/rocm/lib", "-lamdhip64"],
+                       stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
+    assert r.returncode == 0, r.stdout
+    out = subprocess.run([str(exe)], stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True, timeout=60)
+    assert out.returncode == 0, out.stdout
+    got = dict(l.split(" ", 1) for l in out.stdout.splitlines())
+    st, size = got["size"].split()
+    prob = B.gp_problem(0x1000, 0x2000, 100000, 16, 0, 1)
+    opt = B.make_options("bf16x3", 64, 200, 1e-6, 1, 0, 1)
+    assert int(st) == 0 and int(size) == B.gp_workspace_size(prob, opt, 100)
+    assert int(got["bad_d"]) == B.GP_EINVAL
+    assert int(got["null_ws"]) == B.GP_EINVAL
+    assert got["msg"].strip()
+
+
 def _fake_problem(n=100, d=3, kernel=0, ard=1):
     return B.gp_problem(0x1000, 0x2000, n, d, kernel, ard)
 
