@@ -81,6 +81,7 @@ CASES = [
     ("rbf_ard_2d", 1500, 2, "rbf", True, 64, 0.05),       # 138 (quadrature path)
     ("matern32_ard_6d", 1100, 6, "matern32", True, 24, 0.5),  # 175
     ("matern52_iso_3d", 900, 3, "matern52", False, 10, 0.5),  # 116
+    ("ratquad_ard_2d", 1200, 2, "ratquad:1.5", True, 64, 0.2),  # 47 (Gamma-mixture frequencies)
 ]
 
 
@@ -155,6 +156,7 @@ NYS_CASES = [
     ("rbf_ard_4d", 1500, 4, "rbf", True, 40, 0.02),            # 208 (quadrature path)
     ("matern32_ard_6d", 1100, 6, "matern32", True, 24, 0.1),   # 48
     ("matern52_iso_3d", 900, 3, "matern52", False, 16, 0.05),  # 139
+    ("ratquad_ard_3d", 1000, 3, "ratquad:1.5", True, 20, 0.2),  # 59
 ]
 
 
