@@ -383,8 +383,12 @@ __global__ void k_stage_v_fp(const double* __restrict__ V, int64_t nrows, int ld
 }
 
 // W[i][c] = sum_s wpart[s][i][c] + sigma^2 V[i][c] (FP64, fixed order), rows < nrows,
-// columns < ncols; optionally per-block partial dots V[:,c].W[:,c].  Block: 64 rows
-// x 64 columns (thread = column x 4 row lanes), grid (ceil(nrows/64), ceil(ncols/64)).
+// columns < ncols; optionally per-block partial dots V[:,c].W[:,c].  Block: 64 rows x
+// kRedCols columns (thread = column x 3 row lanes; 80 columns hold the 65 of y and 64
+// probes in one block), grid (ceil(nrows/64), ceil(ncols/kRedCols)).  The block shape
+// is fixed, so a column's partial dot has the same summation order however many
+// columns are active.
+constexpr int kRedCols = 80;
 template <typename T>
 __global__ __launch_bounds__(256) void k_khat_reduce(const T* __restrict__ wpart, int nsplit, int64_t n_pad, int tp,
                                                      const double* __restrict__ V, int ldv, double* __restrict__ W,
@@ -393,18 +397,18 @@ __global__ __launch_bounds__(256) void k_khat_reduce(const T* __restrict__ wpart
                                                      const int* __restrict__ nactive,
                                                      const uint32_t* __restrict__ colmax, double fac_s) {
   if (nactive != nullptr && *nactive == 0) return;
-  __shared__ double red[4][64];
-  const int cl = threadIdx.x % 64, lane4 = threadIdx.x / 64;
+  __shared__ double red[3][kRedCols];
+  const int cl = threadIdx.x % kRedCols, lane = threadIdx.x / kRedCols;  // lane 3: the 16 spare threads
   // staged column c carries source column src (results go back to that column)
-  const int c = blockIdx.y * 64 + cl;
-  const int src = staged_source(colmap, c, ncols);
+  const int c = blockIdx.y * kRedCols + cl;
+  const int src = lane < 3 ? staged_source(colmap, c, ncols) : -1;
   const int64_t r0 = (int64_t)blockIdx.x * 64;
   double dot = 0.0;
   // FP16X3 partials carry the factors 2^15 / s (kernel values) and scale_c (column)
   const double fac = (colmax != nullptr && src >= 0) ? fac_s / (double)f16_col_scale(colmax[c]) : 1.0;
   if (src >= 0) {
 #pragma unroll 4
-    for (int q = lane4; q < 64; q += 4) {
+    for (int q = lane; q < 64; q += 3) {
       const int64_t r = r0 + q;
       if (r >= nrows) break;
       double w = 0.0;
@@ -416,10 +420,9 @@ __global__ __launch_bounds__(256) void k_khat_reduce(const T* __restrict__ wpart
     }
   }
   if (dot_part == nullptr) return;
-  red[lane4][cl] = dot;
+  if (lane < 3) red[lane][cl] = dot;
   __syncthreads();
-  if (lane4 == 0 && src >= 0)
-    dot_part[(int64_t)blockIdx.x * ldpart + src] = red[0][cl] + red[1][cl] + red[2][cl] + red[3][cl];
+  if (lane == 0 && src >= 0) dot_part[(int64_t)blockIdx.x * ldpart + src] = red[0][cl] + red[1][cl] + red[2][cl];
 }
 
 #endif  // part 0
@@ -1012,7 +1015,7 @@ hipError_t launch_khat_reduce(const Ctx& c, const double* V, int ldv, double* W,
                               double* dot_part, const int* nact, const int* colmap, int ldpart) {
   if (ldpart <= 0) ldpart = ncols;
   const Layout& L = *c.lay;
-  const dim3 nb((unsigned)((L.n + 63) / 64), (unsigned)((ncols + 63) / 64));
+  const dim3 nb((unsigned)((L.n + 63) / 64), (unsigned)((ncols + kRedCols - 1) / kRedCols));
   const bool f16 = L.prec == GP_PREC_FP16X3;
   const uint32_t* cm = f16 ? c.at<uint32_t>(L.vscale) : nullptr;
   const double fac_s = f16 ? h.s / 32768.0 : 1.0;
