@@ -163,13 +163,22 @@ __global__ void k_cg_beta(const double* __restrict__ part_rz, int nblk, int tp, 
 }
 
 // p = z + beta p (active columns)
+// p = z + beta p on active columns; thread = column x 256 / tp row lanes (tp <= 256),
+// rows_per_block rows per workgroup, as in k_cg_update
 __global__ void k_cg_p(double* __restrict__ P, const double* __restrict__ Z, const double* __restrict__ beta,
-                       const int* __restrict__ active, int64_t n, int tp, const int* __restrict__ nactive) {
+                       const int* __restrict__ active, int64_t n, int tp, int64_t rows_per_block,
+                       const int* __restrict__ nactive) {
   if (*nactive == 0) return;
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= n * tp) return;
-  const int c = (int)(e % tp);
-  if (active[c]) P[e] = Z[e] + beta[c] * P[e];
+  const int G = 256 / tp;
+  const int c = threadIdx.x % tp, rg = threadIdx.x / tp;
+  if (rg >= G || !active[c]) return;
+  const double b = beta[c];
+  const int64_t r0 = (int64_t)blockIdx.x * rows_per_block, r1 = min(n, r0 + rows_per_block);
+#pragma unroll 4
+  for (int64_t r = r0 + rg; r < r1; r += G) {
+    const int64_t e = r * tp + c;
+    P[e] = Z[e] + b * P[e];
+  }
 }
 
 // colmap = active columns in increasing order, then -1 (one lane: tp <= 256)
@@ -437,8 +446,8 @@ hipError_t launch_cg_after_product(const Ctx& c, const Hyper& h, int it, double 
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_cg_beta, dim3(L.tp), dim3(256), 0, c.st, rzpart, nzblk, L.tp, it, L.max_iters,
                      c.at<double>(L.rho), c.at<int>(L.active), beta, c.at<double>(L.blog), nact);
-  hipLaunchKernelGGL(k_cg_p, dim3(nb_for(L.n * L.tp, 256)), dim3(256), 0, c.st, c.at<double>(L.Pd),
-                     c.at<double>(L.W), beta, c.at<int>(L.active), L.n, L.tp, nact);
+  hipLaunchKernelGGL(k_cg_p, dim3(L.nred), dim3(256), 0, c.st, c.at<double>(L.Pd), c.at<double>(L.W), beta,
+                     c.at<int>(L.active), L.n, L.tp, rpb, nact);
   hipLaunchKernelGGL(k_swap_count, dim3(1), dim3(1), 0, c.st, nact, nact_next);
   return hipGetLastError();
 }
