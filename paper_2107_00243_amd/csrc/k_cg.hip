@@ -204,33 +204,48 @@ __global__ void k_swap_count(int* __restrict__ nactive, int* __restrict__ nactiv
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 
 // part[chunk][l][c] = sum over the chunk's rows i of L[l][i] R[i][c], l < kpad,
-// c < tp.  Workgroup (group of 4 blocks of 16 l, chunk); wave w owns l-block
-// 4 * blockIdx.x + w and every 16-column tile of R.  The l-groups of one chunk are
-// neighbours in launch order, so the chunk of R comes from HBM once.
+// c < tp.  Workgroup (group of 4 waves, chunk); a wave owns LB consecutive blocks of 16
+// l (LB = 2 up to 8 column tiles, so one R operand feeds two l-blocks' MFMAs) and every
+// 16-column tile of R.  The l-groups of one chunk are neighbours in launch order, so
+// the chunk of R comes from HBM once.
+template <int NT>
+constexpr int ltr_lblocks() { return NT <= 8 ? 2 : 1; }
+
 template <int NT>
 __global__ __launch_bounds__(256) void k_ltr_mfma(const double* __restrict__ L, const double* __restrict__ R,
                                                   int64_t n, int k, int kpad, int tp, int64_t rows,
                                                   double* __restrict__ part, const int* __restrict__ nactive) {
   if (nactive != nullptr && *nactive == 0) return;
+  constexpr int LB = ltr_lblocks<NT>();
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int mb = blockIdx.x * 4 + wave;
-  if (mb * 16 >= kpad) return;
+  const int mb0 = (blockIdx.x * 4 + wave) * LB;
+  if (mb0 * 16 >= kpad) return;
   const int64_t i0 = (int64_t)blockIdx.y * rows, i1 = min(n, i0 + rows);
   const int m = lane & 15, kq = lane >> 4;
-  const int l = mb * 16 + m;
-  const double* Lc = L + (int64_t)min(l, k - 1) * n;
-  f64x4 acc[NT];
+  bool on[LB];
+  int lr[LB];
+  const double* Lc[LB];
 #pragma unroll
-  for (int nb = 0; nb < NT; ++nb) acc[nb] = f64x4{0.0, 0.0, 0.0, 0.0};
+  for (int b = 0; b < LB; ++b) {
+    on[b] = (mb0 + b) * 16 < kpad;
+    lr[b] = (mb0 + b) * 16 + m;
+    Lc[b] = L + (int64_t)min(lr[b], k - 1) * n;
+  }
+  f64x4 acc[LB][NT];
+#pragma unroll
+  for (int b = 0; b < LB; ++b)
+#pragma unroll
+    for (int nb = 0; nb < NT; ++nb) acc[b][nb] = f64x4{0.0, 0.0, 0.0, 0.0};
   // four K-steps of operands are loaded before their MFMAs (loads in flight together)
   constexpr int U = 4;
   for (int64_t i = i0; i < i1; i += 4 * U) {
-    double av[U], bv[U][NT];
+    double av[LB][U], bv[U][NT];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int64_t ir = i + 4 * u + kq;
       const bool in = ir < i1;
-      av[u] = (in && l < k) ? Lc[ir] : 0.0;
+#pragma unroll
+      for (int b = 0; b < LB; ++b) av[b][u] = (in && lr[b] < k) ? Lc[b][ir] : 0.0;
       const double* Rr = R + (in ? ir : i0) * tp + m;
 #pragma unroll
       for (int nb = 0; nb < NT; ++nb) bv[u][nb] = in ? Rr[nb * 16] : 0.0;
@@ -238,13 +253,21 @@ __global__ __launch_bounds__(256) void k_ltr_mfma(const double* __restrict__ L, 
 #pragma unroll
     for (int u = 0; u < U; ++u)
 #pragma unroll
-      for (int nb = 0; nb < NT; ++nb) acc[nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u], bv[u][nb], acc[nb], 0, 0, 0);
+      for (int b = 0; b < LB; ++b)
+        if (on[b])
+#pragma unroll
+          for (int nb = 0; nb < NT; ++nb)
+            acc[b][nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[b][u], bv[u][nb], acc[b][nb], 0, 0, 0);
   }
-  double* out = part + ((int64_t)blockIdx.y * kpad + mb * 16) * tp;
 #pragma unroll
-  for (int nb = 0; nb < NT; ++nb)
+  for (int b = 0; b < LB; ++b) {
+    if (!on[b]) continue;
+    double* out = part + ((int64_t)blockIdx.y * kpad + (mb0 + b) * 16) * tp;
 #pragma unroll
-    for (int v = 0; v < 4; ++v) out[(int64_t)(kq + 4 * v) * tp + nb * 16 + m] = acc[nb][v];
+    for (int nb = 0; nb < NT; ++nb)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) out[(int64_t)(kq + 4 * v) * tp + nb * 16 + m] = acc[b][nb][v];
+  }
 }
 
 // T[l][c] = sum over chunks of part, l < k: 64 entries per workgroup, its 16
@@ -354,8 +377,9 @@ template <int NT>
 static void ltr_launch(const Ctx& c, const double* Rsrc, double* part, const int* nact) {
   const Layout& L = *c.lay;
   const int kpad = (L.k + 15) / 16 * 16;
-  hipLaunchKernelGGL((k_ltr_mfma<NT>), dim3((kpad / 16 + 3) / 4, L.nchunk_ltr), dim3(256), 0, c.st, c.at<double>(L.L),
-                     Rsrc, L.n, L.k, kpad, L.tp, L.ltr_rows, part, nact);
+  constexpr int wl = 4 * ltr_lblocks<NT>();  // l-blocks per workgroup
+  hipLaunchKernelGGL((k_ltr_mfma<NT>), dim3((kpad / 16 + wl - 1) / wl, L.nchunk_ltr), dim3(256), 0, c.st,
+                     c.at<double>(L.L), Rsrc, L.n, L.k, kpad, L.tp, L.ltr_rows, part, nact);
 }
 
 template <int NT>
