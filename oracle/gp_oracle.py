@@ -176,31 +176,112 @@ def _row_block(n, d, budget=4e7):
     return max(1, int(budget // max(1, n * d)))
 
 
-def khat_matvec(X, theta, kind, ard, V, rows=None):
-    """K_hat[rows, :] @ V with K_hat rows built block by block (matrix-free for large n)."""
+def _over_blocks(fn, starts, workers):
+    """fn(start) for every block start, in order; with workers > 1 the blocks run
+    on a thread pool (NumPy releases the interpreter lock in its array loops), and
+    the results still come back in block order."""
+    if workers <= 1:
+        return [fn(lo) for lo in starts]
+    from concurrent.futures import ThreadPoolExecutor
+    with ThreadPoolExecutor(max_workers=workers) as ex:
+        return list(ex.map(fn, starts))
+
+
+_NATIVE = None
+
+
+def _native():
+    """The plain-C matrix-free products (oracle/khat_native.c), compiled with gcc
+    next to their source on first use (or when the source is newer)."""
+    global _NATIVE
+    if _NATIVE is None:
+        import ctypes
+        import os
+        here = os.path.dirname(os.path.abspath(__file__))
+        src = os.path.join(here, "khat_native.c")
+        lib = os.path.join(here, "liboracle_khat.so")
+        if not os.path.exists(lib) or os.path.getmtime(lib) < os.path.getmtime(src):
+            build_native(src, lib)
+        h = ctypes.CDLL(lib)
+        P = ctypes.POINTER(ctypes.c_double)
+        h.oracle_khat_matvec.argtypes = [ctypes.c_int64, ctypes.c_int32, P, P, ctypes.c_double, ctypes.c_double,
+                                         ctypes.c_int32, ctypes.c_double, ctypes.c_int32, P, ctypes.c_int64,
+                                         ctypes.POINTER(ctypes.c_int64), P]
+        h.oracle_dkhat_lowrank.argtypes = [ctypes.c_int64, ctypes.c_int32, P, P, ctypes.c_double, ctypes.c_int32,
+                                           ctypes.c_double, ctypes.c_int32, P, P, P]
+        _NATIVE = h
+    return _NATIVE
+
+
+def build_native(src=None, lib=None):
+    import os
+    import subprocess
+    here = os.path.dirname(os.path.abspath(__file__))
+    src = src or os.path.join(here, "khat_native.c")
+    lib = lib or os.path.join(here, "liboracle_khat.so")
+    tmp = lib + ".tmp"
+    subprocess.run(["gcc", "-O3", "-fopenmp", "-shared", "-fPIC", src, "-o", tmp, "-lm"], check=True)
+    os.replace(tmp, lib)
+    return lib
+
+
+def _native_kind(kind):
+    alpha = ratquad_shape(kind)
+    if alpha is not None:
+        return 3, alpha
+    return KIND[kind], 0.0
+
+
+def _dptr(a):
+    import ctypes
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def khat_matvec(X, theta, kind, ard, V, rows=None, workers=1, native=False):
+    """K_hat[rows, :] @ V with K_hat rows built block by block (matrix-free for large n).
+    workers: threads over row blocks (each output row is computed the same way).
+    native: the same product by the plain-C loops of khat_native.c."""
     n, d = X.shape
     ls, s, s2 = split_theta(theta, d, ard)
     V = np.asarray(V, dtype=np.float64)
     rows = np.arange(n) if rows is None else np.asarray(rows)
+    if native:
+        import ctypes
+        Xc = np.ascontiguousarray(X, dtype=np.float64)
+        V2 = np.ascontiguousarray(V.reshape(n, -1))
+        rr = np.ascontiguousarray(rows, dtype=np.int64)
+        out = np.empty((rr.size, V2.shape[1]))
+        code, alpha = _native_kind(kind)
+        rc = _native().oracle_khat_matvec(n, d, _dptr(Xc), _dptr(ls), s, s2, code, alpha, V2.shape[1],
+                                          _dptr(V2), rr.size, rr.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                          _dptr(out))
+        if rc != 0:
+            raise ValueError("oracle_khat_matvec failed")
+        return out.reshape((rr.size,) + V.shape[1:])
     out = np.empty((rows.size,) + V.shape[1:])
     blk = _row_block(n, d)
-    for lo in range(0, rows.size, blk):
+
+    def block(lo):
         r = rows[lo:lo + blk]
         Kb = s * kappa(kind, sqdist(X[r], X, ls))
         out[lo:lo + blk] = Kb @ V
         out[lo:lo + blk] += s2 * V[r]
+
+    _over_blocks(block, range(0, rows.size, blk), workers)
     return out
 
 
-def dkhat_contract(X, theta, kind, ard, m_rows):
+def dkhat_contract(X, theta, kind, ard, m_rows, workers=1):
     """sum_pq M_pq dK_hat_pq / dtheta for every theta, with M given block-of-rows
-    at a time by m_rows(rows) -> (|rows|, n).  Order of the result follows theta."""
+    at a time by m_rows(rows) -> (|rows|, n).  Order of the result follows theta.
+    workers: threads over row blocks; the block sums are added in block order."""
     n, d = X.shape
     ls, s, s2 = split_theta(theta, d, ard)
     p = d if ard else 1
-    out = np.zeros(p + 2)
     blk = _row_block(n, d)
-    for lo in range(0, n, blk):
+
+    def block(lo):
+        part = np.zeros(p + 2)
         r = np.arange(lo, min(n, lo + blk))
         Dt = scaled_differences(X[r], X, ls)
         r2 = np.einsum("pqj,pqj->pq", Dt, Dt)
@@ -208,11 +289,39 @@ def dkhat_contract(X, theta, kind, ard, m_rows):
         W = s * gfun(kind, r2) * M
         per_dim = np.einsum("pq,pqj->j", W, Dt * Dt) / ls
         if ard:
-            out[:p] += per_dim
+            part[:p] = per_dim
         else:
-            out[0] += per_dim.sum()
-        out[p] += np.sum(kappa(kind, r2) * M)
-        out[p + 1] += np.sum(M[np.arange(r.size), r])
+            part[0] = per_dim.sum()
+        part[p] = np.sum(kappa(kind, r2) * M)
+        part[p + 1] = np.sum(M[np.arange(r.size), r])
+        return part
+
+    out = np.zeros(p + 2)
+    for part in _over_blocks(block, range(0, n, blk), workers):
+        out += part
+    return out
+
+
+def dkhat_contract_lowrank(X, theta, kind, ard, A, C):
+    """dkhat_contract for M = A C^T by the plain-C loops of khat_native.c."""
+    n, d = X.shape
+    ls, s, _ = split_theta(theta, d, ard)
+    p = d if ard else 1
+    Xc = np.ascontiguousarray(X, dtype=np.float64)
+    Ac = np.ascontiguousarray(A, dtype=np.float64)
+    Cc = np.ascontiguousarray(C, dtype=np.float64)
+    raw = np.zeros(d + 2)
+    code, alpha = _native_kind(kind)
+    rc = _native().oracle_dkhat_lowrank(n, d, _dptr(Xc), _dptr(ls), s, code, alpha, Ac.shape[1], _dptr(Ac),
+                                        _dptr(Cc), _dptr(raw))
+    if rc != 0:
+        raise ValueError("oracle_dkhat_lowrank failed")
+    out = np.zeros(p + 2)
+    if ard:
+        out[:p] = raw[:d]
+    else:
+        out[0] = raw[:d].sum()
+    out[p:] = raw[d:]
     return out
 
 
@@ -646,14 +755,16 @@ def _precond_terms_rff(X, theta, ard, freqs, Z, P, Cs, mode, weights=None):
 
 def estimate_mll(X, y, theta, kind, ard, rank, num_probes, tol, max_iters, seed,
                  grad=True, precond_grad=0, signs=None, dense=None, precond="pivchol", freqs=None,
-                 landmarks=None, qff_nodes=None, probe_mode=0):
+                 landmarks=None, qff_nodes=None, probe_mode=0, workers=1, native=False):
     """Preconditioned estimate of log p (Algorithm 1) and, if grad, of its
     derivative (Algorithm 2) under the readings in the module docstring.
 
     signs: optional (E, H) Rademacher arrays of shapes (n, ell), (rank, ell)
     replacing the SplitMix64 stream.  dense: force (True) or forbid (False) a
     dense K_hat; default dense for n <= 20000.  precond: "pivchol" (partial
-    pivoted Cholesky of the given rank) or "rff" (R-rff; freqs (rank/2, d))."""
+    pivoted Cholesky of the given rank) or "rff" (R-rff; freqs (rank/2, d)).
+    workers: threads over the row blocks of the matrix-free products; native: run
+    the matrix-free products by the plain-C loops of khat_native.c."""
     X = np.ascontiguousarray(X, dtype=np.float64)
     y = np.asarray(y, dtype=np.float64)
     n, d = X.shape
@@ -663,7 +774,7 @@ def estimate_mll(X, y, theta, kind, ard, rank, num_probes, tol, max_iters, seed,
     Kh = khat_dense(X, theta, kind, ard) if dense else None
 
     def matvec(V):
-        return Kh @ V if dense else khat_matvec(X, theta, kind, ard, V)
+        return Kh @ V if dense else khat_matvec(X, theta, kind, ard, V, workers=workers, native=native)
 
     # preconditioner (pivoted Cholesky or random Fourier features) and log det P
     weights = None
@@ -725,7 +836,10 @@ def estimate_mll(X, y, theta, kind, ard, rank, num_probes, tol, max_iters, seed,
     Cs = P.solve(B)
     A1 = Xs
     C1 = np.concatenate([0.5 * u[:, None], -Cs / (2.0 * ell)], axis=1)
-    bil = dkhat_contract(X, theta, kind, ard, lambda r: A1[r] @ C1.T)
+    if native and not dense:
+        bil = dkhat_contract_lowrank(X, theta, kind, ard, A1, C1)
+    else:
+        bil = dkhat_contract(X, theta, kind, ard, lambda r: A1[r] @ C1.T, workers=workers)
     if precond in ("rff", "qff"):
         tr, ctrl = _precond_terms_rff(X, theta, ard, freqs, L, P, Cs, precond_grad, weights)
     else:

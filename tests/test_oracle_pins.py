@@ -726,3 +726,82 @@ def test_sqrt_probes_have_rho0_n_and_unbiased_estimators():
     ex = go.exact_mll(X, y, theta, "rbf", True)
     assert abs(np.mean(vals) - ex["logdet"]) <= 1e-9 * abs(ex["logdet"])
     np.testing.assert_allclose(np.mean(grads, axis=0), ex["grad"], rtol=1e-8, atol=1e-9)
+
+
+# ------------------------------------------------ matrix-free (row-blocked) products
+
+def _sklearn_kernel(kind, ls, s):
+    from sklearn.gaussian_process.kernels import RBF, ConstantKernel, Matern
+    base = RBF(length_scale=ls, length_scale_bounds="fixed") if kind == "rbf" else \
+        Matern(length_scale=ls, length_scale_bounds="fixed", nu={"matern32": 1.5, "matern52": 2.5}[kind])
+    return ConstantKernel(s, constant_value_bounds="fixed") * base
+
+
+@pytest.mark.parametrize("native", [False, True])
+@pytest.mark.parametrize("kind", ["rbf", "matern32", "matern52"])
+def test_khat_matvec_matches_a_library_kernel_across_row_blocks(kind, native):
+    # n * d = 60,000 gives 666-row blocks: 4 full blocks and a ragged tail of 336 rows
+    n, d = 3000, 20
+    X, _, theta = _problem(n, d, kind, True, seed=81, sigma2=0.03, ls=(1.5, 4.0), dist="normal")
+    assert n % go._row_block(n, d) != 0 and n // go._row_block(n, d) >= 3
+    V = np.random.default_rng(82).standard_normal((n, 7))
+    ls, s, s2 = theta[:d], theta[d], theta[d + 1]
+    K = _sklearn_kernel(kind, ls, s)(X)
+    ref = K @ V + s2 * V
+    np.testing.assert_allclose(go.khat_matvec(X, theta, kind, True, V, native=native), ref, rtol=1e-11,
+                               atol=1e-11)
+    # a row subset, unsorted, with a repeat, crossing block edges
+    rows = np.random.default_rng(83).choice(n, size=1500, replace=True)
+    np.testing.assert_allclose(go.khat_matvec(X, theta, kind, True, V, rows=rows, native=native), ref[rows],
+                               rtol=1e-11, atol=1e-11)
+    # a single right-hand side as a vector, and a thread pool over the row blocks
+    np.testing.assert_allclose(go.khat_matvec(X, theta, kind, True, V[:, 0], native=native, workers=3),
+                               ref[:, 0], rtol=1e-11, atol=1e-11)
+
+
+def test_dkhat_contract_matches_dense_derivative_matrices_across_row_blocks():
+    n, d = 2100, 20
+    X, _, theta = _problem(n, d, "matern52", True, seed=84, sigma2=0.02, ls=(1.5, 4.0), dist="normal")
+    assert n // go._row_block(n, d) >= 2
+    rng = np.random.default_rng(85)
+    A, C = rng.standard_normal((n, 3)), rng.standard_normal((n, 3))
+    M = A @ C.T
+    got = go.dkhat_contract(X, theta, "matern52", True, lambda r: M[r])
+    got_threads = go.dkhat_contract(X, theta, "matern52", True, lambda r: M[r], workers=3)
+    got_native = go.dkhat_contract_lowrank(X, theta, "matern52", True, A, C)
+    # derivative matrices by central differences of a library kernel, one parameter at a time
+    ref = np.zeros(d + 2)
+    for j in range(d + 1):
+        h = 1e-5 * theta[j]
+        tp, tm = theta.copy(), theta.copy()
+        tp[j] += h
+        tm[j] -= h
+        Kp = _sklearn_kernel("matern52", tp[:d], tp[d])(X)
+        Km = _sklearn_kernel("matern52", tm[:d], tm[d])(X)
+        ref[j] = np.sum(M * (Kp - Km)) / (2.0 * h)
+    ref[d + 1] = np.trace(M)
+    for g in (got, got_threads, got_native):
+        np.testing.assert_allclose(g, ref, rtol=2e-7, atol=1e-6 * np.max(np.abs(ref)))
+    # isotropic form: one lengthscale, the sum of the per-dimension terms
+    th_iso = np.concatenate([[2.5], theta[d:]])
+    iso = go.dkhat_contract(X, th_iso, "matern52", False, lambda r: M[r])
+    np.testing.assert_allclose(go.dkhat_contract_lowrank(X, th_iso, "matern52", False, A, C), iso, rtol=1e-11)
+
+
+@pytest.mark.parametrize("kind,ard,native", [("rbf", True, False), ("matern32", False, False),
+                                             ("rbf", True, True), ("ratquad:2.0", True, True)])
+def test_matrix_free_estimator_equals_the_dense_one(kind, ard, native):
+    # the row-blocked path (used where a dense K_hat does not fit) must give the dense
+    # path's estimate: identical probes and pivots, the same numbers up to rounding
+    # order.  A fixed number of CG steps (tol 0, the paper's fixed m) keeps a stop
+    # decision near the tolerance from depending on that order.
+    n, d = 2300, 20
+    X, y, theta = _problem(n, d, kind, ard, seed=86, sigma2=0.05, ls=(1.5, 4.0), dist="normal")
+    assert n // go._row_block(n, d) >= 2 and n % go._row_block(n, d) != 0
+    a = go.estimate_mll(X, y, theta, kind, ard, 15, 6, 0.0, 12, 3, dense=True)
+    b = go.estimate_mll(X, y, theta, kind, ard, 15, 6, 0.0, 12, 3, dense=False, native=native)
+    np.testing.assert_array_equal(a["piv"], b["piv"])
+    np.testing.assert_array_equal(a["iters"], b["iters"])
+    assert abs(a["logp"] - b["logp"]) <= 1e-12 * abs(a["logp"])
+    np.testing.assert_allclose(b["gammas"], a["gammas"], rtol=1e-10, atol=1e-10 * np.max(np.abs(a["gammas"])))
+    np.testing.assert_allclose(b["grad"], a["grad"], rtol=1e-10, atol=1e-10 * np.max(np.abs(a["grad"])))
