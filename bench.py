@@ -61,8 +61,8 @@ TILE_COUNTERS = {
 def bf16_tile_source_hash():
     import hashlib
     src = open(os.path.join(ROOT, "paper_2107_00243_amd", "csrc", "k_khat.hip")).read()
-    a = src.index("#if GPMLL_KHAT_PART == 1\n")
-    b = src.index("#endif  // part 1", a)
+    a = src.index("#if GPMLL_KHAT_PART == 1 || GPMLL_KHAT_PART == 4\n")
+    b = src.index("#endif  // parts 1, 4", a)
     return hashlib.sha256(src[a:b].encode()).hexdigest()[:16]
 
 
@@ -298,8 +298,9 @@ def tile_roofline(n, d, t, run, precision):
     the kernel source and grid."""
     flops = tile_flops(n, d, t)
     achieved = flops / (run["tile_ms"] * 1e-3) / 1e12
-    name = {"fp16x3": "k_khat_bf16<RBF, 2, 5, 4, F16> (K_hat V tile, FP16x3)",
-            "bf16x3": "k_khat_bf16<RBF, 2, 5, 4, BF16> (K_hat V tile, BF16x3)"}[precision]
+    name = {"fp16x3": "k_khat_bf16<RBF, 2, 4, 4, F16, 1> (K_hat V tile, FP16x3: 4 MFMA column tiles + 1 VALU column)",
+            "bf16x3": "k_khat_bf16<RBF, 2, 4, 4, BF16, 1> (K_hat V tile, BF16x3: 4 MFMA column tiles + 1 VALU column)"
+            }[precision]
     roof = {"bound": "mfma", "achieved": achieved, "peak": PEAK_BF16_TFLOPS, "unit": "TFLOP/s",
             "frac": achieved / PEAK_BF16_TFLOPS, "traffic": None, "kernel": name,
             "launch_grid": run["tile_grid"], "algorithmic_flops_per_launch": flops, "avg_launch_ms": run["tile_ms"]}

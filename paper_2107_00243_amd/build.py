@@ -55,8 +55,9 @@ def build(verbose: bool = False, jobs: int | None = None, sanitize: bool = False
         units = []
         for src in srcs:
             if os.path.basename(src) == "k_khat.hip":
-                # one translation unit per tile precision, compiled in parallel
-                units += [(src, [f"-DGPMLL_KHAT_PART={p}"], f".part{p}") for p in range(4)]
+                # one translation unit per tile precision (part 0: staging and
+                # reduction; 1 BF16x3, 2 FP32, 3 FP64, 4 FP16x3), compiled in parallel
+                units += [(src, [f"-DGPMLL_KHAT_PART={p}"], f".part{p}") for p in range(5)]
             else:
                 units.append((src, [], ""))
         for src, defs, tag in units:

@@ -138,6 +138,7 @@ Layout make_layout(int64_t n, int d, int ard, int num_probes, int max_iters, int
   L.Pd = take(np * tp * 8);
   L.W = take(np * tp * 8);
   L.vfrag = take(np * tp * (split16 ? 4 : esz));
+  L.vx = take(split16 ? np * 4 : 0);
   L.vscale = take(2 * tp * 4);
   L.wpart = take((size_t)L.nsplit * np * std::max<int64_t>(tp * (prec == GP_PREC_FP64 ? 8 : 4), L.bow * bsz));
   L.rho = take(tp * 8);
@@ -213,14 +214,6 @@ static int check_device() {
 
 int gpmll::gpmll_check_device() { return check_device(); }
 void gpmll::gpmll_set_hip_error(int e) { g_last_hip = e; }
-
-// fewest compiled 16-column tiles holding nact columns (at most full)
-static int compact_ntt(int nact, int full) {
-  static const int ok[] = {1, 2, 3, 4, 5, 6, 8, 12, 16};
-  for (int v : ok)
-    if (16 * v >= nact && v <= full) return v;
-  return full;
-}
 
 static int check_problem(const gp_problem* prob) {
   if (!prob || !prob->X_dev || !prob->y_dev) return GP_EINVAL;
@@ -535,7 +528,6 @@ static int run_cg(const Ctx& c, const Hyper& h, const gp_options* opt) {
   const Layout& L = *c.lay;
   int* nact = c.at<int>(L.nactive);
   const int q = opt->sync_every;
-  const int full_ntt = L.tp / 16;
   int host_nact = L.t;
   for (int it = 0; it < opt->max_iters; ++it) {
     if (q > 0 && it > 0 && it % q == 0) {
@@ -543,16 +535,17 @@ static int run_cg(const Ctx& c, const Hyper& h, const gp_options* opt) {
       HIPCHK(hipStreamSynchronize(c.st));
       if (host_nact == 0) break;
     }
-    int ntt = full_ntt;
+    TilePlan plan = tile_plan(L, L.t);
     const int* cmap = nullptr;
     if (q > 0) {
-      ntt = compact_ntt(host_nact, full_ntt);
+      plan = tile_plan(L, host_nact);
       HIPCHK(launch_colmap(c));
       cmap = c.at<int>(L.colmap);
     }
-    HIPCHK(launch_stage_v(c, c.at<double>(L.Pd), L.tp, 16 * ntt, h, cmap, ntt));
-    HIPCHK(launch_khat_tiles(c, h, nact, ntt));
-    HIPCHK(launch_khat_reduce(c, c.at<double>(L.Pd), L.tp, c.at<double>(L.W), L.tp, 16 * ntt, h,
+    const int nstaged = 16 * plan.ntt + plan.xc;
+    HIPCHK(launch_stage_v(c, c.at<double>(L.Pd), L.tp, nstaged, h, cmap, plan));
+    HIPCHK(launch_khat_tiles(c, h, nact, plan));
+    HIPCHK(launch_khat_reduce(c, c.at<double>(L.Pd), L.tp, c.at<double>(L.W), L.tp, nstaged, h,
                               c.at<double>(L.dot_part), nact, cmap, L.tp));
     HIPCHK(launch_cg_after_product(c, h, it, opt->cg_tol));
   }
@@ -778,8 +771,9 @@ extern "C" int gp_khat_matvec(const gp_problem* prob, const double* theta_host, 
   gpmll_forget_forward(ws_dev);
   HIPCHK(launch_prep(c, prob->X_dev, h));
   HIPCHK(launch_stage_x(c, h));
-  HIPCHK(launch_stage_v(c, V_dev, num_rhs, num_rhs, h));
-  HIPCHK(launch_khat_tiles(c, h, nullptr));
+  const TilePlan plan = tile_plan(L, num_rhs);
+  HIPCHK(launch_stage_v(c, V_dev, num_rhs, num_rhs, h, nullptr, plan));
+  HIPCHK(launch_khat_tiles(c, h, nullptr, plan));
   HIPCHK(launch_khat_reduce(c, V_dev, num_rhs, W_dev, num_rhs, num_rhs, h, nullptr, nullptr));
   return GP_OK;
 }
@@ -815,13 +809,15 @@ extern "C" int gp_khat_profile(const gp_problem* prob, const double* theta_host,
   hipLaunchKernelGGL(k_fill_pattern, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, stream, c.at<double>(L.Pd),
                      L.n, L.n_pad, L.tp);
   HIPCHK(hipGetLastError());
-  HIPCHK(launch_stage_v(c, c.at<double>(L.Pd), L.tp, L.tp, h));
-  HIPCHK(launch_khat_tiles(c, h, nullptr));  // warm-up launch
+  // the product of a CG iteration with every column of [y | probes] active
+  const TilePlan plan = tile_plan(L, L.t);
+  HIPCHK(launch_stage_v(c, c.at<double>(L.Pd), L.tp, L.tp, h, nullptr, plan));
+  HIPCHK(launch_khat_tiles(c, h, nullptr, plan));  // warm-up launch
   hipEvent_t e0, e1;
   HIPCHK(hipEventCreate(&e0));
   HIPCHK(hipEventCreate(&e1));
   hipError_t err = hipEventRecord(e0, stream);
-  for (int r = 0; r < reps && err == hipSuccess; ++r) err = launch_khat_tiles(c, h, nullptr);
+  for (int r = 0; r < reps && err == hipSuccess; ++r) err = launch_khat_tiles(c, h, nullptr, plan);
   if (err == hipSuccess) err = hipEventRecord(e1, stream);
   if (err == hipSuccess) err = hipEventSynchronize(e1);
   float ms = 0.f;

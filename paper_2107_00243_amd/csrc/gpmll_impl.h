@@ -100,7 +100,7 @@ struct Layout {
   size_t precond_end;
   // estimator block
   size_t xfa, xfb, rowterm, colterm, H, Y, ltr, ltr_raw, ltr_part2;
-  size_t Xs, R, Z0, Pd, W, vfrag, vscale, wpart;
+  size_t Xs, R, Z0, Pd, W, vfrag, vx, vscale, wpart;
   size_t rho, rho0, bnorm, rnorm2, pw, active, nactive, iters, colmap, alog, blog;
   size_t dot_part, gamma, slq_work;
   size_t cprime, bxa, bxb, brt, bct, bafrag, bcfrag, bxaug, bwd_part, pg_small, omega, pg_part;
@@ -166,12 +166,21 @@ void gpmll_set_hip_error(int e);
 // Staging and tile launches shared with the batched path (the layout view there
 // describes the concatenation of all problems' padded row blocks).
 hipError_t launch_stage_x(const Ctx& c, const Hyper& h);
+// Staged right-hand side columns of one product: ntt 16-column tiles on the
+// matrix cores (-1: all of tp) and, for the split precisions, xc = 1 more column
+// (staged column 16 ntt) contracted on the vector ALU.
+struct TilePlan {
+  int ntt = -1;
+  int xc = 0;
+};
+// the plan for ncols staged columns (compiled tile counts only)
+TilePlan tile_plan(const Layout& L, int ncols);
 // V staging: ncols staged columns taken through colmap (null: the first ncols
-// columns), laid out for ntt 16-column tiles (0: all of tp).
+// columns), laid out as the plan's tiles (and extra column).
 hipError_t launch_stage_v(const Ctx& c, const double* V, int ldv, int ncols, const Hyper& h,
-                          const int* colmap = nullptr, int ntt = 0);
-// Tile launch over ntt 16-column tiles of staged V (0: all of tp).
-hipError_t launch_khat_tiles(const Ctx& c, const Hyper& h, const int* nact, int ntt = 0);
+                          const int* colmap = nullptr, TilePlan plan = TilePlan{});
+// Tile launch over the plan's staged columns.
+hipError_t launch_khat_tiles(const Ctx& c, const Hyper& h, const int* nact, TilePlan plan = TilePlan{});
 // W (columns through colmap, as staged) = s * sum of split partials + sigma^2 V,
 // and per-64-row-block partials of V.W at dot_part[block * ldpart + column].
 hipError_t launch_khat_reduce(const Ctx& c, const double* V, int ldv, double* W, int ldw, int ncols, const Hyper& h,

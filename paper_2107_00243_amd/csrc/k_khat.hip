@@ -139,6 +139,7 @@ struct TileArgs {
   int64_t cols_per_split;   // multiple of 32
   int tp;                   // leading dimension of the partial output
   int ntt;                  // 16-column tiles of right-hand sides staged for this launch
+  int xc;                   // split precisions: 1 = one more column on the vector ALU
   float s32;
   double s64;
   float alpha32;            // rational quadratic shape
@@ -366,6 +367,18 @@ __global__ void k_stage_v_f16(const double* __restrict__ V, int64_t nrows, int l
   vfrag[((jb * ntt + tt) * 2 + 1) * 64 + lane] = u32x4{l[0], l[1], l[2], l[3]};
 }
 
+// the extra column of the split-precision tiles: FP32 values of staged column
+// xcol (times its FP16 power-of-two scale when cm is given), zero past nrows
+__global__ void k_stage_vx(const double* __restrict__ V, int64_t nrows, int ldv, int xcol, int ncols,
+                           const int* __restrict__ colmap, int64_t n_pad, const uint32_t* __restrict__ cm,
+                           float* __restrict__ vx) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n_pad) return;
+  const int src = staged_source(colmap, xcol, ncols);
+  const double sc = cm != nullptr ? (double)f16_col_scale(cm[xcol]) : 1.0;
+  vx[j] = (j < nrows && src >= 0) ? (float)(sc * V[j * ldv + src]) : 0.0f;
+}
+
 // FP32/FP64: fragment (j16, tt, v) lane l holds row j16*16 + acc_row(l/16, v), column tt*16 + l%16
 template <typename T>
 __global__ void k_stage_v_fp(const double* __restrict__ V, int64_t nrows, int ldv, int ncols,
@@ -427,7 +440,7 @@ __global__ __launch_bounds__(256) void k_khat_reduce(const T* __restrict__ wpart
 
 #endif  // part 0
 
-#if GPMLL_KHAT_PART == 1
+#if GPMLL_KHAT_PART == 1 || GPMLL_KHAT_PART == 4
 // Software-pipelined BF16x3 tile kernel.  Per wave (RG row groups of 16 rows)
 // and per 32-column step j:
 //   distance MFMAs of step j+1          (16 MFMAs for d <= 16)
@@ -456,14 +469,21 @@ __device__ __forceinline__ void bf16_distance(const u32x4* __restrict__ A, const
                                                              0, 0);
 }
 
-// kernel map and hi/lo split of one step: dd -> (ph, pl); DIAG puts s on i == j
-template <int KIND, int RG, bool DIAG, bool F16>
+// kernel map and hi/lo split of one step: dd -> (ph, pl); DIAG puts s on i == j.
+// XC: the FP32 kernel values also meet the extra column (its 32 values follow the
+// column terms in the stage), yacc[rg][js] += sum_v kv[v] y[j(v)] in FP32.
+template <int KIND, int RG, bool DIAG, bool F16, int XC>
 __device__ __forceinline__ void bf16_map(const f32x4 (&dd)[RG][2], const float* __restrict__ ct, u32x4 (&ph)[RG],
-                                         u32x4 (&pl)[RG], int lane, int64_t row0, int64_t c, float s32,
-                                         float alpha) {
+                                         u32x4 (&pl)[RG], float (&yacc)[RG][2], int lane, int64_t row0, int64_t c,
+                                         float s32, float alpha) {
   const int g = lane >> 4, li = lane & 15;
   const f32x4 ct0 = *reinterpret_cast<const f32x4*>(ct + 4 * g);
   const f32x4 ct1 = *reinterpret_cast<const f32x4*>(ct + 16 + 4 * g);
+  f32x4 yv0{}, yv1{};
+  if constexpr (XC != 0) {
+    yv0 = *reinterpret_cast<const f32x4*>(ct + 32 + 4 * g);
+    yv1 = *reinterpret_cast<const f32x4*>(ct + 48 + 4 * g);
+  }
 #pragma unroll
   for (int rg = 0; rg < RG; ++rg)
 #pragma unroll
@@ -476,6 +496,11 @@ __device__ __forceinline__ void bf16_map(const f32x4 (&dd)[RG][2], const float* 
         const int64_t i = row0 + rg * 16 + li;
 #pragma unroll
         for (int v = 0; v < 4; ++v) kv[v] = (i == c + js * 16 + 4 * g + v) ? s32 : kv[v];
+      }
+      if constexpr (XC != 0) {
+        const f32x4 yv = js ? yv1 : yv0;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) yacc[rg][js] = fmaf(kv[v], yv[v], yacc[rg][js]);
       }
       uint32_t h0, l0, h1, l1;
       if constexpr (F16) {
@@ -502,9 +527,9 @@ __device__ __forceinline__ f32x4 mfma16(u32x4 a, u32x4 b, f32x4 c) {
                                                    0);
 }
 
-template <int NTT, int RG, bool F16>
+template <int NTT, int RG, bool F16, int NTA>
 __device__ __forceinline__ void bf16_tile_v(const u32x4* __restrict__ Vf, const u32x4 (&ph)[RG], const u32x4 (&pl)[RG],
-                                            f32x4 (&acc)[RG][NTT], int lane) {
+                                            f32x4 (&acc)[RG][NTA], int lane) {
   if constexpr (F16) {
 #pragma unroll
     for (int tt = 0; tt < NTT; ++tt) {
@@ -548,27 +573,36 @@ __device__ __forceinline__ void bf16_interleave_hint() {
 // Stage for one 32-column step, copied global -> LDS without registers
 // (global_load_lds_dwordx4: each wave instruction moves one contiguous 1 KB
 // chunk): [A fragments 2 x NKC | V fragments NTT x {hi, lo} | column terms].
-template <int NKC, int NTT>
+// The last chunk holds the 32 column terms (units 0-7) and, with XC, the 32 FP32
+// values of the extra right-hand side column (units 8-15).
+template <int NKC, int NTT, int XC>
 __device__ __forceinline__ void bf16_issue_stage(u32x4* dst, const u32x4* __restrict__ xfa,
                                                  const u32x4* __restrict__ vfrag, const float* __restrict__ colterm,
-                                                 int64_t c, int wave, int lane) {
+                                                 const float* __restrict__ vx, int64_t c, int wave, int lane) {
   constexpr int NCH = 2 * NKC + 2 * NTT + 1;
   for (int ch = wave; ch < NCH; ch += 4) {
     const u32x4* src;
     if (ch < 2 * NKC) src = xfa + (c / 16) * NKC * 64 + ch * 64 + lane;
     else if (ch < 2 * NKC + 2 * NTT) src = vfrag + (c / 32) * NTT * 128 + (ch - 2 * NKC) * 64 + lane;
+    else if (XC && lane >= 8 && lane < 16) src = reinterpret_cast<const u32x4*>(vx + c) + (lane - 8);
     else src = reinterpret_cast<const u32x4*>(colterm + c) + (lane < 8 ? lane : 7);
     __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void*)(dst + ch * 64), 16, 0, 0);
   }
 }
 
-template <int KIND, int NKC, int NTT, int RG, bool F16>
+// NTT 16-column tiles of right-hand sides on the matrix cores and, with XC = 1,
+// one more column (staged column 16 NTT) contracted on the vector ALU from the
+// FP32 kernel values: a column count of 16 m + 1 (y and 16 m probes) then needs
+// no mostly-empty sixteen-column tile.
+template <int KIND, int NKC, int NTT, int RG, bool F16, int XC>
 __global__ __launch_bounds__(256, 2) void k_khat_bf16(const u32x4* __restrict__ xfa, const u32x4* __restrict__ xfb,
                                                       const float* __restrict__ rowterm,
                                                       const float* __restrict__ colterm,
-                                                      const u32x4* __restrict__ vfrag, float* __restrict__ wpart,
-                                                      TileArgs a, const int* __restrict__ nactive) {
+                                                      const u32x4* __restrict__ vfrag, const float* __restrict__ vx,
+                                                      float* __restrict__ wpart, TileArgs a,
+                                                      const int* __restrict__ nactive) {
   if (nactive != nullptr && *nactive == 0) return;
+  constexpr int NTA = NTT > 0 ? NTT : 1;  // accumulator array extent
   constexpr int A_U = 2 * NKC * 64, V_U = NTT * 2 * 64, C_U = 64;
   constexpr int STAGE = A_U + V_U + C_U;
   __shared__ u32x4 lds[3][STAGE];
@@ -582,7 +616,8 @@ __global__ __launch_bounds__(256, 2) void k_khat_bf16(const u32x4* __restrict__ 
 
   u32x4 xbv[RG][NKC];
   f32x4 rt[RG];
-  f32x4 acc[RG][NTT];
+  f32x4 acc[RG][NTA];
+  float yacc[RG][2];
 #pragma unroll
   for (int rg = 0; rg < RG; ++rg) {
 #pragma unroll
@@ -590,13 +625,14 @@ __global__ __launch_bounds__(256, 2) void k_khat_bf16(const u32x4* __restrict__ 
     const float r = rowterm[row0 + rg * 16 + li];
     rt[rg] = f32x4{r, r, r, r};
 #pragma unroll
-    for (int tt = 0; tt < NTT; ++tt) acc[rg][tt] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int tt = 0; tt < NTA; ++tt) acc[rg][tt] = f32x4{0.f, 0.f, 0.f, 0.f};
+    yacc[rg][0] = yacc[rg][1] = 0.f;
   }
   auto is_diag = [&](int64_t c) { return (c + 32 > row0) && (c < row0 + 16 * RG); };
 
   // prologue: stages 0 and 1 in flight, P of step 0
-  bf16_issue_stage<NKC, NTT>(lds[0], xfa, vfrag, colterm, c_begin, wave, lane);
-  if (nsteps > 1) bf16_issue_stage<NKC, NTT>(lds[1], xfa, vfrag, colterm, c_begin + 32, wave, lane);
+  bf16_issue_stage<NKC, NTT, XC>(lds[0], xfa, vfrag, colterm, vx, c_begin, wave, lane);
+  if (nsteps > 1) bf16_issue_stage<NKC, NTT, XC>(lds[1], xfa, vfrag, colterm, vx, c_begin + 32, wave, lane);
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
   u32x4 ph[RG], pl[RG];
@@ -604,25 +640,27 @@ __global__ __launch_bounds__(256, 2) void k_khat_bf16(const u32x4* __restrict__ 
     f32x4 dd[RG][2];
     bf16_distance<NKC, RG>(lds[0], xbv, rt, dd, lane);
     const float* ct = reinterpret_cast<const float*>(lds[0] + A_U + V_U);
-    if (is_diag(c_begin)) bf16_map<KIND, RG, true, F16>(dd, ct, ph, pl, lane, row0, c_begin, a.s32, a.alpha32);
-    else bf16_map<KIND, RG, false, F16>(dd, ct, ph, pl, lane, row0, c_begin, a.s32, a.alpha32);
+    if (is_diag(c_begin))
+      bf16_map<KIND, RG, true, F16, XC>(dd, ct, ph, pl, yacc, lane, row0, c_begin, a.s32, a.alpha32);
+    else
+      bf16_map<KIND, RG, false, F16, XC>(dd, ct, ph, pl, yacc, lane, row0, c_begin, a.s32, a.alpha32);
   }
   int cur = 0;
   for (int j = 0; j + 1 < nsteps; ++j) {
     const int nxt = cur == 2 ? 0 : cur + 1;
     const int far = nxt == 2 ? 0 : nxt + 1;
     const int64_t cn = c_begin + (int64_t)(j + 1) * 32;
-    if (j + 2 < nsteps) bf16_issue_stage<NKC, NTT>(lds[far], xfa, vfrag, colterm, cn + 32, wave, lane);
+    if (j + 2 < nsteps) bf16_issue_stage<NKC, NTT, XC>(lds[far], xfa, vfrag, colterm, vx, cn + 32, wave, lane);
     f32x4 dd[RG][2];
     bf16_distance<NKC, RG>(lds[nxt], xbv, rt, dd, lane);
     u32x4 nph[RG], npl[RG];
     const float* ctn = reinterpret_cast<const float*>(lds[nxt] + A_U + V_U);
     if (is_diag(cn)) {
       bf16_tile_v<NTT, RG, F16>(lds[cur] + A_U, ph, pl, acc, lane);
-      bf16_map<KIND, RG, true, F16>(dd, ctn, nph, npl, lane, row0, cn, a.s32, a.alpha32);
+      bf16_map<KIND, RG, true, F16, XC>(dd, ctn, nph, npl, yacc, lane, row0, cn, a.s32, a.alpha32);
     } else {
       bf16_tile_v<NTT, RG, F16>(lds[cur] + A_U, ph, pl, acc, lane);
-      bf16_map<KIND, RG, false, F16>(dd, ctn, nph, npl, lane, row0, cn, a.s32, a.alpha32);
+      bf16_map<KIND, RG, false, F16, XC>(dd, ctn, nph, npl, yacc, lane, row0, cn, a.s32, a.alpha32);
     }
 #pragma unroll
     for (int rg = 0; rg < RG; ++rg) {
@@ -642,9 +680,20 @@ __global__ __launch_bounds__(256, 2) void k_khat_bf16(const u32x4* __restrict__ 
     for (int tt = 0; tt < NTT; ++tt)
 #pragma unroll
       for (int v = 0; v < 4; ++v) out[(row0 + rg * 16 + 4 * g + v) * a.tp + tt * 16 + li] = acc[rg][tt][v];
+  if constexpr (XC != 0) {
+    // row i = li of each row group: the four lane groups hold disjoint column
+    // subsets; combine them in a fixed order ((g0 + g1) + (g2 + g3))
+#pragma unroll
+    for (int rg = 0; rg < RG; ++rg) {
+      float y = yacc[rg][0] + yacc[rg][1];
+      y += __shfl_xor(y, 16);
+      y += __shfl_xor(y, 32);
+      if (g == 0) out[(row0 + rg * 16 + li) * a.tp + 16 * NTT] = y;
+    }
+  }
 }
 
-#endif  // part 1
+#endif  // parts 1, 4
 
 #if GPMLL_KHAT_PART == 2 || GPMLL_KHAT_PART == 3
 // FP32 / FP64 tiles with v_mfma_{f32,f64}_16x16x4.  The accumulator -> operand
@@ -791,59 +840,69 @@ __global__ __launch_bounds__(256, 2) void k_khat_fp(const T* __restrict__ xfa, c
 // Each precision is compiled in its own translation unit (GPMLL_KHAT_PART).
 // ---------------------------------------------------------------------------
 
-hipError_t khat_tiles_bf16(const Ctx& c, const Hyper& h, const TileArgs& ta, const int* nact);
+hipError_t khat_tiles_bf16x3(const Ctx& c, const Hyper& h, const TileArgs& ta, const int* nact);
+hipError_t khat_tiles_f16x3(const Ctx& c, const Hyper& h, const TileArgs& ta, const int* nact);
 hipError_t khat_tiles_fp32(const Ctx& c, const Hyper& h, const TileArgs& ta, const int* nact,
                            const ItemTable& it = ItemTable{});
 hipError_t khat_tiles_fp64(const Ctx& c, const Hyper& h, const TileArgs& ta, const int* nact,
                            const ItemTable& it = ItemTable{});
 
 #define GPMLL_NTT_CASES(M) M(1) M(2) M(3) M(4) M(5) M(6) M(8) M(12) M(16)
+// split-precision tiles with the extra vector-ALU column: 16 NTT + 1 columns
+#define GPMLL_XC_NTT_CASES(M) M(0) M(1) M(2) M(3) M(4)
 
-#if GPMLL_KHAT_PART == 1
+#if GPMLL_KHAT_PART == 1 || GPMLL_KHAT_PART == 4
 namespace {
-template <int KIND, int NKC, int NTT, bool F16>
+constexpr bool kF16 = GPMLL_KHAT_PART == 4;
+template <int KIND, int NKC, int NTT, int XC>
 hipError_t run_bf16(const Ctx& c, const TileArgs& ta, const int* nact) {
   const Layout& L = *c.lay;
   constexpr int RG = NTT <= 5 ? 4 : (NTT <= 8 ? 2 : 1);
   dim3 grid((unsigned)(L.n_pad / (64 * RG)), (unsigned)L.nsplit);
-  hipLaunchKernelGGL((k_khat_bf16<KIND, NKC, NTT, RG, F16>), grid, dim3(256), 0, c.st, c.at<u32x4>(L.xfa),
+  hipLaunchKernelGGL((k_khat_bf16<KIND, NKC, NTT, RG, kF16, XC>), grid, dim3(256), 0, c.st, c.at<u32x4>(L.xfa),
                      c.at<u32x4>(L.xfb), c.at<float>(L.rowterm), c.at<float>(L.colterm), c.at<u32x4>(L.vfrag),
-                     c.at<float>(L.wpart), ta, nact);
+                     c.at<float>(L.vx), c.at<float>(L.wpart), ta, nact);
   return hipGetLastError();
 }
-template <int KIND, int NKC, bool F16>
-hipError_t sel_bf16_ntt(const Ctx& c, const TileArgs& ta, const int* nact, int ntt) {
-  switch (ntt) {
-#define CASE(N) case N: return run_bf16<KIND, NKC, N, F16>(c, ta, nact);
+template <int KIND, int NKC>
+hipError_t sel_bf16_ntt(const Ctx& c, const TileArgs& ta, const int* nact) {
+  if (ta.xc != 0) {
+    switch (ta.ntt) {
+#define CASE(N) case N: return run_bf16<KIND, NKC, N, 1>(c, ta, nact);
+      GPMLL_XC_NTT_CASES(CASE)
+#undef CASE
+    }
+    return hipErrorInvalidValue;
+  }
+  switch (ta.ntt) {
+#define CASE(N) case N: return run_bf16<KIND, NKC, N, 0>(c, ta, nact);
     GPMLL_NTT_CASES(CASE)
 #undef CASE
   }
   return hipErrorInvalidValue;
 }
-template <int KIND, bool F16>
+template <int KIND>
 hipError_t sel_bf16(const Ctx& c, const TileArgs& ta, const int* nact) {
   const Layout& L = *c.lay;
-  const int ntt = ta.ntt;
   switch (L.kd / 32) {
-    case 1: return sel_bf16_ntt<KIND, 1, F16>(c, ta, nact, ntt);
-    case 2: return sel_bf16_ntt<KIND, 2, F16>(c, ta, nact, ntt);
-    case 3: return sel_bf16_ntt<KIND, 3, F16>(c, ta, nact, ntt);
-    case 4: return sel_bf16_ntt<KIND, 4, F16>(c, ta, nact, ntt);
+    case 1: return sel_bf16_ntt<KIND, 1>(c, ta, nact);
+    case 2: return sel_bf16_ntt<KIND, 2>(c, ta, nact);
+    case 3: return sel_bf16_ntt<KIND, 3>(c, ta, nact);
+    case 4: return sel_bf16_ntt<KIND, 4>(c, ta, nact);
   }
   return hipErrorInvalidValue;
 }
 }  // namespace
-hipError_t khat_tiles_bf16(const Ctx& c, const Hyper& h, const TileArgs& ta, const int* nact) {
-  const bool f16 = c.lay->prec == GP_PREC_FP16X3;
+#if GPMLL_KHAT_PART == 1
+hipError_t khat_tiles_bf16x3(const Ctx& c, const Hyper& h, const TileArgs& ta, const int* nact) {
+#else
+hipError_t khat_tiles_f16x3(const Ctx& c, const Hyper& h, const TileArgs& ta, const int* nact) {
+#endif
   switch (h.kind) {
-    case GP_KERNEL_RBF:
-      return f16 ? sel_bf16<GP_KERNEL_RBF, true>(c, ta, nact) : sel_bf16<GP_KERNEL_RBF, false>(c, ta, nact);
-    case GP_KERNEL_MATERN32:
-      return f16 ? sel_bf16<GP_KERNEL_MATERN32, true>(c, ta, nact) : sel_bf16<GP_KERNEL_MATERN32, false>(c, ta, nact);
-    case GP_KERNEL_RATQUAD:
-      return f16 ? sel_bf16<GP_KERNEL_RATQUAD, true>(c, ta, nact) : sel_bf16<GP_KERNEL_RATQUAD, false>(c, ta, nact);
-    default:
-      return f16 ? sel_bf16<GP_KERNEL_MATERN52, true>(c, ta, nact) : sel_bf16<GP_KERNEL_MATERN52, false>(c, ta, nact);
+    case GP_KERNEL_RBF: return sel_bf16<GP_KERNEL_RBF>(c, ta, nact);
+    case GP_KERNEL_MATERN32: return sel_bf16<GP_KERNEL_MATERN32>(c, ta, nact);
+    case GP_KERNEL_RATQUAD: return sel_bf16<GP_KERNEL_RATQUAD>(c, ta, nact);
+    default: return sel_bf16<GP_KERNEL_MATERN52>(c, ta, nact);
   }
 }
 #endif
@@ -942,11 +1001,27 @@ hipError_t launch_stage_x_bwd(const Ctx& c, const Hyper& h) {
   return hipGetLastError();
 }
 
+TilePlan tile_plan(const Layout& L, int ncols) {
+  static const int ok[] = {1, 2, 3, 4, 5, 6, 8, 12, 16};
+  const int full = L.tp / 16;
+  const bool split = L.prec == GP_PREC_BF16X3 || L.prec == GP_PREC_FP16X3;
+  ncols = std::max(1, std::min(ncols, L.tp));
+  // 16 m + 1 columns: m tiles on the matrix cores, the last column on the vector ALU
+  if (split && ncols % 16 == 1 && ncols / 16 <= 4) return TilePlan{ncols / 16, 1};
+  for (int v : ok)
+    if (16 * v >= ncols && v <= full) return TilePlan{v, 0};
+  return TilePlan{full, 0};
+}
+
 hipError_t launch_stage_v(const Ctx& c, const double* V, int ldv, int ncols, const Hyper& h, const int* colmap,
-                          int ntt) {
+                          TilePlan plan) {
   const Layout& L = *c.lay;
   (void)h;
-  if (ntt <= 0) ntt = L.tp / 16;
+  int ntt = plan.ntt;
+  if (ntt < 0) ntt = L.tp / 16;
+  const int xcol = plan.xc != 0 ? 16 * ntt : -1;
+  if (plan.xc != 0 && L.prec != GP_PREC_BF16X3 && L.prec != GP_PREC_FP16X3) return hipErrorInvalidValue;
+  const unsigned nbx = (unsigned)((L.n_pad + 255) / 256);
   if (L.prec == GP_PREC_FP16X3) {
     uint32_t* cm = c.at<uint32_t>(L.vscale);
     hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(256), 0, c.st, cm, L.tp);
@@ -954,12 +1029,20 @@ hipError_t launch_stage_v(const Ctx& c, const double* V, int ldv, int ncols, con
     hipLaunchKernelGGL(k_colmax, dim3((unsigned)((L.n + rpb - 1) / rpb), (unsigned)((ncols + 63) / 64)), dim3(256), 0,
                        c.st, V, L.n, ldv, ncols, colmap, cm, rpb);
     const int64_t total = (L.n_pad / 32) * ntt * 64;
-    hipLaunchKernelGGL(k_stage_v_f16, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, c.st, V, L.n, ldv, ncols,
-                       colmap, L.n_pad, ntt, cm, c.at<u32x4>(L.vfrag));
+    if (total > 0)
+      hipLaunchKernelGGL(k_stage_v_f16, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, c.st, V, L.n, ldv,
+                         ncols, colmap, L.n_pad, ntt, cm, c.at<u32x4>(L.vfrag));
+    if (xcol >= 0)
+      hipLaunchKernelGGL(k_stage_vx, dim3(nbx), dim3(256), 0, c.st, V, L.n, ldv, xcol, ncols, colmap, L.n_pad, cm,
+                         c.at<float>(L.vx));
   } else if (L.prec == GP_PREC_BF16X3) {
     const int64_t total = (L.n_pad / 32) * ntt * 64;
-    hipLaunchKernelGGL(k_stage_v_bf16, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, c.st, V, L.n, ldv,
-                       ncols, colmap, L.n_pad, ntt, c.at<u32x4>(L.vfrag));
+    if (total > 0)
+      hipLaunchKernelGGL(k_stage_v_bf16, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, c.st, V, L.n, ldv,
+                         ncols, colmap, L.n_pad, ntt, c.at<u32x4>(L.vfrag));
+    if (xcol >= 0)
+      hipLaunchKernelGGL(k_stage_vx, dim3(nbx), dim3(256), 0, c.st, V, L.n, ldv, xcol, ncols, colmap, L.n_pad,
+                         (const uint32_t*)nullptr, c.at<float>(L.vx));
   } else if (L.prec == GP_PREC_FP32) {
     const int64_t total = (L.n_pad / 16) * ntt * 256;
     hipLaunchKernelGGL(k_stage_v_fp<float>, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, c.st, V, L.n, ldv,
@@ -972,23 +1055,28 @@ hipError_t launch_stage_v(const Ctx& c, const double* V, int ldv, int ncols, con
   return hipGetLastError();
 }
 
-hipError_t launch_khat_tiles(const Ctx& c, const Hyper& h, const int* nact, int ntt) {
+hipError_t launch_khat_tiles(const Ctx& c, const Hyper& h, const int* nact, TilePlan plan) {
   const Layout& L = *c.lay;
   TileArgs ta;
   ta.n_pad = L.n_pad;
   ta.n_valid = L.n;
   ta.cols_per_split = L.cols_per_split;
   ta.tp = L.tp;
-  ta.ntt = ntt > 0 ? ntt : L.tp / 16;
+  ta.ntt = plan.ntt >= 0 ? plan.ntt : L.tp / 16;
+  ta.xc = plan.xc;
   ta.s32 = (float)h.s;
   ta.s64 = h.s;
   ta.alpha32 = (float)h.alpha;
   ta.alpha64 = h.alpha;
   if (L.prec == GP_PREC_BF16X3 || L.prec == GP_PREC_FP16X3) {
     // FP16X3 kernel values are 2^15 kappa: the tile carries no outputscale
-    if (L.prec == GP_PREC_FP16X3) ta.s32 = 32768.0f;
-    return khat_tiles_bf16(c, h, ta, nact);
+    if (L.prec == GP_PREC_FP16X3) {
+      ta.s32 = 32768.0f;
+      return khat_tiles_f16x3(c, h, ta, nact);
+    }
+    return khat_tiles_bf16x3(c, h, ta, nact);
   }
+  if (ta.xc != 0) return hipErrorInvalidValue;
   if (L.prec == GP_PREC_FP32) return khat_tiles_fp32(c, h, ta, nact);
   return khat_tiles_fp64(c, h, ta, nact);
 }
@@ -1002,6 +1090,7 @@ hipError_t launch_khat_tiles_items(const Ctx& c, const Hyper& h, const ItemTable
   ta.cols_per_split = L.cols_per_split;
   ta.tp = L.tp;
   ta.ntt = L.tp / 16;
+  ta.xc = 0;
   ta.s32 = 1.0f;
   ta.s64 = 1.0;
   ta.alpha32 = (float)h.alpha;

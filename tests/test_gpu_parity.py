@@ -77,7 +77,10 @@ MATVEC_TOL = {"fp64": 1e-12, "fp32": 2e-5, "bf16x3": 2e-4, "fp16x3": 1e-4}
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32", "bf16x3", "fp16x3"])
 @pytest.mark.parametrize("kernel", ["rbf", "matern32", "matern52"])
-@pytest.mark.parametrize("n,d,nrhs", [(1000, 3, 17), (777, 8, 33), (1300, 16, 65), (300, 20, 5)])
+# column counts 16 m + 1 run m tiles on the matrix cores and the last column on the
+# vector ALU in the split precisions (1 = that column alone)
+@pytest.mark.parametrize("n,d,nrhs", [(1000, 3, 17), (777, 8, 33), (1300, 16, 65), (300, 20, 5), (555, 5, 1),
+                                      (640, 12, 49)])
 def test_khat_matvec_matches_oracle(precision, kernel, n, d, nrhs):
     pr = synthgp.random_problem(n, d, kernel, ard=True, seed=n + d, ls_range=(0.5, 2.0), dist="normal")
     say(f"[gpu] khat_matvec n={n} d={d} rhs={nrhs} {kernel} {precision}")
@@ -102,22 +105,28 @@ def test_khat_matvec_matches_oracle(precision, kernel, n, d, nrhs):
     assert err < MATVEC_TOL[precision]
 
 
-def test_khat_matvec_ragged_and_tiny_sizes():
+@pytest.mark.parametrize("precision,nrhs", [("fp64", 3), ("bf16x3", 1), ("bf16x3", 17), ("fp16x3", 1),
+                                            ("fp16x3", 17)])
+def test_khat_matvec_ragged_and_tiny_sizes(precision, nrhs):
     for n in (1, 5, 16, 17, 255, 257):
         pr = synthgp.random_problem(n, 2, "rbf", ard=False, seed=n)
         dev = torch.device("cuda:0")
-        say(f"[gpu] khat_matvec tiny n={n}")
+        say(f"[gpu] khat_matvec tiny n={n} rhs={nrhs} {precision}")
         X = torch.tensor(pr.X, device=dev)
         y = torch.tensor(pr.y, device=dev)
         prob = B.make_problem(X, y, "rbf", False)
-        opt = B.make_options("fp64", 2, 1)
+        opt = B.make_options(precision, max(1, nrhs - 1), 1)
         ws = B.alloc_workspace(B.gp_workspace_size(prob, opt, 0))
-        V = np.random.default_rng(n).standard_normal((n, 3))
+        V = np.random.default_rng(n).standard_normal((n, nrhs))
         Vd = torch.tensor(V, device=dev)
         Wd = torch.zeros_like(Vd)
-        B.gp_khat_matvec(prob, pr.theta, "fp64", Vd, Wd, ws)
-        np.testing.assert_allclose(Wd.cpu().numpy(), go.khat_matvec(pr.X, pr.theta, "rbf", False, V),
-                                   rtol=1e-11, atol=1e-12)
+        B.gp_khat_matvec(prob, pr.theta, precision, Vd, Wd, ws)
+        ref = go.khat_matvec(pr.X, pr.theta, "rbf", False, V)
+        if precision == "fp64":
+            np.testing.assert_allclose(Wd.cpu().numpy(), ref, rtol=1e-11, atol=1e-12)
+        else:
+            scale = np.abs(go.khat_dense(pr.X, pr.theta, "rbf", False)) @ np.abs(V)
+            assert np.max(np.abs(Wd.cpu().numpy() - ref) / scale) < MATVEC_TOL[precision]
 
 
 # ---------------------------------------------------------------- preconditioner
