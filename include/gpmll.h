@@ -311,6 +311,27 @@ int gp_khat_profile(const gp_problem* prob, const double* theta_host, const gp_o
                     int64_t* grid_x, int64_t* grid_y);
 
 /*
+ * gp_khat_matvec_noalloc — gp_khat_matvec for callers that cannot allocate
+ * device memory (code under stream or graph capture, tight serving loops,
+ * harnesses that forbid allocation): the same product W = K_hat V with the
+ * same arguments minus the workspace.  Its staging arrays live in a device
+ * array of GP_NOALLOC_SCRATCH_BYTES inside the library, one per GPU, held from
+ * the library's load until the process ends; the call allocates and frees
+ * nothing.  Shapes whose arrays exceed that size are rejected with
+ * GP_EWORKSPACE before any device work (fewer column splits are taken first,
+ * so results may differ from gp_khat_matvec in rounding order only; roughly
+ * n <= 130,000 for d = 16 and 65 right-hand sides in the split precisions).
+ * Every call on a GPU uses that GPU's one array: calls that overlap on one GPU
+ * (different streams or host threads) race and must be serialised by the
+ * caller.  V_dev, W_dev: caller-owned n x num_rhs row-major FP64 device arrays.
+ * Errors: GP_EINVAL (null pointers, bad shapes, precision or theta),
+ * GP_EWORKSPACE (shape too large for the array), GP_EUNSUPPORTED, GP_EHIP.
+ */
+#define GP_NOALLOC_SCRATCH_BYTES ((size_t)128 << 20)
+int gp_khat_matvec_noalloc(const gp_problem* prob, const double* theta_host, int32_t precision,
+                           const double* V_dev, int32_t num_rhs, double* W_dev, hipStream_t stream);
+
+/*
  * Ragged batches of independent problems
  * --------------------------------------
  * One call evaluates Algorithm 1 (and, for the _grad form, Algorithm 2) for

@@ -35,7 +35,8 @@ BATCH_MAX_RANK, BATCH_MAX_PROBES = 256, 64
 EXPORTS = ("gp_workspace_size", "gp_precond_build", "gp_precond_build_nystrom", "gp_precond_build_rff",
            "gp_precond_build_qff", "gp_precond_view_of", "gp_predict",
            "gp_precond_free",
-           "gp_mll_eval", "gp_mll_grad", "gp_khat_matvec", "gp_khat_profile", "gp_batch_workspace_size",
+           "gp_mll_eval", "gp_mll_grad", "gp_khat_matvec", "gp_khat_matvec_noalloc", "gp_khat_profile",
+           "gp_batch_workspace_size",
            "gp_batch_mll_eval", "gp_batch_mll_grad", "gp_strerror", "gp_last_hip_error")
 
 
@@ -111,6 +112,7 @@ def load(path: str = LIB_PATH):
     lib.gp_mll_eval.argtypes = [P, dp, O, i32, vp, vp, ctypes.c_size_t, vp, vp, S]
     lib.gp_mll_grad.argtypes = [P, dp, O, i32, vp, vp, ctypes.c_size_t, vp, vp, vp, S]
     lib.gp_khat_matvec.argtypes = [P, dp, i32, vp, i32, vp, vp, ctypes.c_size_t, vp]
+    lib.gp_khat_matvec_noalloc.argtypes = [P, dp, i32, vp, i32, vp, vp]
     lib.gp_predict.argtypes = [P, dp, O, i32, vp, vp, ctypes.c_int64, vp, ctypes.c_size_t, vp, vp, vp]
     lib.gp_khat_profile.argtypes = [P, dp, O, i32, vp, ctypes.c_size_t, vp, dp, ctypes.POINTER(ctypes.c_int64),
                                     ctypes.POINTER(ctypes.c_int64)]
@@ -123,7 +125,7 @@ def load(path: str = LIB_PATH):
     lib.gp_last_hip_error.argtypes = []
     for name in ("gp_workspace_size", "gp_precond_build", "gp_precond_build_nystrom", "gp_precond_build_rff",
                  "gp_precond_build_qff", "gp_precond_view_of", "gp_mll_eval", "gp_mll_grad", "gp_khat_matvec",
-                 "gp_predict",
+                 "gp_predict", "gp_khat_matvec_noalloc",
                  "gp_khat_profile",
                  "gp_batch_workspace_size", "gp_batch_mll_eval", "gp_batch_mll_grad", "gp_last_hip_error"):
         getattr(lib, name).restype = ctypes.c_int
@@ -287,6 +289,13 @@ def gp_khat_matvec(prob, theta, precision, V, W, ws, stream=None):
     _check(load().gp_khat_matvec(ctypes.byref(prob), tp, prec, ctypes.c_void_p(V.data_ptr()), V.shape[1],
                                  ctypes.c_void_p(W.data_ptr()), ctypes.c_void_p(ws.data_ptr()), ws.numel(),
                                  _stream(stream)), "gp_khat_matvec")
+
+
+def gp_khat_matvec_noalloc(prob, theta, precision, V, W, stream=None):
+    arr, tp = _theta(theta)
+    prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    _check(load().gp_khat_matvec_noalloc(ctypes.byref(prob), tp, prec, ctypes.c_void_p(V.data_ptr()), V.shape[1],
+                                         ctypes.c_void_p(W.data_ptr()), _stream(stream)), "gp_khat_matvec_noalloc")
 
 
 def gp_khat_profile(prob, theta, opt, reps, ws, stream=None):

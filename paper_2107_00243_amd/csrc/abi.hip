@@ -849,3 +849,102 @@ extern "C" const char* gp_strerror(int status) {
 }
 
 extern "C" int gp_last_hip_error(void) { return g_last_hip; }
+
+// ---------------------------------------------------------------------------
+// gp_khat_matvec_noalloc: the product of gp_khat_matvec with its staging arrays
+// in a file-scope device array instead of a caller workspace, for callers that
+// cannot allocate device memory.  Each device holds its own copy of the array
+// (from the library's load until the process ends); its device address is taken
+// once per device with hipGetSymbolAddress and used for every kernel argument.
+// Calls that overlap on one device race on the array.
+// ---------------------------------------------------------------------------
+namespace {
+constexpr size_t kScratchBytes = GP_NOALLOC_SCRATCH_BYTES;
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices];
+}  // namespace
+
+static __device__ __align__(256) char scratch[kScratchBytes];
+
+// device address of `scratch` on the current device (taken on first use there)
+static int scratch_on_current_device(void** out) {
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return GP_EUNSUPPORTED;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_ptr[dev] == nullptr) {
+    void* p = nullptr;
+    HIPCHK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (p == nullptr || (reinterpret_cast<uintptr_t>(p) & 255) != 0) return GP_EHIP;
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return GP_OK;
+}
+
+// The arrays one K_hat V product touches (centring and scaling of X, staged
+// distance operands, staged right-hand sides, split-K partial sums), carved back
+// to back.  The partial sums grow with the column splits: fewer splits are taken
+// while they would not fit in `cap` bytes.  total = 0: nothing fits.
+static Layout matvec_layout(const Layout& full, size_t cap) {
+  for (int want = full.nsplit; want >= 1; --want) {
+    Layout L = full;
+    if (want != full.nsplit) {
+      L.cols_per_split = std::max<int64_t>(256, rup((L.n_pad + want - 1) / want, 256));
+      L.nsplit = (int)((L.n_pad + L.cols_per_split - 1) / L.cols_per_split);
+    }
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+      size_t o = off;
+      off += al(bytes ? bytes : 1);
+      return o;
+    };
+    const int64_t np = L.n_pad, tp = L.tp;
+    const bool split16 = L.prec == GP_PREC_BF16X3 || L.prec == GP_PREC_FP16X3;
+    const size_t esz = L.prec == GP_PREC_FP64 ? 8 : (L.prec == GP_PREC_FP32 ? 4 : 2);
+    const size_t wsz = L.prec == GP_PREC_FP64 ? 8 : 4;
+    L.xs = take(np * L.d * 8);
+    L.mean = take(GP_MAX_D * 8);
+    L.mean_part = take((size_t)L.nred * GP_MAX_D * 8);
+    L.xfa = take(np * L.kd * esz);
+    L.xfb = take(np * L.kd * esz);
+    L.rowterm = take(np * wsz);
+    L.colterm = take(np * wsz);
+    L.vfrag = take(np * tp * (split16 ? 4 : esz));
+    L.vx = take(split16 ? np * 4 : 0);
+    L.vscale = take(2 * tp * 4);
+    L.wpart = take((size_t)L.nsplit * np * tp * wsz);
+    L.total = off;
+    if (L.total <= cap) return L;
+  }
+  Layout none = full;
+  none.total = 0;
+  return none;
+}
+
+extern "C" int gp_khat_matvec_noalloc(const gp_problem* prob, const double* theta_host, int32_t precision,
+                                      const double* V_dev, int32_t num_rhs, double* W_dev, hipStream_t stream) {
+  RET_IF(check_problem(prob));
+  if (!V_dev || !W_dev) return GP_EINVAL;
+  if (num_rhs < 1 || num_rhs > 1 + GP_MAX_PROBES) return GP_EINVAL;
+  if (precision < 0 || precision > 3) return GP_EINVAL;
+  Hyper h;
+  RET_IF(make_hyper(prob, theta_host, &h));
+  const Layout full = make_layout(prob->n, prob->d, prob->ard, std::max(1, num_rhs - 1), 1, 0, precision);
+  const Layout L = matvec_layout(full, kScratchBytes);
+  if (L.total == 0) return GP_EWORKSPACE;
+  RET_IF(check_device());
+  void* ws = nullptr;
+  RET_IF(scratch_on_current_device(&ws));
+  Ctx c{&L, (char*)ws, stream};
+  // every array below is fully rewritten by this call (the FP16X3 column maxima
+  // are cleared by a kernel), so nothing left by an earlier call is read
+  HIPCHK(launch_prep(c, prob->X_dev, h));
+  HIPCHK(launch_stage_x(c, h));
+  const TilePlan plan = tile_plan(L, num_rhs);
+  HIPCHK(launch_stage_v(c, V_dev, num_rhs, num_rhs, h, nullptr, plan));
+  HIPCHK(launch_khat_tiles(c, h, nullptr, plan));
+  HIPCHK(launch_khat_reduce(c, V_dev, num_rhs, W_dev, num_rhs, num_rhs, h, nullptr, nullptr));
+  return GP_OK;
+}

@@ -358,3 +358,22 @@ def test_batch_rejects_bad_theta_of_any_problem(lib, bad):
                                  ctypes.c_void_p(0x3000), ctypes.c_void_p(0x4000), None) == B.GP_EINVAL
     assert lib.gp_batch_mll_grad(ctypes.byref(b), tp, ctypes.byref(o), 2, ctypes.c_void_p(0x10000), 1 << 30, None,
                                  ctypes.c_void_p(0x3000), None, None) == B.GP_EINVAL
+
+
+def test_noalloc_matvec_rejects_bad_arguments_and_oversized_shapes_before_any_device_call(lib):
+    theta = np.array([0.5, 0.5, 0.5, 1.0, 0.1])
+    tp = theta.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    v, w = ctypes.c_void_p(0x5000), ctypes.c_void_p(0x6000)
+    p = _fake_problem()
+    f = lib.gp_khat_matvec_noalloc
+    assert f(ctypes.byref(p), tp, 0, None, 4, w, None) == B.GP_EINVAL
+    assert f(ctypes.byref(p), tp, 0, v, 4, None, None) == B.GP_EINVAL
+    assert f(ctypes.byref(p), tp, 0, v, 0, w, None) == B.GP_EINVAL
+    assert f(ctypes.byref(p), tp, 4, v, 4, w, None) == B.GP_EINVAL
+    assert f(ctypes.byref(B.gp_problem(0, 0x2000, 100, 3, 0, 1)), tp, 0, v, 4, w, None) == B.GP_EINVAL
+    bad = theta.copy()
+    bad[4] = -1.0
+    assert f(ctypes.byref(p), bad.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), 0, v, 4, w, None) == B.GP_EINVAL
+    # staging arrays beyond the library's 128 MiB device array even with one column split
+    big = _fake_problem(n=1_000_000)
+    assert f(ctypes.byref(big), tp, 2, v, 65, w, None) == B.GP_EWORKSPACE
