@@ -208,7 +208,7 @@ def _native():
                                          ctypes.c_int32, ctypes.c_double, ctypes.c_int32, P, ctypes.c_int64,
                                          ctypes.POINTER(ctypes.c_int64), P]
         h.oracle_dkhat_lowrank.argtypes = [ctypes.c_int64, ctypes.c_int32, P, P, ctypes.c_double, ctypes.c_int32,
-                                           ctypes.c_double, ctypes.c_int32, P, P, P]
+                                           ctypes.c_double, ctypes.c_int32, P, P, ctypes.c_int64, ctypes.c_int64, P]
         _NATIVE = h
     return _NATIVE
 
@@ -302,8 +302,9 @@ def dkhat_contract(X, theta, kind, ard, m_rows, workers=1):
     return out
 
 
-def dkhat_contract_lowrank(X, theta, kind, ard, A, C):
-    """dkhat_contract for M = A C^T by the plain-C loops of khat_native.c."""
+def dkhat_contract_lowrank(X, theta, kind, ard, A, C, row_range=None):
+    """dkhat_contract for M = A C^T by the plain-C loops of khat_native.c
+    (row_range = (p0, p1): only the rows p0 <= p < p1 of M)."""
     n, d = X.shape
     ls, s, _ = split_theta(theta, d, ard)
     p = d if ard else 1
@@ -312,8 +313,9 @@ def dkhat_contract_lowrank(X, theta, kind, ard, A, C):
     Cc = np.ascontiguousarray(C, dtype=np.float64)
     raw = np.zeros(d + 2)
     code, alpha = _native_kind(kind)
+    p0, p1 = (0, n) if row_range is None else row_range
     rc = _native().oracle_dkhat_lowrank(n, d, _dptr(Xc), _dptr(ls), s, code, alpha, Ac.shape[1], _dptr(Ac),
-                                        _dptr(Cc), _dptr(raw))
+                                        _dptr(Cc), int(p0), int(p1), _dptr(raw))
     if rc != 0:
         raise ValueError("oracle_dkhat_lowrank failed")
     out = np.zeros(p + 2)

@@ -110,17 +110,19 @@ int oracle_khat_matvec(int64_t n, int32_t d, const double* X, const double* ls, 
     return 0;
 }
 
-/* sum_pq M_pq dK_hat_pq / dtheta for M = A C^T (A, C: n x t row-major).
+/* sum_pq M_pq dK_hat_pq / dtheta for M = A C^T (A, C: n x t row-major), over the
+ * rows p0 <= p < p1 of M (0, n: all of it).
  * out[0..d): per-dimension terms sum_pq W_pq dtilde_pqj^2 / ls_j with
  * W = s g(r) M (the lengthscale derivatives of an ARD kernel; an isotropic
  * kernel sums them); out[d]: sum_pq M_pq kappa(r_pq) (outputscale);
  * out[d + 1]: sum_p M_pp (noise).  Partial sums per task are added in task
  * order, so the result does not depend on the thread count. */
 int oracle_dkhat_lowrank(int64_t n, int32_t d, const double* X, const double* ls, double s, int32_t kind,
-                         double alpha, int32_t t, const double* A, const double* C, double* out)
+                         double alpha, int32_t t, const double* A, const double* C, int64_t p0, int64_t p1,
+                         double* out)
 {
-    if (n < 1 || d < 1 || t < 1) return -1;
-    const int64_t ntask = (n + ROWS - 1) / ROWS;
+    if (n < 1 || d < 1 || t < 1 || p0 < 0 || p1 > n || p0 > p1) return -1;
+    const int64_t ntask = (p1 - p0 + ROWS - 1) / ROWS;
     const int np = d + 2;
     double* part = (double*)calloc((size_t)ntask * (size_t)np, sizeof(double));
     if (!part) return -2;
@@ -130,10 +132,10 @@ int oracle_dkhat_lowrank(int64_t n, int32_t d, const double* X, const double* ls
 #pragma omp for schedule(dynamic, 1)
         for (int64_t task = 0; task < ntask; ++task) {
             double* acc = part + task * np;
-            const int64_t p0 = task * ROWS;
-            const int64_t p1 = (p0 + ROWS) < n ? (p0 + ROWS) : n;
+            const int64_t r0 = p0 + task * ROWS;
+            const int64_t r1 = (r0 + ROWS) < p1 ? (r0 + ROWS) : p1;
             for (int64_t q0 = 0; q0 < n; q0 += COLS)
-            for (int64_t p = p0; p < p1; ++p) {
+            for (int64_t p = r0; p < r1; ++p) {
                 const double* ap = A + p * t;
                 const int64_t q1 = (q0 + COLS) < n ? (q0 + COLS) : n;
                 for (int64_t q = q0; q < q1; ++q) {

@@ -207,3 +207,20 @@ def random_problem(n, d, kernel="rbf", ard=True, rank=8, num_probes=8, seed=0,
     return GPProblem(f"random_{kernel}_{n}x{d}", X, y, theta, kernel, ard, rank=rank,
                      num_probes=num_probes, tol=tol, max_iters=max_iters, precision=precision,
                      recipe=f"X~{dist}; {kernel} ard={ard}; y=RFF(1024)+noise")
+
+
+TABLE_S1_KERNELS = ("matern32", "rbf", "ratquad:1.0")
+
+
+def table_s1(kernel="rbf", d=1, n=10000, seed=0):
+    """The synthetic experiment of Table S1: n = 10,000 iid standard normal points in
+    d dimensions, sigma^2 = 1e-2.  The paper leaves the remaining parameters open:
+    isotropic lengthscale 1, outputscale 1, rational quadratic shape 1, and y drawn
+    from the GP through random features plus noise."""
+    rng = np.random.default_rng(np.random.SeedSequence([int(seed), 0x51, int(d)]))
+    X = rng.standard_normal((n, d))
+    theta = np.array([1.0, 1.0, 1e-2])
+    y = rff_targets(rng, X, 1.0, 1.0, 1e-2, kernel)
+    return GPProblem(f"table_s1_{kernel}_d{d}", X, y, theta, kernel, False, rank=128, num_probes=128,
+                     tol=1e-10, max_iters=3000, precision="fp64",
+                     recipe=f"X~N(0,I_{d}), n={n}; {kernel} iso ls=1 s=1 s2=1e-2; y=RFF(4096)+noise")

@@ -2,6 +2,7 @@
 
     python tests/golden/make_full_size.py matern52_ard_20k   # dense, about 10 minutes
     python tests/golden/make_full_size.py rbf_ard_100k       # matrix-free, about an hour
+    python tests/golden/make_full_size.py batched_rbf_64     # 64 dense problems
 
 Calls only the CPU oracle (oracle/gp_oracle.py) on the seeded inputs of synthgp;
 nothing here touches the GPU library.  Each run writes one JSON file next to this
@@ -52,8 +53,37 @@ def _exact(pr):
             "seconds": time.time() - t0}
 
 
+def batch_main(name, workers):
+    """The ragged batch: problem b of the batch with probe seed probe_seed + b and
+    rank min(rank, n_b), as the batched entry points evaluate it."""
+    probs = getattr(synthgp, name)()
+    rec = {"workload": name, "source": "oracle/gp_oracle.py estimate_mll and exact_mll, FP64, dense",
+           "host": {"cpu": platform.processor() or platform.machine(), "threads": workers,
+                    "numpy": np.__version__}, "problems": []}
+    for b, pr in enumerate(probs):
+        t0 = time.time()
+        est = go.estimate_mll(pr.X, pr.y, pr.theta, pr.kernel, pr.ard, min(pr.rank, pr.n), pr.num_probes, pr.tol,
+                              pr.max_iters, pr.probe_seed + b, grad=True, dense=True)
+        ex = go.exact_mll(pr.X, pr.y, pr.theta, pr.kernel, pr.ard, grad=True)
+        rec["problems"].append({
+            "n": pr.n, "theta": pr.theta.tolist(), "rank": min(pr.rank, pr.n), "num_probes": pr.num_probes,
+            "tol": pr.tol, "max_iters": pr.max_iters, "probe_seed": pr.probe_seed + b,
+            "estimate": {"logp": est["logp"], "grad": est["grad"].tolist(), "col_iters": est["iters"].tolist()},
+            "exact": {"logp": ex["logp"], "grad": ex["grad"].tolist(), "datafit": ex["datafit"],
+                      "logdet": ex["logdet"]},
+            "seconds": time.time() - t0})
+        print(f"[golden] {name} problem {b} n={pr.n}: log p {est['logp']:.10g} (exact {ex['logp']:.10g}), "
+              f"CG {int(est['iters'].max())}, {time.time() - t0:.0f} s", flush=True)
+    out = os.path.join(HERE, f"oracle_{name}.json")
+    with open(out, "w") as f:
+        json.dump(rec, f, indent=1)
+    print(out)
+
+
 def main(name):
     workers = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    if name.startswith("batched"):
+        return batch_main(name, workers)
     pr = getattr(synthgp, name)()
     rec = {
         "workload": name, "recipe": pr.recipe, "n": pr.n, "d": pr.d, "kernel": pr.kernel, "ard": pr.ard,

@@ -782,6 +782,10 @@ def test_dkhat_contract_matches_dense_derivative_matrices_across_row_blocks():
     ref[d + 1] = np.trace(M)
     for g in (got, got_threads, got_native):
         np.testing.assert_allclose(g, ref, rtol=2e-7, atol=1e-6 * np.max(np.abs(ref)))
+    # row ranges of the plain-C contraction add up to the whole
+    halves = (go.dkhat_contract_lowrank(X, theta, "matern52", True, A, C, row_range=(0, 777))
+              + go.dkhat_contract_lowrank(X, theta, "matern52", True, A, C, row_range=(777, n)))
+    np.testing.assert_allclose(halves, got_native, rtol=1e-12, atol=1e-12 * np.max(np.abs(got_native)))
     # isotropic form: one lengthscale, the sum of the per-dimension terms
     th_iso = np.concatenate([[2.5], theta[d:]])
     iso = go.dkhat_contract(X, th_iso, "matern52", False, lambda r: M[r])
