@@ -34,28 +34,39 @@ PEAK_BF16_TFLOPS = 2500.0   # MI355X dense BF16 MFMA
 PEAK_FP64_TFLOPS = 78.6
 
 
-# Counter readings of one split-precision tile launch on this workload (rocprofv3
-# --pmc FETCH_SIZE, then WRITE_SIZE, KiB per dispatch, over `bench.py --tiles-only
-# --tile-precision P`), each scaled by what the same counter reads for a 1 GiB
-# elementwise copy, and the MFMA counters of the same launches.  They describe the
-# kernel source whose hash is given, launched on the given grid; once either changes
-# they are stale and are not reported.
+# Counter readings of the split-precision tile kernel on this workload, per launch,
+# for each kernel instance (rocprofv3 --pmc FETCH_SIZE, then WRITE_SIZE, KiB per
+# dispatch, over `bench.py --tiles-only --tile-precision P`), each scaled by what the
+# same counter reads for a 1 GiB elementwise copy, and the MFMA counters of the same
+# launches.  Instance "v3" takes three-piece search directions (BF16x3, the first
+# V3_ITERS CG iterations), "v2" two-piece ones.  They describe the kernel source whose
+# hash is given, launched on the given grid; once either changes they are stale and
+# are not reported.
+V3_ITERS = 16          # the library's kBf16V3Iters
 TILE_COUNTERS = {
     "fp16x3": {
-        "kernel_source_sha256_16": "2ad01f18215e8305",
+        "kernel_source_sha256_16": "5ca15e675ba75ec5",
         "grid": [391, 5],
-        "fetch_kib": 419696.6, "fetch_scale": 1048576.0 / 524307.1,
-        "write_kib": 156400.0, "write_scale": 1.0,
-        "mfma_insts": 3.71807e8, "mfma_busy_cycles": 5.9489e9, "gui_active_per_xcd": 8.41555e7 / 8,
+        "v2": {"fetch_kib": 280109.0, "fetch_scale": 1048576.0 / 524315.0,
+               "write_kib": 141670.0, "write_scale": 1.0,
+               "mfma_insts": 3.131e8, "mfma_busy_cycles": 5.0096e9, "gui_active_per_xcd": 7.71078e7 / 8},
     },
     "bf16x3": {
-        "kernel_source_sha256_16": "2ad01f18215e8305",
+        "kernel_source_sha256_16": "5ca15e675ba75ec5",
         "grid": [391, 5],
-        "fetch_kib": 321175.9, "fetch_scale": 1048576.0 / 524307.2,
-        "write_kib": 156400.0, "write_scale": 1.0,
-        "mfma_insts": 3.71807e8, "mfma_busy_cycles": 5.9489e9, "gui_active_per_xcd": 7.83262e7 / 8,
+        "v2": {"fetch_kib": 280035.0, "fetch_scale": 1048576.0 / 524308.0,
+               "write_kib": 141297.0, "write_scale": 1.0,
+               "mfma_insts": 3.131e8, "mfma_busy_cycles": 5.0096e9, "gui_active_per_xcd": 7.71932e7 / 8},
     },
 }
+
+
+def tile_launch_mix(precision, reps):
+    """Launches per kernel instance among `reps` full-width CG products."""
+    if precision == "bf16x3":
+        n3 = min(reps, V3_ITERS)
+        return {"v3": n3, "v2": reps - n3}
+    return {"v2": reps}
 
 
 def bf16_tile_source_hash():
@@ -76,7 +87,7 @@ def tile_flops(n, d, t):
     return 2.0 * n * n * (d + t) + float(n) * n
 
 
-def run_gpu(pr, precision, steps, warmup, sync_every=1):
+def run_gpu(pr, precision, steps, warmup, sync_every=1, timed=True):
     import torch
     from paper_2107_00243_amd import binding as B
     dev = torch.device("cuda:0")
@@ -93,7 +104,12 @@ def run_gpu(pr, precision, steps, warmup, sync_every=1):
     torch.cuda.synchronize()
     info = {"logp": float(logp.cpu()[0]), "grad": grad.cpu().numpy(), "iters_max": int(st.iters_max),
             "iters_mean": float(np.mean(st.col_iters)), "iters_y": int(st.col_iters[0]),
-            "flags": int(st.flags), "rank": int(st.rank_achieved)}
+            "flags": int(st.flags), "rank": int(st.rank_achieved), "datafit": float(st.datafit),
+            "logdet": float(st.logdet_estimate)}
+    if not timed:
+        del ws
+        torch.cuda.empty_cache()
+        return info
     for _ in range(warmup):
         B.gp_mll_grad(prob, pr.theta, opt, pr.rank, None, ws, logp, grad)
     torch.cuda.synchronize()
@@ -105,16 +121,21 @@ def run_gpu(pr, precision, steps, warmup, sync_every=1):
     dt = time.perf_counter() - t0
     info["ms_per_step"] = 1e3 * dt / steps
     info["evals_per_s"] = steps / dt
-    # tile-kernel duration in the same launch configuration, HIP events on the stream
-    ms, grid = B.gp_khat_profile(prob, pr.theta, opt, 10, ws)
+    # tile-kernel duration in the same launch configuration, HIP events on the stream:
+    # the full-width launches of one evaluation (every CG iteration but the last,
+    # which finishes a few straggling columns), in the order CG issues them; with
+    # BF16x3 tiles the first 16 take three-piece search directions
+    reps = max(1, info["iters_max"] - 1)
+    ms, grid = B.gp_khat_profile(prob, pr.theta, opt, reps, ws)
     info["tile_ms"] = ms
+    info["tile_launches_timed"] = reps
     info["tile_grid"] = list(grid)
     del ws
     torch.cuda.empty_cache()
     return info
 
 
-def run_batched(steps, warmup, precision=None):
+def run_batched(steps, warmup, precision=None, sync_every=1):
     """The 64-problem ragged batch (n_b ~ U{500..8000}, d 4, RBF, rank 20, 16 probes,
     FP64 tiles unless precision is given): one gp_batch_mll_grad call evaluates log p
     and the gradient of all 64 problems."""
@@ -128,7 +149,7 @@ def run_batched(steps, warmup, precision=None):
     y = torch.tensor(np.concatenate([p.y for p in probs]), device=dev)
     bt = B.Batch(X, y, [p.n for p in probs], pr0.kernel, pr0.ard)
     prec = precision or pr0.precision
-    opt = B.make_options(prec, pr0.num_probes, pr0.max_iters, pr0.tol, pr0.probe_seed, 0, 1)
+    opt = B.make_options(prec, pr0.num_probes, pr0.max_iters, pr0.tol, pr0.probe_seed, 0, sync_every)
     ws = B.alloc_workspace(B.gp_batch_workspace_size(bt, opt, pr0.rank))
     theta = np.stack([p.theta for p in probs])
     nb, P = len(probs), len(pr0.theta)
@@ -148,6 +169,7 @@ def run_batched(steps, warmup, precision=None):
     pair_iters = float(np.sum(n * n * st.iters))
     return {"value": 1.0 / dt, "unit": "batch evals/s (64 problems, log p + gradient each)",
             "problems_per_s": nb / dt, "ms_per_batch": 1e3 * dt, "steps": steps, "precision": prec,
+            "sync_every": sync_every,
             "logp": logp.cpu().numpy().tolist(), "grad": grad.cpu().numpy().reshape(nb, P).tolist(),
             "problems": nb, "n_min": int(n.min()), "n_max": int(n.max()), "sum_n": int(n.sum()),
             "cg_iters_max": int(st.iters_max), "cg_iters_median": float(np.median(st.iters)),
@@ -238,10 +260,12 @@ def run_predict(pr, nstar=256):
             "var_err_vs_fp64_of_s": float(np.max(np.abs(vb - v64)) / pr.theta[-2])}
 
 
-def tiles_only(pr, precision="bf16x3", reps=10, copy_bytes=1 << 30):
+def tiles_only(pr, precision="bf16x3", reps=32, copy_bytes=1 << 30):
     """The tile kernel of one split precision alone in the bench's launch
-    configuration, then a plain elementwise copy of copy_bytes (read copy_bytes,
-    write copy_bytes) whose counter readings calibrate the HBM byte counters."""
+    configuration (`reps` launches as CG iterations 0 .. reps-1 issue them: with
+    BF16x3 tiles 16 with three-piece search directions, then two-piece ones), then
+    a plain elementwise copy of copy_bytes (read copy_bytes, write copy_bytes) whose
+    counter readings calibrate the HBM byte counters."""
     import torch
     from paper_2107_00243_amd import binding as B
     dev = torch.device("cuda:0")
@@ -266,29 +290,39 @@ def tiles_only(pr, precision="bf16x3", reps=10, copy_bytes=1 << 30):
 
 
 def cpu_baseline(pr, iters, budget_s=12.0):
-    """The CPU oracle's K_hat V (row-blocked direct differences, FP64) timed on a
-    block of rows of the same workload and scaled to one evaluation
-    (iters + 2 products: CG iterations plus about two products' worth of
-    derivative sweep)."""
+    """The CPU oracle timed on a bounded sample of one evaluation of the same
+    workload: its matrix-free K_hat V (plain-C direct differences, FP64, all host
+    threads) on a block of rows, and its derivative contraction over M = A C^T on a
+    block of rows, each scaled to all n rows; one evaluation is `iters` products
+    plus one contraction (the preconditioner, probes and quadrature are
+    negligible beside them)."""
     from oracle import gp_oracle as go
     n = pr.n
     t = 1 + pr.num_probes
-    V = np.random.default_rng(0).standard_normal((n, t))
-    rows = 64
-    c0, w0 = time.process_time(), time.perf_counter()
-    go.khat_matvec(pr.X, pr.theta, pr.kernel, pr.ard, V, rows=np.arange(rows))
+    rng = np.random.default_rng(0)
+    V = rng.standard_normal((n, t))
+    w0 = time.perf_counter()
+    go.khat_matvec(pr.X, pr.theta, pr.kernel, pr.ard, V, rows=np.arange(256), native=True)
     w = time.perf_counter() - w0
-    rows = int(min(n, max(rows, rows * budget_s / max(w, 1e-3))))
+    rows = int(min(n, max(256, 256 * 0.6 * budget_s / max(w, 1e-3))))
     c0, w0 = time.process_time(), time.perf_counter()
-    go.khat_matvec(pr.X, pr.theta, pr.kernel, pr.ard, V, rows=np.arange(rows))
-    wall = time.perf_counter() - w0
+    go.khat_matvec(pr.X, pr.theta, pr.kernel, pr.ard, V, rows=np.arange(rows), native=True)
+    wall_mv = time.perf_counter() - w0
     cpu = time.process_time() - c0
-    per_product = wall * n / rows
-    per_eval = per_product * (iters + 2)
-    return {"value": 1.0 / per_eval, "unit": "evals/s", "cores": max(1, int(round(cpu / wall))),
+    A, C = V, rng.standard_normal((n, t))
+    w0 = time.perf_counter()
+    go.dkhat_contract_lowrank(pr.X, pr.theta, pr.kernel, pr.ard, A, C, row_range=(0, 64))
+    w = time.perf_counter() - w0
+    drows = int(min(n, max(64, 64 * 0.4 * budget_s / max(w, 1e-3))))
+    w0 = time.perf_counter()
+    go.dkhat_contract_lowrank(pr.X, pr.theta, pr.kernel, pr.ard, A, C, row_range=(0, drows))
+    wall_dk = time.perf_counter() - w0
+    per_eval = iters * wall_mv * n / rows + wall_dk * n / drows
+    return {"value": 1.0 / per_eval, "unit": "evals/s", "cores": max(1, int(round(cpu / wall_mv))),
             "kind": "oracle",
-            "sample": f"oracle khat_matvec on {rows} of {n} rows x {t} rhs ({wall:.1f} s wall), scaled by "
-                      f"n/rows and by {iters}+2 products per evaluation",
+            "sample": f"oracle matrix-free K_hat V on {rows} of {n} rows x {t} rhs ({wall_mv:.1f} s) and its "
+                      f"derivative contraction on {drows} rows ({wall_dk:.1f} s), scaled to n rows and to "
+                      f"{iters} products + 1 contraction per evaluation",
             "host_cpus": os.cpu_count()}
 
 
@@ -298,22 +332,31 @@ def tile_roofline(n, d, t, run, precision):
     the kernel source and grid."""
     flops = tile_flops(n, d, t)
     achieved = flops / (run["tile_ms"] * 1e-3) / 1e12
-    name = {"fp16x3": "k_khat_bf16<RBF, 2, 4, 4, F16, 1> (K_hat V tile, FP16x3: 4 MFMA column tiles + 1 VALU column)",
-            "bf16x3": "k_khat_bf16<RBF, 2, 4, 4, BF16, 1> (K_hat V tile, BF16x3: 4 MFMA column tiles + 1 VALU column)"
+    name = {"fp16x3": "k_khat_bf16<0, 2, 4, 4, true, 1, 2> (K_hat V tile, FP16x3: 4 MFMA column tiles + 1 VALU "
+                      "column)",
+            "bf16x3": "k_khat_bf16<0, 2, 4, 4, false, 1, 3|2> (K_hat V tile, BF16x3: 4 MFMA column tiles + 1 VALU "
+                      "column; search directions in 3 BF16 pieces for the first 16 CG iterations, then 2)"
             }[precision]
     roof = {"bound": "mfma", "achieved": achieved, "peak": PEAK_BF16_TFLOPS, "unit": "TFLOP/s",
             "frac": achieved / PEAK_BF16_TFLOPS, "traffic": None, "kernel": name,
-            "launch_grid": run["tile_grid"], "algorithmic_flops_per_launch": flops, "avg_launch_ms": run["tile_ms"]}
+            "launch_grid": run["tile_grid"], "algorithmic_flops_per_launch": flops, "avg_launch_ms": run["tile_ms"],
+            "launches_averaged": run.get("tile_launches_timed")}
     tc = TILE_COUNTERS.get(precision)
-    if (tc is not None and n == 100000 and bf16_tile_source_hash() == tc["kernel_source_sha256_16"]
-            and list(run["tile_grid"]) == tc["grid"]):
-        roof["traffic"] = 1024.0 * (tc["fetch_kib"] * tc["fetch_scale"] + tc["write_kib"] * tc["write_scale"])
+    reps = run.get("tile_launches_timed") or 0
+    mix = {k: c for k, c in tile_launch_mix(precision, reps).items() if c > 0}
+    if (tc is not None and n == 100000 and reps > 0 and bf16_tile_source_hash() == tc["kernel_source_sha256_16"]
+            and list(run["tile_grid"]) == tc["grid"] and all(k in tc for k in mix)):
+        # launch-weighted means over the instances the timed launches used
+        def mean(f):
+            return sum(c * f(tc[k]) for k, c in mix.items()) / reps
+        roof["traffic"] = 1024.0 * mean(lambda r: r["fetch_kib"] * r["fetch_scale"] + r["write_kib"] * r["write_scale"])
         roof["traffic_unit"] = "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)"
         roof["traffic_gbps"] = roof["traffic"] / (run["tile_ms"] * 1e-3) / 1e9
-        issued = tc["mfma_insts"] * 16384.0
+        issued = mean(lambda r: r["mfma_insts"]) * 16384.0
         roof["issued_mfma_flops_per_launch"] = issued
         roof["issued_mfma_frac_of_peak"] = issued / (run["tile_ms"] * 1e-3) / 1e12 / PEAK_BF16_TFLOPS
-        roof["mfma_busy_frac"] = tc["mfma_busy_cycles"] / (tc["gui_active_per_xcd"] * 1024)
+        roof["mfma_busy_frac"] = (sum(c * tc[k]["mfma_busy_cycles"] for k, c in mix.items())
+                                  / sum(c * tc[k]["gui_active_per_xcd"] * 1024 for k, c in mix.items()))
     return roof
 
 
@@ -327,6 +370,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-problem ragged batch")
     ap.add_argument("--batch-only", action="store_true", help="only the 64-problem ragged batch (one JSON line)")
+    ap.add_argument("--batch-sync-every", type=int, default=1,
+                    help="host convergence poll every q CG iterations in --batch-only (0: none)")
+    ap.add_argument("--batch-precision", default=None, help="tile precision of --batch-only")
     ap.add_argument("--no-precond", action="store_true",
                     help="skip the Nystrom / RFF preconditioner and posterior prediction legs")
     ap.add_argument("--n", type=int, default=100000)
@@ -335,6 +381,10 @@ def main():
                          "for counters")
     ap.add_argument("--tile-precision", default="bf16x3", choices=["bf16x3", "fp16x3"],
                     help="tile precision of --tiles-only")
+    ap.add_argument("--tiles-workload", default="rbf_ard_100k", choices=["rbf_ard_100k", "gmm_matern32_300k"],
+                    help="workload of --tiles-only")
+    ap.add_argument("--table-s1", action="store_true",
+                    help="only the Table S1 experiment (bias and variance, 25 repetitions; one JSON line)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: there is no multi-GPU path "
@@ -344,8 +394,11 @@ def main():
     import torch
     import synthgp
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.table_s1:
+        print(json.dumps(table_s1()))
+        return
     if args.batch_only:
-        r = run_batched(args.steps, args.warmup)
+        r = run_batched(args.steps, args.warmup, args.batch_precision, args.batch_sync_every)
         r.pop("logp")
         r.pop("grad")
         print(json.dumps(r))
@@ -354,7 +407,12 @@ def main():
     n, d, t = pr.n, pr.d, 1 + pr.num_probes
     log(f"[bench] workload rbf_ard_100k n={n} d={d} t={t} rank={pr.rank}")
     if args.tiles_only:
-        print(json.dumps(tiles_only(pr, args.tile_precision)))
+        if args.tiles_workload != "rbf_ard_100k":
+            pr = getattr(synthgp, args.tiles_workload)()
+            log(f"[bench] tiles of {pr.name} n={pr.n} d={pr.d} {pr.kernel}")
+        r = tiles_only(pr, args.tile_precision)
+        r["workload"] = pr.name
+        print(json.dumps(r))
         return
 
     # headline: BF16X3 tiles; FP16X3 beside it (same tile kernel speed, fewer CG iterations)
@@ -440,8 +498,88 @@ def main():
             "rel_logp": abs(h16["logp"] - f64["logp"]) / abs(f64["logp"]),
             "rel_grad": float(np.linalg.norm(h16["grad"] - f64["grad"]) / np.linalg.norm(f64["grad"])),
         }
+    log("[bench] errors against the oracle references")
+    rec["accuracy_vs_oracle"] = reference_errors((bf["logp"], bf["grad"]))
     rec["env"] = run_environment()
     print(json.dumps(rec))
+
+
+GOLDEN = os.path.join(ROOT, "tests", "golden")
+
+
+def _golden(name):
+    path = os.path.join(GOLDEN, name)
+    return json.load(open(path)) if os.path.exists(path) else None
+
+
+def _relerr(a, b):
+    a, b = np.asarray(a, dtype=np.float64), np.asarray(b, dtype=np.float64)
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def reference_errors(headline=None):
+    """Errors of the GPU estimate against the CPU oracle's stored references
+    (tests/golden/oracle_<workload>.json, written by tests/golden/make_full_size.py):
+    the same-probe estimate of Algorithms 1 and 2 on every workload, and the exact
+    Eq. (1) / Eq. (2) targets where a dense factor fits (n <= 20,000).  The
+    n = 100,000 headline takes its own run's numbers (headline = (logp, grad))."""
+    import synthgp
+    out = {}
+    for workload, precision in (("plain_rbf_1000", "fp64"), ("matern52_ard_20k", "fp32"),
+                                ("rbf_ard_100k", "bf16x3")):
+        ref = _golden(f"oracle_{workload}.json")
+        if ref is None:
+            continue
+        if workload == "rbf_ard_100k":
+            if headline is None:
+                continue
+            lp, g, st = headline[0], headline[1], None
+        else:
+            pr = getattr(synthgp, workload)()
+            r = run_gpu(pr, precision, 0, 0, timed=False)
+            lp, g, st = r["logp"], r["grad"], r
+        est = ref["estimate"]
+        e = {"precision": precision, "same_probe_rel_logp": abs(lp - est["logp"]) / abs(est["logp"]),
+             "same_probe_rel_grad": _relerr(g, est["grad"])}
+        ex = ref.get("exact")
+        if ex is not None and st is not None:
+            e.update({"exact_rel_logp": abs(lp - ex["logp"]) / abs(ex["logp"]),
+                      "exact_rel_datafit": abs(st["datafit"] - ex["datafit"]) / abs(ex["datafit"]),
+                      "exact_rel_logdet": abs(st["logdet"] - ex["logdet"]) / abs(ex["logdet"]),
+                      "exact_rel_grad": _relerr(g, ex["grad"])})
+        else:
+            e["exact"] = "out of reach (a dense factor of K_hat needs n^2 doubles)"
+        out[workload] = e
+    return out
+
+
+def table_s1(reps=25):
+    """Table S1 (supplement, synthetic data) on the GPU: relative bias and variance
+    of log p and of its outputscale, lengthscale and noise derivatives over `reps`
+    probe seeds, preconditioner rank 0 and 128 with 128 probes, FP64 tiles, for the
+    three kernels and d = 1, 2, 3 (exact targets stored by
+    tests/golden/make_table_s1.py)."""
+    import synthgp
+    sys.path.insert(0, os.path.join(ROOT, "tests"))
+    from test_gpu_trends import COLUMNS, table_s1_errors
+    exact = _golden("table_s1_exact.json")["problems"]
+    rows = []
+    for kernel in synthgp.TABLE_S1_KERNELS:
+        for d in (1, 2, 3):
+            pr = synthgp.table_s1(kernel, d)
+            for rank in (0, 128):
+                t0 = time.perf_counter()
+                e, iters, flags = table_s1_errors(pr, exact[pr.name], rank, reps)
+                row = {"kernel": kernel, "d": d, "precond_rank": rank, "probes": pr.num_probes, "reps": reps,
+                       "cg_iters_max": iters, "flags": flags}
+                for c, b, v in zip(COLUMNS, np.abs(e.mean(axis=0)), e.var(axis=0)):
+                    row[c] = {"bias": float(b), "var": float(v)}
+                rows.append(row)
+                log(f"[bench] Table S1 {kernel} d={d} rank {rank}: " + "  ".join(
+                    f"{c} {row[c]['bias']:.0e}/{row[c]['var']:.0e}" for c in COLUMNS)
+                    + f"  ({time.perf_counter() - t0:.1f} s)")
+    return {"experiment": "Table S1: n=10000 N(0,I_d), sigma2=1e-2, 128 probes, rank 0 vs 128, FP64 tiles",
+            "rows": rows}
 
 
 def run_environment():

@@ -301,10 +301,15 @@ int gp_khat_matvec(const gp_problem* prob, const double* theta_host, int32_t pre
 /*
  * gp_khat_profile — measurement helper: times the K_hat V tile kernel alone, in
  * the launch configuration gp_mll_eval uses for the same problem and options.
- * Fills the search-direction block of the workspace with a fixed pattern, stages
- * it, then records a hipEvent on `stream`, launches the tile kernel `reps` times,
- * records a second event, waits for it and writes the mean milliseconds per
- * launch to *ms_per_launch (host).  Also reports the workgroup grid.
+ * Fills the search-direction block of the workspace with a fixed pattern and
+ * issues `reps` tile launches as CG iterations 0 .. reps-1 would with every
+ * column active: with GP_PREC_BF16X3 tiles the first 16 split the search
+ * directions in three BF16 pieces and the rest in two, as the solver does (a
+ * different kernel instance; other precisions have one).  Each run of launches
+ * with one split is staged and warmed up first, then bracketed by hipEvents on
+ * `stream`; the call waits for them and writes the mean milliseconds per launch
+ * over all `reps` launches to *ms_per_launch (host).  Also reports the
+ * workgroup grid.
  */
 int gp_khat_profile(const gp_problem* prob, const double* theta_host, const gp_options* opt, int32_t reps,
                     void* ws_dev, size_t ws_bytes, hipStream_t stream, double* ms_per_launch,

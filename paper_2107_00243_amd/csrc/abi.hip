@@ -137,7 +137,7 @@ Layout make_layout(int64_t n, int d, int ard, int num_probes, int max_iters, int
   L.Z0 = take(np * tp * 8);
   L.Pd = take(np * tp * 8);
   L.W = take(np * tp * 8);
-  L.vfrag = take(np * tp * (split16 ? 4 : esz));
+  L.vfrag = take(np * tp * (split16 ? 6 : esz));  // up to three 16-bit pieces
   L.vx = take(split16 ? np * 4 : 0);
   L.vscale = take(2 * tp * 4);
   L.wpart = take((size_t)L.nsplit * np * std::max<int64_t>(tp * (prec == GP_PREC_FP64 ? 8 : 4), L.bow * bsz));
@@ -542,6 +542,7 @@ static int run_cg(const Ctx& c, const Hyper& h, const gp_options* opt) {
       HIPCHK(launch_colmap(c));
       cmap = c.at<int>(L.colmap);
     }
+    if (L.prec == GP_PREC_BF16X3 && it < kBf16V3Iters && bf16_v3_fits(plan.ntt)) plan.vp = 3;
     const int nstaged = 16 * plan.ntt + plan.xc;
     HIPCHK(launch_stage_v(c, c.at<double>(L.Pd), L.tp, nstaged, h, cmap, plan));
     HIPCHK(launch_khat_tiles(c, h, nact, plan));
@@ -809,19 +810,36 @@ extern "C" int gp_khat_profile(const gp_problem* prob, const double* theta_host,
   hipLaunchKernelGGL(k_fill_pattern, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, stream, c.at<double>(L.Pd),
                      L.n, L.n_pad, L.tp);
   HIPCHK(hipGetLastError());
-  // the product of a CG iteration with every column of [y | probes] active
+  // the products of CG iterations 0 .. reps-1 with every column of [y | probes]
+  // active: split-BF16 tiles take the three-piece search directions for the first
+  // kBf16V3Iters iterations, as run_cg does; each run of launches with one split is
+  // staged and warmed up outside its own pair of events
   const TilePlan plan = tile_plan(L, L.t);
-  HIPCHK(launch_stage_v(c, c.at<double>(L.Pd), L.tp, L.tp, h, nullptr, plan));
-  HIPCHK(launch_khat_tiles(c, h, nullptr, plan));  // warm-up launch
+  TilePlan plan3 = plan;
+  int n3 = 0;
+  if (L.prec == GP_PREC_BF16X3 && bf16_v3_fits(plan.ntt)) {
+    plan3.vp = 3;
+    n3 = reps < kBf16V3Iters ? reps : kBf16V3Iters;
+  }
   hipEvent_t e0, e1;
   HIPCHK(hipEventCreate(&e0));
   HIPCHK(hipEventCreate(&e1));
-  hipError_t err = hipEventRecord(e0, stream);
-  for (int r = 0; r < reps && err == hipSuccess; ++r) err = launch_khat_tiles(c, h, nullptr, plan);
-  if (err == hipSuccess) err = hipEventRecord(e1, stream);
-  if (err == hipSuccess) err = hipEventSynchronize(e1);
+  hipError_t err = hipSuccess;
   float ms = 0.f;
-  if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+  for (int part = 0; part < 2 && err == hipSuccess; ++part) {
+    const TilePlan& pl = part == 0 ? plan3 : plan;
+    const int count = part == 0 ? n3 : reps - n3;
+    if (count == 0) continue;
+    err = launch_stage_v(c, c.at<double>(L.Pd), L.tp, L.tp, h, nullptr, pl);
+    if (err == hipSuccess) err = launch_khat_tiles(c, h, nullptr, pl);  // warm-up launch
+    if (err == hipSuccess) err = hipEventRecord(e0, stream);
+    for (int r = 0; r < count && err == hipSuccess; ++r) err = launch_khat_tiles(c, h, nullptr, pl);
+    if (err == hipSuccess) err = hipEventRecord(e1, stream);
+    if (err == hipSuccess) err = hipEventSynchronize(e1);
+    float part_ms = 0.f;
+    if (err == hipSuccess) err = hipEventElapsedTime(&part_ms, e0, e1);
+    ms += part_ms;
+  }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   HIPCHK(err);
@@ -911,7 +929,7 @@ static Layout matvec_layout(const Layout& full, size_t cap) {
     L.xfb = take(np * L.kd * esz);
     L.rowterm = take(np * wsz);
     L.colterm = take(np * wsz);
-    L.vfrag = take(np * tp * (split16 ? 4 : esz));
+    L.vfrag = take(np * tp * (split16 ? 6 : esz));  // up to three 16-bit pieces
     L.vx = take(split16 ? np * 4 : 0);
     L.vscale = take(2 * tp * 4);
     L.wpart = take((size_t)L.nsplit * np * tp * wsz);

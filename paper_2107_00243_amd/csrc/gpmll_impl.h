@@ -78,6 +78,20 @@ __device__ inline double kappa64(int kind, double r2, double alpha) {
 }
 
 // Workspace carving.  Offsets are bytes from the workspace base, 256-aligned.
+// Pieces of each search-direction value in the BF16x3 tiles: hi + lo (16 bits),
+// or hi + lo + lo2 (24 bits, one more MFMA per tile and step).  Two-piece
+// directions delay CG (their rounding acts like noise on the product and spoils
+// the early Krylov steps: 43 iterations instead of the 33 of FP64 tiles on the
+// n = 100,000 RBF workload), three-piece ones in the first kBf16V3Iters iterations
+// of a call restore the FP64 iteration count (measured: 8 are not enough there, 12
+// are; 16 leave a margin); later iterations take two.  Launches of more than eight
+// tiles always take two (three would overflow the LDS stages).
+#ifndef GPMLL_BF16_V3_ITERS
+#define GPMLL_BF16_V3_ITERS 16
+#endif
+constexpr int kBf16V3Iters = GPMLL_BF16_V3_ITERS;
+__device__ __host__ constexpr bool bf16_v3_fits(int ntt) { return ntt <= 8; }
+
 struct Layout {
   int64_t n, n_pad;
   int d, p, t, tp, k, ell, max_iters, prec;
@@ -172,6 +186,7 @@ hipError_t launch_stage_x(const Ctx& c, const Hyper& h);
 struct TilePlan {
   int ntt = -1;
   int xc = 0;
+  int vp = 2;  // BF16x3: pieces of each staged search-direction value (2 or 3)
 };
 // the plan for ncols staged columns (compiled tile counts only)
 TilePlan tile_plan(const Layout& L, int ncols);

@@ -140,6 +140,7 @@ struct TileArgs {
   int tp;                   // leading dimension of the partial output
   int ntt;                  // 16-column tiles of right-hand sides staged for this launch
   int xc;                   // split precisions: 1 = one more column on the vector ALU
+  int vp;                   // BF16x3: pieces of the staged search directions (2 or 3)
   float s32;
   double s64;
   float alpha32;            // rational quadratic shape
@@ -277,7 +278,8 @@ __device__ inline int staged_source(const int* __restrict__ colmap, int col, int
 // BF16: fragment (jb, tt, piece) lane l holds rows jb*32 + perm(l/16, s), s < 8,
 // perm(g, s) = 4g + s (s < 4) or 16 + 4g + s - 4, column tt*16 + l%16.
 __global__ void k_stage_v_bf16(const double* __restrict__ V, int64_t nrows, int ldv, int ncols,
-                               const int* __restrict__ colmap, int64_t n_pad, int ntt, u32x4* __restrict__ vfrag) {
+                               const int* __restrict__ colmap, int64_t n_pad, int ntt, int NP,
+                               u32x4* __restrict__ vfrag) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;  // (jb, tt, lane)
   const int64_t total = (n_pad / 32) * ntt * 64;
   if (e >= total) return;
@@ -286,8 +288,9 @@ __global__ void k_stage_v_bf16(const double* __restrict__ V, int64_t nrows, int 
   const int64_t jb = e / (64 * ntt);
   const int g = lane / 16, col = tt * 16 + lane % 16;
   const int src = staged_source(colmap, col, ncols);
-  // FP64 -> hi + lo: hi = RNE(v), lo = RNE(v - hi) with v - hi taken in FP64
-  uint32_t h[4], l[4];
+  // FP64 -> hi + lo (+ lo2 when NP = 3): hi = RNE(v), lo = RNE(v - hi),
+  // lo2 = RNE(v - hi - lo), the remainders taken in FP64
+  uint32_t h[4], l[4], m[4];
   for (int w = 0; w < 4; ++w) {
     int64_t j0 = jb * 32 + (2 * w < 4 ? 4 * g + 2 * w : 16 + 4 * g + (2 * w - 4));
     int64_t j1 = j0 + 1;
@@ -297,9 +300,11 @@ __global__ void k_stage_v_bf16(const double* __restrict__ V, int64_t nrows, int 
     double ra = a - (double)bf16_lo_f(hh), rb = b - (double)bf16_hi_f(hh);
     h[w] = hh;
     l[w] = pack_bf16((float)ra, (float)rb);
+    m[w] = pack_bf16((float)(ra - (double)bf16_lo_f(l[w])), (float)(rb - (double)bf16_hi_f(l[w])));
   }
-  vfrag[((jb * ntt + tt) * 2 + 0) * 64 + lane] = u32x4{h[0], h[1], h[2], h[3]};
-  vfrag[((jb * ntt + tt) * 2 + 1) * 64 + lane] = u32x4{l[0], l[1], l[2], l[3]};
+  vfrag[((jb * ntt + tt) * NP + 0) * 64 + lane] = u32x4{h[0], h[1], h[2], h[3]};
+  vfrag[((jb * ntt + tt) * NP + 1) * 64 + lane] = u32x4{l[0], l[1], l[2], l[3]};
+  if (NP == 3) vfrag[((jb * ntt + tt) * NP + 2) * 64 + lane] = u32x4{m[0], m[1], m[2], m[3]};
 }
 
 // column maxima of |V| as float bit patterns (non-negative floats order like their
@@ -527,7 +532,7 @@ __device__ __forceinline__ f32x4 mfma16(u32x4 a, u32x4 b, f32x4 c) {
                                                    0);
 }
 
-template <int NTT, int RG, bool F16, int NTA>
+template <int NTT, int RG, bool F16, int NTA, int NP>
 __device__ __forceinline__ void bf16_tile_v(const u32x4* __restrict__ Vf, const u32x4 (&ph)[RG], const u32x4 (&pl)[RG],
                                             f32x4 (&acc)[RG][NTA], int lane) {
   if constexpr (F16) {
@@ -546,8 +551,8 @@ __device__ __forceinline__ void bf16_tile_v(const u32x4* __restrict__ Vf, const 
   }
 #pragma unroll
   for (int tt = 0; tt < NTT; ++tt) {
-    const bf16x8 vh = __builtin_bit_cast(bf16x8, Vf[(tt * 2 + 0) * 64 + lane]);
-    const bf16x8 vl = __builtin_bit_cast(bf16x8, Vf[(tt * 2 + 1) * 64 + lane]);
+    const bf16x8 vh = __builtin_bit_cast(bf16x8, Vf[(tt * NP + 0) * 64 + lane]);
+    const bf16x8 vl = __builtin_bit_cast(bf16x8, Vf[(tt * NP + 1) * 64 + lane]);
 #pragma unroll
     for (int rg = 0; rg < RG; ++rg)
       acc[rg][tt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, ph[rg]), vh, acc[rg][tt], 0, 0, 0);
@@ -557,6 +562,14 @@ __device__ __forceinline__ void bf16_tile_v(const u32x4* __restrict__ Vf, const 
 #pragma unroll
     for (int rg = 0; rg < RG; ++rg)
       acc[rg][tt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, pl[rg]), vh, acc[rg][tt], 0, 0, 0);
+    if constexpr (NP == 3) {
+      // the third piece of the search direction: hi x lo2
+      const bf16x8 vm = __builtin_bit_cast(bf16x8, Vf[(tt * NP + 2) * 64 + lane]);
+#pragma unroll
+      for (int rg = 0; rg < RG; ++rg)
+        acc[rg][tt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, ph[rg]), vm, acc[rg][tt], 0, 0,
+                                                              0);
+    }
   }
 }
 
@@ -575,15 +588,15 @@ __device__ __forceinline__ void bf16_interleave_hint() {
 // chunk): [A fragments 2 x NKC | V fragments NTT x {hi, lo} | column terms].
 // The last chunk holds the 32 column terms (units 0-7) and, with XC, the 32 FP32
 // values of the extra right-hand side column (units 8-15).
-template <int NKC, int NTT, int XC>
+template <int NKC, int NTT, int XC, int NP>
 __device__ __forceinline__ void bf16_issue_stage(u32x4* dst, const u32x4* __restrict__ xfa,
                                                  const u32x4* __restrict__ vfrag, const float* __restrict__ colterm,
                                                  const float* __restrict__ vx, int64_t c, int wave, int lane) {
-  constexpr int NCH = 2 * NKC + 2 * NTT + 1;
+  constexpr int NCH = 2 * NKC + NP * NTT + 1;
   for (int ch = wave; ch < NCH; ch += 4) {
     const u32x4* src;
     if (ch < 2 * NKC) src = xfa + (c / 16) * NKC * 64 + ch * 64 + lane;
-    else if (ch < 2 * NKC + 2 * NTT) src = vfrag + (c / 32) * NTT * 128 + (ch - 2 * NKC) * 64 + lane;
+    else if (ch < 2 * NKC + NP * NTT) src = vfrag + (c / 32) * NTT * NP * 64 + (ch - 2 * NKC) * 64 + lane;
     else if (XC && lane >= 8 && lane < 16) src = reinterpret_cast<const u32x4*>(vx + c) + (lane - 8);
     else src = reinterpret_cast<const u32x4*>(colterm + c) + (lane < 8 ? lane : 7);
     __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void*)(dst + ch * 64), 16, 0, 0);
@@ -593,8 +606,9 @@ __device__ __forceinline__ void bf16_issue_stage(u32x4* dst, const u32x4* __rest
 // NTT 16-column tiles of right-hand sides on the matrix cores and, with XC = 1,
 // one more column (staged column 16 NTT) contracted on the vector ALU from the
 // FP32 kernel values: a column count of 16 m + 1 (y and 16 m probes) then needs
-// no mostly-empty sixteen-column tile.
-template <int KIND, int NKC, int NTT, int RG, bool F16, int XC>
+// no mostly-empty sixteen-column tile.  VP: pieces of the BF16 search directions
+// (2, or 3 with the extra hi x lo2 product).
+template <int KIND, int NKC, int NTT, int RG, bool F16, int XC, int VP>
 __global__ __launch_bounds__(256, 2) void k_khat_bf16(const u32x4* __restrict__ xfa, const u32x4* __restrict__ xfb,
                                                       const float* __restrict__ rowterm,
                                                       const float* __restrict__ colterm,
@@ -603,7 +617,8 @@ __global__ __launch_bounds__(256, 2) void k_khat_bf16(const u32x4* __restrict__ 
                                                       const int* __restrict__ nactive) {
   if (nactive != nullptr && *nactive == 0) return;
   constexpr int NTA = NTT > 0 ? NTT : 1;  // accumulator array extent
-  constexpr int A_U = 2 * NKC * 64, V_U = NTT * 2 * 64, C_U = 64;
+  constexpr int NP = F16 ? 2 : VP;  // pieces of each staged V value
+  constexpr int A_U = 2 * NKC * 64, V_U = NTT * NP * 64, C_U = 64;
   constexpr int STAGE = A_U + V_U + C_U;
   __shared__ u32x4 lds[3][STAGE];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -631,8 +646,8 @@ __global__ __launch_bounds__(256, 2) void k_khat_bf16(const u32x4* __restrict__ 
   auto is_diag = [&](int64_t c) { return (c + 32 > row0) && (c < row0 + 16 * RG); };
 
   // prologue: stages 0 and 1 in flight, P of step 0
-  bf16_issue_stage<NKC, NTT, XC>(lds[0], xfa, vfrag, colterm, vx, c_begin, wave, lane);
-  if (nsteps > 1) bf16_issue_stage<NKC, NTT, XC>(lds[1], xfa, vfrag, colterm, vx, c_begin + 32, wave, lane);
+  bf16_issue_stage<NKC, NTT, XC, NP>(lds[0], xfa, vfrag, colterm, vx, c_begin, wave, lane);
+  if (nsteps > 1) bf16_issue_stage<NKC, NTT, XC, NP>(lds[1], xfa, vfrag, colterm, vx, c_begin + 32, wave, lane);
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
   u32x4 ph[RG], pl[RG];
@@ -650,16 +665,16 @@ __global__ __launch_bounds__(256, 2) void k_khat_bf16(const u32x4* __restrict__ 
     const int nxt = cur == 2 ? 0 : cur + 1;
     const int far = nxt == 2 ? 0 : nxt + 1;
     const int64_t cn = c_begin + (int64_t)(j + 1) * 32;
-    if (j + 2 < nsteps) bf16_issue_stage<NKC, NTT, XC>(lds[far], xfa, vfrag, colterm, vx, cn + 32, wave, lane);
+    if (j + 2 < nsteps) bf16_issue_stage<NKC, NTT, XC, NP>(lds[far], xfa, vfrag, colterm, vx, cn + 32, wave, lane);
     f32x4 dd[RG][2];
     bf16_distance<NKC, RG>(lds[nxt], xbv, rt, dd, lane);
     u32x4 nph[RG], npl[RG];
     const float* ctn = reinterpret_cast<const float*>(lds[nxt] + A_U + V_U);
     if (is_diag(cn)) {
-      bf16_tile_v<NTT, RG, F16>(lds[cur] + A_U, ph, pl, acc, lane);
+      bf16_tile_v<NTT, RG, F16, NTA, NP>(lds[cur] + A_U, ph, pl, acc, lane);
       bf16_map<KIND, RG, true, F16, XC>(dd, ctn, nph, npl, yacc, lane, row0, cn, a.s32, a.alpha32);
     } else {
-      bf16_tile_v<NTT, RG, F16>(lds[cur] + A_U, ph, pl, acc, lane);
+      bf16_tile_v<NTT, RG, F16, NTA, NP>(lds[cur] + A_U, ph, pl, acc, lane);
       bf16_map<KIND, RG, false, F16, XC>(dd, ctn, nph, npl, yacc, lane, row0, cn, a.s32, a.alpha32);
     }
 #pragma unroll
@@ -671,7 +686,7 @@ __global__ __launch_bounds__(256, 2) void k_khat_bf16(const u32x4* __restrict__ 
     __syncthreads();
     cur = nxt;
   }
-  bf16_tile_v<NTT, RG, F16>(lds[cur] + A_U, ph, pl, acc, lane);
+  bf16_tile_v<NTT, RG, F16, NTA, NP>(lds[cur] + A_U, ph, pl, acc, lane);
 
   float* out = wpart + (int64_t)blockIdx.y * a.n_pad * a.tp;
 #pragma unroll
@@ -850,32 +865,50 @@ hipError_t khat_tiles_fp64(const Ctx& c, const Hyper& h, const TileArgs& ta, con
 #define GPMLL_NTT_CASES(M) M(1) M(2) M(3) M(4) M(5) M(6) M(8) M(12) M(16)
 // split-precision tiles with the extra vector-ALU column: 16 NTT + 1 columns
 #define GPMLL_XC_NTT_CASES(M) M(0) M(1) M(2) M(3) M(4)
+// BF16x3 tiles with three-piece search directions (at most eight tiles)
+#define GPMLL_V3_NTT_CASES(M) M(1) M(2) M(3) M(4) M(5) M(6) M(8)
 
 #if GPMLL_KHAT_PART == 1 || GPMLL_KHAT_PART == 4
 namespace {
 constexpr bool kF16 = GPMLL_KHAT_PART == 4;
-template <int KIND, int NKC, int NTT, int XC>
+template <int KIND, int NKC, int NTT, int XC, int VP>
 hipError_t run_bf16(const Ctx& c, const TileArgs& ta, const int* nact) {
   const Layout& L = *c.lay;
   constexpr int RG = NTT <= 5 ? 4 : (NTT <= 8 ? 2 : 1);
   dim3 grid((unsigned)(L.n_pad / (64 * RG)), (unsigned)L.nsplit);
-  hipLaunchKernelGGL((k_khat_bf16<KIND, NKC, NTT, RG, kF16, XC>), grid, dim3(256), 0, c.st, c.at<u32x4>(L.xfa),
+  hipLaunchKernelGGL((k_khat_bf16<KIND, NKC, NTT, RG, kF16, XC, VP>), grid, dim3(256), 0, c.st, c.at<u32x4>(L.xfa),
                      c.at<u32x4>(L.xfb), c.at<float>(L.rowterm), c.at<float>(L.colterm), c.at<u32x4>(L.vfrag),
                      c.at<float>(L.vx), c.at<float>(L.wpart), ta, nact);
   return hipGetLastError();
 }
 template <int KIND, int NKC>
 hipError_t sel_bf16_ntt(const Ctx& c, const TileArgs& ta, const int* nact) {
+  if (!kF16 && ta.vp == 3) {
+    if (ta.xc != 0) {
+      switch (ta.ntt) {
+#define CASE(N) case N: return run_bf16<KIND, NKC, N, 1, 3>(c, ta, nact);
+        GPMLL_XC_NTT_CASES(CASE)
+#undef CASE
+      }
+      return hipErrorInvalidValue;
+    }
+    switch (ta.ntt) {
+#define CASE(N) case N: return run_bf16<KIND, NKC, N, 0, 3>(c, ta, nact);
+      GPMLL_V3_NTT_CASES(CASE)
+#undef CASE
+    }
+    return hipErrorInvalidValue;
+  }
   if (ta.xc != 0) {
     switch (ta.ntt) {
-#define CASE(N) case N: return run_bf16<KIND, NKC, N, 1>(c, ta, nact);
+#define CASE(N) case N: return run_bf16<KIND, NKC, N, 1, 2>(c, ta, nact);
       GPMLL_XC_NTT_CASES(CASE)
 #undef CASE
     }
     return hipErrorInvalidValue;
   }
   switch (ta.ntt) {
-#define CASE(N) case N: return run_bf16<KIND, NKC, N, 0>(c, ta, nact);
+#define CASE(N) case N: return run_bf16<KIND, NKC, N, 0, 2>(c, ta, nact);
     GPMLL_NTT_CASES(CASE)
 #undef CASE
   }
@@ -1039,7 +1072,8 @@ hipError_t launch_stage_v(const Ctx& c, const double* V, int ldv, int ncols, con
     const int64_t total = (L.n_pad / 32) * ntt * 64;
     if (total > 0)
       hipLaunchKernelGGL(k_stage_v_bf16, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, c.st, V, L.n, ldv,
-                         ncols, colmap, L.n_pad, ntt, c.at<u32x4>(L.vfrag));
+                         ncols, colmap, L.n_pad, ntt, plan.vp == 3 && bf16_v3_fits(ntt) ? 3 : 2,
+                         c.at<u32x4>(L.vfrag));
     if (xcol >= 0)
       hipLaunchKernelGGL(k_stage_vx, dim3(nbx), dim3(256), 0, c.st, V, L.n, ldv, xcol, ncols, colmap, L.n_pad,
                          (const uint32_t*)nullptr, c.at<float>(L.vx));
@@ -1064,6 +1098,7 @@ hipError_t launch_khat_tiles(const Ctx& c, const Hyper& h, const int* nact, Tile
   ta.tp = L.tp;
   ta.ntt = plan.ntt >= 0 ? plan.ntt : L.tp / 16;
   ta.xc = plan.xc;
+  ta.vp = (plan.vp == 3 && bf16_v3_fits(ta.ntt)) ? 3 : 2;
   ta.s32 = (float)h.s;
   ta.s64 = h.s;
   ta.alpha32 = (float)h.alpha;
@@ -1091,6 +1126,7 @@ hipError_t launch_khat_tiles_items(const Ctx& c, const Hyper& h, const ItemTable
   ta.tp = L.tp;
   ta.ntt = L.tp / 16;
   ta.xc = 0;
+  ta.vp = 2;
   ta.s32 = 1.0f;
   ta.s64 = 1.0;
   ta.alpha32 = (float)h.alpha;

@@ -129,26 +129,40 @@ def test_fp32_batch_of_the_batched_recipe_at_reduced_sizes():
         assert relvec(g[b], ref["grad"]) < FP32_G, (b, g[b], ref["grad"])
 
 
-def test_full_64_problem_batch_against_oracle_samples():
-    # the 64-problem recipe with its FP64 tiles; oracle on the two smallest problems
+def test_full_64_problem_batch_against_the_oracle_reference():
+    # the 64-problem recipe with its FP64 tiles against the oracle's same-probe
+    # estimate of every problem (tests/golden/oracle_batched_rbf_64.json, written by
+    # tests/golden/make_full_size.py); the exact Eq. (1) / Eq. (2) errors are stated
+    import json
+    import os
+    ref = json.load(open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                                      "oracle_batched_rbf_64.json")))["problems"]
     probs = synthgp.batched_rbf_64()
+    assert [p.n for p in probs] == [r["n"] for r in ref]
     lp64, g64, st = run_batch(probs, "fp64", 20, 16, 1e-6, 2500)
     assert st.flags_any & B.FLAG_NOT_CONVERGED == 0
     assert np.all(st.rank == 20)
-    for b in np.argsort([p.n for p in probs])[:2]:
-        pr = probs[b]
-        say(f"[gpu] oracle for problem {b} n={pr.n}")
-        ref = go.estimate_mll(pr.X, pr.y, pr.theta, "rbf", False, 20, 16, 1e-6, 2500, 1 + int(b))
-        # same arithmetic; CG stops at 1e-6 on problems with cond(K_hat) up to ~1e6
-        assert rel(lp64[b], ref["logp"]) < 1e-6, (b, lp64[b], ref["logp"])
-        assert relvec(g64[b], ref["grad"]) < 1e-4, (b, g64[b], ref["grad"])
-    # FP32 tiles on the same batch: log p of every problem within the bar (the
-    # noise gradient of the worst-conditioned problems is not: FP32 rounding of
-    # K_hat entries is a visible fraction of sigma^2 ~ 2e-3 at n ~ 7000)
+    e_lp = np.array([rel(lp64[b], r["estimate"]["logp"]) for b, r in enumerate(ref)])
+    e_g = np.array([relvec(g64[b], r["estimate"]["grad"]) for b, r in enumerate(ref)])
+    x_lp = np.array([rel(lp64[b], r["exact"]["logp"]) for b, r in enumerate(ref)])
+    x_g = np.array([relvec(g64[b], r["exact"]["grad"]) for b, r in enumerate(ref)])
+    say(f"    same-probe oracle, all 64: log p rel <= {e_lp.max():.2e}, gradient rel <= {e_g.max():.2e}")
+    say(f"    exact (Eq. 1, Eq. 2): log p rel median {np.median(x_lp):.2e} max {x_lp.max():.2e}; "
+        f"gradient rel median {np.median(x_g):.2e} max {x_g.max():.2e}")
+    # same arithmetic; CG stops at 1e-6 on problems with cond(K_hat) up to ~1e6
+    assert e_lp.max() < 1e-6 and e_g.max() < 1e-4, (int(np.argmax(e_lp)), int(np.argmax(e_g)))
+    # FP32 tiles on the same batch: log p of every problem within 1e-4 of the
+    # oracle; the gradient error is stated (the noise component of the
+    # worst-conditioned problems moves by about 2 %: FP32 rounding of the K_hat
+    # entries is a visible fraction of sigma^2 ~ 2e-3 at n ~ 7000)
     lp32, g32, st32 = run_batch(probs, "fp32", 20, 16, 1e-6, 2500)
     assert st32.flags_any & B.FLAG_NOT_CONVERGED == 0
-    for b in range(len(probs)):
-        assert rel(lp32[b], lp64[b]) < FP32_LP, (b, lp32[b], lp64[b])
+    f_lp = np.array([rel(lp32[b], r["estimate"]["logp"]) for b, r in enumerate(ref)])
+    f_g = np.array([relvec(g32[b], r["estimate"]["grad"]) for b, r in enumerate(ref)])
+    say(f"    FP32 tiles against the same-probe oracle: log p rel <= {f_lp.max():.2e}; gradient rel median "
+        f"{np.median(f_g):.2e}, max {f_g.max():.2e} (problem {int(np.argmax(f_g))}), "
+        f"{int(np.sum(f_g < 1e-2))} of 64 within 1e-2")
+    assert f_lp.max() < 1e-4
 
 
 def test_batch_precond_grad_mode_one_and_no_preconditioner():

@@ -59,8 +59,9 @@ def max_case():
     return pr, ref
 
 
-@pytest.mark.parametrize("precision,lp_tol,g_tol", [("fp64", 1e-7, 1e-5), ("bf16x3", 1e-3, 1e-2),
-                                                    ("fp16x3", 1e-3, 1e-2)])
+# measured against the FP64 oracle: BF16x3 1.3e-7 / 1.4e-4, FP16x3 3.7e-8 / 1.5e-4
+@pytest.mark.parametrize("precision,lp_tol,g_tol", [("fp64", 1e-7, 1e-5), ("bf16x3", 1e-6, 1e-3),
+                                                    ("fp16x3", 2e-7, 1e-3)])
 def test_maximum_dimension_probes_and_rank_together(max_case, precision, lp_tol, g_tol):
     pr, ref = max_case
     say(f"[gpu] limits n=3000 d={B.MAX_D} ell={B.MAX_PROBES} rank={B.MAX_RANK} {precision}")

@@ -62,8 +62,10 @@ def test_ratquad_khat_matvec_matches_oracle(precision, alpha, n, d, nrhs):
     assert err < MATVEC_TOL[precision]
 
 
-@pytest.mark.parametrize("precision,lp_tol,g_tol", [("fp64", 1e-7, 1e-5), ("fp32", 1e-3, 1e-2),
-                                                     ("bf16x3", 1e-3, 1e-2), ("fp16x3", 1e-3, 1e-2)])
+# split and FP32 tiles: about five times the measured distance over both shapes
+# (FP32 1.4e-6 / 3.9e-5, BF16x3 1.4e-5 / 5.6e-4, FP16x3 1.0e-6 / 9.3e-5)
+@pytest.mark.parametrize("precision,lp_tol,g_tol", [("fp64", 1e-7, 1e-5), ("fp32", 1e-5, 2e-4),
+                                                     ("bf16x3", 1e-4, 5e-3), ("fp16x3", 1e-5, 5e-4)])
 @pytest.mark.parametrize("alpha,ard", [(0.8, True), (3.0, False)])
 def test_ratquad_estimator_and_gradient_match_oracle(alpha, ard, precision, lp_tol, g_tol):
     kind = f"ratquad:{alpha}"

@@ -1,22 +1,30 @@
-"""The trend of Table S1 / Fig. 3 on the HIP path: with a preconditioner of
-growing rank k and as many probes (ell = k), the bias and the variance of the
-log-likelihood estimate fall by orders of magnitude.  Synthetic n = 10,000,
-sigma^2 = 1e-2 as in the paper's experiment, with its three kernels (RBF,
-Matern-3/2, rational quadratic); X ~ N(0, I_d), unit lengthscale and
-outputscale, y drawn from the GP through random features (the paper leaves y
-and theta unspecified).  Exact log p from the oracle's dense Cholesky.  Marked gpu."""
+"""The Table S1 experiment on the HIP path (supplement, synthetic data): with
+ell = 128 probes, a rank-128 partial Cholesky preconditioner cuts the bias and the
+variance of the stochastic estimates of log p and of its derivatives with respect
+to the outputscale, the lengthscale and the noise, against no preconditioner
+(rank 0).  Synthetic n = 10,000, sigma^2 = 1e-2, d in {1, 2, 3}, the paper's three
+kernels (RBF, Matern-3/2, rational quadratic); the problems of synthgp.table_s1.
+Exact targets from the oracle's dense Cholesky, stored by
+tests/golden/make_table_s1.py.  Relative errors est / exact - 1 per quantity
+(scale-free, so the outputscale and noise parameterisation does not matter);
+bias = |mean|, variance over the repetitions.  bench.py --table-s1 runs the
+paper's 25 repetitions; the tests run 6.  Marked gpu."""
+import json
+import os
 import sys
 
 import numpy as np
 import pytest
 
 import synthgp
-from oracle import gp_oracle as go
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 from paper_2107_00243_amd import binding as B  # noqa: E402
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "table_s1_exact.json")
+COLUMNS = ("log p", "d/do", "d/dl", "d/dsigma")
 
 
 def say(msg):
@@ -24,41 +32,55 @@ def say(msg):
     sys.stdout.flush()
 
 
-@pytest.mark.parametrize("kernel,d", [("rbf", 1), ("rbf", 2), ("matern32", 1), ("ratquad:1.0", 1)])
-def test_bias_and_variance_fall_with_preconditioner_rank(kernel, d):
+def table_s1_errors(pr, exact, rank, reps, seed0=0):
+    """Relative errors (reps x 4) of log p and the outputscale, lengthscale and
+    noise derivatives from gp_mll_grad with FP64 tiles and `reps` probe seeds."""
+    dev = torch.device("cuda:0")
+    X, y = torch.tensor(pr.X, device=dev), torch.tensor(pr.y, device=dev)
+    prob = B.make_problem(X, y, pr.kernel, pr.ard)
+    opt = B.make_options("fp64", pr.num_probes, pr.max_iters, pr.tol, 1, 0, 1)
+    ws = B.alloc_workspace(B.gp_workspace_size(prob, opt, rank))
+    logp = torch.zeros(1, dtype=torch.float64, device=dev)
+    g = torch.zeros(3, dtype=torch.float64, device=dev)
+    ex = np.array([exact["logp"], exact["grad"][1], exact["grad"][0], exact["grad"][2]])
+    errs, iters, flags = [], 0, 0
+    for r in range(reps):
+        opt.seed = seed0 + 1009 * rank + r
+        st = B.Stats(pr.num_probes, rank)
+        B.gp_mll_grad(prob, pr.theta, opt, rank, None, ws, logp, g, st)
+        gr = g.cpu().numpy()
+        est = np.array([float(logp.cpu()[0]), gr[1], gr[0], gr[2]])
+        errs.append(est / ex - 1.0)
+        iters = max(iters, int(st.iters_max))
+        flags |= int(st.flags)
+    del ws
+    torch.cuda.empty_cache()
+    return np.array(errs), iters, flags
+
+
+@pytest.mark.parametrize("d", [1, 2, 3])
+@pytest.mark.parametrize("kernel", synthgp.TABLE_S1_KERNELS)
+def test_table_s1_preconditioning_cuts_bias_and_variance(kernel, d):
     if not torch.cuda.is_available():
         pytest.fail("no GPU visible")
-    n, s2 = 10000, 1e-2
-    rng = np.random.default_rng(100 + d)
-    X = rng.standard_normal((n, d))
-    theta = np.array([1.0, 1.0, s2])
-    y = synthgp.rff_targets(rng, X, 1.0, 1.0, s2, kernel)
-    exact = go.exact_mll(X, y, theta, kernel, False, grad=False)["logp"]
-    dev = torch.device("cuda:0")
-    Xd, yd = torch.tensor(X, device=dev), torch.tensor(y, device=dev)
-    prob = B.make_problem(Xd, yd, kernel, False)
-    logp = torch.zeros(1, dtype=torch.float64, device=dev)
-    stats = {}
-    for k in (2, 8, 32, 128):
-        opt = B.make_options("fp64", k, 2000, 1e-10, 1, 0, 1)
-        ws = B.alloc_workspace(B.gp_workspace_size(prob, opt, k))
-        vals, iters = [], []
-        for seed in range(8):
-            opt.seed = 1000 * k + seed
-            st = B.Stats(k, k)
-            B.gp_mll_eval(prob, theta, opt, k, None, ws, logp, st)
-            vals.append(float(logp.cpu()[0]))
-            iters.append(st.iters_max)
-        vals = np.array(vals)
-        bias = abs(vals.mean() - exact) / abs(exact)
-        var = float(vals.var())
-        stats[k] = (bias, var, float(vals.std()) / abs(exact))
-        say(f"[gpu] {kernel} d={d} k=ell={k}: rel bias {bias:.3e}, variance {var:.3e}, CG iterations <= {max(iters)}")
-        del ws
-    # the paper's trend: the variance falls by orders of magnitude from the smallest to
-    # the largest rank, and the error of the rank-128 mean is a small fraction of the
-    # spread of single rank-2 estimates (a sample mean of 8 estimates resolves the
-    # rank-2 bias itself only to that spread)
-    assert stats[128][1] < 1e-3 * stats[2][1]
-    assert stats[128][0] < 0.1 * stats[2][2] + 1e-12
-    assert stats[32][1] < stats[8][1] < stats[2][1]
+    pr = synthgp.table_s1(kernel, d)
+    exact = json.load(open(GOLDEN))["problems"][pr.name]
+    assert np.allclose(exact["theta"], pr.theta) and exact["n"] == pr.n
+    rows = {}
+    for rank in (0, 128):
+        e, iters, flags = table_s1_errors(pr, exact, rank, reps=6)
+        assert flags & B.FLAG_NOT_CONVERGED == 0
+        bias, var = np.abs(e.mean(axis=0)), e.var(axis=0)
+        rows[rank] = (bias, var)
+        say(f"[gpu] Table S1 {kernel} d={d} rank {rank:3d} (CG <= {iters}): "
+            + "  ".join(f"{c} {b:.0e}/{v:.0e}" for c, b, v in zip(COLUMNS, bias, var)))
+    # every column's variance falls with the rank-128 preconditioner, by more than
+    # tenfold in one dimension (Table S1: 1e2 to 1e7; measured here: about 60x for
+    # the Matern-3/2 derivatives, whose pivoted Cholesky error decays slowest); the
+    # rank-128 estimates stay well inside the spread of the unpreconditioned ones
+    b0, v0 = rows[0]
+    b1, v1 = rows[128]
+    assert np.all(v1 < v0)
+    if d == 1:
+        assert np.all(v1 < 0.1 * v0)
+    assert np.all(b1 < b0 + 3.0 * np.sqrt(v0 / 6))
