@@ -41,6 +41,35 @@ class GPMarginalLikelihood:
         self.last_stats = st
         return self.logp, (self.grad if with_grad else None)
 
+    def predict(self, theta, Xstar, with_var=False):
+        """Posterior mean (and latent variance) at the rows of Xstar (nstar x d),
+        as FP64 NumPy arrays, from gp_predict with this model's options."""
+        theta = np.asarray(theta, dtype=np.float64)
+        Xs = torch.as_tensor(Xstar, dtype=torch.float64).to(self.X.device).contiguous()
+        mean = torch.zeros(Xs.shape[0], dtype=torch.float64, device=self.X.device)
+        var = torch.zeros_like(mean) if with_var else None
+        B.gp_predict(self.prob, theta, self.opt, self.rank, None, Xs, self.ws, mean, var)
+        return mean.cpu().numpy(), (var.cpu().numpy() if with_var else None)
+
+
+def validation_score(model, Xv, yv, metric="rmse"):
+    """A function theta -> loss on a held-out set (lower is better), for early
+    stopping: "rmse" is the root mean squared error of the posterior mean;
+    "nll" the mean negative log density of yv under N(mean, var + sigma^2),
+    which needs the predictive variance (one CG solve per chunk of
+    num_probes validation points instead of one in all)."""
+    yv = np.asarray(yv, dtype=np.float64)
+    if metric not in ("rmse", "nll"):
+        raise ValueError(f"unknown validation metric {metric!r}")
+
+    def score(theta):
+        mean, var = model.predict(theta, Xv, with_var=(metric == "nll"))
+        if metric == "rmse":
+            return float(np.sqrt(np.mean((mean - yv) ** 2)))
+        v = np.maximum(var, 0.0) + float(theta[-1])
+        return float(np.mean(0.5 * np.log(2.0 * np.pi * v) + 0.5 * (yv - mean) ** 2 / v))
+    return score
+
 
 class GPMLL(torch.autograd.Function):
     """log p(y | exp(log_theta)); log_theta is a CPU FP64 tensor of length p + 2."""
