@@ -127,20 +127,20 @@ __device__ inline void kappa_g_t(int kind, T q, T s, T alpha, T* kap, T* sg) {
       const float b = fmaf(q0, 0.5f / alpha, 1.0f);
       const float k = __builtin_amdgcn_exp2f(-alpha * __builtin_amdgcn_logf(b));
       *kap = k;
-      *sg = s * k / b;
+      *sg = s * k * __builtin_amdgcn_rcpf(b);
     } else if (kind == GP_KERNEL_RBF) {
       const float e = __builtin_amdgcn_exp2f(-0.5f * log2e * q0);
       *kap = e;
       *sg = s * e;
     } else if (kind == GP_KERNEL_MATERN32) {
       const float a = 1.7320508075688772f;
-      const float r = __builtin_sqrtf(q0);
+      const float r = __builtin_amdgcn_sqrtf(q0);
       const float e = __builtin_amdgcn_exp2f(-a * log2e * r);
       *kap = fmaf(a, r, 1.0f) * e;
       *sg = s * 3.0f * e;
     } else {
       const float a = 2.23606797749979f;
-      const float r = __builtin_sqrtf(q0);
+      const float r = __builtin_amdgcn_sqrtf(q0);
       const float e = __builtin_amdgcn_exp2f(-a * log2e * r);
       *kap = fmaf(5.0f / 3.0f, q0, fmaf(a, r, 1.0f)) * e;
       *sg = s * (5.0f / 3.0f) * fmaf(a, r, 1.0f) * e;
@@ -382,7 +382,7 @@ __device__ inline void bw_map(float q, float s, float rbf_sg, float rbf_kap, flo
     const float b = 1.0f + fabsf(q);
     const float k = __builtin_amdgcn_exp2f(-alpha * __builtin_amdgcn_logf(b));
     *kap = k;
-    *sg = s * k / b;
+    *sg = s * k * __builtin_amdgcn_rcpf(b);
   } else if (KIND == GP_KERNEL_RBF) {
     const float k = __builtin_amdgcn_exp2f(q);  // q: log2 of the staged kernel value
     *sg = k * rbf_sg;
@@ -390,7 +390,7 @@ __device__ inline void bw_map(float q, float s, float rbf_sg, float rbf_kap, flo
   } else {
     // split-precision staging: q = rho^2 with rho = a log2(e) r, a r = ln2 rho
     const float ln2 = 0.6931471805599453f;
-    const float rho = __builtin_sqrtf(fabsf(q));
+    const float rho = __builtin_amdgcn_sqrtf(fabsf(q));
     const float e = __builtin_amdgcn_exp2f(-rho);
     const float ar = ln2 * rho;
     if (KIND == GP_KERNEL_MATERN32) {

@@ -93,7 +93,7 @@ __device__ inline float map_split(float q, float s, float alpha) {
     return s * __builtin_amdgcn_exp2f(-alpha * __builtin_amdgcn_logf(1.0f + fabsf(q)));
   } else {
     const float ln2 = 0.6931471805599453f;
-    const float rho = __builtin_sqrtf(fabsf(q));
+    const float rho = __builtin_amdgcn_sqrtf(fabsf(q));
     const float e = __builtin_amdgcn_exp2f(-rho);
     float poly;
     if (KIND == GP_KERNEL_MATERN32) poly = fmaf(s * ln2, rho, s);
@@ -111,13 +111,13 @@ __device__ inline float map32(float q, float s, float alpha) {
     return s * __builtin_amdgcn_exp2f(-alpha * __builtin_amdgcn_logf(fmaf(fmaxf(q, 0.0f), 0.5f / alpha, 1.0f)));
   } else if (KIND == GP_KERNEL_MATERN32) {
     const float a = 1.7320508075688772f;
-    float r = __builtin_sqrtf(fmaxf(q, 0.0f));
+    float r = __builtin_amdgcn_sqrtf(fmaxf(q, 0.0f));
     float e = __builtin_amdgcn_exp2f(-a * kLog2e * r);
     return s * fmaf(a, r, 1.0f) * e;
   } else {
     const float a = 2.23606797749979f;
     float q0 = fmaxf(q, 0.0f);
-    float r = __builtin_sqrtf(q0);
+    float r = __builtin_amdgcn_sqrtf(q0);
     float e = __builtin_amdgcn_exp2f(-a * kLog2e * r);
     return s * fmaf(5.0f / 3.0f, q0, fmaf(a, r, 1.0f)) * e;
   }
