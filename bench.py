@@ -45,18 +45,21 @@ PEAK_FP64_TFLOPS = 78.6
 V3_ITERS = 16          # the library's kBf16V3Iters
 TILE_COUNTERS = {
     "fp16x3": {
-        "kernel_source_sha256_16": "5ca15e675ba75ec5",
+        "kernel_source_sha256_16": "9401c72b157dcbbf",
         "grid": [391, 5],
         "v2": {"fetch_kib": 280109.0, "fetch_scale": 1048576.0 / 524315.0,
                "write_kib": 141670.0, "write_scale": 1.0,
                "mfma_insts": 3.131e8, "mfma_busy_cycles": 5.0096e9, "gui_active_per_xcd": 7.71078e7 / 8},
     },
     "bf16x3": {
-        "kernel_source_sha256_16": "5ca15e675ba75ec5",
+        "kernel_source_sha256_16": "369f22306a8f61d7",
         "grid": [391, 5],
-        "v2": {"fetch_kib": 280035.0, "fetch_scale": 1048576.0 / 524308.0,
-               "write_kib": 141297.0, "write_scale": 1.0,
-               "mfma_insts": 3.131e8, "mfma_busy_cycles": 5.0096e9, "gui_active_per_xcd": 7.71932e7 / 8},
+        "v3": {"fetch_kib": 363602.0, "fetch_scale": 1048576.0 / 524309.0,
+               "write_kib": 141345.0, "write_scale": 1.0,
+               "mfma_insts": 3.91375e8, "mfma_busy_cycles": 6.26201e9, "gui_active_per_xcd": 8.92932e7 / 8},
+        "v2": {"fetch_kib": 280107.0, "fetch_scale": 1048576.0 / 524309.0,
+               "write_kib": 141212.0, "write_scale": 1.0,
+               "mfma_insts": 3.131e8, "mfma_busy_cycles": 5.0096e9, "gui_active_per_xcd": 7.79578e7 / 8},
     },
 }
 
@@ -70,11 +73,13 @@ def tile_launch_mix(precision, reps):
 
 
 def bf16_tile_source_hash():
+    """First 16 hex digits of the SHA-256 of the tile kernel's sources (k_khat.hip
+    and the shared header gpmll_impl.h, whole)."""
     import hashlib
-    src = open(os.path.join(ROOT, "paper_2107_00243_amd", "csrc", "k_khat.hip")).read()
-    a = src.index("#if GPMLL_KHAT_PART == 1 || GPMLL_KHAT_PART == 4\n")
-    b = src.index("#endif  // parts 1, 4", a)
-    return hashlib.sha256(src[a:b].encode()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for f in ("k_khat.hip", "gpmll_impl.h"):
+        h.update(open(os.path.join(ROOT, "paper_2107_00243_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
 
 
 def log(msg):
@@ -443,10 +448,10 @@ def main():
     batched = None
     if not args.no_batch:
         log("[bench] 64-problem ragged batch")
-        batched = run_batched(2, 1)
+        batched = run_batched(2, 1, sync_every=8)
         log(f"[bench] batch: {batched['ms_per_batch']:.1f} ms per call, iters max {batched['cg_iters_max']}")
         # FP32 tiles on the same batch: faster, and how far from the FP64-tile results
-        b32 = run_batched(1, 0, "fp32")
+        b32 = run_batched(1, 0, "fp32", sync_every=8)
         lp64, lp32 = np.array(batched.pop("logp")), np.array(b32.pop("logp"))
         g64, g32 = np.array(batched.pop("grad")), np.array(b32.pop("grad"))
         relg = np.linalg.norm(g32 - g64, axis=1) / np.linalg.norm(g64, axis=1)
