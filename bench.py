@@ -45,11 +45,11 @@ PEAK_FP64_TFLOPS = 78.6
 V3_ITERS = 16          # the library's kBf16V3Iters
 TILE_COUNTERS = {
     "fp16x3": {
-        "kernel_source_sha256_16": "9401c72b157dcbbf",
+        "kernel_source_sha256_16": "369f22306a8f61d7",
         "grid": [391, 5],
-        "v2": {"fetch_kib": 280109.0, "fetch_scale": 1048576.0 / 524315.0,
-               "write_kib": 141670.0, "write_scale": 1.0,
-               "mfma_insts": 3.131e8, "mfma_busy_cycles": 5.0096e9, "gui_active_per_xcd": 7.71078e7 / 8},
+        "v2": {"fetch_kib": 280079.0, "fetch_scale": 1048576.0 / 524309.0,
+               "write_kib": 141653.0, "write_scale": 1.0,
+               "mfma_insts": 3.131e8, "mfma_busy_cycles": 5.0096e9, "gui_active_per_xcd": 7.71614e7 / 8},
     },
     "bf16x3": {
         "kernel_source_sha256_16": "369f22306a8f61d7",

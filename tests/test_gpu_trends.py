@@ -78,8 +78,11 @@ def test_table_s1_bias_and_variance_at_rank_0_and_128(kernel, d):
         # with solves run to convergence both estimators are unbiased (Theorems 4
         # and 5): the mean error over the repetitions stays within a few standard
         # errors of zero (t with REPS - 1 degrees of freedom, |t| > 6 has
-        # probability below 0.2 %)
-        assert np.all(np.abs(mean) <= 6.0 * np.sqrt(var / REPS) + 1e-12), (rank, mean, var)
+        # probability below 0.2 %), up to FP64 rounding of the whole evaluation
+        # against the oracle's dense factorisation (1e-7 relative; where rank 128
+        # makes the preconditioner exact the errors are that rounding alone, the
+        # same in every repetition)
+        assert np.all(np.abs(mean) <= 6.0 * np.sqrt(var / REPS) + 1e-7), (rank, mean, var)
     (b0, v0, it0), (b1, v1, it1) = rows[0], rows[128]
     # the preconditioned solves need fewer iterations in every case
     assert it1 < it0
