@@ -593,7 +593,8 @@ __device__ __forceinline__ void bf16_issue_stage(u32x4* dst, const u32x4* __rest
                                                  const u32x4* __restrict__ vfrag, const float* __restrict__ colterm,
                                                  const float* __restrict__ vx, int64_t c, int wave, int lane) {
   constexpr int NCH = 2 * NKC + NP * NTT + 1;
-  for (int ch = wave; ch < NCH; ch += 4) {
+  // the chunk walk is the same for the whole wave: keep it on the scalar unit
+  for (int ch = __builtin_amdgcn_readfirstlane(wave); ch < NCH; ch += 4) {
     const u32x4* src;
     if (ch < 2 * NKC) src = xfa + (c / 16) * NKC * 64 + ch * 64 + lane;
     else if (ch < 2 * NKC + NP * NTT) src = vfrag + (c / 32) * NTT * NP * 64 + (ch - 2 * NKC) * 64 + lane;

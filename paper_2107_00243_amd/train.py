@@ -248,7 +248,8 @@ def main(argv=None):
         validate = validation_score(model, Xv, yv, args.validation_metric)
         print(f"[{args.optimizer}] {len(yv)} validation points ({args.validation_metric}), patience "
               f"{args.patience}", flush=True)
-    print(f"[{args.optimizer}] {pr.name}: n={pr.n} d={pr.d} {pr.kernel} rank={pr.rank} probes={pr.num_probes} "
+    print(f"[{args.optimizer}] {pr.name}: n={len(y)} training points of {pr.n}, d={pr.d} {pr.kernel} rank={pr.rank} "
+          f"probes={pr.num_probes} "
           f"max_iters={pr.max_iters} precision={args.precision}", flush=True)
     fit = adam_fit if args.optimizer == "adam" else lbfgs_fit
     lr = args.lr if args.optimizer == "adam" or args.lr != 0.1 else 1.0
