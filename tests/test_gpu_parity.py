@@ -246,6 +246,22 @@ def test_rbf_ard_100k_recipe_at_reduced_n_split_precision(precision, lp_tol, g_t
     _check_tight(out, ref, lp_tol, g_tol)
 
 
+@pytest.mark.parametrize("precision,lp_tol,g_tol", [("bf16x3", 5e-7, 5e-4), ("fp16x3", 5e-7, 5e-4)])
+def test_gmm_matern32_recipe_at_reduced_n_split_precision(precision, lp_tol, g_tol):
+    # measured 6.8e-8 / 5.7e-5 (BF16x3), 2.9e-8 / 5.3e-5 (FP16x3)
+    # the n = 300,000 Adam workload (Matern-3/2 ARD in d = 20: three distance
+    # K-chunks, the square-root map) at n = 3,000 with its rank 200 and 64 probes,
+    # at a theta like the one its Adam run reaches (lengthscales 2.5, s 1.2,
+    # sigma^2 0.07; 24 CG iterations, where the starting theta needs 8): log p and
+    # the full gradient against the oracle on the same probes
+    pr = synthgp.gmm_matern32_300k(n=3000)
+    pr.theta = np.concatenate([np.full(20, 2.5), [1.2, 0.07]])
+    out = run_estimator(pr, precision)
+    ref = oracle(pr)
+    assert out["stats"].flags & B.FLAG_NOT_CONVERGED == 0
+    _check_tight(out, ref, lp_tol, g_tol)
+
+
 @pytest.mark.parametrize("precond_grad", [0, 1])
 def test_precond_grad_modes(precond_grad):
     pr = synthgp.random_problem(900, 3, "matern32", ard=True, seed=5, rank=15, num_probes=8, tol=1e-8)
