@@ -403,6 +403,28 @@ __device__ inline void bw_map(float q, float s, float rbf_sg, float rbf_kap, flo
   }
 }
 
+// One step's operands of the split-precision derivative sweep, global -> LDS
+// without registers (each wave instruction moves one contiguous 1 KB chunk):
+// [A fragments 2 NKC | C' fragments 2 NKM | [x~ | x~^2] fragments 2 NXT | column
+// terms (units 0-7 of the last chunk)].  The chunk walk is wave-uniform.
+template <int NKC, int NKM, int NXT>
+__device__ __forceinline__ void bwd_issue_stage(u32x4* dst, const u32x4* __restrict__ xfa,
+                                                const u32x4* __restrict__ cfr, const u32x4* __restrict__ xau,
+                                                const float* __restrict__ colterm, int64_t c, int wave, int lane) {
+  constexpr int NA = 2 * NKC, NC = 2 * NKM, NX = 2 * NXT;
+  constexpr int NCH = NA + NC + NX + 1;
+  for (int ch = __builtin_amdgcn_readfirstlane(wave); ch < NCH; ch += 4) {
+    const u32x4* src;
+    if (ch < NA) src = xfa + (c / 16) * NKC * 64 + ch * 64 + lane;
+    else if (ch < NA + NC) src = cfr + (c / 16) * NKM * 64 + (ch - NA) * 64 + lane;
+    else if (ch < NA + NC + NX) src = xau + (c / 32) * NXT * 128 + (ch - NA - NC) * 64 + lane;
+    else src = reinterpret_cast<const u32x4*>(colterm + c) + (lane < 8 ? lane : 7);
+    __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void*)(dst + ch * 64), 16, 0, 0);
+  }
+}
+
+constexpr int kLdsBytesPerCu = 163840;
+
 template <int KIND, int NKC, int NKM, int NXT, int RG>
 __global__ __launch_bounds__(256, 2) void k_bwd_bf16(const u32x4* __restrict__ xfa, const u32x4* __restrict__ xfb,
                                                      const float* __restrict__ rowterm,
@@ -410,10 +432,16 @@ __global__ __launch_bounds__(256, 2) void k_bwd_bf16(const u32x4* __restrict__ x
                                                      const u32x4* __restrict__ afr, const u32x4* __restrict__ cfr,
                                                      const u32x4* __restrict__ xau, float* __restrict__ out,
                                                      BwdBfArgs a) {
-  constexpr int A_U = 2 * NKC * 64, C_U = 2 * NKM * 64, X_U = NXT * 2 * 64, T_U = 8;
+  constexpr int A_U = 2 * NKC * 64, C_U = 2 * NKM * 64, X_U = NXT * 2 * 64;
+  // two-stage ring filled by global -> LDS loads (the column terms take a whole
+  // 64-unit chunk there) while two stages keep two workgroups per CU; otherwise
+  // one stage filled through registers
+  constexpr int STAGE_RING = A_U + C_U + X_U + 64;
+  constexpr bool RING = 2 * STAGE_RING * 16 <= kLdsBytesPerCu / 2;
+  constexpr int T_U = RING ? 64 : 8;
   constexpr int STAGE = A_U + C_U + X_U + T_U;
   constexpr int PER = (STAGE + 255) / 256;
-  __shared__ u32x4 lds[STAGE];
+  __shared__ u32x4 lds[RING ? 2 : 1][STAGE];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int g = lane >> 4, li = lane & 15;
   const int64_t row0 = (int64_t)blockIdx.x * (64 * RG) + wave * (16 * RG);
@@ -437,80 +465,154 @@ __global__ __launch_bounds__(256, 2) void k_bwd_bf16(const u32x4* __restrict__ x
     rs[rg] = 0.f;
     mk[rg] = 0.f;
   }
-  for (int64_t c = c_begin; c < c_end; c += 32) {
-    u32x4 pre[PER];
-#pragma unroll
-    for (int q = 0; q < PER; ++q) {
-      int e = tid + q * 256;
-      e = e < STAGE ? e : STAGE - 1;
-      const u32x4* src;
-      if (e < A_U) src = xfa + (c / 16) * NKC * 64 + e;
-      else if (e < A_U + C_U) src = cfr + (c / 16) * NKM * 64 + (e - A_U);
-      else if (e < A_U + C_U + X_U) src = xau + (c / 32) * NXT * 128 + (e - A_U - C_U);
-      else src = reinterpret_cast<const u32x4*>(colterm + c) + (e - A_U - C_U - X_U);
-      pre[q] = *src;
-    }
+  const int nsteps = (int)((c_end - c_begin) / 32);
+  if constexpr (RING) {
+    // step s sits in lds[s & 1]; iteration j loads step j + 1 into the buffer step
+    // j - 1 left, then works on step j
+    bwd_issue_stage<NKC, NKM, NXT>(lds[0], xfa, cfr, xau, colterm, c_begin, wave, lane);
+    __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
-#pragma unroll
-    for (int q = 0; q < PER; ++q) {
-      const int e = tid + q * 256;
-      if (e < STAGE) lds[e] = pre[q];
-    }
-    __syncthreads();
-    const u32x4* A = lds;
-    const u32x4* Cf = lds + A_U;
-    const u32x4* Xf = Cf + C_U;
-    const float* ct = reinterpret_cast<const float*>(Xf + X_U);
-    const bool diag = (c + 32 > row0) && (c < row0 + 16 * RG);
-    u32x4 wh[RG], wl[RG];
-#pragma unroll
-    for (int rg = 0; rg < RG; ++rg) {
-#pragma unroll
-      for (int js = 0; js < 2; ++js) {
-        f32x4 dd = rt[rg];
-#pragma unroll
-        for (int kc = 0; kc < NKC; ++kc)
-          dd = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, A[(js * NKC + kc) * 64 + lane]),
-                                                       __builtin_bit_cast(bf16x8, xbv[rg][kc]), dd, 0, 0, 0);
-        f32x4 mm = f32x4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-        for (int kc = 0; kc < NKM; ++kc)
-          mm = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, Cf[(js * NKM + kc) * 64 + lane]),
-                                                       __builtin_bit_cast(bf16x8, abv[rg][kc]), mm, 0, 0, 0);
-        const f32x4 ctv = *reinterpret_cast<const f32x4*>(ct + js * 16 + 4 * g);
-        float wv[4];
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          float kap, sg;
-          bw_map<KIND>(dd[v] + ctv[v], a.s, a.rbf_sg, a.rbf_kap, a.alpha, &kap, &sg);
-          if (diag && row0 + rg * 16 + li == c + js * 16 + 4 * g + v) {
-            kap = 1.0f;
-            sg = 0.0f;
-          }
-          wv[v] = sg * mm[v];
-          rs[rg] += wv[v];
-          mk[rg] += kap * mm[v];
-        }
-        uint32_t h0, l0, h1, l1;
-        bw_split_pair(wv[0], wv[1], &h0, &l0);
-        bw_split_pair(wv[2], wv[3], &h1, &l1);
-        wh[rg][2 * js] = h0;
-        wh[rg][2 * js + 1] = h1;
-        wl[rg][2 * js] = l0;
-        wl[rg][2 * js + 1] = l1;
-      }
-    }
-#pragma unroll
-    for (int tt = 0; tt < NXT; ++tt) {
-      const bf16x8 xh = __builtin_bit_cast(bf16x8, Xf[(tt * 2 + 0) * 64 + lane]);
-      const bf16x8 xl = __builtin_bit_cast(bf16x8, Xf[(tt * 2 + 1) * 64 + lane]);
+    for (int j = 0; j < nsteps; ++j) {
+      const int64_t c = c_begin + (int64_t)j * 32;
+      if (j + 1 < nsteps)
+        bwd_issue_stage<NKC, NKM, NXT>(lds[(j + 1) & 1], xfa, cfr, xau, colterm, c + 32, wave, lane);
+      const u32x4* base = lds[j & 1];
+      const u32x4* A = base;
+      const u32x4* Cf = A + A_U;
+      const u32x4* Xf = Cf + C_U;
+      const float* ct = reinterpret_cast<const float*>(Xf + X_U);
+      const bool diag = (c + 32 > row0) && (c < row0 + 16 * RG);
+      u32x4 wh[RG], wl[RG];
 #pragma unroll
       for (int rg = 0; rg < RG; ++rg) {
-        const bf16x8 h = __builtin_bit_cast(bf16x8, wh[rg]);
-        const bf16x8 l = __builtin_bit_cast(bf16x8, wl[rg]);
-        acc[rg][tt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(h, xh, acc[rg][tt], 0, 0, 0);
-        acc[rg][tt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(h, xl, acc[rg][tt], 0, 0, 0);
-        acc[rg][tt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(l, xh, acc[rg][tt], 0, 0, 0);
+#pragma unroll
+        for (int js = 0; js < 2; ++js) {
+          f32x4 dd = rt[rg];
+#pragma unroll
+          for (int kc = 0; kc < NKC; ++kc)
+            dd = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, A[(js * NKC + kc) * 64 + lane]),
+                                                         __builtin_bit_cast(bf16x8, xbv[rg][kc]), dd, 0, 0, 0);
+          f32x4 mm = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+          for (int kc = 0; kc < NKM; ++kc)
+            mm = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, Cf[(js * NKM + kc) * 64 + lane]),
+                                                         __builtin_bit_cast(bf16x8, abv[rg][kc]), mm, 0, 0, 0);
+          const f32x4 ctv = *reinterpret_cast<const f32x4*>(ct + js * 16 + 4 * g);
+          float wv[4];
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            float kap, sg;
+            bw_map<KIND>(dd[v] + ctv[v], a.s, a.rbf_sg, a.rbf_kap, a.alpha, &kap, &sg);
+            if (diag && row0 + rg * 16 + li == c + js * 16 + 4 * g + v) {
+              kap = 1.0f;
+              sg = 0.0f;
+            }
+            wv[v] = sg * mm[v];
+            rs[rg] += wv[v];
+            mk[rg] += kap * mm[v];
+          }
+          uint32_t h0, l0, h1, l1;
+          bw_split_pair(wv[0], wv[1], &h0, &l0);
+          bw_split_pair(wv[2], wv[3], &h1, &l1);
+          wh[rg][2 * js] = h0;
+          wh[rg][2 * js + 1] = h1;
+          wl[rg][2 * js] = l0;
+          wl[rg][2 * js + 1] = l1;
+        }
+      }
+#pragma unroll
+      for (int tt = 0; tt < NXT; ++tt) {
+        const bf16x8 xh = __builtin_bit_cast(bf16x8, Xf[(tt * 2 + 0) * 64 + lane]);
+        const bf16x8 xl = __builtin_bit_cast(bf16x8, Xf[(tt * 2 + 1) * 64 + lane]);
+#pragma unroll
+        for (int rg = 0; rg < RG; ++rg) {
+          const bf16x8 h = __builtin_bit_cast(bf16x8, wh[rg]);
+          const bf16x8 l = __builtin_bit_cast(bf16x8, wl[rg]);
+          acc[rg][tt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(h, xh, acc[rg][tt], 0, 0, 0);
+          acc[rg][tt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(h, xl, acc[rg][tt], 0, 0, 0);
+          acc[rg][tt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(l, xh, acc[rg][tt], 0, 0, 0);
+        }
+      }
+      __builtin_amdgcn_s_waitcnt(0);
+      __syncthreads();
+    }
+  } else {
+    u32x4* lds1 = lds[0];
+    for (int64_t c = c_begin; c < c_end; c += 32) {
+      u32x4 pre[PER];
+#pragma unroll
+      for (int q = 0; q < PER; ++q) {
+        int e = tid + q * 256;
+        e = e < STAGE ? e : STAGE - 1;
+        const u32x4* src;
+        if (e < A_U) src = xfa + (c / 16) * NKC * 64 + e;
+        else if (e < A_U + C_U) src = cfr + (c / 16) * NKM * 64 + (e - A_U);
+        else if (e < A_U + C_U + X_U) src = xau + (c / 32) * NXT * 128 + (e - A_U - C_U);
+        else src = reinterpret_cast<const u32x4*>(colterm + c) + (e - A_U - C_U - X_U);
+        pre[q] = *src;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int q = 0; q < PER; ++q) {
+        const int e = tid + q * 256;
+        if (e < STAGE) lds1[e] = pre[q];
+      }
+      __syncthreads();
+      const u32x4* A = lds1;
+      const u32x4* Cf = A + A_U;
+      const u32x4* Xf = Cf + C_U;
+      const float* ct = reinterpret_cast<const float*>(Xf + X_U);
+      const bool diag = (c + 32 > row0) && (c < row0 + 16 * RG);
+      u32x4 wh[RG], wl[RG];
+#pragma unroll
+      for (int rg = 0; rg < RG; ++rg) {
+#pragma unroll
+        for (int js = 0; js < 2; ++js) {
+          f32x4 dd = rt[rg];
+#pragma unroll
+          for (int kc = 0; kc < NKC; ++kc)
+            dd = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, A[(js * NKC + kc) * 64 + lane]),
+                                                         __builtin_bit_cast(bf16x8, xbv[rg][kc]), dd, 0, 0, 0);
+          f32x4 mm = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+          for (int kc = 0; kc < NKM; ++kc)
+            mm = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, Cf[(js * NKM + kc) * 64 + lane]),
+                                                         __builtin_bit_cast(bf16x8, abv[rg][kc]), mm, 0, 0, 0);
+          const f32x4 ctv = *reinterpret_cast<const f32x4*>(ct + js * 16 + 4 * g);
+          float wv[4];
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            float kap, sg;
+            bw_map<KIND>(dd[v] + ctv[v], a.s, a.rbf_sg, a.rbf_kap, a.alpha, &kap, &sg);
+            if (diag && row0 + rg * 16 + li == c + js * 16 + 4 * g + v) {
+              kap = 1.0f;
+              sg = 0.0f;
+            }
+            wv[v] = sg * mm[v];
+            rs[rg] += wv[v];
+            mk[rg] += kap * mm[v];
+          }
+          uint32_t h0, l0, h1, l1;
+          bw_split_pair(wv[0], wv[1], &h0, &l0);
+          bw_split_pair(wv[2], wv[3], &h1, &l1);
+          wh[rg][2 * js] = h0;
+          wh[rg][2 * js + 1] = h1;
+          wl[rg][2 * js] = l0;
+          wl[rg][2 * js + 1] = l1;
+        }
+      }
+#pragma unroll
+      for (int tt = 0; tt < NXT; ++tt) {
+        const bf16x8 xh = __builtin_bit_cast(bf16x8, Xf[(tt * 2 + 0) * 64 + lane]);
+        const bf16x8 xl = __builtin_bit_cast(bf16x8, Xf[(tt * 2 + 1) * 64 + lane]);
+#pragma unroll
+        for (int rg = 0; rg < RG; ++rg) {
+          const bf16x8 h = __builtin_bit_cast(bf16x8, wh[rg]);
+          const bf16x8 l = __builtin_bit_cast(bf16x8, wl[rg]);
+          acc[rg][tt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(h, xh, acc[rg][tt], 0, 0, 0);
+          acc[rg][tt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(h, xl, acc[rg][tt], 0, 0, 0);
+          acc[rg][tt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(l, xh, acc[rg][tt], 0, 0, 0);
+        }
       }
     }
   }
