@@ -121,6 +121,7 @@ Layout make_layout(int64_t n, int d, int ard, int num_probes, int max_iters, int
   L.freq = take((size_t)(kk / 2 + 1) * GP_MAX_D * 8);
   L.landmarks = take(kk * 4);
   L.famp = take((kk / 2 + 1) * 8);
+  L.lf_ltr = take(k > 0 ? rup(n, 64) * rup(k, 16) * 8 : 0);
   L.precond_end = off;
   // estimator block
   L.xfa = take(np * L.kd * esz);

@@ -111,6 +111,10 @@ struct Layout {
   size_t freq;          // m x d spectral samples of the random Fourier feature preconditioner
   size_t landmarks;     // k prescribed pivot rows of the Nystrom preconditioner
   size_t famp;          // m per-frequency amplitudes of weighted Fourier features
+  // L in the operand order of the L^T R MFMAs (each wave load one contiguous 512-byte
+  // run): lf_ltr[(i/4, l/16)][lane (i%4, l%16)], rup(n, 64) x rup(k, 16) entries,
+  // zero past n and k; written with the preconditioner
+  size_t lf_ltr;
   size_t precond_end;
   // estimator block
   size_t xfa, xfb, rowterm, colterm, H, Y, ltr, ltr_raw, ltr_part2;

@@ -207,13 +207,16 @@ typedef double f64x4 __attribute__((ext_vector_type(4)));
 // c < tp.  Workgroup (group of 4 waves, chunk); a wave owns LB consecutive blocks of 16
 // l (LB = 2 up to 8 column tiles, so one R operand feeds two l-blocks' MFMAs) and every
 // 16-column tile of R.  The l-groups of one chunk are neighbours in launch order, so
-// the chunk of R comes from HBM once.
+// the chunk of R comes from HBM once.  XC = 1: R has 16 NT + 1 meaningful columns
+// (y and 16 NT probes) in 16 (NT + 1); the NT tiles run on the matrix cores and column
+// 16 NT on the vector ALU (one FP64 FMA per L value instead of a sixteen-column MFMA
+// tile that carries one column), and the padding columns of part are written as zero.
 template <int NT>
 constexpr int ltr_lblocks() { return NT <= 8 ? 2 : 1; }
 
-template <int NT>
-__global__ __launch_bounds__(256) void k_ltr_mfma(const double* __restrict__ L, const double* __restrict__ R,
-                                                  int64_t n, int k, int kpad, int tp, int64_t rows,
+template <int NT, int XC>
+__global__ __launch_bounds__(256) void k_ltr_mfma(const double* __restrict__ lf, const double* __restrict__ R,
+                                                  int64_t n, int kpad, int tp, int64_t rows,
                                                   double* __restrict__ part, const int* __restrict__ nactive) {
   if (nactive != nullptr && *nactive == 0) return;
   constexpr int LB = ltr_lblocks<NT>();
@@ -222,42 +225,55 @@ __global__ __launch_bounds__(256) void k_ltr_mfma(const double* __restrict__ L, 
   if (mb0 * 16 >= kpad) return;
   const int64_t i0 = (int64_t)blockIdx.y * rows, i1 = min(n, i0 + rows);
   const int m = lane & 15, kq = lane >> 4;
+  const int nlb = kpad / 16;
   bool on[LB];
-  int lr[LB];
-  const double* Lc[LB];
+#pragma unroll
+  for (int b = 0; b < LB; ++b) on[b] = (mb0 + b) * 16 < kpad;
+  f64x4 acc[LB][NT];
+  double xacc[LB];
 #pragma unroll
   for (int b = 0; b < LB; ++b) {
-    on[b] = (mb0 + b) * 16 < kpad;
-    lr[b] = (mb0 + b) * 16 + m;
-    Lc[b] = L + (int64_t)min(lr[b], k - 1) * n;
-  }
-  f64x4 acc[LB][NT];
-#pragma unroll
-  for (int b = 0; b < LB; ++b)
+    xacc[b] = 0.0;
 #pragma unroll
     for (int nb = 0; nb < NT; ++nb) acc[b][nb] = f64x4{0.0, 0.0, 0.0, 0.0};
-  // four K-steps of operands are loaded before their MFMAs (loads in flight together)
+  }
+  // four K-steps of operands are loaded before their MFMAs (loads in flight together);
+  // L comes operand-ordered (lf: zero past n and k), so its loads need no masks: a
+  // chunk holds a multiple of 16 rows except the last, which ends at n
   constexpr int U = 4;
   for (int64_t i = i0; i < i1; i += 4 * U) {
-    double av[LB][U], bv[U][NT];
+    double av[LB][U], bv[U][NT], xv[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int64_t ir = i + 4 * u + kq;
       const bool in = ir < i1;
 #pragma unroll
-      for (int b = 0; b < LB; ++b) av[b][u] = (in && lr[b] < k) ? Lc[b][ir] : 0.0;
-      const double* Rr = R + (in ? ir : i0) * tp + m;
+      for (int b = 0; b < LB; ++b) av[b][u] = on[b] ? lf[((i / 4 + u) * nlb + mb0 + b) * 64 + lane] : 0.0;
+      // loads from a clamped row, then a select: a lane-dependent condition on the
+      // load itself would become a branch around every load
+      const double* Rr = R + (in ? ir : i0) * tp;
 #pragma unroll
-      for (int nb = 0; nb < NT; ++nb) bv[u][nb] = in ? Rr[nb * 16] : 0.0;
+      for (int nb = 0; nb < NT; ++nb) {
+        const double t = Rr[nb * 16 + m];
+        bv[u][nb] = in ? t : 0.0;
+      }
+      if constexpr (XC != 0) {
+        const double t = Rr[16 * NT];
+        xv[u] = in ? t : 0.0;
+      } else {
+        xv[u] = 0.0;
+      }
     }
 #pragma unroll
     for (int u = 0; u < U; ++u)
 #pragma unroll
       for (int b = 0; b < LB; ++b)
-        if (on[b])
+        if (on[b]) {
 #pragma unroll
           for (int nb = 0; nb < NT; ++nb)
             acc[b][nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[b][u], bv[u][nb], acc[b][nb], 0, 0, 0);
+          if constexpr (XC != 0) xacc[b] = fma(av[b][u], xv[u], xacc[b]);
+        }
   }
 #pragma unroll
   for (int b = 0; b < LB; ++b) {
@@ -267,6 +283,14 @@ __global__ __launch_bounds__(256) void k_ltr_mfma(const double* __restrict__ L, 
     for (int nb = 0; nb < NT; ++nb)
 #pragma unroll
       for (int v = 0; v < 4; ++v) out[(int64_t)(kq + 4 * v) * tp + nb * 16 + m] = acc[b][nb][v];
+    if constexpr (XC != 0) {
+      // lane (m, kq) holds row l = m over the chunk rows i = kq (mod 4): add the
+      // four lane groups in a fixed order ((0 + 1) + (2 + 3))
+      double x = xacc[b];
+      x += __shfl_xor(x, 16);
+      x += __shfl_xor(x, 32);
+      for (int cc = kq; cc < 16; cc += 4) out[(int64_t)m * tp + 16 * NT + cc] = cc == 0 ? x : 0.0;
+    }
   }
 }
 
@@ -309,14 +333,16 @@ __global__ void k_cinv_apply(const double* __restrict__ Cinv, const double* __re
 }
 
 // Z = (R - L Y) / sigma^2 on 64 rows per workgroup (16 per wave), plus the
-// per-block partial r.z of every column
-template <int NT>
+// per-block partial r.z of every column.  XC = 1 as in k_ltr_mfma: column 16 NT of
+// L Y on the vector ALU, and in the padding columns (where Y is zero) z = r / sigma^2.
+template <int NT, int XC>
 __global__ __launch_bounds__(256) void k_zapply_mfma(const double* __restrict__ L, const double* __restrict__ Y,
                                                      const double* __restrict__ R, int64_t n, int k, int tp,
                                                      double inv_s2, double* __restrict__ Z, double* __restrict__ part,
                                                      const int* __restrict__ nactive) {
   if (nactive != nullptr && *nactive == 0) return;
   __shared__ double red[16][16 * NT];
+  __shared__ double redx[XC ? 4 : 1][16][16];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int m = lane & 15, kq = lane >> 4;
   const int64_t r0 = (int64_t)blockIdx.x * 64 + wave * 16;
@@ -324,22 +350,40 @@ __global__ __launch_bounds__(256) void k_zapply_mfma(const double* __restrict__ 
   f64x4 acc[NT];
 #pragma unroll
   for (int nb = 0; nb < NT; ++nb) acc[nb] = f64x4{0.0, 0.0, 0.0, 0.0};
+  double xacc = 0.0;
+  // loads from clamped addresses, then a select: a lane-dependent condition on a
+  // load would become a branch around it.  (An operand-ordered copy of L, one
+  // contiguous 512-byte load per K-step as k_ltr_mfma reads it, and prefetching the
+  // next K-group's L into registers were both measured no faster here.)
   constexpr int U = 4;
   for (int l0 = 0; l0 < k; l0 += 4 * U) {
-    double av[U], bv[U][NT];
+    double av[U], bv[U][NT], xv[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int l = l0 + 4 * u + kq;
       const bool in = l < k;
-      av[u] = (in && ra < n) ? L[(int64_t)l * n + ra] : 0.0;
-      const double* Yr = Y + (int64_t)(in ? l : 0) * tp + m;
+      const bool inl = in && ra < n;
+      const double t = L[inl ? (int64_t)l * n + ra : 0];
+      av[u] = inl ? t : 0.0;
+      const double* Yr = Y + (int64_t)(in ? l : 0) * tp;
 #pragma unroll
-      for (int nb = 0; nb < NT; ++nb) bv[u][nb] = in ? Yr[nb * 16] : 0.0;
+      for (int nb = 0; nb < NT; ++nb) {
+        const double y = Yr[nb * 16 + m];
+        bv[u][nb] = in ? y : 0.0;
+      }
+      if constexpr (XC != 0) {
+        const double y = Yr[16 * NT];
+        xv[u] = in ? y : 0.0;
+      } else {
+        xv[u] = 0.0;
+      }
     }
 #pragma unroll
-    for (int u = 0; u < U; ++u)
+    for (int u = 0; u < U; ++u) {
 #pragma unroll
       for (int nb = 0; nb < NT; ++nb) acc[nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u], bv[u][nb], acc[nb], 0, 0, 0);
+      if constexpr (XC != 0) xacc = fma(av[u], xv[u], xacc);
+    }
   }
   // lane holds rows r0 + kq + 4v, column nb * 16 + m
 #pragma unroll
@@ -358,12 +402,40 @@ __global__ __launch_bounds__(256) void k_zapply_mfma(const double* __restrict__ 
     }
     red[wave * 4 + kq][nb * 16 + m] = rz;
   }
+  if constexpr (XC != 0) {
+    // row ra: the four lane groups' partial sums in a fixed order, then lane (m, kq)
+    // takes columns 16 NT + kq + 4 j of that row
+    double x = xacc;
+    x += __shfl_xor(x, 16);
+    x += __shfl_xor(x, 32);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int cc = kq + 4 * j;
+      double rz = 0.0;
+      if (ra < n) {
+        const int64_t e = ra * tp + 16 * NT + cc;
+        const double rv = R[e];
+        const double z = (cc == 0 ? rv - x : rv) * inv_s2;
+        Z[e] = z;
+        rz = rv * z;
+      }
+      redx[wave][m][cc] = rz;
+    }
+  }
   if (part == nullptr) return;
   __syncthreads();
   for (int c = threadIdx.x; c < 16 * NT; c += 256) {
     double s = 0.0;
     for (int q = 0; q < 16; ++q) s += red[q][c];
     part[(int64_t)blockIdx.x * tp + c] = s;
+  }
+  if constexpr (XC != 0) {
+    if (threadIdx.x < 16) {
+      double s = 0.0;
+      for (int w = 0; w < 4; ++w)
+        for (int q = 0; q < 16; ++q) s += redx[w][q][threadIdx.x];
+      part[(int64_t)blockIdx.x * tp + 16 * NT + threadIdx.x] = s;
+    }
   }
 }
 
@@ -373,35 +445,48 @@ __global__ __launch_bounds__(256) void k_zapply_mfma(const double* __restrict__ 
 
 static unsigned nb_for(int64_t count, int bs) { return (unsigned)((count + bs - 1) / bs); }
 
-template <int NT>
+template <int NT, int XC>
 static void ltr_launch(const Ctx& c, const double* Rsrc, double* part, const int* nact) {
   const Layout& L = *c.lay;
   const int kpad = (L.k + 15) / 16 * 16;
   constexpr int wl = 4 * ltr_lblocks<NT>();  // l-blocks per workgroup
-  hipLaunchKernelGGL((k_ltr_mfma<NT>), dim3((kpad / 16 + wl - 1) / wl, L.nchunk_ltr), dim3(256), 0, c.st,
-                     c.at<double>(L.L), Rsrc, L.n, L.k, kpad, L.tp, L.ltr_rows, part, nact);
+  hipLaunchKernelGGL((k_ltr_mfma<NT, XC>), dim3((kpad / 16 + wl - 1) / wl, L.nchunk_ltr), dim3(256), 0, c.st,
+                     c.at<double>(L.lf_ltr), Rsrc, L.n, kpad, L.tp, L.ltr_rows, part, nact);
 }
 
-template <int NT>
+template <int NT, int XC>
 static void zapply_launch(const Ctx& c, const Hyper& h, const double* Rsrc, double* Zdst, double* rz_part,
                           const int* nact) {
   const Layout& L = *c.lay;
-  hipLaunchKernelGGL((k_zapply_mfma<NT>), dim3(nb_for(L.n, 64)), dim3(256), 0, c.st, c.at<double>(L.L),
+  hipLaunchKernelGGL((k_zapply_mfma<NT, XC>), dim3(nb_for(L.n, 64)), dim3(256), 0, c.st, c.at<double>(L.L),
                      c.at<double>(L.Y), Rsrc, L.n, L.k, L.tp, 1.0 / h.s2, Zdst, rz_part, nact);
 }
 
 #define GPMLL_TP_CASES(M) M(1) M(2) M(3) M(4) M(5) M(6) M(8) M(12) M(16)
+
+// the Woodbury products take the extra-column route when the tp columns hold
+// 16 m + 1 meaningful ones (y and 16 m probes, m = tp / 16 - 1 <= 5); returns m, else 0
+static int woodbury_xc_tiles(const Layout& L) {
+  const int m = L.tp / 16 - 1;
+  return (m >= 1 && m <= 5 && L.t == 16 * m + 1) ? m : 0;
+}
 
 // dst (k x tp) = L^T Rsrc
 hipError_t launch_ltr(const Ctx& c, const double* Rsrc, double* dst, const int* nact) {
   const Layout& L = *c.lay;
   const int kpad = (L.k + 15) / 16 * 16;
   double* part = c.at<double>(L.ltr_part2);
-  switch (L.tp / 16) {
-#define CASE(N) case N: ltr_launch<N>(c, Rsrc, part, nact); break;
-    GPMLL_TP_CASES(CASE)
+  switch (woodbury_xc_tiles(L)) {
+#define CASE(N) case N: ltr_launch<N, 1>(c, Rsrc, part, nact); break;
+    CASE(1) CASE(2) CASE(3) CASE(4) CASE(5)
 #undef CASE
-    default: return hipErrorInvalidValue;
+    default:
+      switch (L.tp / 16) {
+#define CASE(N) case N: ltr_launch<N, 0>(c, Rsrc, part, nact); break;
+        GPMLL_TP_CASES(CASE)
+#undef CASE
+        default: return hipErrorInvalidValue;
+      }
   }
   hipLaunchKernelGGL(k_ltr_sum, dim3(nb_for((int64_t)L.k * L.tp, 64)), dim3(1024), 0, c.st, part, L.nchunk_ltr, L.k,
                      kpad, L.tp, dst, nact);
@@ -417,11 +502,17 @@ hipError_t launch_woodbury(const Ctx& c, const Hyper& h, const double* Rsrc, dou
     hipLaunchKernelGGL(k_cinv_apply, dim3(nb_for((int64_t)L.k * L.tp, 256)), dim3(256), 0, c.st,
                        c.at<double>(L.Cinv), c.at<double>(L.ltr), L.k, L.tp, c.at<double>(L.Y), nact);
   }
-  switch (L.tp / 16) {
-#define CASE(N) case N: zapply_launch<N>(c, h, Rsrc, Zdst, rz_part, nact); break;
-    GPMLL_TP_CASES(CASE)
+  switch (woodbury_xc_tiles(L)) {
+#define CASE(N) case N: zapply_launch<N, 1>(c, h, Rsrc, Zdst, rz_part, nact); break;
+    CASE(1) CASE(2) CASE(3) CASE(4) CASE(5)
 #undef CASE
-    default: return hipErrorInvalidValue;
+    default:
+      switch (L.tp / 16) {
+#define CASE(N) case N: zapply_launch<N, 0>(c, h, Rsrc, Zdst, rz_part, nact); break;
+        GPMLL_TP_CASES(CASE)
+#undef CASE
+        default: return hipErrorInvalidValue;
+      }
   }
   return hipGetLastError();
 }

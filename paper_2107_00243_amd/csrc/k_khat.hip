@@ -402,45 +402,91 @@ __global__ void k_stage_v_fp(const double* __restrict__ V, int64_t nrows, int ld
 
 // W[i][c] = sum_s wpart[s][i][c] + sigma^2 V[i][c] (FP64, fixed order), rows < nrows,
 // columns < ncols; optionally per-block partial dots V[:,c].W[:,c].  Block: 64 rows x
-// kRedCols columns (thread = column x 3 row lanes; 80 columns hold the 65 of y and 64
-// probes in one block), grid (ceil(nrows/64), ceil(ncols/kRedCols)).  The block shape
-// is fixed, so a column's partial dot has the same summation order however many
-// columns are active.
+// kRedCols columns, 320 threads = 20 column quads x 16 row lanes: a thread reads four
+// consecutive partial columns with one vector load per split and row (a wave covers
+// about three whole 80-column partial rows per load), for the rows rl, rl + 16,
+// rl + 32 and rl + 48 of the block, all loads in flight before the sums.  The 16 row
+// lanes' dot sums are added in a fixed order and the block shape is fixed, so a
+// column's partial dot has the same summation order however many columns are active.
 constexpr int kRedCols = 80;
+constexpr int kRedQuads = kRedCols / 4;
+constexpr int kRedLanes = 16;
+constexpr int kRedThreads = kRedQuads * kRedLanes;
 template <typename T>
-__global__ __launch_bounds__(256) void k_khat_reduce(const T* __restrict__ wpart, int nsplit, int64_t n_pad, int tp,
-                                                     const double* __restrict__ V, int ldv, double* __restrict__ W,
-                                                     int ldw, int64_t nrows, int ncols, const int* __restrict__ colmap,
-                                                     int ldpart, double s2, double* __restrict__ dot_part,
-                                                     const int* __restrict__ nactive,
-                                                     const uint32_t* __restrict__ colmax, double fac_s) {
+__global__ __launch_bounds__(kRedThreads) void k_khat_reduce(const T* __restrict__ wpart, int nsplit, int64_t n_pad,
+                                                             int tp, const double* __restrict__ V, int ldv,
+                                                             double* __restrict__ W, int ldw, int64_t nrows, int ncols,
+                                                             const int* __restrict__ colmap, int ldpart, double s2,
+                                                             double* __restrict__ dot_part,
+                                                             const int* __restrict__ nactive,
+                                                             const uint32_t* __restrict__ colmax, double fac_s) {
   if (nactive != nullptr && *nactive == 0) return;
-  __shared__ double red[3][kRedCols];
-  const int cl = threadIdx.x % kRedCols, lane = threadIdx.x / kRedCols;  // lane 3: the 16 spare threads
-  // staged column c carries source column src (results go back to that column)
-  const int c = blockIdx.y * kRedCols + cl;
-  const int src = lane < 3 ? staged_source(colmap, c, ncols) : -1;
+  typedef T T4 __attribute__((ext_vector_type(4)));
+  __shared__ double red[kRedLanes][kRedCols];
+  const int cq = threadIdx.x % kRedQuads, rl = threadIdx.x / kRedQuads;
+  // staged column c0 + v carries source column src[v] (results go back to that column)
+  const int c0 = blockIdx.y * kRedCols + 4 * cq;
+  int src[4];
+  double fac[4];
+  bool any = false;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    src[v] = staged_source(colmap, c0 + v, ncols);
+    // FP16X3 partials carry the factors 2^15 / s (kernel values) and scale_c (column)
+    fac[v] = (colmax != nullptr && src[v] >= 0) ? fac_s / (double)f16_col_scale(colmax[c0 + v]) : 1.0;
+    any = any || src[v] >= 0;
+  }
   const int64_t r0 = (int64_t)blockIdx.x * 64;
-  double dot = 0.0;
-  // FP16X3 partials carry the factors 2^15 / s (kernel values) and scale_c (column)
-  const double fac = (colmax != nullptr && src >= 0) ? fac_s / (double)f16_col_scale(colmax[c]) : 1.0;
-  if (src >= 0) {
-#pragma unroll 4
-    for (int q = lane; q < 64; q += 3) {
-      const int64_t r = r0 + q;
-      if (r >= nrows) break;
-      double w = 0.0;
-      for (int s = 0; s < nsplit; ++s) w += (double)wpart[((int64_t)s * n_pad + r) * tp + c];
-      const double v = V[r * ldv + src];
-      w = w * fac + s2 * v;
-      W[r * ldw + src] = w;
-      dot += v * w;
+  double dot[4] = {0.0, 0.0, 0.0, 0.0};
+  // an active column lies below ncols <= tp, so a quad with one is inside the partial row
+  if (any) {
+    double w[4][4];
+    bool rin[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      rin[q] = r0 + rl + 16 * q < nrows;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) w[q][v] = 0.0;
+    }
+    // partial rows exist up to n_pad >= 64 * gridDim.x, so the loads need no row
+    // condition (rows past nrows are summed and never used)
+    for (int s = 0; s < nsplit; ++s) {
+      T4 pv[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        pv[q] = *reinterpret_cast<const T4*>(wpart + ((int64_t)s * n_pad + r0 + rl + 16 * q) * tp + c0);
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) w[q][v] += (double)pv[q][v];
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      if (!rin[q]) continue;
+      const int64_t r = r0 + rl + 16 * q;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        if (src[v] < 0) continue;
+        const double vv = V[r * ldv + src[v]];
+        const double ww = w[q][v] * fac[v] + s2 * vv;
+        W[r * ldw + src[v]] = ww;
+        dot[v] += vv * ww;
+      }
     }
   }
   if (dot_part == nullptr) return;
-  if (lane < 3) red[lane][cl] = dot;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) red[rl][4 * cq + v] = dot[v];
   __syncthreads();
-  if (lane == 0 && src >= 0) dot_part[(int64_t)blockIdx.x * ldpart + src] = red[0][cl] + red[1][cl] + red[2][cl];
+  if (rl == 0) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      if (src[v] < 0) continue;
+      double t = 0.0;
+      for (int l = 0; l < kRedLanes; ++l) t += red[l][4 * cq + v];
+      dot_part[(int64_t)blockIdx.x * ldpart + src[v]] = t;
+    }
+  }
 }
 
 #endif  // part 0
@@ -1146,10 +1192,10 @@ hipError_t launch_khat_reduce(const Ctx& c, const double* V, int ldv, double* W,
   const uint32_t* cm = f16 ? c.at<uint32_t>(L.vscale) : nullptr;
   const double fac_s = f16 ? h.s / 32768.0 : 1.0;
   if (L.prec == GP_PREC_FP64)
-    hipLaunchKernelGGL(k_khat_reduce<double>, nb, dim3(256), 0, c.st, c.at<double>(L.wpart), L.nsplit, L.n_pad,
+    hipLaunchKernelGGL(k_khat_reduce<double>, nb, dim3(kRedThreads), 0, c.st, c.at<double>(L.wpart), L.nsplit, L.n_pad,
                        L.tp, V, ldv, W, ldw, L.n, ncols, colmap, ldpart, h.s2, dot_part, nact, cm, fac_s);
   else
-    hipLaunchKernelGGL(k_khat_reduce<float>, nb, dim3(256), 0, c.st, c.at<float>(L.wpart), L.nsplit, L.n_pad,
+    hipLaunchKernelGGL(k_khat_reduce<float>, nb, dim3(kRedThreads), 0, c.st, c.at<float>(L.wpart), L.nsplit, L.n_pad,
                        L.tp, V, ldv, W, ldw, L.n, ncols, colmap, ldpart, h.s2, dot_part, nact, cm, fac_s);
   return hipGetLastError();
 }

@@ -325,11 +325,32 @@ hipError_t launch_rff(const Ctx& c, const Hyper& h, bool weighted) {
   return hipGetLastError();
 }
 
+// L (k x n, row l contiguous) in the operand order of the L^T R MFMAs: entry e of
+// rup(n, 64) x kpad, zero outside l < k, i < n; group (i/4, l/16), lane (kq, m) holds
+// l = 16 (group % (kpad/16)) + m, i = 4 (group / (kpad/16)) + kq
+__global__ void k_stage_l_frag(const double* __restrict__ L, int64_t n, int k, int kpad, int64_t total,
+                               double* __restrict__ lf_ltr) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= total) return;
+  const int lane = (int)(e & 63), m = lane & 15, kq = lane >> 4;
+  const int64_t g = e >> 6;
+  const int nlb = kpad / 16;
+  const int l = (int)(g % nlb) * 16 + m;
+  const int64_t i = (g / nlb) * 4 + kq;
+  lf_ltr[e] = (l < k && i < n) ? L[(int64_t)l * n + i] : 0.0;
+}
+
 hipError_t launch_precond_finish(const Ctx& c, const Hyper& h) {
   const Layout& L = *c.lay;
   if (L.k == 0) {
     hipLaunchKernelGGL(k_logdet_noprecond, dim3(1), dim3(1), 0, c.st, L.n, h.s2, c.at<double>(L.logdetP));
     return hipGetLastError();
+  }
+  {
+    const int kpad = (L.k + 15) / 16 * 16;
+    const int64_t total = (L.n + 63) / 64 * 64 * kpad;
+    hipLaunchKernelGGL(k_stage_l_frag, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, c.st, c.at<double>(L.L),
+                       L.n, L.k, kpad, total, c.at<double>(L.lf_ltr));
   }
   const int tiles = (L.k + 15) / 16;
   hipLaunchKernelGGL(k_gram_part, dim3(tiles, tiles, L.nchunk), dim3(256), 0, c.st, c.at<double>(L.L), L.n,
