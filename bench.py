@@ -45,21 +45,21 @@ PEAK_FP64_TFLOPS = 78.6
 V3_ITERS = 16          # the library's kBf16V3Iters
 TILE_COUNTERS = {
     "fp16x3": {
-        "kernel_source_sha256_16": "8581de511f4d2e34",
+        "kernel_source_sha256_16": "14c490649bbfb821",
         "grid": [391, 5],
-        "v2": {"fetch_kib": 280600.1, "fetch_scale": 1048576.0 / 524307.8,
-               "write_kib": 143754.1, "write_scale": 1.0,
-               "mfma_insts": 3.131e8, "mfma_busy_cycles": 5.0096e9, "gui_active_per_xcd": 7.3898e7 / 8},
+        "v2": {"fetch_kib": 280408.0, "fetch_scale": 1048576.0 / 524304.0,
+               "write_kib": 143761.0, "write_scale": 1.0,
+               "mfma_insts": 3.131e8, "mfma_busy_cycles": 5.0096e9, "gui_active_per_xcd": 7.47607e7 / 8},
     },
     "bf16x3": {
-        "kernel_source_sha256_16": "8581de511f4d2e34",
+        "kernel_source_sha256_16": "14c490649bbfb821",
         "grid": [391, 5],
-        "v3": {"fetch_kib": 365608.8, "fetch_scale": 1048576.0 / 524304.0,
-               "write_kib": 141747.1, "write_scale": 1.0,
-               "mfma_insts": 3.91375e8, "mfma_busy_cycles": 6.2620e9, "gui_active_per_xcd": 8.5758e7 / 8},
-        "v2": {"fetch_kib": 280104.4, "fetch_scale": 1048576.0 / 524304.0,
-               "write_kib": 142050.5, "write_scale": 1.0,
-               "mfma_insts": 3.131e8, "mfma_busy_cycles": 5.0096e9, "gui_active_per_xcd": 7.3904e7 / 8},
+        "v3": {"fetch_kib": 363819.0, "fetch_scale": 1048576.0 / 524310.0,
+               "write_kib": 141717.0, "write_scale": 1.0,
+               "mfma_insts": 3.91375e8, "mfma_busy_cycles": 6.26201e9, "gui_active_per_xcd": 8.71291e7 / 8},
+        "v2": {"fetch_kib": 280158.0, "fetch_scale": 1048576.0 / 524310.0,
+               "write_kib": 141916.0, "write_scale": 1.0,
+               "mfma_insts": 3.131e8, "mfma_busy_cycles": 5.0096e9, "gui_active_per_xcd": 7.47617e7 / 8},
     },
 }
 
