@@ -129,7 +129,7 @@ Layout make_layout(int64_t n, int d, int ard, int num_probes, int max_iters, int
   L.rowterm = take(np * (prec == GP_PREC_FP64 ? 8 : 4));
   L.colterm = take(np * (prec == GP_PREC_FP64 ? 8 : 4));
   L.H = take(kk * num_probes * 8);
-  L.Y = take(kk * tp * 8);
+  L.Y = take(rup(kk, 64) * tp * 8);  // rows past k zero (whole LDS chunks in the z-apply)
   L.ltr = take(kk * tp * 8);
   L.ltr_raw = take(kk * tp * 8);
   L.ltr_part2 = take((size_t)L.nchunk_ltr * rup(kk, 16) * tp * 8);

@@ -318,13 +318,18 @@ __global__ __launch_bounds__(1024) void k_ltr_sum(const double* __restrict__ par
   }
 }
 
-// Y = C^-1 T (k x k times k x tp)
+// Y = C^-1 T (k x k times k x tp), and zero rows k .. rup(k, 64) - 1 (k_zapply_mfma
+// copies Y to LDS in whole chunks of up to 64 rows)
 __global__ void k_cinv_apply(const double* __restrict__ Cinv, const double* __restrict__ T, int k, int tp,
                              double* __restrict__ Y, const int* __restrict__ nactive) {
   if (nactive != nullptr && *nactive == 0) return;
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= k * tp) return;
+  if (e >= (k + 63) / 64 * 64 * tp) return;
   const int l = e / tp, c = e % tp;
+  if (l >= k) {
+    Y[e] = 0.0;
+    return;
+  }
   double s = 0.0;
   // unrolled so that the loads of several terms are in flight together (same order)
 #pragma unroll 8
@@ -332,17 +337,32 @@ __global__ void k_cinv_apply(const double* __restrict__ Cinv, const double* __re
   Y[e] = s;
 }
 
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+// rows of Y per LDS chunk in k_zapply_mfma: 64, 32 or 16 (a divisor of 64), so that a
+// chunk of rows x tp doubles fits in 32 KB
+__host__ __device__ constexpr int zy_rows(int tp) { return tp <= 64 ? 64 : (tp <= 128 ? 32 : 16); }
+constexpr int kZyLdsDoubles = 4096;
+
 // Z = (R - L Y) / sigma^2 on 64 rows per workgroup (16 per wave), plus the
 // per-block partial r.z of every column.  XC = 1 as in k_ltr_mfma: column 16 NT of
 // L Y on the vector ALU, and in the padding columns (where Y is zero) z = r / sigma^2.
+// Y is copied once per workgroup into LDS, LC rows at a time, so the loop's only
+// global loads are L's; each K-group's L loads are issued one group ahead and stay
+// in flight across the LDS reads and MFMAs of the current group.
 template <int NT, int XC>
 __global__ __launch_bounds__(256) void k_zapply_mfma(const double* __restrict__ L, const double* __restrict__ Y,
                                                      const double* __restrict__ R, int64_t n, int k, int tp,
                                                      double inv_s2, double* __restrict__ Z, double* __restrict__ part,
                                                      const int* __restrict__ nactive) {
   if (nactive != nullptr && *nactive == 0) return;
-  __shared__ double red[16][16 * NT];
-  __shared__ double redx[XC ? 4 : 1][16][16];
+  constexpr int RED = 16 * 16 * NT + (XC ? 4 * 16 * 16 : 0);
+  // the Y chunks during the K-loop (rows of tp doubles, as in Y), the r.z partials after it
+  __shared__ __attribute__((aligned(16))) double smem[kZyLdsDoubles > RED ? kZyLdsDoubles : RED];
+  double* ys = smem;
+  const int LC = zy_rows(tp);
+  double(*red)[16 * NT] = reinterpret_cast<double(*)[16 * NT]>(smem);
+  double(*redx)[16][16] = reinterpret_cast<double(*)[16][16]>(smem + 16 * 16 * NT);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int m = lane & 15, kq = lane >> 4;
   const int64_t r0 = (int64_t)blockIdx.x * 64 + wave * 16;
@@ -351,40 +371,53 @@ __global__ __launch_bounds__(256) void k_zapply_mfma(const double* __restrict__ 
 #pragma unroll
   for (int nb = 0; nb < NT; ++nb) acc[nb] = f64x4{0.0, 0.0, 0.0, 0.0};
   double xacc = 0.0;
-  // loads from clamped addresses, then a select: a lane-dependent condition on a
-  // load would become a branch around it.  (An operand-ordered copy of L, one
-  // contiguous 512-byte load per K-step as k_ltr_mfma reads it, and prefetching the
-  // next K-group's L into registers were both measured no faster here.)
   constexpr int U = 4;
-  for (int l0 = 0; l0 < k; l0 += 4 * U) {
-    double av[U], bv[U][NT], xv[U];
+  // L[l0 + 4u + kq][ra] from a clamped address, then a select (a lane-dependent
+  // condition on the load itself would become a branch around it)
+  auto load_l = [&](int l0, double (&av)[U]) {
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int l = l0 + 4 * u + kq;
-      const bool in = l < k;
-      const bool inl = in && ra < n;
-      const double t = L[inl ? (int64_t)l * n + ra : 0];
-      av[u] = inl ? t : 0.0;
-      const double* Yr = Y + (int64_t)(in ? l : 0) * tp;
-#pragma unroll
-      for (int nb = 0; nb < NT; ++nb) {
-        const double y = Yr[nb * 16 + m];
-        bv[u][nb] = in ? y : 0.0;
-      }
-      if constexpr (XC != 0) {
-        const double y = Yr[16 * NT];
-        xv[u] = in ? y : 0.0;
-      } else {
-        xv[u] = 0.0;
-      }
+      const bool in = l < k && ra < n;
+      const double t = L[in ? (int64_t)l * n + ra : 0];
+      av[u] = in ? t : 0.0;
+    }
+  };
+  // K-groups of 16 l; group g uses the L values in one register set while the next
+  // group's land in the other (a ping-pong, so no register copy waits on a load)
+  auto group = [&](int g, const double (&cur)[U], double (&nxt)[U]) {
+    const int l0 = 16 * g;
+    load_l(l0 + 16, nxt);  // past k the clamped loads give zeros
+    if (l0 % LC == 0) {
+      // rows l0 .. l0 + LC - 1 of Y (zero past k; Y holds rup(k, 64) rows) are one
+      // contiguous run: copied global -> LDS in 1 KB units, no registers in between
+      __syncthreads();  // every wave is done with the previous chunk
+      const u32x4* src = reinterpret_cast<const u32x4*>(Y + (int64_t)l0 * tp);
+      u32x4* dst = reinterpret_cast<u32x4*>(ys);
+      const int units = LC * tp / 128;
+      for (int un = __builtin_amdgcn_readfirstlane(wave); un < units; un += 4)
+        __builtin_amdgcn_global_load_lds(src + un * 64 + lane, (__attribute__((address_space(3))) void*)(dst + un * 64),
+                                         16, 0, 0);
+      __builtin_amdgcn_s_waitcnt(0);
+      __syncthreads();
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
+      const double* yr = ys + (l0 % LC + 4 * u + kq) * tp;
 #pragma unroll
-      for (int nb = 0; nb < NT; ++nb) acc[nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u], bv[u][nb], acc[nb], 0, 0, 0);
-      if constexpr (XC != 0) xacc = fma(av[u], xv[u], xacc);
+      for (int nb = 0; nb < NT; ++nb)
+        acc[nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(cur[u], yr[nb * 16 + m], acc[nb], 0, 0, 0);
+      if constexpr (XC != 0) xacc = fma(cur[u], yr[16 * NT], xacc);
     }
+  };
+  const int ng = (k + 15) / 16;
+  double a0[U], a1[U];
+  if (ng > 0) load_l(0, a0);
+  for (int g = 0; g < ng; g += 2) {
+    group(g, a0, a1);
+    if (g + 1 < ng) group(g + 1, a1, a0);
   }
+  __syncthreads();  // the LDS now holds the r.z partials
   // lane holds rows r0 + kq + 4v, column nb * 16 + m
 #pragma unroll
   for (int nb = 0; nb < NT; ++nb) {
@@ -499,7 +532,7 @@ hipError_t launch_woodbury(const Ctx& c, const Hyper& h, const double* Rsrc, dou
   if (L.k > 0) {
     hipError_t e = launch_ltr(c, Rsrc, c.at<double>(L.ltr), nact);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_cinv_apply, dim3(nb_for((int64_t)L.k * L.tp, 256)), dim3(256), 0, c.st,
+    hipLaunchKernelGGL(k_cinv_apply, dim3(nb_for((int64_t)(L.k + 63) / 64 * 64 * L.tp, 256)), dim3(256), 0, c.st,
                        c.at<double>(L.Cinv), c.at<double>(L.ltr), L.k, L.tp, c.at<double>(L.Y), nact);
   }
   switch (woodbury_xc_tiles(L)) {
