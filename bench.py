@@ -45,14 +45,14 @@ PEAK_FP64_TFLOPS = 78.6
 V3_ITERS = 16          # the library's kBf16V3Iters
 TILE_COUNTERS = {
     "fp16x3": {
-        "kernel_source_sha256_16": "14c490649bbfb821",
+        "kernel_source_sha256_16": "4db75bbb45375324",
         "grid": [391, 5],
         "v2": {"fetch_kib": 280408.0, "fetch_scale": 1048576.0 / 524304.0,
                "write_kib": 143761.0, "write_scale": 1.0,
                "mfma_insts": 3.131e8, "mfma_busy_cycles": 5.0096e9, "gui_active_per_xcd": 7.47607e7 / 8},
     },
     "bf16x3": {
-        "kernel_source_sha256_16": "14c490649bbfb821",
+        "kernel_source_sha256_16": "4db75bbb45375324",
         "grid": [391, 5],
         "v3": {"fetch_kib": 363819.0, "fetch_scale": 1048576.0 / 524310.0,
                "write_kib": 141717.0, "write_scale": 1.0,
@@ -72,13 +72,21 @@ def tile_launch_mix(precision, reps):
     return {"v2": reps}
 
 
+def tile_source_text(khat: str) -> str:
+    """k_khat.hip without its part-0 sections (the staging and reduction kernels,
+    compiled as a translation unit of their own, not the tile kernels)."""
+    import re
+    return re.sub(r"#if GPMLL_KHAT_PART == 0\n.*?#endif  // part 0\n", "", khat, flags=re.S)
+
+
 def bf16_tile_source_hash():
-    """First 16 hex digits of the SHA-256 of the tile kernel's sources (k_khat.hip
-    and the shared header gpmll_impl.h, whole)."""
+    """First 16 hex digits of the SHA-256 of the split-precision tile kernel's sources:
+    k_khat.hip without its part-0 sections, then the shared header gpmll_impl.h."""
     import hashlib
+    csrc = os.path.join(ROOT, "paper_2107_00243_amd", "csrc")
     h = hashlib.sha256()
-    for f in ("k_khat.hip", "gpmll_impl.h"):
-        h.update(open(os.path.join(ROOT, "paper_2107_00243_amd", "csrc", f), "rb").read())
+    h.update(tile_source_text(open(os.path.join(csrc, "k_khat.hip")).read()).encode())
+    h.update(open(os.path.join(csrc, "gpmll_impl.h"), "rb").read())
     return h.hexdigest()[:16]
 
 

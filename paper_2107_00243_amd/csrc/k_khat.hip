@@ -448,6 +448,17 @@ __global__ __launch_bounds__(kRedThreads) void k_khat_reduce(const T* __restrict
 #pragma unroll
       for (int v = 0; v < 4; ++v) w[q][v] = 0.0;
     }
+    // the V values first (clamped addresses, then a select), so they are in flight
+    // with the partial-sum loads
+    double vvp[4][4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const bool in = rin[q] && src[v] >= 0;
+        const double t = V[in ? (r0 + rl + 16 * q) * ldv + src[v] : 0];
+        vvp[q][v] = in ? t : 0.0;
+      }
     // partial rows exist up to n_pad >= 64 * gridDim.x, so the loads need no row
     // condition (rows past nrows are summed and never used)
     for (int s = 0; s < nsplit; ++s) {
@@ -467,7 +478,7 @@ __global__ __launch_bounds__(kRedThreads) void k_khat_reduce(const T* __restrict
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         if (src[v] < 0) continue;
-        const double vv = V[r * ldv + src[v]];
+        const double vv = vvp[q][v];
         const double ww = w[q][v] * fac[v] + s2 * vv;
         W[r * ldw + src[v]] = ww;
         dot[v] += vv * ww;
