@@ -202,6 +202,7 @@ __global__ void k_swap_count(int* __restrict__ nactive, int* __restrict__ nactiv
 // ---------------------------------------------------------------------------
 
 typedef double f64x4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
 // part[chunk][l][c] = sum over the chunk's rows i of L[l][i] R[i][c], l < kpad,
 // c < tp.  Workgroup (group of 4 waves, chunk); a wave owns LB consecutive blocks of 16
@@ -220,9 +221,12 @@ __global__ __launch_bounds__(256) void k_ltr_mfma(const double* __restrict__ lf,
                                                   double* __restrict__ part, const int* __restrict__ nactive) {
   if (nactive != nullptr && *nactive == 0) return;
   constexpr int LB = ltr_lblocks<NT>();
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  // R rows of 16 (NT + XC) doubles (tp), 16 rows per group, two LDS buffers
+  constexpr int TPC = 16 * (NT + XC);
+  __shared__ __attribute__((aligned(16))) double rs[2][16 * TPC];
+  // the wave index through the scalar unit, so the l-block tests below are uniform branches
+  const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int mb0 = (blockIdx.x * 4 + wave) * LB;
-  if (mb0 * 16 >= kpad) return;
   const int64_t i0 = (int64_t)blockIdx.y * rows, i1 = min(n, i0 + rows);
   const int m = lane & 15, kq = lane >> 4;
   const int nlb = kpad / 16;
@@ -237,43 +241,60 @@ __global__ __launch_bounds__(256) void k_ltr_mfma(const double* __restrict__ lf,
 #pragma unroll
     for (int nb = 0; nb < NT; ++nb) acc[b][nb] = f64x4{0.0, 0.0, 0.0, 0.0};
   }
-  // four K-steps of operands are loaded before their MFMAs (loads in flight together);
-  // L comes operand-ordered (lf: zero past n and k), so its loads need no masks: a
-  // chunk holds a multiple of 16 rows except the last, which ends at n
+  // Per group of 16 rows (four K-steps): the group's R rows were copied global -> LDS
+  // (global_load_lds, 1 KB per wave instruction, shared by the four waves) and its L
+  // operands loaded into registers during the previous group; L comes operand-ordered
+  // (lf: zero past n and k) and needs no masks.  A chunk holds a multiple of 16 rows
+  // except the last, which ends at n; R has n_pad >= rup(n, 16) rows, and rows past
+  // the chunk are zeroed by a select.
   constexpr int U = 4;
-  for (int64_t i = i0; i < i1; i += 4 * U) {
-    double av[LB][U], bv[U][NT], xv[U];
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int64_t ir = i + 4 * u + kq;
-      const bool in = ir < i1;
-#pragma unroll
-      for (int b = 0; b < LB; ++b) av[b][u] = on[b] ? lf[((i / 4 + u) * nlb + mb0 + b) * 64 + lane] : 0.0;
-      // loads from a clamped row, then a select: a lane-dependent condition on the
-      // load itself would become a branch around every load
-      const double* Rr = R + (in ? ir : i0) * tp;
-#pragma unroll
-      for (int nb = 0; nb < NT; ++nb) {
-        const double t = Rr[nb * 16 + m];
-        bv[u][nb] = in ? t : 0.0;
-      }
-      if constexpr (XC != 0) {
-        const double t = Rr[16 * NT];
-        xv[u] = in ? t : 0.0;
-      } else {
-        xv[u] = 0.0;
-      }
-    }
+  const int ng = (int)((i1 - i0 + 15) / 16);
+  auto issue = [&](int g, double (&av)[LB][U]) {
+    const int64_t i = i0 + 16 * g;
+    const u32x4* src = reinterpret_cast<const u32x4*>(R + i * tp);
+    u32x4* dst = reinterpret_cast<u32x4*>(rs[g & 1]);
+    for (int un = wave; un < TPC / 8; un += 4)
+      __builtin_amdgcn_global_load_lds(src + un * 64 + lane, (__attribute__((address_space(3))) void*)(dst + un * 64),
+                                       16, 0, 0);
 #pragma unroll
     for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int b = 0; b < LB; ++b) av[b][u] = on[b] ? lf[((i / 4 + u) * nlb + mb0 + b) * 64 + lane] : 0.0;
+  };
+  auto group = [&](int g, const double (&av)[LB][U], double (&an)[LB][U]) {
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();  // group g's rows are in LDS; every wave is done with group g - 1's
+    if (g + 1 < ng) issue(g + 1, an);
+    const int64_t i = i0 + 16 * g;
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const bool in = i + 4 * u + kq < i1;
+      const double* rr = rs[g & 1] + (4 * u + kq) * TPC;
+      double bv[NT], xv = 0.0;
+#pragma unroll
+      for (int nb = 0; nb < NT; ++nb) {
+        const double t = rr[nb * 16 + m];
+        bv[nb] = in ? t : 0.0;
+      }
+      if constexpr (XC != 0) {
+        const double t = rr[16 * NT];
+        xv = in ? t : 0.0;
+      }
 #pragma unroll
       for (int b = 0; b < LB; ++b)
         if (on[b]) {
 #pragma unroll
           for (int nb = 0; nb < NT; ++nb)
-            acc[b][nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[b][u], bv[u][nb], acc[b][nb], 0, 0, 0);
-          if constexpr (XC != 0) xacc[b] = fma(av[b][u], xv[u], xacc[b]);
+            acc[b][nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[b][u], bv[nb], acc[b][nb], 0, 0, 0);
+          if constexpr (XC != 0) xacc[b] = fma(av[b][u], xv, xacc[b]);
         }
+    }
+  };
+  double a0[LB][U], a1[LB][U];
+  if (ng > 0) issue(0, a0);
+  for (int g = 0; g < ng; g += 2) {
+    group(g, a0, a1);
+    if (g + 1 < ng) group(g + 1, a1, a0);
   }
 #pragma unroll
   for (int b = 0; b < LB; ++b) {
@@ -336,8 +357,6 @@ __global__ void k_cinv_apply(const double* __restrict__ Cinv, const double* __re
   for (int m = 0; m < k; ++m) s += Cinv[l * k + m] * T[m * tp + c];
   Y[e] = s;
 }
-
-typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
 // rows of Y per LDS chunk in k_zapply_mfma: 64, 32 or 16 (a divisor of 64), so that a
 // chunk of rows x tp doubles fits in 32 KB
