@@ -97,7 +97,11 @@ __global__ void k_cg_alpha(const double* __restrict__ part_pw, int nblk, int tp,
   }
 }
 
-// x += alpha p; r -= alpha w (active columns); partial ||r||^2
+typedef double f64x4v __attribute__((ext_vector_type(4)));
+
+// x += alpha p; r -= alpha w (active columns); partial ||r||^2.  Thread = column x
+// 256 / tp row lanes.  (Four-column vector loads, as k_cg_p and k_khat_reduce use,
+// were measured slower here at n = 100k: 84.5 against 68.9 us.)
 __global__ void k_cg_update(double* __restrict__ X, double* __restrict__ R, const double* __restrict__ P,
                             const double* __restrict__ W, const double* __restrict__ alpha,
                             const int* __restrict__ active, int64_t n, int tp, int64_t rows_per_block,
@@ -162,22 +166,37 @@ __global__ void k_cg_beta(const double* __restrict__ part_rz, int nblk, int tp, 
   }
 }
 
-// p = z + beta p (active columns)
-// p = z + beta p on active columns; thread = column x 256 / tp row lanes (tp <= 256),
-// rows_per_block rows per workgroup, as in k_cg_update
-__global__ void k_cg_p(double* __restrict__ P, const double* __restrict__ Z, const double* __restrict__ beta,
-                       const int* __restrict__ active, int64_t n, int tp, int64_t rows_per_block,
-                       const int* __restrict__ nactive) {
+// p = z + beta p on active columns; thread = four consecutive columns (one 32-byte
+// load per array and row) x 1024 / tp row lanes (tp <= 256), rows_per_block rows per
+// workgroup as in k_cg_update; a quad with no active column is skipped
+__global__ __launch_bounds__(256) void k_cg_p(double* __restrict__ P, const double* __restrict__ Z,
+                                              const double* __restrict__ beta, const int* __restrict__ active,
+                                              int64_t n, int tp, int64_t rows_per_block,
+                                              const int* __restrict__ nactive) {
   if (*nactive == 0) return;
-  const int G = 256 / tp;
-  const int c = threadIdx.x % tp, rg = threadIdx.x / tp;
-  if (rg >= G || !active[c]) return;
-  const double b = beta[c];
+  const int nq = tp / 4, G = 256 / nq;
+  const int cq = threadIdx.x % nq, rg = threadIdx.x / nq;
+  if (rg >= G) return;
+  bool act[4];
+  double b[4];
+  bool any = false;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    act[v] = active[4 * cq + v] != 0;
+    b[v] = act[v] ? beta[4 * cq + v] : 0.0;
+    any = any || act[v];
+  }
+  if (!any) return;
   const int64_t r0 = (int64_t)blockIdx.x * rows_per_block, r1 = min(n, r0 + rows_per_block);
-#pragma unroll 4
+#pragma unroll 2
   for (int64_t r = r0 + rg; r < r1; r += G) {
-    const int64_t e = r * tp + c;
-    P[e] = Z[e] + b * P[e];
+    const int64_t e = r * tp + 4 * cq;
+    const f64x4v z = *reinterpret_cast<const f64x4v*>(Z + e);
+    f64x4v p = *reinterpret_cast<const f64x4v*>(P + e);
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+      if (act[v]) p[v] = z[v] + b[v] * p[v];
+    *reinterpret_cast<f64x4v*>(P + e) = p;
   }
 }
 
