@@ -68,3 +68,17 @@ def test_stale_counters_are_not_reported():
     finally:
         bench.TILE_COUNTERS["bf16x3"].clear()
         bench.TILE_COUNTERS["bf16x3"].update(saved)
+
+
+def test_tile_source_hash_covers_the_tile_kernels_but_not_the_staging_section():
+    khat = open(os.path.join(ROOT, "paper_2107_00243_amd", "csrc", "k_khat.hip")).read()
+    kept = bench.tile_source_text(khat)
+    # the part-0 sections (staging, split-K reduction) are gone, the tile kernels stay
+    assert "#if GPMLL_KHAT_PART == 0" in khat and "#if GPMLL_KHAT_PART == 0" not in kept
+    assert "k_khat_reduce(" in khat and "k_khat_reduce(" not in kept
+    assert "void k_khat_bf16(" in kept and "void k_khat_fp(" in kept
+    # an edit inside a part-0 section leaves the text unchanged, one in the tile kernel does not
+    i = khat.index("#if GPMLL_KHAT_PART == 0\n") + len("#if GPMLL_KHAT_PART == 0\n")
+    assert bench.tile_source_text(khat[:i] + "// edit\n" + khat[i:]) == kept
+    j = khat.index("void k_khat_bf16(")
+    assert bench.tile_source_text(khat[:j] + "// edit\n" + khat[j:]) != kept
