@@ -224,18 +224,20 @@ typedef double f64x4 __attribute__((ext_vector_type(4)));
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
 // part[chunk][l][c] = sum over the chunk's rows i of L[l][i] R[i][c], l < kpad,
-// c < tp.  Workgroup (group of 4 waves, chunk); a wave owns LB consecutive blocks of 16
-// l (LB = 2 up to 8 column tiles, so one R operand feeds two l-blocks' MFMAs) and every
-// 16-column tile of R.  The l-groups of one chunk are neighbours in launch order, so
-// the chunk of R comes from HBM once.  XC = 1: R has 16 NT + 1 meaningful columns
-// (y and 16 NT probes) in 16 (NT + 1); the NT tiles run on the matrix cores and column
-// 16 NT on the vector ALU (one FP64 FMA per L value instead of a sixteen-column MFMA
-// tile that carries one column), and the padding columns of part are written as zero.
+// c < tp.  Workgroup (group of kLtrWaves waves, chunk); a wave owns LB consecutive
+// blocks of 16 l and every 16-column tile of R, which the workgroup's waves read from
+// LDS (one l-block per wave measured faster than two once R came from LDS).  The
+// l-groups of one chunk are neighbours in launch order, so the chunk of R comes from
+// HBM once.  XC = 1: R has 16 NT + 1 meaningful columns (y and 16 NT probes) in
+// 16 (NT + 1); the NT tiles run on the matrix cores and column 16 NT on the vector ALU
+// (one FP64 FMA per L value instead of a sixteen-column MFMA tile that carries one
+// column), and the padding columns of part are written as zero.
 template <int NT>
-constexpr int ltr_lblocks() { return NT <= 8 ? 2 : 1; }
+constexpr int ltr_lblocks() { return 1; }
+constexpr int kLtrWaves = 8;
 
 template <int NT, int XC>
-__global__ __launch_bounds__(256) void k_ltr_mfma(const double* __restrict__ lf, const double* __restrict__ R,
+__global__ __launch_bounds__(64 * kLtrWaves) void k_ltr_mfma(const double* __restrict__ lf, const double* __restrict__ R,
                                                   int64_t n, int kpad, int tp, int64_t rows,
                                                   double* __restrict__ part, const int* __restrict__ nactive) {
   if (nactive != nullptr && *nactive == 0) return;
@@ -245,7 +247,7 @@ __global__ __launch_bounds__(256) void k_ltr_mfma(const double* __restrict__ lf,
   __shared__ __attribute__((aligned(16))) double rs[2][16 * TPC];
   // the wave index through the scalar unit, so the l-block tests below are uniform branches
   const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int mb0 = (blockIdx.x * 4 + wave) * LB;
+  const int mb0 = (blockIdx.x * kLtrWaves + wave) * LB;
   const int64_t i0 = (int64_t)blockIdx.y * rows, i1 = min(n, i0 + rows);
   const int m = lane & 15, kq = lane >> 4;
   const int nlb = kpad / 16;
@@ -261,7 +263,7 @@ __global__ __launch_bounds__(256) void k_ltr_mfma(const double* __restrict__ lf,
     for (int nb = 0; nb < NT; ++nb) acc[b][nb] = f64x4{0.0, 0.0, 0.0, 0.0};
   }
   // Per group of 16 rows (four K-steps): the group's R rows were copied global -> LDS
-  // (global_load_lds, 1 KB per wave instruction, shared by the four waves) and its L
+  // (global_load_lds, 1 KB per wave instruction, shared by the workgroup) and its L
   // operands loaded into registers during the previous group; L comes operand-ordered
   // (lf: zero past n and k) and needs no masks.  A chunk holds a multiple of 16 rows
   // except the last, which ends at n; R has n_pad >= rup(n, 16) rows, and rows past
@@ -272,7 +274,7 @@ __global__ __launch_bounds__(256) void k_ltr_mfma(const double* __restrict__ lf,
     const int64_t i = i0 + 16 * g;
     const u32x4* src = reinterpret_cast<const u32x4*>(R + i * tp);
     u32x4* dst = reinterpret_cast<u32x4*>(rs[g & 1]);
-    for (int un = wave; un < TPC / 8; un += 4)
+    for (int un = wave; un < TPC / 8; un += kLtrWaves)
       __builtin_amdgcn_global_load_lds(src + un * 64 + lane, (__attribute__((address_space(3))) void*)(dst + un * 64),
                                        16, 0, 0);
 #pragma unroll
@@ -520,8 +522,8 @@ template <int NT, int XC>
 static void ltr_launch(const Ctx& c, const double* Rsrc, double* part, const int* nact) {
   const Layout& L = *c.lay;
   const int kpad = (L.k + 15) / 16 * 16;
-  constexpr int wl = 4 * ltr_lblocks<NT>();  // l-blocks per workgroup
-  hipLaunchKernelGGL((k_ltr_mfma<NT, XC>), dim3((kpad / 16 + wl - 1) / wl, L.nchunk_ltr), dim3(256), 0, c.st,
+  constexpr int wl = kLtrWaves * ltr_lblocks<NT>();  // l-blocks per workgroup
+  hipLaunchKernelGGL((k_ltr_mfma<NT, XC>), dim3((kpad / 16 + wl - 1) / wl, L.nchunk_ltr), dim3(64 * kLtrWaves), 0, c.st,
                      c.at<double>(L.lf_ltr), Rsrc, L.n, kpad, L.tp, L.ltr_rows, part, nact);
 }
 
