@@ -445,7 +445,10 @@ __global__ void kb_zero_i32(int* __restrict__ p, int64_t count) {
   if (e < count) p[e] = 0;
 }
 
-// W = s (sum of the problem's split partials) + sigma^2 P; partial p.w
+// W = s (sum of the problem's split partials) + sigma^2 P; partial p.w.  Thread = four
+// consecutive columns (one vector load per split and row) x 1024 / tp row lanes; four
+// rows per pass, all their split loads in flight together; rows past the problem's n
+// get W = 0.  The row lanes' dot sums are added in a fixed order.
 template <typename T>
 __global__ __launch_bounds__(256) void kb_reduce(const BDesc* __restrict__ desc, const int32_t* __restrict__ blkprob,
                                                  const T* __restrict__ wpart, int64_t N, int tp,
@@ -453,32 +456,61 @@ __global__ __launch_bounds__(256) void kb_reduce(const BDesc* __restrict__ desc,
                                                  double* __restrict__ part, const int* __restrict__ nactive,
                                                  const int* __restrict__ pact) {
   if (*nactive == 0) return;
-  __shared__ double red[256];
+  typedef T T4 __attribute__((ext_vector_type(4)));
+  typedef double D4 __attribute__((ext_vector_type(4)));
+  __shared__ double red[1024];
   const int b = blkprob[blockIdx.x];
   if (pact[b] == 0) return;
   const BDesc& D = desc[b];
-  const int G = 256 / tp;
-  const int c = threadIdx.x % tp, rg = threadIdx.x / tp;
+  const int nq = tp / 4, G = 256 / nq;
+  const int cq = threadIdx.x % nq, rg = threadIdx.x / nq;
   const int64_t i0 = (int64_t)(blockIdx.x - D.blk0) * kBRows;
-  double dot = 0.0;
+  double dot[4] = {0.0, 0.0, 0.0, 0.0};
   if (rg < G) {
-    for (int q = rg; q < kBRows; q += G) {
-      const int64_t i = i0 + q;
-      const int64_t row = D.off + i;
-      const int64_t e = row * tp + c;
-      if (i >= D.n) {
-        W[e] = 0.0;
-        continue;
+    for (int q0 = rg; q0 < kBRows; q0 += 4 * G) {
+      int64_t row[4];
+      bool inb[4];
+      double w[4][4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int q = q0 + j * G;
+        inb[j] = q < kBRows;
+        // the block's rows all exist in the partials, so a clamped row needs no condition
+        row[j] = D.off + i0 + (inb[j] ? q : kBRows - 1);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) w[j][v] = 0.0;
       }
-      double w = 0.0;
-      for (int s = 0; s < D.nsplit; ++s) w += (double)wpart[((int64_t)s * N + row) * tp + c];
-      const double pv = P[e];
-      w = D.s * w + D.s2 * pv;
-      W[e] = w;
-      dot += pv * w;
+      for (int s = 0; s < D.nsplit; ++s) {
+        T4 pv[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) pv[j] = *reinterpret_cast<const T4*>(wpart + ((int64_t)s * N + row[j]) * tp + 4 * cq);
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) w[j][v] += (double)pv[j][v];
+      }
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        if (!inb[j]) continue;
+        const int64_t e = row[j] * tp + 4 * cq;
+        if (i0 + q0 + j * G >= D.n) {
+          *reinterpret_cast<D4*>(W + e) = D4{0.0, 0.0, 0.0, 0.0};
+          continue;
+        }
+        const D4 pv = *reinterpret_cast<const D4*>(P + e);
+        D4 wv;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          wv[v] = D.s * w[j][v] + D.s2 * pv[v];
+          dot[v] += pv[v] * wv[v];
+        }
+        *reinterpret_cast<D4*>(W + e) = wv;
+      }
     }
   }
-  red[threadIdx.x] = rg < G ? dot : 0.0;
+#pragma unroll
+  for (int v = 0; v < 4; ++v)
+    if (rg < G) red[rg * tp + 4 * cq + v] = dot[v];
   __syncthreads();
   if ((int)threadIdx.x < tp) {
     double s = 0.0;
